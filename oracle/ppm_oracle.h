@@ -1,0 +1,132 @@
+/*
+ * ppm_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 CPU implementation of the dimensionally split
+ * direct-Eulerian PPM update of the Enzo method paper (arXiv:1307.2265,
+ * Sec. "Hydrodynamics: The PPM method", Eqs. mass_diff, momentum_diff,
+ * energy_diff, gasenergy_diff, the dual-energy selection rules, the
+ * two-shock Riemann solver with HLL fallback of Sec. "Riemann Solvers and
+ * Fallback", and the hydro CFL condition of Sec. "Timestepping").  The
+ * reconstruction, steepening, flattening and characteristic tracing that the
+ * paper defers to Colella & Woodward (1984, "CW84") follow CW84's equations
+ * 1.6-1.10, 1.14-1.17, 3.5-3.7 and its appendix, as read for a uniform grid.
+ *
+ * Only tests, the smoke check and the benchmark's CPU-baseline leg may call
+ * this library.  It shares no code with the HIP path.
+ *
+ * Conventions (all host pointers, owned by the caller):
+ *   - A grid has nx*ny*nz active cells and `ghost` ghost layers per side (3, as
+ *     the paper's PPM stencil needs; 3..6 accepted).  With 3 layers the CW84
+ *     flattening coefficient of the outermost reconstructed cell cannot see its
+ *     outer neighbour and omits it; 4 layers give every needed cell its full
+ *     stencil.
+ *     Every field is an array of (nz+2g)*(ny+2g)*(nx+2g) doubles, x fastest.
+ *   - Fields: rho (density), vx, vy, vz (velocity), etot (specific total
+ *     energy E), eint (specific internal energy e, the dual-energy field).
+ *   - flux_reg (nullable) receives dt*F at the six active-region boundary
+ *     faces: [face: -x,+x,-y,+y,-z,+z][field: rho,mx,my,mz,E,e][t2][t1],
+ *     t1/t2 the two transverse axes in increasing order (t1 fastest); faces
+ *     normal to x hold ny*nz values per field, y: nx*nz, z: nx*ny.
+ * Return values: 0 on success, -1 on an invalid argument.
+ */
+#ifndef PPM_ORACLE_H
+#define PPM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PPMO_STEEPEN = 1u,      /* CW84 contact steepening of the density parabola */
+  PPMO_FLATTEN = 2u,      /* CW84 appendix shock flattening */
+  PPMO_DUAL_ENERGY = 4u,  /* eta1 pressure selection and eta2 resync */
+  PPMO_FALLBACK_HLL = 8u  /* re-solve faces of non-positive cells with HLL */
+};
+
+typedef struct {
+  double gamma;        /* ratio of specific heats, > 1 */
+  double cfl;          /* kappa_hydro in (0, 1] */
+  double eta1, eta2;   /* dual-energy thresholds (1e-3 and 0.1 in the paper) */
+  double rho_floor, p_floor, e_floor;
+  double riemann_rtol; /* relative convergence tolerance on p* */
+  int32_t riemann_max_iter;
+  uint32_t flags;
+} ppmo_params;
+
+typedef struct {
+  int32_t nx, ny, nz, ghost;
+  double dx, dy, dz;
+  double *rho, *vx, *vy, *vz, *etot, *eint;
+  double *flux_reg; /* nullable */
+} ppmo_grid;
+
+/* Counters of the rare numerical events of a sweep or step. */
+typedef struct {
+  int64_t fallback_faces; /* faces re-solved with HLL */
+  int64_t floored_cells;  /* cells still non-positive after the fallback */
+} ppmo_counts;
+
+/* Number of doubles one grid's flux register holds. */
+int64_t ppmo_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
+
+/* One full step: three 1-D sweeps in the order given by sweep_order
+ * (0:xyz 1:zyx 2:xzy 3:yxz 4:yzx 5:zxy).  Sweep k updates the cells that are
+ * active along the axes already swept and along its own axis, and every
+ * index (ghosts included) along the axes still to come.  counts may be NULL. */
+int ppmo_step(ppmo_grid *g, const ppmo_params *p, double dt, int32_t sweep_order,
+              ppmo_counts *counts);
+
+/* One sweep along `axis` (0,1,2).  Bit a of active_mask set means the
+ * transverse axis a is restricted to its active range, else all indices. */
+int ppmo_sweep(ppmo_grid *g, const ppmo_params *p, double dt, int32_t axis,
+               int32_t active_mask, ppmo_counts *counts);
+
+/* One 1-D pencil of n = N + 2*ghost cells, updated in place (active cells
+ * ghost..n-ghost-1).  u is the normal velocity, v1/v2 the transverse ones.
+ * reg_lo/reg_hi (nullable) receive dt*(F_rho, F_u, F_v1, F_v2, F_E, F_e) at the
+ * first and last active faces. */
+int ppmo_pencil(const ppmo_params *p, int32_t n, int32_t ghost, double dt, double dx,
+                double *rho, double *u, double *v1, double *v2, double *etot,
+                double *eint, double *reg_lo, double *reg_hi, ppmo_counts *counts);
+
+/* max over active cells of sum_d (c_s + |v_d|)/dx_d, and kappa / that max. */
+double ppmo_cfl_signal_max(const ppmo_grid *g, const ppmo_params *p);
+double ppmo_cfl_dt(const ppmo_grid *g, const ppmo_params *p);
+
+/* Periodic ghost fill of all six fields: q(ghost i) = q(active image of i). */
+int ppmo_fill_periodic(ppmo_grid *g);
+
+/* Two-shock Riemann solver on (rho,u,p) left/right states.
+ * out[0]=p*, out[1]=u*, out[2..4] = sampled (rho,u,p) at x/t=0,
+ * out[5] = iterations taken, out[6] = 1 if the left side is upwind. */
+void ppmo_two_shock(const ppmo_params *p, const double left[3], const double right[3],
+                    double out[7]);
+
+/* HLL flux (Davis wave speeds) on traced states (rho,u,v1,v2,p), each
+ * state's internal energy being p/((gamma-1) rho):
+ * out = F_rho, F_u, F_v1, F_v2, F_E, F_e, face velocity. */
+void ppmo_hll_flux(const ppmo_params *p, const double left[5], const double right[5],
+                   double out[7]);
+
+/* Exact Riemann solution of the Euler equations (ideal gas) by bisection on
+ * the pressure function; samples rho,u,p at x/t = xi[k].  star[0]=p*,
+ * star[1]=u*, star[2]=rho*_L, star[3]=rho*_R. */
+void ppmo_exact_riemann(double gamma, const double left[3], const double right[3],
+                        int32_t nxi, const double *xi, double *rho, double *u,
+                        double *p, double star[4]);
+
+/* Algorithmic operation counts of one step on the given grid (the grid is
+ * advanced exactly as ppmo_step does).  ops = {add/sub, mul, div, sqrt,
+ * compare, cell-sweeps performed}. */
+int ppmo_count_ops(ppmo_grid *g, const ppmo_params *p, double dt, int32_t sweep_order,
+                   int64_t ops[6]);
+
+/* Threads the OpenMP runtime will use (1 without OpenMP). */
+int ppmo_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,131 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module holds none of the method's arithmetic: it draws random primitive
+fields and converts them to the stored variables (density, velocity, specific
+total energy E = p/((gamma-1) rho) + |v|^2/2 and specific internal energy
+e = p/((gamma-1) rho)), which is the definition of the initial state.  Ghost
+zones are left at zero for periodic grids (each path fills its own), or drawn
+like the active cells for patches whose ghosts are seeded.
+
+Recipe (numpy PCG64, one generator per grid; whole arrays are drawn in C
+order (z, y, x) in the order rho, vx, vy, vz, p):
+  * density: mean-one lognormal, rho = exp(sigma Z - sigma^2/2);
+  * velocity: independent Gaussians per component with standard deviation
+    vel_sigma * c_ref, c_ref = sqrt(gamma <p>/<rho>) = sqrt(gamma);
+  * pressure: 1 + amp U(-1, 1) ("uniform") or a mean-one lognormal.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+GAMMA = 5.0 / 3.0
+GHOST = 3
+
+
+@dataclass(frozen=True)
+class FieldRecipe:
+    rho_sigma: float          # sigma of ln(rho)
+    vel_sigma: float          # per-component std of v in units of c_ref
+    p_kind: str               # "uniform" or "lognormal"
+    p_param: float            # amplitude (uniform) or sigma of ln(p)
+
+
+# config 0/1: gentle white noise; config 2/3: strongly shocked (rms Mach 5).
+GENTLE = FieldRecipe(0.5, 0.5, "uniform", 0.1)
+SHOCKED = FieldRecipe(2.0, 5.0 / np.sqrt(3.0), "lognormal", 1.0)
+
+
+def _draw(rng: np.random.Generator, shape, recipe: FieldRecipe, gamma: float):
+    c_ref = np.sqrt(gamma)
+    s = recipe.rho_sigma
+    rho = np.exp(s * rng.standard_normal(shape) - 0.5 * s * s)
+    v = [recipe.vel_sigma * c_ref * rng.standard_normal(shape) for _ in range(3)]
+    if recipe.p_kind == "uniform":
+        p = 1.0 + recipe.p_param * rng.uniform(-1.0, 1.0, shape)
+    else:
+        sp = recipe.p_param
+        p = np.exp(sp * rng.standard_normal(shape) - 0.5 * sp * sp)
+    return rho, v, p
+
+
+def stored_from_primitive(rho, vx, vy, vz, p, gamma: float):
+    """(rho, v, p) -> stored fields (rho, vx, vy, vz, E, e)."""
+    e = p / ((gamma - 1.0) * rho)
+    etot = e + 0.5 * (vx * vx + vy * vy + vz * vz)
+    return rho, vx, vy, vz, etot, e
+
+
+def random_grid(nx: int, ny: int, nz: int, seed: int, recipe: FieldRecipe = GENTLE,
+                gamma: float = GAMMA, seeded_ghosts: bool = False,
+                ghost: int = GHOST) -> dict:
+    """Return dict of six float64 arrays of shape (nz+2g, ny+2g, nx+2g).
+
+    With seeded_ghosts=False only the active cells are drawn and the ghosts
+    are zero (to be filled periodically); otherwise the whole box is drawn.
+    """
+    g = ghost
+    full = (nz + 2 * g, ny + 2 * g, nx + 2 * g)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = full if seeded_ghosts else (nz, ny, nx)
+    rho, (vx, vy, vz), p = _draw(rng, shape, recipe, gamma)
+    stored = stored_from_primitive(rho, vx, vy, vz, p, gamma)
+    out = {}
+    for name, a in zip(("rho", "vx", "vy", "vz", "etot", "eint"), stored):
+        if seeded_ghosts:
+            out[name] = np.ascontiguousarray(a, dtype=np.float64)
+        else:
+            b = np.zeros(full)
+            b[g:g + nz, g:g + ny, g:g + nx] = a
+            out[name] = b
+    return out
+
+
+def uniform_grid(nx, ny, nz, rho, v, p, gamma=GAMMA, ghost=GHOST) -> dict:
+    g = ghost
+    full = (nz + 2 * g, ny + 2 * g, nx + 2 * g)
+    st = stored_from_primitive(np.float64(rho), np.float64(v[0]), np.float64(v[1]),
+                               np.float64(v[2]), np.float64(p), gamma)
+    return {n: np.full(full, a, dtype=np.float64)
+            for n, a in zip(("rho", "vx", "vy", "vz", "etot", "eint"), st)}
+
+
+# ---------------------------------------------------------------------------
+# Batched AMR patches (uneven sizes and levels, seeded ghosts).
+
+PATCH_DIMS = (8, 12, 16, 24, 32)
+
+
+@dataclass
+class PatchSpec:
+    nx: int
+    ny: int
+    nz: int
+    level: int
+    dx: float
+    seed: int
+
+
+def patch_specs(npatch: int, seed: int, max_level: int = 6, dims=PATCH_DIMS) -> list:
+    """Per-axis dims i.i.d. from `dims`, level uniform in 0..max_level, dx = 2^-level."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = rng.choice(np.asarray(dims), size=(npatch, 3))
+    lev = rng.integers(0, max_level + 1, size=npatch)
+    sub = rng.integers(0, 2**62, size=npatch)
+    return [PatchSpec(int(a), int(b), int(c), int(l), 2.0 ** -int(l), int(s))
+            for (a, b, c), l, s in zip(d, lev, sub)]
+
+
+def patch_fields(spec: PatchSpec, recipe: FieldRecipe = SHOCKED, gamma: float = GAMMA) -> dict:
+    return random_grid(spec.nx, spec.ny, spec.nz, spec.seed, recipe, gamma, seeded_ghosts=True)
+
+
+# ---------------------------------------------------------------------------
+# Named workloads.
+
+CONFIGS = {
+    0: dict(n=32, recipe=GENTLE, seed=1000, steps=1),
+    1: dict(n=256, recipe=GENTLE, seed=1001, steps=10),
+    2: dict(n=512, recipe=SHOCKED, seed=1002, steps=20),
+}
