@@ -1,0 +1,166 @@
+/*
+ * ppm.h -- C ABI of the MI355X PPM hydrodynamics library (libppm.so).
+ *
+ * The library advances block-structured grid patches by one step of the
+ * dimensionally split, direct-Eulerian piecewise parabolic method described
+ * in the Enzo method paper (arXiv:1307.2265), Sec. "Hydrodynamics: The PPM
+ * method": per 1-D sweep, dual-energy pressure (Sec. "The dual energy
+ * formulation", pressure selection rule with eta1), CW84 parabolic
+ * reconstruction with monotonicity limiting, contact steepening and shock
+ * flattening, characteristic tracing, a two-shock Riemann solver with HLL
+ * fallback (Sec. "Riemann Solvers and Fallback"), the conservative update
+ * (Eqs. mass_diff, momentum_diff, energy_diff) with the internal-energy
+ * update (Eq. gasenergy_diff) and the eta2 resync (Eq. dualselect), the
+ * boundary fluxes that flux correction needs (Sec. "Flux correction"), and
+ * the hydro CFL timestep (Sec. "Timestepping", harmonic multi-D form).
+ * Cosmological expansion and gravity source terms are not included (a = 1,
+ * g = 0).
+ *
+ * Data layout.  Every patch holds nx*ny*nz active cells surrounded by `ghost`
+ * ghost layers (Sec. "Adaptive mesh refinement": 3 for PPM).  Each field is a
+ * separate device array of (nz+2g)*(ny+2g)*(nx+2g) elements, x fastest.
+ * Fields: rho (density), vx, vy, vz (velocity), etot (specific total energy
+ * E = e + |v|^2/2), eint (specific internal energy e, the dual-energy field).
+ * PPM_FP64 stores all six as double.  PPM_MIXED stores rho, vx, vy, vz as
+ * float and etot, eint as double; it reconstructs and traces in float and
+ * keeps the Riemann iteration, the energy updates and the dual-energy
+ * selection in double.
+ *
+ * Flux registers (optional, per patch, device, double): dt * F at the six
+ * faces of the active region, laid out
+ *   [face: -x,+x,-y,+y,-z,+z][field: rho, mx, my, mz, E, e][t2][t1]
+ * with t1 < t2 the axes transverse to the face (t1 fastest), so a face normal
+ * to x holds ny*nz values per field, normal to y nx*nz, normal to z nx*ny.
+ * The mass flux through a face is rho*u, the momentum fluxes rho*u*v (+p on
+ * the normal component), the energy flux rho*u*E + u*p, and the internal
+ * energy flux rho*u*e; the p div v term of the internal-energy equation is a
+ * source, not a flux, and is not recorded.
+ *
+ * Ownership.  The caller owns every field, register and dt array (device
+ * memory, e.g. torch tensors); a plan owns only its own metadata and
+ * workspace.  ppm_fill_periodic, ppm_cfl_dt, ppm_step and ppm_sweep allocate
+ * nothing and only enqueue work on the given stream, so they can be captured
+ * into a HIP graph; dt stays on the device between them.  A plan must be
+ * used from one stream at a time.
+ *
+ * Errors.  Every call validates its arguments before it launches anything
+ * and returns PPM_EINVAL (nothing launched) with a message readable through
+ * ppm_last_error() (thread-local).  HIP runtime failures return PPM_EHIP.
+ * Numerical events (HLL fallback faces, floored cells) are counters, not
+ * errors.
+ */
+#ifndef PPM_H
+#define PPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PPM_OK = 0,
+  PPM_EINVAL = -1,      /* invalid argument; nothing was launched */
+  PPM_ENOMEM = -2,      /* device or host allocation failed (plan creation only) */
+  PPM_EHIP = -3,        /* a HIP runtime call failed */
+  PPM_EUNSUPPORTED = -4 /* valid request this build does not support */
+} ppm_status;
+
+typedef enum { PPM_FP64 = 0, PPM_MIXED = 1 } ppm_precision;
+
+enum {
+  PPM_STEEPEN = 1u,      /* contact steepening of the density parabola */
+  PPM_FLATTEN = 2u,      /* shock flattening of all parabolas */
+  PPM_DUAL_ENERGY = 4u,  /* eta1 pressure selection and eta2 resync of e */
+  PPM_FALLBACK_HLL = 8u, /* re-solve the faces of non-positive cells with HLL */
+  PPM_ALL_FLAGS = 15u
+};
+
+/* One grid patch.  All pointers are device pointers owned by the caller. */
+typedef struct {
+  int32_t nx, ny, nz; /* active cells per axis, >= 1 */
+  int32_t ghost;      /* ghost layers per side, 3..6 (3 in the paper) */
+  int32_t level;      /* index into the per-level dt array, 0 <= level < nlevels */
+  int32_t reserved;   /* must be 0 */
+  double dx, dy, dz;  /* cell widths, > 0 */
+  void *rho, *vx, *vy, *vz; /* double (PPM_FP64) or float (PPM_MIXED) */
+  double *etot, *eint;      /* double in both precisions */
+  double *flux_reg;         /* nullable; ppm_flux_reg_size(nx,ny,nz) doubles */
+} ppm_patch;
+
+typedef struct {
+  double gamma;            /* ratio of specific heats, > 1 */
+  double cfl;              /* kappa_hydro, 0 < cfl <= 1 */
+  double eta1, eta2;       /* dual-energy thresholds (paper: 1e-3, 0.1) */
+  double rho_floor, p_floor, e_floor; /* positive floors */
+  double riemann_rtol;     /* relative tolerance on the two-shock p*, > 0 */
+  int32_t riemann_max_iter;/* Newton iteration cap, >= 1 */
+  uint32_t flags;          /* PPM_STEEPEN | PPM_FLATTEN | ... */
+} ppm_params;
+
+typedef struct ppm_plan ppm_plan;
+
+/* Number of doubles in one patch's flux register. */
+int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
+
+/* Create a plan over `npatch` patches (host array, copied).  nlevels is the
+ * length of every dt array later passed in.  tile_config (nullable) is a
+ * text of "key=value" pairs separated by spaces that overrides the launch
+ * shapes; unknown keys are an error.  Keys:
+ *   lanes=M        axis bitmask: sweeps along axis a (bit a) give each pencil
+ *                  to a wavefront with its cells across the lanes; the other
+ *                  sweeps give each pencil to one thread that marches it.
+ *                  Default 1 (x only) for one patch, 0 for several.
+ *   block=B        threads per block of the marching kernel (64..256).
+ *   lanes_block=B  threads per block of the lane-parallel kernel (64..256).
+ *   cfl_cells=C    active cells per block of the CFL reduction.
+ * Results do not depend on the launch shapes.  Uploads the patch table to
+ * the device on `hip_stream` (0 = default stream) and allocates the event
+ * counters.  On success *out owns the plan. */
+ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npatch,
+                           int32_t nlevels, ppm_precision prec, const ppm_params *params,
+                           const char *tile_config, void *hip_stream);
+
+/* Release a plan (synchronises with nothing; the caller must make sure no
+ * enqueued work still uses it).  NULL is accepted. */
+ppm_status ppm_plan_destroy(ppm_plan *plan);
+
+/* Periodic ghost fill of every patch of the plan (each patch is treated as a
+ * periodic box of its own): ghost cell i takes the value of the active cell
+ * g + ((i - g) mod N) along every axis. */
+ppm_status ppm_fill_periodic(ppm_plan *plan, void *hip_stream);
+
+/* Hydro CFL timestep per level (Sec. "Timestepping"):
+ *   dt_dev[l] = cfl / max over the active cells of the level's patches of
+ *               sum_d (c_s + |v_d|) / dx_d,
+ * with c_s from the same dual-energy pressure the sweeps use.  dt_dev is a
+ * device array of nlevels doubles; levels without patches get +inf. */
+ppm_status ppm_cfl_dt(ppm_plan *plan, double *dt_dev, void *hip_stream);
+
+/* One full step of every patch with its level's dt (device array of nlevels
+ * doubles): three 1-D sweeps in the order sweep_order (0:xyz 1:zyx 2:xzy
+ * 3:yxz 4:yzx 5:zxy).  The k-th sweep updates the cells that are active along
+ * the axes swept so far and along its own axis, and every index (ghosts
+ * included) along the axes still to come, so one ghost fill per step
+ * suffices.  Fields are updated in place; flux registers (if given) are
+ * overwritten with dt*F of the face's own sweep. */
+ppm_status ppm_step(ppm_plan *plan, const double *dt_dev, int32_t sweep_order,
+                    void *hip_stream);
+
+/* One sweep along `axis` (0,1,2) of every patch; bit a of active_mask
+ * restricts transverse axis a to its active range (else all indices). */
+ppm_status ppm_sweep(ppm_plan *plan, const double *dt_dev, int32_t axis, int32_t active_mask,
+                     void *hip_stream);
+
+/* Read (synchronising `hip_stream`) and optionally reset the plan's event
+ * counters: faces re-solved with HLL, cells floored after the fallback. */
+ppm_status ppm_event_counts(ppm_plan *plan, int64_t *fallback_faces, int64_t *floored_cells,
+                            int32_t reset, void *hip_stream);
+
+const char *ppm_status_str(ppm_status s);
+const char *ppm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

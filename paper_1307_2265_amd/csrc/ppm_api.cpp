@@ -1,0 +1,369 @@
+// ppm_api.cpp -- the C ABI declared in include/ppm.h.
+//
+// A plan holds a device copy of the patch table and, for every sweep axis and
+// every choice of restricted transverse axes, a prefix array of pencil-chunk
+// counts, so that a sweep over any set of uneven patches is one launch of a
+// flat grid.  Argument validation happens here, before anything is enqueued.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ppm.h"
+#include "ppm_kernels.hpp"
+
+using ppm::PatchDev;
+
+struct ppm_plan {
+  int32_t npatch = 0, nlevels = 0;
+  ppm_precision prec = PPM_FP64;
+  ppm::Params P{};
+  int32_t block = 256;            // threads (pencils) per marching-sweep block
+  int32_t lanes_block = 256;      // threads per lane-parallel block (64 per pencil)
+  int32_t lanes_mask = 1;         // bit a: sweeps along axis a use the lane-parallel kernel
+  int32_t cfl_cells = 4096;       // active cells per CFL block
+  std::vector<PatchDev> host;
+  PatchDev *d_patches = nullptr;
+  int32_t *d_chunks = nullptr;    // 12 marching, 12 lane-parallel prefix arrays, then CFL
+  int32_t nblocks[24] = {};
+  int32_t cfl_blocks = 0;
+  unsigned long long *d_counters = nullptr;  // fallback faces, floored cells
+  unsigned long long *d_smax = nullptr;      // per-level max signal speed bits
+  int device = 0;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ppm_status fail(ppm_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+ppm_status hip_fail(hipError_t e, const char *what) {
+  return fail(PPM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+const int kOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
+
+inline int t1_of(int axis) { return axis == 0 ? 1 : 0; }
+inline int t2_of(int axis) { return axis == 2 ? 1 : 2; }
+inline int tmask_of(int axis, int mask) {
+  return ((mask >> t1_of(axis)) & 1) | (((mask >> t2_of(axis)) & 1) << 1);
+}
+
+ppm_status check_params(const ppm_params *p) {
+  if (!p) return fail(PPM_EINVAL, "params is NULL");
+  if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(PPM_EINVAL, "gamma must be > 1");
+  if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(PPM_EINVAL, "cfl must be in (0, 1]");
+  if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(PPM_EINVAL, "eta1/eta2 must be >= 0");
+  if (!(p->rho_floor > 0.0) || !(p->p_floor > 0.0) || !(p->e_floor > 0.0))
+    return fail(PPM_EINVAL, "floors must be > 0");
+  if (!(p->riemann_rtol > 0.0)) return fail(PPM_EINVAL, "riemann_rtol must be > 0");
+  if (p->riemann_max_iter < 1 || p->riemann_max_iter > 1000)
+    return fail(PPM_EINVAL, "riemann_max_iter must be in [1, 1000]");
+  if (p->flags & ~uint32_t(PPM_ALL_FLAGS)) return fail(PPM_EINVAL, "unknown flag bits 0x%x", p->flags);
+  return PPM_OK;
+}
+
+ppm_status check_patch(const ppm_patch &q, int i, int32_t nlevels) {
+  if (q.nx < 1 || q.ny < 1 || q.nz < 1)
+    return fail(PPM_EINVAL, "patch %d: active dims must be >= 1", i);
+  if (q.ghost < 3 || q.ghost > 6) return fail(PPM_EINVAL, "patch %d: ghost must be in 3..6", i);
+  if (q.level < 0 || q.level >= nlevels)
+    return fail(PPM_EINVAL, "patch %d: level %d outside [0, %d)", i, q.level, nlevels);
+  if (q.reserved != 0) return fail(PPM_EINVAL, "patch %d: reserved must be 0", i);
+  if (!(q.dx > 0.0) || !(q.dy > 0.0) || !(q.dz > 0.0) || !std::isfinite(q.dx) ||
+      !std::isfinite(q.dy) || !std::isfinite(q.dz))
+    return fail(PPM_EINVAL, "patch %d: cell widths must be finite and > 0", i);
+  if (!q.rho || !q.vx || !q.vy || !q.vz || !q.etot || !q.eint)
+    return fail(PPM_EINVAL, "patch %d: NULL field pointer", i);
+  const int64_t lim = int64_t(1) << 30;
+  const int64_t nf[3] = {int64_t(q.nx) + 2 * q.ghost, int64_t(q.ny) + 2 * q.ghost,
+                         int64_t(q.nz) + 2 * q.ghost};
+  if (nf[0] > lim || nf[1] > lim || nf[2] > lim || nf[0] * nf[1] > lim)
+    return fail(PPM_EINVAL, "patch %d: too large (a face of the ghosted box exceeds 2^30 cells)", i);
+  return PPM_OK;
+}
+
+ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
+  if (!cfg) return PPM_OK;
+  std::istringstream ss(cfg);
+  std::string tok;
+  while (ss >> tok) {
+    const size_t eq = tok.find('=');
+    if (eq == std::string::npos) return fail(PPM_EINVAL, "tile_config: bad token '%s'", tok.c_str());
+    const std::string k = tok.substr(0, eq);
+    char *end = nullptr;
+    const long v = strtol(tok.c_str() + eq + 1, &end, 10);
+    if (!end || *end) return fail(PPM_EINVAL, "tile_config: bad value in '%s'", tok.c_str());
+    if (k == "block") {
+      if (v < 64 || v > ppm::kMaxBlock || v % 64) return fail(PPM_EINVAL, "tile_config: block must be 64..256, a multiple of 64");
+      pl->block = int32_t(v);
+    } else if (k == "lanes") {
+      if (v < 0 || v > 7) return fail(PPM_EINVAL, "tile_config: lanes is an axis bitmask 0..7");
+      pl->lanes_mask = int32_t(v);
+    } else if (k == "lanes_block") {
+      if (v < 64 || v > ppm::kMaxBlock || v % 64) return fail(PPM_EINVAL, "tile_config: lanes_block must be 64..256, a multiple of 64");
+      pl->lanes_block = int32_t(v);
+    } else if (k == "cfl_cells") {
+      if (v < 256 || v > (1 << 24)) return fail(PPM_EINVAL, "tile_config: cfl_cells out of range");
+      pl->cfl_cells = int32_t(v);
+    } else {
+      return fail(PPM_EINVAL, "tile_config: unknown key '%s'", k.c_str());
+    }
+  }
+  return PPM_OK;
+}
+
+void free_plan(ppm_plan *p) {
+  if (!p) return;
+  if (p->d_patches) (void)hipFree(p->d_patches);
+  if (p->d_chunks) (void)hipFree(p->d_chunks);
+  if (p->d_counters) (void)hipFree(p->d_counters);
+  if (p->d_smax) (void)hipFree(p->d_smax);
+  delete p;
+}
+
+template <class Prec>
+hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, hipStream_t s) {
+  const int tm = tmask_of(axis, mask);
+  if ((pl->lanes_mask >> axis) & 1) {
+    const int slot = 12 + axis * 4 + tm;
+    if (pl->nblocks[slot] == 0) return hipSuccess;
+    return ppm::launch_sweep_lanes<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
+                                         pl->npatch, pl->nblocks[slot], pl->lanes_block, axis,
+                                         mask, dt, pl->P, pl->d_counters, s);
+  }
+  const int slot = axis * 4 + tm;
+  if (pl->nblocks[slot] == 0) return hipSuccess;
+  return ppm::launch_sweep<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
+                                 pl->npatch, pl->nblocks[slot], pl->block, axis, mask, dt, pl->P,
+                                 pl->d_counters, s);
+}
+
+hipError_t sweep_any(ppm_plan *pl, const double *dt, int axis, int mask, hipStream_t s) {
+  return pl->prec == PPM_FP64 ? do_sweep<ppm::PrecF64>(pl, dt, axis, mask, s)
+                              : do_sweep<ppm::PrecMixed>(pl, dt, axis, mask, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz) {
+  return 12 * (int64_t(ny) * nz + int64_t(nx) * nz + int64_t(nx) * ny);
+}
+
+ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npatch,
+                           int32_t nlevels, ppm_precision prec, const ppm_params *params,
+                           const char *tile_config, void *hip_stream) {
+  if (!out) return fail(PPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!patches) return fail(PPM_EINVAL, "patches is NULL");
+  if (npatch < 1) return fail(PPM_EINVAL, "npatch must be >= 1");
+  if (nlevels < 1 || nlevels > 64) return fail(PPM_EINVAL, "nlevels must be in 1..64");
+  if (prec != PPM_FP64 && prec != PPM_MIXED) return fail(PPM_EINVAL, "unknown precision %d", int(prec));
+  ppm_status st = check_params(params);
+  if (st != PPM_OK) return st;
+  for (int i = 0; i < npatch; ++i)
+    if ((st = check_patch(patches[i], i, nlevels)) != PPM_OK) return st;
+
+  ppm_plan *pl = new (std::nothrow) ppm_plan();
+  if (!pl) return fail(PPM_ENOMEM, "host allocation failed");
+  pl->npatch = npatch;
+  pl->nlevels = nlevels;
+  pl->prec = prec;
+  std::memcpy(&pl->P, params, sizeof(ppm::Params));
+  static_assert(sizeof(ppm::Params) == sizeof(ppm_params), "params layout");
+  if (npatch > 1) {  // uneven small patches: finer chunks, every sweep marches
+    pl->block = 64;
+    pl->lanes_mask = 0;
+  }
+  if ((st = parse_tiles(pl, tile_config)) != PPM_OK) {
+    delete pl;
+    return st;
+  }
+  (void)hipGetDevice(&pl->device);
+  pl->host.resize(npatch);
+  for (int i = 0; i < npatch; ++i) {
+    const ppm_patch &q = patches[i];
+    PatchDev &d = pl->host[i];
+    d.n[0] = q.nx; d.n[1] = q.ny; d.n[2] = q.nz;
+    d.ghost = q.ghost; d.level = q.level; d.pad = 0;
+    d.dx[0] = q.dx; d.dx[1] = q.dy; d.dx[2] = q.dz;
+    d.rho = q.rho; d.vel[0] = q.vx; d.vel[1] = q.vy; d.vel[2] = q.vz;
+    d.etot = q.etot; d.eint = q.eint; d.flux_reg = q.flux_reg;
+  }
+  // prefix arrays of work chunks
+  const int stride = npatch + 1;
+  std::vector<int32_t> chunks(size_t(25) * stride, 0);
+  for (int kind = 0; kind < 2; ++kind)  // 0: marching (a thread per pencil), 1: lanes
+    for (int axis = 0; axis < 3; ++axis)
+      for (int tm = 0; tm < 4; ++tm) {
+        const int slot = kind * 12 + axis * 4 + tm;
+        const int64_t per_block = kind == 0 ? pl->block : pl->lanes_block / 64;
+        int64_t acc = 0;
+        int32_t *c = &chunks[size_t(slot) * stride];
+        const int t1 = t1_of(axis), t2 = t2_of(axis);
+        for (int i = 0; i < npatch; ++i) {
+          const PatchDev &d = pl->host[i];
+          const int64_t w1 = (tm & 1) ? d.n[t1] : d.n[t1] + 2 * d.ghost;
+          const int64_t w2 = (tm & 2) ? d.n[t2] : d.n[t2] + 2 * d.ghost;
+          c[i] = int32_t(acc);
+          acc += (w1 * w2 + per_block - 1) / per_block;
+          if (acc > std::numeric_limits<int32_t>::max() / 2) {
+            delete pl;
+            return fail(PPM_EINVAL, "too many pencils for one launch");
+          }
+        }
+        c[npatch] = int32_t(acc);
+        pl->nblocks[slot] = int32_t(acc);
+      }
+  {
+    int64_t acc = 0;
+    int32_t *c = &chunks[size_t(24) * stride];
+    for (int i = 0; i < npatch; ++i) {
+      const PatchDev &d = pl->host[i];
+      const int64_t cells = int64_t(d.n[0]) * d.n[1] * d.n[2];
+      c[i] = int32_t(acc);
+      acc += (cells + pl->cfl_cells - 1) / pl->cfl_cells;
+      if (acc > std::numeric_limits<int32_t>::max() / 2) {
+        delete pl;
+        return fail(PPM_EINVAL, "too many cells for one CFL launch");
+      }
+    }
+    c[npatch] = int32_t(acc);
+    pl->cfl_blocks = int32_t(acc);
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  if ((e = hipMalloc(&pl->d_patches, sizeof(PatchDev) * npatch)) != hipSuccess ||
+      (e = hipMalloc(&pl->d_chunks, sizeof(int32_t) * chunks.size())) != hipSuccess ||
+      (e = hipMalloc(&pl->d_counters, 2 * sizeof(unsigned long long))) != hipSuccess ||
+      (e = hipMalloc(&pl->d_smax, nlevels * sizeof(unsigned long long))) != hipSuccess) {
+    free_plan(pl);
+    return fail(PPM_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
+  }
+  std::vector<unsigned long long> zeros(size_t(nlevels) + 2, 0ull);
+  if ((e = hipMemcpyAsync(pl->d_patches, pl->host.data(), sizeof(PatchDev) * npatch,
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(pl->d_chunks, chunks.data(), sizeof(int32_t) * chunks.size(),
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(pl->d_counters, zeros.data(), 2 * sizeof(unsigned long long),
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(pl->d_smax, zeros.data(), nlevels * sizeof(unsigned long long),
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    free_plan(pl);
+    return hip_fail(e, "plan upload");
+  }
+  *out = pl;
+  return PPM_OK;
+}
+
+ppm_status ppm_plan_destroy(ppm_plan *plan) {
+  free_plan(plan);
+  return PPM_OK;
+}
+
+ppm_status ppm_fill_periodic(ppm_plan *plan, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  for (int i = 0; i < plan->npatch; ++i) {
+    hipError_t e = plan->prec == PPM_FP64 ? ppm::launch_fill<ppm::PrecF64>(plan->host[i], s)
+                                          : ppm::launch_fill<ppm::PrecMixed>(plan->host[i], s);
+    if (e != hipSuccess) return hip_fail(e, "fill_periodic launch");
+  }
+  return PPM_OK;
+}
+
+ppm_status ppm_cfl_dt(ppm_plan *plan, double *dt_dev, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int32_t *cs = plan->d_chunks + size_t(24) * (plan->npatch + 1);
+  hipError_t e = plan->prec == PPM_FP64
+      ? ppm::launch_cfl<ppm::PrecF64>(plan->d_patches, cs, plan->npatch, plan->cfl_blocks,
+                                      plan->cfl_cells, plan->nlevels, plan->P, plan->d_smax,
+                                      dt_dev, s)
+      : ppm::launch_cfl<ppm::PrecMixed>(plan->d_patches, cs, plan->npatch, plan->cfl_blocks,
+                                        plan->cfl_cells, plan->nlevels, plan->P, plan->d_smax,
+                                        dt_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "cfl launch");
+  return PPM_OK;
+}
+
+ppm_status ppm_sweep(ppm_plan *plan, const double *dt_dev, int32_t axis, int32_t active_mask,
+                     void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
+  if (axis < 0 || axis > 2) return fail(PPM_EINVAL, "axis must be 0, 1 or 2");
+  if (active_mask < 0 || active_mask > 7) return fail(PPM_EINVAL, "active_mask must be in 0..7");
+  hipError_t e = sweep_any(plan, dt_dev, axis, active_mask & ~(1 << axis),
+                           static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  return PPM_OK;
+}
+
+ppm_status ppm_step(ppm_plan *plan, const double *dt_dev, int32_t sweep_order,
+                    void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
+  if (sweep_order < 0 || sweep_order > 5) return fail(PPM_EINVAL, "sweep_order must be in 0..5");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int mask = 0;
+  for (int k = 0; k < 3; ++k) {
+    const int axis = kOrders[sweep_order][k];
+    hipError_t e = sweep_any(plan, dt_dev, axis, mask, s);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    mask |= 1 << axis;
+  }
+  return PPM_OK;
+}
+
+ppm_status ppm_event_counts(ppm_plan *plan, int64_t *fallback_faces, int64_t *floored_cells,
+                            int32_t reset, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  unsigned long long h[2] = {0, 0};
+  hipError_t e = hipMemcpyAsync(h, plan->d_counters, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "event counter read");
+  if (fallback_faces) *fallback_faces = int64_t(h[0]);
+  if (floored_cells) *floored_cells = int64_t(h[1]);
+  if (reset) {
+    static const unsigned long long z[2] = {0, 0};
+    e = hipMemcpyAsync(plan->d_counters, z, sizeof z, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "event counter reset");
+  }
+  return PPM_OK;
+}
+
+const char *ppm_status_str(ppm_status st) {
+  switch (st) {
+    case PPM_OK: return "PPM_OK";
+    case PPM_EINVAL: return "PPM_EINVAL: invalid argument";
+    case PPM_ENOMEM: return "PPM_ENOMEM: allocation failed";
+    case PPM_EHIP: return "PPM_EHIP: HIP runtime error";
+    case PPM_EUNSUPPORTED: return "PPM_EUNSUPPORTED: not supported";
+  }
+  return "unknown ppm_status";
+}
+
+const char *ppm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,321 @@
+// ppm_kernels.hip -- HIP kernels of the PPM library for gfx950.
+//
+//   * sweep_kernel: one 1-D PPM sweep over a set of patches.  The grid is a
+//     flat list of (patch, chunk of pencils) work items: block b finds its
+//     patch by binary search in a prefix array of chunk counts, and each
+//     thread of the block marches one pencil (ppm_sweep.hpp).  A single big
+//     grid is the one-patch case of the same kernel.
+//   * cfl_reduce_kernel / cfl_finalize_kernel: the hydro CFL timestep of
+//     every level (Sec. "Timestepping"): a wave-level max of the per-cell
+//     signal speed sum_d (c_s + |v_d|)/dx_d, a block max through LDS, and a
+//     device-wide max by atomicMax on the bit pattern of the non-negative
+//     double; the finalise kernel turns the max into dt and clears it.
+//   * fill_periodic_kernel: periodic ghost fill of one patch over its ghost
+//     shell only.
+#include "ppm_kernels.hpp"
+#include "ppm_lanes.hpp"
+
+namespace ppm {
+
+__device__ __forceinline__ int find_patch(const int32_t *start, int32_t npatch, int32_t b) {
+  int lo = 0, hi = npatch - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Select one of three values by a (wave-uniform) axis index without
+// indexing a private array, which would live in scratch memory.
+template <class V> __device__ __forceinline__ V pick3(int i, V a, V b, V c) {
+  return i == 0 ? a : (i == 1 ? b : c);
+}
+
+// Offset of the block of face (2*axis + hi) in a patch's flux register.
+__device__ __forceinline__ int64_t reg_face_offset(int64_t nx, int64_t ny, int64_t nz, int axis,
+                                                   int hi) {
+  const int64_t ax = ny * nz, ay = nx * nz, az = nx * ny;
+  const int64_t before = axis == 0 ? 0 : (axis == 1 ? 2 * ax : 2 * (ax + ay));
+  return 6 * (before + (hi ? pick3<int64_t>(axis, ax, ay, az) : 0));
+}
+
+// The pencil (i1, i2) of a sweep along `axis` of one patch.
+template <class S>
+__device__ __forceinline__ PencilRef<S> make_pencil(const PatchDev &pd, int axis, int i1, int i2) {
+  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+  const int g = pd.ghost;
+  const int N0 = pd.n[0], N1 = pd.n[1], N2 = pd.n[2];
+  const int nf0 = N0 + 2 * g, nf1 = N1 + 2 * g;
+  const int Na = pick3(axis, N0, N1, N2), Nt1 = pick3(t1, N0, N1, N2), Nt2 = pick3(t2, N0, N1, N2);
+  const int64_t sx = 1, sy = nf0, sz = int64_t(nf0) * nf1;
+  PencilRef<S> pc;
+  pc.rho = static_cast<S *>(pd.rho);
+  pc.u = static_cast<S *>(pick3(axis, pd.vel[0], pd.vel[1], pd.vel[2]));
+  pc.v1 = static_cast<S *>(pick3(t1, pd.vel[0], pd.vel[1], pd.vel[2]));
+  pc.v2 = static_cast<S *>(pick3(t2, pd.vel[0], pd.vel[1], pd.vel[2]));
+  pc.E = pd.etot;
+  pc.e = pd.eint;
+  pc.base = i1 * pick3(t1, sx, sy, sz) + i2 * pick3(t2, sx, sy, sz);
+  pc.stride = pick3(axis, sx, sy, sz);
+  pc.n = Na + 2 * g;
+  pc.g = g;
+  pc.dx = pick3(axis, pd.dx[0], pd.dx[1], pd.dx[2]);
+  pc.reg_lo = pc.reg_hi = nullptr;
+  pc.reg_stride = 0;
+  pc.lab[0] = 0; pc.lab[1] = 1 + axis; pc.lab[2] = 1 + t1; pc.lab[3] = 1 + t2;
+  pc.lab[4] = 4; pc.lab[5] = 5;
+  if (pd.flux_reg && i1 >= g && i1 < g + Nt1 && i2 >= g && i2 < g + Nt2) {
+    const int64_t ro = int64_t(i2 - g) * Nt1 + (i1 - g);
+    pc.reg_lo = pd.flux_reg + reg_face_offset(N0, N1, N2, axis, 0) + ro;
+    pc.reg_hi = pd.flux_reg + reg_face_offset(N0, N1, N2, axis, 1) + ro;
+    pc.reg_stride = int64_t(Nt1) * Nt2;
+  }
+  return pc;
+}
+
+// Pencil `idx` of the sweep's pencil set in one patch: transverse axes
+// restricted to their active range where `mask` says so.  False if idx is
+// past the end.
+__device__ __forceinline__ bool pencil_index(const PatchDev &pd, int axis, int mask, int idx,
+                                             int &i1, int &i2) {
+  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+  const int g = pd.ghost;
+  const int Nt1 = pick3(t1, pd.n[0], pd.n[1], pd.n[2]);
+  const int Nt2 = pick3(t2, pd.n[0], pd.n[1], pd.n[2]);
+  const bool r1 = (mask >> t1) & 1, r2 = (mask >> t2) & 1;
+  const int lo1 = r1 ? g : 0, w1 = r1 ? Nt1 : Nt1 + 2 * g;
+  const int lo2 = r2 ? g : 0, w2 = r2 ? Nt2 : Nt2 + 2 * g;
+  if (idx >= w1 * w2) return false;
+  i1 = lo1 + idx % w1;
+  i2 = lo2 + idx / w1;
+  return true;
+}
+
+// One thread marches one pencil.
+template <class Prec>
+__global__ void __launch_bounds__(kMaxBlock, 2)
+sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
+             int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
+             Params P, unsigned long long *__restrict__ counters) {
+  using S = typename Prec::S;
+  extern __shared__ double lds[];
+  const int p = find_patch(chunk_start, npatch, blockIdx.x);
+  const PatchDev pd = patches[p];
+  const int idx = (blockIdx.x - chunk_start[p]) * blockDim.x + threadIdx.x;
+  int i1, i2;
+  if (!pencil_index(pd, axis, mask, idx, i1, i2)) return;
+  const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+  const double dt = dt_dev[pd.level];
+  uint32_t nfb = 0, nfl = 0;
+  march_pencil<Prec>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl);
+  if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
+  if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
+}
+
+// One wavefront walks one pencil with its cells across the lanes.
+template <class Prec>
+__global__ void __launch_bounds__(kMaxBlock)
+sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
+                   int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
+                   Params P, unsigned long long *__restrict__ counters) {
+  using S = typename Prec::S;
+  const int p = find_patch(chunk_start, npatch, blockIdx.x);
+  const PatchDev pd = patches[p];
+  const int waves = blockDim.x >> 6;
+  const int idx = (blockIdx.x - chunk_start[p]) * waves + (threadIdx.x >> 6);
+  int i1, i2;
+  if (!pencil_index(pd, axis, mask, idx, i1, i2)) return;  // the whole wave leaves
+  const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+  const double dt = dt_dev[pd.level];
+  uint32_t nfb = 0, nfl = 0;
+  sweep_pencil_lanes<Prec>(P, pc, dt, nfb, nfl);
+  if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
+  if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
+}
+
+// ---------------------------------------------------------------------------
+// CFL reduction
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+template <class Prec>
+__global__ void __launch_bounds__(256)
+cfl_reduce_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
+                  int32_t npatch, int32_t cells_per_block, Params P,
+                  unsigned long long *__restrict__ smax_bits) {
+  using S = typename Prec::S;
+  __shared__ double wmax[kMaxBlock / 64];
+  const int p = find_patch(chunk_start, npatch, blockIdx.x);
+  const PatchDev pd = patches[p];
+  const int g = pd.ghost;
+  const int64_t nx = pd.n[0], ny = pd.n[1];
+  const int64_t total = nx * ny * pd.n[2];
+  const int64_t nfx = nx + 2 * g, nfy = ny + 2 * g;
+  const int64_t c0 = int64_t(blockIdx.x - chunk_start[p]) * cells_per_block;
+  const int64_t c1 = c0 + cells_per_block < total ? c0 + cells_per_block : total;
+  const S *rho = static_cast<const S *>(pd.rho);
+  const S *vx = static_cast<const S *>(pd.vel[0]);
+  const S *vy = static_cast<const S *>(pd.vel[1]);
+  const S *vz = static_cast<const S *>(pd.vel[2]);
+  double smax = 0.0;
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    const int64_t x = c % nx, yz = c / nx;
+    const int64_t y = yz % ny, z = yz / ny;
+    const int64_t o = ((z + g) * nfy + (y + g)) * nfx + (x + g);
+    const double r = double(rho[o]), u = double(vx[o]), v = double(vy[o]), w = double(vz[o]);
+    double pp, cs;
+    eos(P, r, u, v, w, pd.etot[o], pd.eint[o], pp, cs);
+    const double s = (cs + fabs(u)) / pd.dx[0] + (cs + fabs(v)) / pd.dx[1] + (cs + fabs(w)) / pd.dx[2];
+    smax = s > smax ? s : smax;
+  }
+  smax = wave_max(smax);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) wmax[wid] = smax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = wmax[0];
+    for (int i = 1; i < int(blockDim.x >> 6); ++i) m = wmax[i] > m ? wmax[i] : m;
+    // non-negative doubles order like their bit patterns
+    atomicMax(&smax_bits[pd.level], (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__global__ void cfl_finalize_kernel(int32_t nlevels, double cfl,
+                                    unsigned long long *__restrict__ smax_bits,
+                                    double *__restrict__ dt_dev) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlevels) return;
+  const double s = __longlong_as_double((long long)smax_bits[l]);
+  dt_dev[l] = s > 0.0 ? cfl / s : __longlong_as_double(0x7ff0000000000000LL);
+  smax_bits[l] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Periodic ghost fill of one patch: only ghost cells are visited.  The shell
+// is split into the two z slabs (full x, y), the two y slabs of the active z
+// range (full x), and the two x slabs of the active y, z range.
+
+template <class Prec>
+__global__ void __launch_bounds__(256)
+fill_periodic_kernel(PatchDev pd) {
+  using S = typename Prec::S;
+  const int g = pd.ghost;
+  const int64_t N[3] = {pd.n[0], pd.n[1], pd.n[2]};
+  const int64_t nf[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
+  const int64_t sz = 2 * g * nf[1] * nf[0];
+  const int64_t sy = N[2] * 2 * g * nf[0];
+  const int64_t sx = N[2] * N[1] * 2 * g;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= sz + sy + sx) return;
+  int64_t x, y, z;
+  if (t < sz) {
+    x = t % nf[0];
+    y = (t / nf[0]) % nf[1];
+    const int64_t k = t / (nf[0] * nf[1]);
+    z = k < g ? k : N[2] + k;
+  } else if (t < sz + sy) {
+    const int64_t u = t - sz;
+    x = u % nf[0];
+    const int64_t j = (u / nf[0]) % (2 * g);
+    y = j < g ? j : N[1] + j;
+    z = g + u / (nf[0] * 2 * g);
+  } else {
+    const int64_t u = t - sz - sy;
+    const int64_t i = u % (2 * g);
+    x = i < g ? i : N[0] + i;
+    y = g + (u / (2 * g)) % N[1];
+    z = g + u / (2 * g * N[1]);
+  }
+  auto wrap = [&](int64_t i, int d) { return g + (((i - g) % N[d]) + N[d]) % N[d]; };
+  const int64_t dst = (z * nf[1] + y) * nf[0] + x;
+  const int64_t src = (wrap(z, 2) * nf[1] + wrap(y, 1)) * nf[0] + wrap(x, 0);
+  S *rho = static_cast<S *>(pd.rho);
+  S *vx = static_cast<S *>(pd.vel[0]);
+  S *vy = static_cast<S *>(pd.vel[1]);
+  S *vz = static_cast<S *>(pd.vel[2]);
+  rho[dst] = rho[src];
+  vx[dst] = vx[src];
+  vy[dst] = vy[src];
+  vz[dst] = vz[src];
+  pd.etot[dst] = pd.etot[src];
+  pd.eint[dst] = pd.eint[src];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+template <class Prec>
+hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                        int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
+                        const double *dt_dev, const Params &P, unsigned long long *counters,
+                        hipStream_t s) {
+  const size_t lds = (P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block * sizeof(double) : 0;
+  hipLaunchKernelGGL(sweep_kernel<Prec>, dim3(nblocks), dim3(block), lds, s, patches,
+                     chunk_start, npatch, axis, mask, dt_dev, P, counters);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                              int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
+                              const double *dt_dev, const Params &P,
+                              unsigned long long *counters, hipStream_t s) {
+  hipLaunchKernelGGL(sweep_lanes_kernel<Prec>, dim3(nblocks), dim3(block), 0, s, patches,
+                     chunk_start, npatch, axis, mask, dt_dev, P, counters);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                      int32_t nblocks, int32_t cells_per_block, int32_t nlevels, const Params &P,
+                      unsigned long long *smax_bits, double *dt_dev, hipStream_t s) {
+  hipLaunchKernelGGL(cfl_reduce_kernel<Prec>, dim3(nblocks), dim3(256), 0, s, patches,
+                     chunk_start, npatch, cells_per_block, P, smax_bits);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cfl_finalize_kernel, dim3((nlevels + 63) / 64), dim3(64), 0, s, nlevels,
+                     P.cfl, smax_bits, dt_dev);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
+  const int64_t g = pd.ghost;
+  const int64_t N[3] = {pd.n[0], pd.n[1], pd.n[2]};
+  const int64_t nf[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
+  const int64_t total = 2 * g * nf[1] * nf[0] + N[2] * 2 * g * nf[0] + N[2] * N[1] * 2 * g;
+  const int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(fill_periodic_kernel<Prec>, dim3(unsigned(blocks)), dim3(256), 0, s, pd);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sweep<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
+                                          int32_t, int32_t, int32_t, const double *,
+                                          const Params &, unsigned long long *, hipStream_t);
+template hipError_t launch_sweep<PrecMixed>(const PatchDev *, const int32_t *, int32_t, int32_t,
+                                            int32_t, int32_t, int32_t, const double *,
+                                            const Params &, unsigned long long *, hipStream_t);
+template hipError_t launch_sweep_lanes<PrecF64>(const PatchDev *, const int32_t *, int32_t,
+                                                int32_t, int32_t, int32_t, int32_t,
+                                                const double *, const Params &,
+                                                unsigned long long *, hipStream_t);
+template hipError_t launch_sweep_lanes<PrecMixed>(const PatchDev *, const int32_t *, int32_t,
+                                                  int32_t, int32_t, int32_t, int32_t,
+                                                  const double *, const Params &,
+                                                  unsigned long long *, hipStream_t);
+template hipError_t launch_cfl<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
+                                        int32_t, int32_t, const Params &, unsigned long long *,
+                                        double *, hipStream_t);
+template hipError_t launch_cfl<PrecMixed>(const PatchDev *, const int32_t *, int32_t, int32_t,
+                                          int32_t, int32_t, const Params &, unsigned long long *,
+                                          double *, hipStream_t);
+template hipError_t launch_fill<PrecF64>(const PatchDev &, hipStream_t);
+template hipError_t launch_fill<PrecMixed>(const PatchDev &, hipStream_t);
+
+}  // namespace ppm

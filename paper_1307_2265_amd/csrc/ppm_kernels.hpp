@@ -1,0 +1,33 @@
+// ppm_kernels.hpp -- launcher declarations shared by the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ppm_sweep.hpp"
+
+namespace ppm {
+
+constexpr int kMaxBlock = 256;
+
+template <class Prec>
+hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                        int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
+                        const double *dt_dev, const Params &P, unsigned long long *counters,
+                        hipStream_t s);
+
+// Lane-parallel variant (one wavefront per pencil); block = 64 * pencils per block.
+template <class Prec>
+hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                              int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
+                              const double *dt_dev, const Params &P,
+                              unsigned long long *counters, hipStream_t s);
+
+template <class Prec>
+hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                      int32_t nblocks, int32_t cells_per_block, int32_t nlevels, const Params &P,
+                      unsigned long long *smax_bits, double *dt_dev, hipStream_t s);
+
+template <class Prec>
+hipError_t launch_fill(const PatchDev &pd, hipStream_t s);
+
+}  // namespace ppm

@@ -1,0 +1,244 @@
+// ppm_lanes.hpp -- the 1-D PPM sweep with the cells of a pencil across the
+// lanes of a wave (device).
+//
+// Used for sweeps along x, the contiguous axis: a wavefront owns one pencil
+// and walks it in segments of 64 consecutive cells, so every load and store
+// is one fully coalesced 512-byte access per field, and every stage of the
+// update is evaluated for 64 cells at once, reading its neighbours' values
+// from the adjacent lanes with cross-lane shuffles.  The update of a cell
+// depends on the five cells either side of it (the flattening of its
+// neighbours' parabolas reaches three cells out, the HLL fallback of a
+// neighbouring face two more), so a segment writes its 54 middle cells and
+// the 5 lanes at each end only supply halo values.  Segments overlap by 10
+// cells; since the pencil is updated in place, the next segment takes those
+// cells' inputs from the registers of the previous one (a lane permute)
+// rather than from memory, where some were already overwritten.  Every stage
+// tests the global index of its cell against the same ranges the
+// pencil-marching sweep uses, so both give the same result bit for bit.
+#pragma once
+
+#include "ppm_sweep.hpp"
+
+namespace ppm {
+
+constexpr int kLaneHalo = 5;
+constexpr int kLaneOut = 64 - 2 * kLaneHalo;  // cells written per wave
+
+template <class V> __device__ __forceinline__ V from_left(V v) { return __shfl_up(v, 1, 64); }
+template <class V> __device__ __forceinline__ V from_right(V v) { return __shfl_down(v, 1, 64); }
+template <class V> __device__ __forceinline__ V from_left2(V v) { return __shfl_up(v, 2, 64); }
+template <class V> __device__ __forceinline__ V from_right2(V v) { return __shfl_down(v, 2, 64); }
+
+__device__ __forceinline__ Flux flux_from_left(const Flux &F) {
+  Flux o;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) o.f[k] = from_left(F.f[k]);
+  return o;
+}
+
+template <class T> __device__ __forceinline__ State<T> state_from_right(const State<T> &s) {
+  return State<T>{from_right(s.r), from_right(s.u), from_right(s.v1), from_right(s.v2),
+                  from_right(s.p)};
+}
+
+// Input of one cell as loaded (rho and velocities promoted to double).
+struct CellLoad {
+  double r, u, v1, v2, E, e;
+};
+
+// One segment: cells j0 .. j0+63 of the pencil (j0 may be negative or run
+// past the end; such lanes hold a benign placeholder that no valid result
+// uses).  `in` is this lane's input cell; writes cells [out_lo, out_hi).
+template <class Prec>
+__device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
+                              int j0, int out_lo, int out_hi, const CellLoad &in,
+                              uint32_t &n_fallback, uint32_t &n_floor) {
+  using S = typename Prec::S;
+  using T = typename Prec::T;
+  const int lane = threadIdx.x & 63;
+  const int n = pc.n, g = pc.g;
+  const int a0 = g, a1 = n - g - 1;
+  const int j = j0 + lane;
+  const double lam = dt / pc.dx;
+  const T tlam = T(lam);
+  const double gam = P.gamma;
+  const bool steepen = (P.flags & kSteepen) != 0;
+  const bool flatten = (P.flags & kFlatten) != 0;
+  const bool fallback = (P.flags & kFallbackHLL) != 0;
+
+  // ---- equation of state
+  const bool has = j >= 0 && j < n;
+  const int64_t o = pc.base + int64_t(has ? j : 0) * pc.stride;
+  const double r = in.r, u = in.u, v1 = in.v1, v2 = in.v2, E = in.E, e = in.e;
+  double pd, cd;
+  eos(P, r, u, v1, v2, E, e, pd, cd);
+  T q[5] = {T(r), T(u), T(v1), T(v2), T(pd)};
+  const double rE = r * E;
+
+  // ---- neighbours
+  T qm[5], qp[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    qm[k] = from_left(q[k]);
+    qp[k] = from_right(q[k]);
+  }
+  const double rEm = from_left(rE), rEp = from_right(rE);
+  const double m3 = vmax<double>(vmax<double>(rEm, rE), rEp);
+
+  // ---- limited slopes (cells 1..n-2), density second difference
+  T dm[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) dm[k] = limited_slope<T>(qm[k], q[k], qp[k]);
+  const T d2 = second_diff<T>(qm[0], q[0], qp[0]);
+
+  // ---- interface value at face j+1/2 (cells 1..n-3)
+  T face[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) face[k] = interface_value<T>(q[k], qp[k], dm[k], from_right(dm[k]));
+
+  // ---- flattening indicator (cells 2..n-3, else zero)
+  T ft = T(0);
+  if (flatten) {
+    const T pm2 = from_left2(q[4]), pp2 = from_right2(q[4]);
+    if (j >= 2 && j <= n - 3) ft = flatten_indicator<T>(pm2, qm[4], qp[4], pp2, qm[1], qp[1]);
+  }
+
+  // ---- parabola of cell j, traced to both edges
+  T l[5], rr[5], dq[5], q6[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    l[k] = from_left(face[k]);  // face (j-1)+1/2
+    rr[k] = face[k];
+  }
+  if (steepen) {
+    const T d2m = from_left(d2), d2p = from_right(d2);
+    const T dmm = from_left(dm[0]), dmp = from_right(dm[0]);
+    T eta = steepen_eta<T>(gam, qm[0], qp[0], qm[4], qp[4], d2m, d2p);
+    if (eta != T(0)) {
+      l[0] = l[0] * (T(1) - eta) + (qm[0] + T(0.5) * dmm) * eta;
+      rr[0] = rr[0] * (T(1) - eta) + (qp[0] - T(0.5) * dmp) * eta;
+    }
+  }
+  if (flatten) {
+    const T ftm = from_left(ft), ftp = from_right(ft);
+    T fn = (qp[4] - qm[4] > T(0)) ? ftm : ftp;
+    T f = vmax<T>(ft, fn);
+    if (f != T(0)) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        l[k] = f * q[k] + (T(1) - f) * l[k];
+        rr[k] = f * q[k] + (T(1) - f) * rr[k];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k) monotonize<T>(q[k], l[k], rr[k], dq[k], q6[k]);
+  const T rho_floor = T(P.rho_floor), p_floor = T(P.p_floor);
+  const T cc = T(cd);
+  // left state of face j+1/2 (from this cell) and right state of face
+  // (j-1)+1/2 (from this cell); face j+1/2 takes its right state from lane j+1
+  const State<T> sl = trace_edge<T, true>(gam, l, rr, dq, q6, q[1], cc, tlam, rho_floor, p_floor);
+  const State<T> srown = trace_edge<T, false>(gam, l, rr, dq, q6, q[1], cc, tlam, rho_floor, p_floor);
+  const State<T> sr = state_from_right(srown);
+
+  // ---- Riemann problem at face j+1/2 (faces a0-1..a1)
+  const bool face_ok = j >= a0 - 1 && j <= a1;
+  Flux F;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) F.f[k] = 0.0;
+  if (face_ok) {
+    int iters;
+    F = two_shock_flux(P, double(sl.r), double(sl.u), double(sl.v1), double(sl.v2),
+                       double(sl.p), double(sr.r), double(sr.u), double(sr.v1), double(sr.v2),
+                       double(sr.p), iters);
+  }
+
+  // ---- provisional update of cell j (a0..a1)
+  const bool cell_ok = j >= a0 && j <= a1;
+  CellIn cin;
+  cin.rho = r; cin.u = u; cin.v1 = v1; cin.v2 = v2; cin.E = E; cin.e = e; cin.p = pd;
+  cin.rhoEmax = m3;
+  double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  Flux Fm = flux_from_left(F);
+  bool bad = false;
+  if (cell_ok) bad = update_cell(P, lam, cin, Fm, F, out);
+  const bool mine = j >= out_lo && j < out_hi;
+
+  // ---- HLL fallback on faces next to a non-positive cell, then redo
+  if (fallback) {
+    const bool bad_next = from_right(int(bad)) != 0;
+    const bool hll = face_ok && (bad || bad_next);
+    if (__any(hll)) {
+      if (hll) {
+        const double L5[5] = {double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p)};
+        const double R5[5] = {double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p)};
+        F = hll_flux(P, L5, R5);
+        // face j+1/2 is counted by the wave that writes cell j (or cell a0 for the first face)
+        if (mine || (j == a0 - 1 && a0 >= out_lo && a0 < out_hi)) ++n_fallback;
+      }
+      const bool hll_prev = from_left(int(hll)) != 0;
+      Fm = flux_from_left(F);
+      if (cell_ok && (hll || hll_prev)) bad = update_cell(P, lam, cin, Fm, F, out);
+    }
+  }
+  if (cell_ok && bad) {
+    floor_cell(P, cin, out);
+    if (mine) ++n_floor;
+  }
+
+  // ---- boundary flux registers and write-back
+  if (pc.reg_lo && j == a0 - 1 && a0 >= out_lo && a0 < out_hi) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pc.reg_lo[pc.lab[k] * pc.reg_stride] = dt * F.f[k];
+  }
+  if (pc.reg_hi && j == a1 && mine) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pc.reg_hi[pc.lab[k] * pc.reg_stride] = dt * F.f[k];
+  }
+  if (cell_ok && mine) {
+    pc.rho[o] = S(out[0]);
+    pc.u[o] = S(out[1]);
+    pc.v1[o] = S(out[2]);
+    pc.v2[o] = S(out[3]);
+    pc.E[o] = out[4];
+    pc.e[o] = out[5];
+  }
+}
+
+// One wave walks one pencil segment by segment.
+template <class Prec>
+__device__ void sweep_pencil_lanes(const Params &P, const PencilRef<typename Prec::S> &pc,
+                                   double dt, uint32_t &n_fallback, uint32_t &n_floor) {
+  const int lane = threadIdx.x & 63;
+  const int n = pc.n, g = pc.g;
+  const int N = n - 2 * g;
+  const int nseg = (N + kLaneOut - 1) / kLaneOut;
+  CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
+  for (int s = 0; s < nseg; ++s) {
+    const int j0 = g - kLaneHalo + s * kLaneOut;
+    const int j = j0 + lane;
+    // the first 2*halo lanes overlap the previous segment's last lanes
+    CellLoad prev;
+    prev.r = __shfl(cur.r, lane + kLaneOut, 64);
+    prev.u = __shfl(cur.u, lane + kLaneOut, 64);
+    prev.v1 = __shfl(cur.v1, lane + kLaneOut, 64);
+    prev.v2 = __shfl(cur.v2, lane + kLaneOut, 64);
+    prev.E = __shfl(cur.E, lane + kLaneOut, 64);
+    prev.e = __shfl(cur.e, lane + kLaneOut, 64);
+    if (s > 0 && lane < 2 * kLaneHalo) {
+      cur = prev;
+    } else if (j >= 0 && j < n) {
+      const int64_t o = pc.base + int64_t(j) * pc.stride;
+      cur.r = double(pc.rho[o]); cur.u = double(pc.u[o]);
+      cur.v1 = double(pc.v1[o]); cur.v2 = double(pc.v2[o]);
+      cur.E = pc.E[o]; cur.e = pc.e[o];
+    } else {
+      cur = CellLoad{1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
+    }
+    const int out_lo = g + s * kLaneOut;
+    const int out_hi = min(out_lo + kLaneOut, n - g);
+    sweep_segment<Prec>(P, pc, dt, j0, out_lo, out_hi, cur, n_fallback, n_floor);
+  }
+}
+
+}  // namespace ppm

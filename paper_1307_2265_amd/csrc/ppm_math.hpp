@@ -1,0 +1,370 @@
+// ppm_math.hpp -- per-cell and per-face arithmetic of the PPM sweep (device).
+//
+// Each function is one step of the direct-Eulerian PPM update of the Enzo
+// method paper (Sec. "Hydrodynamics: The PPM method"), written for a single
+// cell or face so that the sweep kernel can stream a pencil through them.
+// The library is compiled with -ffp-contract=off and without fast-math: in
+// double precision every expression below is evaluated exactly as written,
+// operation by operation, so its result is fixed by IEEE-754 alone.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace ppm {
+
+// Parabola coefficients (CW84 Eqs. 1.5-1.6 on a uniform grid).
+constexpr double kC16 = 1.0 / 6.0;
+constexpr double kC23 = 2.0 / 3.0;
+// Contact steepening (CW84 Eqs. 1.16-1.17 and the contact test, Eq. 3.2).
+constexpr double kSteepEps = 0.01;
+constexpr double kSteepK0 = 0.1;
+constexpr double kSteepEta1 = 20.0;
+constexpr double kSteepEta2 = 0.05;
+// Shock flattening (CW84 appendix).
+constexpr double kFlatOmega1 = 0.75;
+constexpr double kFlatOmega2 = 10.0;
+constexpr double kFlatEps = 0.33;
+
+enum : uint32_t { kSteepen = 1u, kFlatten = 2u, kDualEnergy = 4u, kFallbackHLL = 8u };
+
+struct Params {
+  double gamma, cfl, eta1, eta2, rho_floor, p_floor, e_floor, riemann_rtol;
+  int32_t riemann_max_iter;
+  uint32_t flags;
+};
+
+template <class T> __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
+template <class T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
+template <class T> __device__ __forceinline__ T clamp01(T x) {
+  return x < T(0) ? T(0) : (x > T(1) ? T(1) : x);
+}
+
+// ---------------------------------------------------------------------------
+// Pressure from the dual-energy selection rule (eta1) and the sound speed.
+// Velocities in pencil order: normal u, then the two transverse components.
+__device__ __forceinline__ void eos(const Params &P, double rho, double u, double v1, double v2,
+                                    double E, double e, double &p, double &c) {
+  const double g = P.gamma;
+  double ke = 0.5 * (u * u + v1 * v1 + v2 * v2);
+  double eps = E - ke;
+  if ((P.flags & kDualEnergy) && !(eps / E > P.eta1)) eps = e;
+  double pp = (g - 1.0) * rho * eps;
+  if (pp < P.p_floor) pp = P.p_floor;
+  p = pp;
+  c = sqrt(g * pp / rho);
+}
+
+// CW84 limited slope of a cell from its two neighbours.
+template <class T> __device__ __forceinline__ T limited_slope(T qm, T q0, T qp) {
+  T dl = q0 - qm, dr = qp - q0;
+  T dc = T(0.5) * (qp - qm);
+  T m = T(0);
+  if (dl * dr > T(0)) {
+    m = fabs(dc);
+    if (T(2) * fabs(dl) < m) m = T(2) * fabs(dl);
+    if (T(2) * fabs(dr) < m) m = T(2) * fabs(dr);
+    if (dc < T(0)) m = -m;
+  }
+  return m;
+}
+
+// Fourth-order interface value between two cells from their limited slopes.
+template <class T> __device__ __forceinline__ T interface_value(T q0, T q1, T dm0, T dm1) {
+  return T(0.5) * (q0 + q1) - T(kC16) * (dm1 - dm0);
+}
+
+// Second difference of the density centred on a cell.
+template <class T> __device__ __forceinline__ T second_diff(T qm, T q0, T qp) {
+  return qp - T(2) * q0 + qm;
+}
+
+// Contact-steepening weight eta of a cell (0 = no steepening).
+// rm/rp, pm/pp: density and pressure of the two neighbours; d2m/d2p: second
+// differences centred on the two neighbours.
+template <class T>
+__device__ __forceinline__ T steepen_eta(double g, T rm, T rp, T pm, T pp, T d2m, T d2p) {
+  T drho = rp - rm;
+  T eta = T(0);
+  if (d2p * d2m < T(0) && fabs(drho) - T(kSteepEps) * vmin<T>(fabs(rp), fabs(rm)) > T(0) &&
+      T(g * kSteepK0) * fabs(drho) / vmin<T>(rp, rm) >= fabs(pp - pm) / vmin<T>(pp, pm)) {
+    T etat = -(d2p - d2m) / (T(6) * drho);
+    eta = clamp01<T>(T(kSteepEta1) * (etat - T(kSteepEta2)));
+  }
+  return eta;
+}
+
+// Flattening indicator f~ of a cell from the pressures two cells either side
+// and the velocities of its neighbours.
+template <class T>
+__device__ __forceinline__ T flatten_indicator(T pm2, T pm1, T pp1, T pp2, T um1, T up1) {
+  T dp = pp1 - pm1;
+  T f = T(0);
+  if (fabs(dp) / vmin<T>(pp1, pm1) > T(kFlatEps) && um1 - up1 > T(0)) {
+    T den = pp2 - pm2;
+    if (den == T(0)) f = T(1);
+    else f = clamp01<T>(T(kFlatOmega2) * (dp / den - T(kFlatOmega1)));
+  }
+  return f;
+}
+
+// CW84 Eq. 1.10: make the parabola monotone, then return Delta q and q_6.
+template <class T> __device__ __forceinline__ void monotonize(T q, T &l, T &r, T &dq, T &q6) {
+  if ((r - q) * (q - l) <= T(0)) {
+    l = q;
+    r = q;
+  } else {
+    T d = r - l;
+    T s = d * (q - T(0.5) * (l + r));
+    T d2 = d * d * T(kC16);
+    if (s > d2) l = T(3) * q - T(2) * r;
+    else if (-d2 > s) r = T(3) * q - T(2) * l;
+  }
+  dq = r - l;
+  q6 = T(6) * (q - T(0.5) * (l + r));
+}
+
+// Average of the parabola over the right-edge domain of a right-moving wave
+// of Courant number y, and over the left-edge domain of a left-moving one.
+template <class T> __device__ __forceinline__ T avg_right(T qr, T dq, T q6, T y) {
+  return qr - T(0.5) * y * (dq - (T(1) - T(kC23) * y) * q6);
+}
+template <class T> __device__ __forceinline__ T avg_left(T ql, T dq, T q6, T y) {
+  return ql + T(0.5) * y * (dq + (T(1) - T(kC23) * y) * q6);
+}
+
+// A cell's parabola for the five reconstructed quantities.
+template <class T> struct Parabola {
+  T l[5], dq[5], q6[5];  // left edge value, Delta q, q_6; r = l + dq
+};
+
+// Traced interface state (rho, u, v1, v2, p).
+template <class T> struct State {
+  T r, u, v1, v2, p;
+};
+
+// CW84 characteristic tracing (Eqs. 3.5-3.7) of one cell edge.
+// RightEdge: the left state of the face to the right of the cell, built from
+// the waves moving right (u-c, u, u+c > 0); the reference state is the
+// average over the u+c domain, so the u+c correction vanishes identically.
+// Left edge: the mirror image, with the u-c domain as reference.
+// q: cell-centre u; c: sound speed; lam = dt/dx.
+template <class T, bool RightEdge>
+__device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const T (&qrr)[5],
+                                               const T (&dq)[5], const T (&q6)[5], T u, T c,
+                                               T lam, T rho_floor, T p_floor) {
+  // quantity indices: 0 rho, 1 u, 2 v1, 3 v2, 4 p
+  State<T> s;
+  T yref, yslow, y0;
+  if (RightEdge) {
+    yslow = clamp01<T>((u - c) * lam);
+    y0 = clamp01<T>(u * lam);
+    yref = clamp01<T>((u + c) * lam);
+  } else {
+    yslow = clamp01<T>(-(u + c) * lam);
+    y0 = clamp01<T>(-u * lam);
+    yref = clamp01<T>(-(u - c) * lam);
+  }
+  auto avg = [&](int k, T y) -> T {
+    return RightEdge ? avg_right<T>(qrr[k], dq[k], q6[k], y) : avg_left<T>(ql[k], dq[k], q6[k], y);
+  };
+  T rt = avg(0, yref), ut = avg(1, yref), pt = avg(4, yref);
+  T C = sqrt(T(g) * pt * rt);
+  T iC = T(1) / C;
+  // b_fast: correction of the other acoustic wave; b0: entropy wave.  The
+  // reference wave's own correction is exactly zero.
+  T bslow = T(0), b0 = T(0);
+  const bool slow_on = RightEdge ? (u - c > T(0)) : (u + c < T(0));
+  const bool zero_on = RightEdge ? (u > T(0)) : (u < T(0));
+  if (slow_on) {
+    T us = avg(1, yslow), ps = avg(4, yslow);
+    if (RightEdge) bslow = T(0.5) * iC * ((ut - us) - (pt - ps) * iC);          // beta-minus
+    else bslow = T(-0.5) * iC * ((ut - us) + (pt - ps) * iC);                   // beta-plus
+  }
+  if (zero_on) {
+    T r0 = avg(0, y0), p0 = avg(4, y0);
+    b0 = (pt - p0) * iC * iC + T(1) / rt - T(1) / r0;
+  }
+  // With the reference wave's beta at zero: bp + bm = bslow, bp - bm = -+bslow.
+  T bp = RightEdge ? T(0) : bslow;
+  T bm = RightEdge ? bslow : T(0);
+  T ps = pt + C * C * (bp + bm);
+  T us = ut + C * (bp - bm);
+  T tau = T(1) / rt - (bp + bm + b0);
+  T rs = tau > T(0) ? T(1) / tau : rt;
+  s.r = vmax<T>(rs, rho_floor);
+  s.u = us;
+  s.p = vmax<T>(ps, p_floor);
+  s.v1 = avg(2, y0);
+  s.v2 = avg(3, y0);
+  return s;
+}
+
+// Face flux: F_rho, F_u, F_v1, F_v2, F_E, F_e and the face velocity.
+struct Flux {
+  double f[7];
+};
+
+// Two-shock Riemann solver (Sec. "Riemann Solvers and Fallback"), sampled at
+// x/t = 0, and the fluxes of the sampled state.  Newton iteration on
+// u*_R(p) - u*_L(p) = 0 with the Lagrangian shock speeds W_s.
+__device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, double ul, double v1l,
+                                               double v2l, double pl, double rr, double ur,
+                                               double v1r, double v2r, double pr, int &iters) {
+  const double g = P.gamma;
+  const double G1 = (g + 1.0) / (2.0 * g);
+  double cl = sqrt(g * pl * rl);
+  double cr = sqrt(g * pr * rr);
+  double ipl = 1.0 / pl, ipr = 1.0 / pr;
+  double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) / (cl + cr);
+  if (ps < P.p_floor) ps = P.p_floor;
+  int it = 0;
+  for (; it < P.riemann_max_iter;) {
+    double wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
+    double wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
+    double iwl = 1.0 / wl, iwr = 1.0 / wr;
+    double usl = ul - (ps - pl) * iwl;
+    double usr = ur + (ps - pr) * iwr;
+    double izl = (wl * wl + cl * cl) * (0.5 * iwl * iwl * iwl);
+    double izr = (wr * wr + cr * cr) * (0.5 * iwr * iwr * iwr);
+    double pn = ps - (usr - usl) / (izl + izr);
+    if (pn < P.p_floor) pn = P.p_floor;
+    ++it;
+    bool done = fabs(pn - ps) <= P.riemann_rtol * pn;
+    ps = pn;
+    if (done) break;
+  }
+  iters = it;
+  double wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
+  double wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
+  double iwl = 1.0 / wl, iwr = 1.0 / wr;
+  double usl = ul - (ps - pl) * iwl;
+  double usr = ur + (ps - pr) * iwr;
+  double us = 0.5 * (usl + usr);
+  // sample the upwind side of the contact at x/t = 0
+  const bool left = us >= 0.0;
+  double rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
+  double iwK = left ? iwl : iwr;
+  double rs = 1.0 / (1.0 / rK - (ps - pK) * iwK * iwK);
+  if (rs < P.rho_floor) rs = P.rho_floor;
+  double rb, ub, pb;
+  if (ps > pK) {  // shock on the upwind side
+    bool keep;
+    if (left) keep = (ul - wl / rl) >= 0.0;
+    else keep = (ur + wr / rr) <= 0.0;
+    if (keep) { rb = rK; ub = uK; pb = pK; }
+    else { rb = rs; ub = us; pb = ps; }
+  } else {        // rarefaction: linear through the fan
+    double head, tail;
+    if (left) { head = ul - sqrt(g * pl / rl); tail = us - sqrt(g * ps / rs); }
+    else { head = ur + sqrt(g * pr / rr); tail = us + sqrt(g * ps / rs); }
+    bool outside = left ? head >= 0.0 : head <= 0.0;
+    bool star = left ? tail <= 0.0 : tail >= 0.0;
+    if (outside) { rb = rK; ub = uK; pb = pK; }
+    else if (star) { rb = rs; ub = us; pb = ps; }
+    else {
+      double w = left ? -head / (tail - head) : head / (head - tail);
+      rb = (1.0 - w) * rK + w * rs;
+      ub = (1.0 - w) * uK + w * us;
+      pb = (1.0 - w) * pK + w * ps;
+    }
+  }
+  double v1 = left ? v1l : v1r;
+  double v2 = left ? v2l : v2r;
+  Flux F;
+  double fr = rb * ub;
+  F.f[0] = fr;
+  F.f[1] = fr * ub + pb;
+  F.f[2] = fr * v1;
+  F.f[3] = fr * v2;
+  double eb = pb / ((g - 1.0) * rb);
+  double Eb = eb + 0.5 * (ub * ub + v1 * v1 + v2 * v2);
+  F.f[4] = fr * Eb + ub * pb;
+  F.f[5] = fr * eb;
+  F.f[6] = ub;
+  return F;
+}
+
+// HLL flux with Davis wave speeds (the fallback solver).
+__device__ __forceinline__ Flux hll_flux(const Params &P, const double (&sl)[5],
+                                         const double (&sr)[5]) {
+  const double g = P.gamma;
+  double rl = sl[0], ul = sl[1], pl = sl[4];
+  double rr = sr[0], ur = sr[1], pr = sr[4];
+  double cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+  double el = pl / ((g - 1.0) * rl), er = pr / ((g - 1.0) * rr);
+  double El = el + 0.5 * (ul * ul + sl[2] * sl[2] + sl[3] * sl[3]);
+  double Er = er + 0.5 * (ur * ur + sr[2] * sr[2] + sr[3] * sr[3]);
+  double Ul[6] = {rl, rl * ul, rl * sl[2], rl * sl[3], rl * El, rl * el};
+  double Ur[6] = {rr, rr * ur, rr * sr[2], rr * sr[3], rr * Er, rr * er};
+  double Fl[6] = {rl * ul, rl * ul * ul + pl, rl * ul * sl[2], rl * ul * sl[3],
+                  ul * (rl * El + pl), rl * ul * el};
+  double Fr[6] = {rr * ur, rr * ur * ur + pr, rr * ur * sr[2], rr * ur * sr[3],
+                  ur * (rr * Er + pr), rr * ur * er};
+  double sL = vmin<double>(ul - cl, ur - cr);
+  double sR = vmax<double>(ul + cl, ur + cr);
+  Flux F;
+  if (sL >= 0.0) {
+    for (int k = 0; k < 6; ++k) F.f[k] = Fl[k];
+    F.f[6] = ul;
+  } else if (sR <= 0.0) {
+    for (int k = 0; k < 6; ++k) F.f[k] = Fr[k];
+    F.f[6] = ur;
+  } else {
+    double id = 1.0 / (sR - sL);
+    for (int k = 0; k < 6; ++k) F.f[k] = (sR * Fl[k] - sL * Fr[k] + sL * sR * (Ur[k] - Ul[k])) * id;
+    double um_r = (sR * Ur[0] - sL * Ul[0] - (Fr[0] - Fl[0])) * id;
+    double um_m = (sR * Ur[1] - sL * Ul[1] - (Fr[1] - Fl[1])) * id;
+    F.f[6] = um_m / um_r;
+  }
+  return F;
+}
+
+// Sweep-input state of a cell as the update needs it.
+struct CellIn {
+  double rho, u, v1, v2, E, e, p, rhoEmax;
+};
+
+// Conservative update of one cell from its two face fluxes (Eqs. mass_diff,
+// momentum_diff, energy_diff, gasenergy_diff with the flux difference taken
+// with a minus sign), then the eta2 resync (Eq. dualselect).  Returns true
+// when the new density or the eta1-selected internal energy is not positive.
+__device__ __forceinline__ bool update_cell(const Params &P, double lam, const CellIn &c,
+                                            const Flux &Fm, const Flux &Fp, double (&out)[6]) {
+  const bool dual = (P.flags & kDualEnergy) != 0;
+  double rn = c.rho - lam * (Fp.f[0] - Fm.f[0]);
+  double mu = c.rho * c.u - lam * (Fp.f[1] - Fm.f[1]);
+  double m1 = c.rho * c.v1 - lam * (Fp.f[2] - Fm.f[2]);
+  double m2 = c.rho * c.v2 - lam * (Fp.f[3] - Fm.f[3]);
+  double mE = c.rho * c.E - lam * (Fp.f[4] - Fm.f[4]);
+  double me = c.rho * c.e - lam * (Fp.f[5] - Fm.f[5]) - lam * c.p * (Fp.f[6] - Fm.f[6]);
+  double ir = 1.0 / rn;
+  double un = mu * ir, v1n = m1 * ir, v2n = m2 * ir, En = mE * ir, eraw = me * ir;
+  double ke = 0.5 * (un * un + v1n * v1n + v2n * v2n);
+  double epsE = En - ke;
+  bool bad = !(rn > P.rho_floor);
+  double sel = epsE;
+  if (dual && !(epsE / En > P.eta1)) sel = eraw;
+  if (!(sel > 0.0)) bad = true;
+  double en = eraw < P.e_floor ? P.e_floor : eraw;
+  if (dual && rn * epsE / c.rhoEmax > P.eta2) en = epsE;
+  out[0] = rn; out[1] = un; out[2] = v1n; out[3] = v2n; out[4] = En; out[5] = en;
+  return bad;
+}
+
+// A cell still non-positive after the fallback: density raised to the floor
+// (keeping the old velocity if so), pressure set to the floor.
+__device__ __forceinline__ void floor_cell(const Params &P, const CellIn &c, double (&out)[6]) {
+  const double g = P.gamma;
+  if (!(out[0] > P.rho_floor)) {
+    out[0] = P.rho_floor;
+    out[1] = c.u; out[2] = c.v1; out[3] = c.v2;
+  }
+  double eps = P.p_floor / ((g - 1.0) * out[0]);
+  out[5] = eps;
+  out[4] = eps + 0.5 * (out[1] * out[1] + out[2] * out[2] + out[3] * out[3]);
+}
+
+}  // namespace ppm

@@ -1,0 +1,356 @@
+// ppm_sweep.hpp -- the streaming 1-D PPM sweep of one pencil (device).
+//
+// One thread owns one pencil and walks it from its first to its last cell
+// once.  Every quantity a later stage needs is kept in a short sliding window
+// of registers, so each input cell is read from HBM once and each updated cell
+// written once, with no LDS staging and no second pass.  With the head of the
+// walk at cell k:
+//   * cell k is loaded and its pressure and sound speed evaluated;
+//   * the limited slope of cell k-1 and the interface value between k-2 and
+//     k-1 are formed, and the flattening indicator of cell k-2;
+//   * the parabola of cell r = k-3 is completed (steepening, flattening,
+//     monotonicity) and traced to both of its edges;
+//   * the Riemann problem at face (r-1)+1/2 is solved, giving the provisional
+//     update of cell r-1;
+//   * cell r-2 is finalised and written.  Holding the write back by one cell
+//     lets the HLL fallback (Sec. "Riemann Solvers and Fallback") re-solve
+//     both faces of a cell whose provisional update went non-positive and
+//     redo its neighbours before anything reaches memory.  The traced states
+//     the HLL solver needs are parked in LDS (one private slot pair per
+//     thread) since they are read only when a fallback actually happens.
+#pragma once
+
+#include "ppm_math.hpp"
+
+namespace ppm {
+
+// Storage and compute types of a precision.  S: storage of rho and the
+// velocity; T: reconstruction and tracing.  Energies are stored in double,
+// and the pressure selection, Riemann iteration and updates run in double.
+struct PrecF64 {
+  using S = double;
+  using T = double;
+};
+struct PrecMixed {
+  using S = float;
+  using T = float;
+};
+
+// Device copy of one patch.
+struct PatchDev {
+  int32_t n[3];      // active cells per axis
+  int32_t ghost;
+  int32_t level;
+  int32_t pad;
+  double dx[3];
+  void *rho, *vel[3];
+  double *etot, *eint;
+  double *flux_reg;
+};
+
+// One pencil as the marcher sees it: fields in pencil order (normal velocity
+// first), the offset of its cell 0 and the element stride along it.
+template <class S> struct PencilRef {
+  S *rho, *u, *v1, *v2;
+  double *E, *e;
+  int64_t base, stride;
+  int n, g;
+  double dx;
+  double *reg_lo, *reg_hi;  // nullable: register slots of this pencil
+  int64_t reg_stride;       // stride between the six register fields
+  int lab[6];               // lab field index of each pencil-order flux slot
+};
+
+constexpr int kSlotDoubles = 10;  // traced L and R states of one face
+
+template <class Prec>
+__device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
+                             double *lds_slots, int slot_stride, uint32_t &n_fallback,
+                             uint32_t &n_floor) {
+  using S = typename Prec::S;
+  using T = typename Prec::T;
+  // with T = double the window already holds the exact pressure
+  constexpr bool kExactP = sizeof(T) == sizeof(double);
+  const int n = pc.n, g = pc.g;
+  const int a0 = g, a1 = n - g - 1;
+  const double lam = dt / pc.dx;
+  const T tlam = T(lam);
+  const double gam = P.gamma;
+  const bool steepen = (P.flags & kSteepen) != 0;
+  const bool flatten = (P.flags & kFlatten) != 0;
+  const bool fallback = (P.flags & kFallbackHLL) != 0;
+  const T rho_floor = T(P.rho_floor), p_floor = T(P.p_floor);
+
+  // Sliding windows; index 0 is the oldest cell.
+  T q[5][5];       // cells k-4..k: rho, u, v1, v2, p
+  double pd[5];    // cells k-4..k: pressure in double (update source term)
+  T cw[2];         // cells k-3 and k-2: sound speed (cw[0] is cell r)
+  double c_head;   // sound speed of the head cell
+  double c_km1;
+  double rE[3];    // cells k-2..k: rho*E of the sweep input
+  double m3[5];    // cells k-5..k-1: max of rho*E over the cell and its neighbours
+  T dm[4][5];      // cells k-4..k-1: limited slopes
+  T d2[4];         // cells k-4..k-1: density second differences
+  T ft[3];         // cells k-4..k-2: flattening indicators
+  T fc[3][5];      // faces (k-4)+1/2 .. (k-2)+1/2: interface values
+  State<T> lcarry; // left state of face r+1/2 from the previous iteration
+  Flux ft_b;       // two-shock flux at face (r-2)+1/2
+  Flux ff_a;       // final flux at face (r-3)+1/2
+  bool hll_a = false;
+  double prov_a[6];
+  bool bad_a = false;
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) q[i][j] = T(0);
+    pd[i] = 0.0;
+    m3[i] = 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) dm[i][j] = T(0);
+    d2[i] = T(0);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    ft[i] = T(0);
+    rE[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) fc[i][j] = T(0);
+  }
+  cw[0] = cw[1] = T(0);
+  c_head = c_km1 = 0.0;
+  lcarry = State<T>{T(0), T(0), T(0), T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < 7; ++j) ft_b.f[j] = ff_a.f[j] = 0.0;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) prov_a[j] = 0.0;
+
+  // prefetch of the head cell
+  S nr = S(0), nu = S(0), nv1 = S(0), nv2 = S(0);
+  double nE = 0.0, ne = 0.0;
+  if (n > 0) {
+    const int64_t o = pc.base;
+    nr = pc.rho[o]; nu = pc.u[o]; nv1 = pc.v1[o]; nv2 = pc.v2[o]; nE = pc.E[o]; ne = pc.e[o];
+  }
+
+  const int kend = n - g + 4;  // the iteration that finalises cell a1
+  for (int k = 0; k <= kend; ++k) {
+    // energies of cell B = k-4 (updated below), fetched early to hide latency
+    double EB = 0.0, eB = 0.0;
+    if (k - 4 >= a0 && k - 4 <= a1) {
+      const int64_t o = pc.base + int64_t(k - 4) * pc.stride;
+      EB = pc.E[o];
+      eB = pc.e[o];
+    }
+    // ---- 1. head cell: load and equation of state
+    if (k < n) {
+      const double r = double(nr), u = double(nu), v1 = double(nv1), v2 = double(nv2);
+      const double E = nE, e = ne;
+      if (k + 1 < n) {
+        const int64_t o = pc.base + int64_t(k + 1) * pc.stride;
+        nr = pc.rho[o]; nu = pc.u[o]; nv1 = pc.v1[o]; nv2 = pc.v2[o]; nE = pc.E[o]; ne = pc.e[o];
+      }
+      double p, c;
+      eos(P, r, u, v1, v2, E, e, p, c);
+      q[4][0] = T(r); q[4][1] = T(u); q[4][2] = T(v1); q[4][3] = T(v2); q[4][4] = T(p);
+      if (!kExactP) pd[4] = p;
+      c_head = c;
+      rE[2] = r * E;
+    }
+    // ---- 2. slope and second difference of cell k-1, max rho*E around it
+    if (k >= 2 && k <= n - 1) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) dm[3][j] = limited_slope<T>(q[2][j], q[3][j], q[4][j]);
+      d2[3] = second_diff<T>(q[2][0], q[3][0], q[4][0]);
+      m3[4] = vmax<double>(vmax<double>(rE[0], rE[1]), rE[2]);
+    }
+    // ---- 3. interface value between cells k-2 and k-1
+    if (k >= 3 && k <= n - 1) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) fc[2][j] = interface_value<T>(q[2][j], q[3][j], dm[2][j], dm[3][j]);
+    }
+    // ---- 4. flattening indicator of cell k-2 (zero where its stencil leaves the pencil)
+    ft[2] = T(0);
+    if (flatten && k >= 4 && k <= n - 1)
+      ft[2] = flatten_indicator<T>(q[0][4], q[1][4], q[3][4], q[4][4], q[1][1], q[3][1]);
+
+    // ---- 5. parabola of cell r = k-3, traced to both edges
+    const int r = k - 3;
+    State<T> rstate = lcarry, lnew = lcarry;
+    const bool need_left_edge = r >= a0 && r <= a1 + 1;   // right state of face (r-1)+1/2
+    const bool need_right_edge = r >= a0 - 1 && r <= a1;  // left state of face r+1/2
+    if (need_left_edge || need_right_edge) {
+      T l[5], rr[5], dq[5], q6[5];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        l[j] = fc[0][j];   // face (r-1)+1/2
+        rr[j] = fc[1][j];  // face r+1/2
+      }
+      if (steepen) {
+        T eta = steepen_eta<T>(gam, q[0][0], q[2][0], q[0][4], q[2][4], d2[0], d2[2]);
+        if (eta != T(0)) {
+          l[0] = l[0] * (T(1) - eta) + (q[0][0] + T(0.5) * dm[0][0]) * eta;
+          rr[0] = rr[0] * (T(1) - eta) + (q[2][0] - T(0.5) * dm[2][0]) * eta;
+        }
+      }
+      if (flatten) {
+        T fn = (q[2][4] - q[0][4] > T(0)) ? ft[0] : ft[2];
+        T f = vmax<T>(ft[1], fn);
+        if (f != T(0)) {
+#pragma unroll
+          for (int j = 0; j < 5; ++j) {
+            l[j] = f * q[1][j] + (T(1) - f) * l[j];
+            rr[j] = f * q[1][j] + (T(1) - f) * rr[j];
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 5; ++j) monotonize<T>(q[1][j], l[j], rr[j], dq[j], q6[j]);
+      const T u = q[1][1], c = cw[0];
+      if (need_left_edge)
+        rstate = trace_edge<T, false>(gam, l, rr, dq, q6, u, c, tlam, rho_floor, p_floor);
+      if (need_right_edge)
+        lnew = trace_edge<T, true>(gam, l, rr, dq, q6, u, c, tlam, rho_floor, p_floor);
+    }
+
+    // ---- 6. Riemann problem at face fc = (r-1)+1/2
+    Flux ft_c;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) ft_c.f[j] = 0.0;
+    double *slot_c = lds_slots + (k & 1) * kSlotDoubles * slot_stride;
+    if (r - 1 >= a0 - 1 && r - 1 <= a1) {
+      int iters;
+      ft_c = two_shock_flux(P, double(lcarry.r), double(lcarry.u), double(lcarry.v1),
+                            double(lcarry.v2), double(lcarry.p), double(rstate.r),
+                            double(rstate.u), double(rstate.v1), double(rstate.v2),
+                            double(rstate.p), iters);
+      if (fallback) {
+        slot_c[0 * slot_stride] = double(lcarry.r);
+        slot_c[1 * slot_stride] = double(lcarry.u);
+        slot_c[2 * slot_stride] = double(lcarry.v1);
+        slot_c[3 * slot_stride] = double(lcarry.v2);
+        slot_c[4 * slot_stride] = double(lcarry.p);
+        slot_c[5 * slot_stride] = double(rstate.r);
+        slot_c[6 * slot_stride] = double(rstate.u);
+        slot_c[7 * slot_stride] = double(rstate.v1);
+        slot_c[8 * slot_stride] = double(rstate.v2);
+        slot_c[9 * slot_stride] = double(rstate.p);
+      }
+    }
+
+    // ---- 7. provisional update of cell B = r-1 with the two-shock fluxes
+    const int B = r - 1;
+    bool bad_b = false;
+    double prov_b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (B >= a0 && B <= a1) {
+      CellIn cin;
+      cin.rho = double(q[0][0]); cin.u = double(q[0][1]);
+      cin.v1 = double(q[0][2]); cin.v2 = double(q[0][3]);
+      cin.E = EB; cin.e = eB;
+      cin.p = kExactP ? double(q[0][4]) : pd[0];
+      cin.rhoEmax = m3[1];
+      bad_b = update_cell(P, lam, cin, ft_b, ft_c, prov_b);
+    }
+
+    // ---- 8. face fb = (r-2)+1/2 becomes final: HLL if a neighbour went bad
+    const int A = r - 2;
+    const int fb = r - 2;  // face index: fb+1/2 lies between cells A and B
+    Flux ff_b = ft_b;
+    bool hll_b = false;
+    if (fb >= a0 - 1 && fb <= a1) {
+      hll_b = fallback && (bad_a || bad_b);
+      if (hll_b) {
+        const double *slot_b = lds_slots + ((k - 1) & 1) * kSlotDoubles * slot_stride;
+        double sl[5], sr[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+          sl[j] = slot_b[j * slot_stride];
+          sr[j] = slot_b[(5 + j) * slot_stride];
+        }
+        ff_b = hll_flux(P, sl, sr);
+        ++n_fallback;
+      }
+      if (fb == a0 - 1 && pc.reg_lo) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) pc.reg_lo[pc.lab[j] * pc.reg_stride] = dt * ff_b.f[j];
+      }
+      if (fb == a1 && pc.reg_hi) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) pc.reg_hi[pc.lab[j] * pc.reg_stride] = dt * ff_b.f[j];
+      }
+    }
+
+    // ---- 9. finalise and write cell A = r-2
+    if (A >= a0 && A <= a1) {
+      const int64_t o = pc.base + int64_t(A) * pc.stride;
+      double out[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) out[j] = prov_a[j];
+      bool bad = bad_a;
+      if (hll_a || hll_b) {
+        // redo the update with the final fluxes (input of A is still in memory)
+        CellIn cin;
+        cin.rho = double(pc.rho[o]); cin.u = double(pc.u[o]);
+        cin.v1 = double(pc.v1[o]); cin.v2 = double(pc.v2[o]);
+        cin.E = pc.E[o]; cin.e = pc.e[o];
+        double pp, cc;
+        eos(P, cin.rho, cin.u, cin.v1, cin.v2, cin.E, cin.e, pp, cc);
+        cin.p = pp;
+        cin.rhoEmax = m3[0];
+        bad = update_cell(P, lam, cin, ff_a, ff_b, out);
+      }
+      if (bad) {
+        CellIn cin;
+        cin.rho = double(pc.rho[o]); cin.u = double(pc.u[o]);
+        cin.v1 = double(pc.v1[o]); cin.v2 = double(pc.v2[o]);
+        cin.E = pc.E[o]; cin.e = pc.e[o]; cin.p = 0.0; cin.rhoEmax = 0.0;
+        floor_cell(P, cin, out);
+        ++n_floor;
+      }
+      pc.rho[o] = S(out[0]);
+      pc.u[o] = S(out[1]);
+      pc.v1[o] = S(out[2]);
+      pc.v2[o] = S(out[3]);
+      pc.E[o] = out[4];
+      pc.e[o] = out[5];
+    }
+
+    // ---- 10. carry the face and cell state one step
+    ff_a = ff_b;
+    hll_a = hll_b;
+    ft_b = ft_c;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) prov_a[j] = prov_b[j];
+    bad_a = bad_b;
+    lcarry = lnew;
+
+    // ---- 11. shift the windows
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) q[i][j] = q[i + 1][j];
+      if (!kExactP) pd[i] = pd[i + 1];
+      m3[i] = m3[i + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j < 5; ++j) dm[i][j] = dm[i + 1][j];
+      d2[i] = d2[i + 1];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ft[i] = ft[i + 1];
+      rE[i] = rE[i + 1];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) fc[i][j] = fc[i + 1][j];
+    }
+    cw[0] = cw[1];
+    cw[1] = T(c_km1);
+    c_km1 = c_head;
+  }
+}
+
+}  // namespace ppm

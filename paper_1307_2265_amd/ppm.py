@@ -1,0 +1,196 @@
+"""Thin Python binding of libppm.so (include/ppm.h).
+
+Argument marshalling only: every function below forwards to the C ABI of the
+same name, and every step of the PPM update runs in the HIP kernels of that
+library.  PyTorch supplies device memory and streams.  There is no fallback:
+if the library is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppm.so")
+
+PPM_OK, PPM_EINVAL, PPM_ENOMEM, PPM_EHIP, PPM_EUNSUPPORTED = 0, -1, -2, -3, -4
+PPM_FP64, PPM_MIXED = 0, 1
+PPM_STEEPEN, PPM_FLATTEN, PPM_DUAL_ENERGY, PPM_FALLBACK_HLL = 1, 2, 4, 8
+PPM_ALL_FLAGS = 15
+ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
+
+# Every function the header declares, with (restype, argtypes).
+_vp = C.c_void_p
+
+
+class ppm_patch(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("ghost", C.c_int32),
+                ("level", C.c_int32), ("reserved", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("rho", _vp), ("vx", _vp), ("vy", _vp), ("vz", _vp),
+                ("etot", _vp), ("eint", _vp), ("flux_reg", _vp)]
+
+
+class ppm_params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("eta1", C.c_double),
+                ("eta2", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
+                ("e_floor", C.c_double), ("riemann_rtol", C.c_double),
+                ("riemann_max_iter", C.c_int32), ("flags", C.c_uint32)]
+
+
+SIGNATURES = {
+    "ppm_flux_reg_size": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
+    "ppm_plan_create": (C.c_int, [C.POINTER(_vp), C.POINTER(ppm_patch), C.c_int32, C.c_int32,
+                                  C.c_int, C.POINTER(ppm_params), C.c_char_p, _vp]),
+    "ppm_plan_destroy": (C.c_int, [_vp]),
+    "ppm_fill_periodic": (C.c_int, [_vp, _vp]),
+    "ppm_cfl_dt": (C.c_int, [_vp, _vp, _vp]),
+    "ppm_step": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
+    "ppm_sweep": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, _vp]),
+    "ppm_event_counts": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32,
+                                   _vp]),
+    "ppm_status_str": (C.c_char_p, [C.c_int]),
+    "ppm_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+class PPMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def lib():
+    """Load libppm.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_1307_2265_amd/build.py` (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != PPM_OK:
+        msg = lib().ppm_last_error().decode() or lib().ppm_status_str(status).decode()
+        raise PPMError(status, f"{what}: {msg}")
+
+
+def params(gamma=5.0 / 3.0, cfl=0.4, eta1=1e-3, eta2=0.1, rho_floor=1e-20, p_floor=1e-20,
+           e_floor=1e-30, riemann_rtol=1e-13, riemann_max_iter=20,
+           flags=PPM_ALL_FLAGS) -> ppm_params:
+    return ppm_params(gamma, cfl, eta1, eta2, rho_floor, p_floor, e_floor, riemann_rtol,
+                      riemann_max_iter, flags)
+
+
+def ppm_flux_reg_size(nx: int, ny: int, nz: int) -> int:
+    return int(lib().ppm_flux_reg_size(nx, ny, nz))
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream or None
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+@dataclass
+class Patch:
+    """One patch: six device tensors of shape (nz+2g, ny+2g, nx+2g).
+
+    rho, vx, vy, vz are float64 (PPM_FP64) or float32 (PPM_MIXED); etot and
+    eint are float64.  flux_reg is an optional float64 tensor of
+    ppm_flux_reg_size(nx, ny, nz) elements.
+    """
+    rho: object
+    vx: object
+    vy: object
+    vz: object
+    etot: object
+    eint: object
+    dx: float
+    dy: float
+    dz: float
+    ghost: int = 3
+    level: int = 0
+    flux_reg: object = None
+
+    @property
+    def dims(self):
+        nz, ny, nx = self.rho.shape
+        g = self.ghost
+        return nx - 2 * g, ny - 2 * g, nz - 2 * g
+
+    def fields(self):
+        return [self.rho, self.vx, self.vy, self.vz, self.etot, self.eint]
+
+    def to_c(self) -> ppm_patch:
+        nx, ny, nz = self.dims
+        shp = tuple(self.rho.shape)
+        for t in self.fields():
+            if tuple(t.shape) != shp or not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError("patch fields must be contiguous CUDA tensors of one shape")
+        ptr = lambda t: None if t is None else t.data_ptr()
+        return ppm_patch(nx, ny, nz, self.ghost, self.level, 0, self.dx, self.dy, self.dz,
+                         *[ptr(t) for t in self.fields()], ptr(self.flux_reg))
+
+
+class Plan:
+    """Owns a ppm_plan; the methods mirror the C functions of the same names."""
+
+    def __init__(self, patches: list, nlevels: int = 1, precision: int = PPM_FP64,
+                 prm: ppm_params | None = None, tile_config: str | None = None, stream=None):
+        self._patches = list(patches)  # keep the tensors alive
+        arr = (ppm_patch * len(patches))(*[p.to_c() for p in patches])
+        self.params = prm if prm is not None else params()
+        self.nlevels = nlevels
+        self.precision = precision
+        h = _vp()
+        cfg = tile_config.encode() if tile_config else None
+        _check(lib().ppm_plan_create(C.byref(h), arr, len(patches), nlevels, precision,
+                                     C.byref(self.params), cfg, _stream_handle(stream)),
+               "ppm_plan_create")
+        self._h = h
+
+    def ppm_fill_periodic(self, stream=None):
+        _check(lib().ppm_fill_periodic(self._h, _stream_handle(stream)), "ppm_fill_periodic")
+
+    def ppm_cfl_dt(self, dt_dev, stream=None):
+        _check(lib().ppm_cfl_dt(self._h, dt_dev.data_ptr(), _stream_handle(stream)), "ppm_cfl_dt")
+
+    def ppm_step(self, dt_dev, sweep_order=0, stream=None):
+        sweep_order = ORDERS.get(sweep_order, sweep_order)
+        _check(lib().ppm_step(self._h, dt_dev.data_ptr(), int(sweep_order),
+                              _stream_handle(stream)), "ppm_step")
+
+    def ppm_sweep(self, dt_dev, axis: int, active_mask: int, stream=None):
+        _check(lib().ppm_sweep(self._h, dt_dev.data_ptr(), axis, active_mask,
+                               _stream_handle(stream)), "ppm_sweep")
+
+    def ppm_event_counts(self, reset=False, stream=None):
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().ppm_event_counts(self._h, C.byref(a), C.byref(b), int(bool(reset)),
+                                      _stream_handle(stream)), "ppm_event_counts")
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ppm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,3 +18,16 @@ def O():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    """Name each test, flushed, before it runs (a hang then names its case)."""
+    line = f"[start] {request.node.nodeid}\n"
+    sys.stderr.write(line)
+    sys.stderr.flush()
+    out = os.path.join(ROOT, "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "test_progress.log"), "a") as f:
+            f.write(line)
+    yield

@@ -1,0 +1,84 @@
+"""The C ABI library: it loads, exports every function include/ppm.h declares,
+and rejects invalid arguments before touching the GPU (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1307_2265_amd import ppm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "ppm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ppm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    names = _declared_functions()
+    assert "ppm_step" in names and "ppm_cfl_dt" in names and len(names) >= 10
+    L = C.CDLL(ppm.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(ppm.SIGNATURES), set(names) ^ set(ppm.SIGNATURES)
+
+
+def test_status_strings_and_reg_size():
+    L = ppm.lib()
+    assert L.ppm_status_str(ppm.PPM_EINVAL).startswith(b"PPM_EINVAL")
+    assert ppm.ppm_flux_reg_size(4, 5, 6) == 12 * (5 * 6 + 4 * 6 + 4 * 5)
+
+
+def _patch(**kw):
+    base = dict(nx=8, ny=8, nz=8, ghost=3, level=0, reserved=0, dx=0.1, dy=0.1, dz=0.1,
+                rho=1, vx=1, vy=1, vz=1, etot=1, eint=1, flux_reg=None)
+    base.update(kw)
+    return ppm.ppm_patch(**base)
+
+
+@pytest.mark.parametrize("patch_kw,prm_kw,msg", [
+    (dict(ghost=2), {}, "ghost"),
+    (dict(nx=0), {}, "dims"),
+    (dict(level=3), {}, "level"),
+    (dict(dx=0.0), {}, "cell widths"),
+    (dict(rho=None), {}, "NULL field"),
+    (dict(reserved=1), {}, "reserved"),
+    ({}, dict(gamma=1.0), "gamma"),
+    ({}, dict(cfl=1.5), "cfl"),
+    ({}, dict(riemann_max_iter=0), "riemann_max_iter"),
+    ({}, dict(flags=99), "flag"),
+])
+def test_plan_create_rejects_invalid_arguments(patch_kw, prm_kw, msg):
+    L = ppm.lib()
+    arr = (ppm.ppm_patch * 1)(_patch(**patch_kw))
+    prm = ppm.params(**prm_kw)
+    h = C.c_void_p()
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 2, ppm.PPM_FP64, C.byref(prm), None, None)
+    assert st == ppm.PPM_EINVAL
+    assert not h.value
+    assert msg in L.ppm_last_error().decode()
+
+
+def test_calls_on_null_plan_are_rejected():
+    L = ppm.lib()
+    assert L.ppm_step(None, None, 0, None) == ppm.PPM_EINVAL
+    assert L.ppm_cfl_dt(None, None, None) == ppm.PPM_EINVAL
+    assert L.ppm_fill_periodic(None, None) == ppm.PPM_EINVAL
+    assert L.ppm_sweep(None, None, 0, 0, None) == ppm.PPM_EINVAL
+    assert L.ppm_event_counts(None, None, None, 0, None) == ppm.PPM_EINVAL
+    assert L.ppm_plan_destroy(None) == ppm.PPM_OK
+
+
+def test_bad_tile_config_is_rejected():
+    L = ppm.lib()
+    arr = (ppm.ppm_patch * 1)(_patch())
+    prm = ppm.params()
+    h = C.c_void_p()
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"block=100",
+                           None)
+    assert st == ppm.PPM_EINVAL and "block" in L.ppm_last_error().decode()
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"warp=3", None)
+    assert st == ppm.PPM_EINVAL and "unknown key" in L.ppm_last_error().decode()
