@@ -108,12 +108,21 @@ int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
  * text of "key=value" pairs separated by spaces that overrides the launch
  * shapes; unknown keys are an error.  Keys:
  *   lanes=M        axis bitmask: sweeps along axis a (bit a) give each pencil
- *                  to a wavefront with its cells across the lanes; the other
- *                  sweeps give each pencil to one thread that marches it.
- *                  Default 1 (x only) for one patch, 0 for several.
- *   block=B        threads per block of the marching kernel (64..256).
- *   lanes_block=B  threads per block of the lane-parallel kernel (64..256).
+ *                  to a wavefront with its cells across the lanes (pencils of
+ *                  at most 64 cells are packed side by side, 64/n per wave);
+ *                  the other sweeps give each pencil to one thread that
+ *                  marches it.  Default 1 (x only).
+ *   block=B        threads per block of the marching kernel (64..256;
+ *                  default 256 for one patch, 64 for several).
+ *   lanes_block=B  threads per block of the lane-parallel kernel (64..256;
+ *                  default 256 for one patch, 64 for several).
  *   cfl_cells=C    active cells per block of the CFL reduction.
+ *   persistent=0|1 ppm_step as one persistent launch: workgroups take whole
+ *                  patches from a queue (largest first) and run their three
+ *                  sweeps back to back (default 1 for several patches, 0 for
+ *                  one); with 0, one launch per sweep over all patches.
+ *   batch_block=B  threads per workgroup of the persistent launch (64..256).
+ *   batch_blocks=W workgroups of the persistent launch (default: 512/B per CU).
  * Results do not depend on the launch shapes.  Uploads the patch table to
  * the device on `hip_stream` (0 = default stream) and allocates the event
  * counters.  On success *out owns the plan. */
@@ -156,6 +165,19 @@ ppm_status ppm_sweep(ppm_plan *plan, const double *dt_dev, int32_t axis, int32_t
  * counters: faces re-solved with HLL, cells floored after the fallback. */
 ppm_status ppm_event_counts(ppm_plan *plan, int64_t *fallback_faces, int64_t *floored_cells,
                             int32_t reset, void *hip_stream);
+
+/* HIP graph of one step, for callers that launch the same step repeatedly
+ * (and for capture-friendly batching): the parts selected by `parts`, in the
+ * order fill -> CFL -> step, with the given dt array and sweep order, are
+ * captured once into an executable graph (on a private stream; nothing is
+ * executed).  The graph records only kernel launches.  It refers to the
+ * plan, its patches and dt_dev, which must outlive it. */
+typedef struct ppm_graph ppm_graph;
+enum { PPM_GRAPH_FILL = 1u, PPM_GRAPH_CFL = 2u, PPM_GRAPH_STEP = 4u };
+ppm_status ppm_graph_create(ppm_graph **out, ppm_plan *plan, double *dt_dev,
+                            int32_t sweep_order, uint32_t parts, void *hip_stream);
+ppm_status ppm_graph_launch(ppm_graph *graph, void *hip_stream);
+ppm_status ppm_graph_destroy(ppm_graph *graph); /* NULL is accepted */
 
 const char *ppm_status_str(ppm_status s);
 const char *ppm_last_error(void);

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <limits>
 #include <sstream>
@@ -28,6 +29,11 @@ struct ppm_plan {
   int32_t lanes_block = 256;      // threads per lane-parallel block (64 per pencil)
   int32_t lanes_mask = 1;         // bit a: sweeps along axis a use the lane-parallel kernel
   int32_t cfl_cells = 4096;       // active cells per CFL block
+  int32_t persistent = 0;         // ppm_step as one persistent launch over all patches
+  int32_t batch_block = 256;      // threads per workgroup of the persistent kernel
+  int32_t batch_blocks = 0;       // workgroups of the persistent kernel
+  int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
+  unsigned int *d_queue = nullptr;  // persistent queue head and exit count
   std::vector<PatchDev> host;
   PatchDev *d_patches = nullptr;
   int32_t *d_chunks = nullptr;    // 12 marching, 12 lane-parallel prefix arrays, then CFL
@@ -118,6 +124,15 @@ ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
     } else if (k == "lanes_block") {
       if (v < 64 || v > ppm::kMaxBlock || v % 64) return fail(PPM_EINVAL, "tile_config: lanes_block must be 64..256, a multiple of 64");
       pl->lanes_block = int32_t(v);
+    } else if (k == "persistent") {
+      if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: persistent must be 0 or 1");
+      pl->persistent = int32_t(v);
+    } else if (k == "batch_block") {
+      if (v < 64 || v > ppm::kMaxBlock || v % 64) return fail(PPM_EINVAL, "tile_config: batch_block must be 64..256, a multiple of 64");
+      pl->batch_block = int32_t(v);
+    } else if (k == "batch_blocks") {
+      if (v < 1 || v > (1 << 20)) return fail(PPM_EINVAL, "tile_config: batch_blocks out of range");
+      pl->batch_blocks = int32_t(v);
     } else if (k == "cfl_cells") {
       if (v < 256 || v > (1 << 24)) return fail(PPM_EINVAL, "tile_config: cfl_cells out of range");
       pl->cfl_cells = int32_t(v);
@@ -134,6 +149,8 @@ void free_plan(ppm_plan *p) {
   if (p->d_chunks) (void)hipFree(p->d_chunks);
   if (p->d_counters) (void)hipFree(p->d_counters);
   if (p->d_smax) (void)hipFree(p->d_smax);
+  if (p->d_order) (void)hipFree(p->d_order);
+  if (p->d_queue) (void)hipFree(p->d_queue);
   delete p;
 }
 
@@ -188,9 +205,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   pl->prec = prec;
   std::memcpy(&pl->P, params, sizeof(ppm::Params));
   static_assert(sizeof(ppm::Params) == sizeof(ppm_params), "params layout");
-  if (npatch > 1) {  // uneven small patches: finer chunks, every sweep marches
+  if (npatch > 1) {  // uneven small patches: finer chunks, one persistent launch
     pl->block = 64;
-    pl->lanes_mask = 0;
+    pl->lanes_block = 64;
+    pl->persistent = 1;
   }
   if ((st = parse_tiles(pl, tile_config)) != PPM_OK) {
     delete pl;
@@ -214,7 +232,6 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     for (int axis = 0; axis < 3; ++axis)
       for (int tm = 0; tm < 4; ++tm) {
         const int slot = kind * 12 + axis * 4 + tm;
-        const int64_t per_block = kind == 0 ? pl->block : pl->lanes_block / 64;
         int64_t acc = 0;
         int32_t *c = &chunks[size_t(slot) * stride];
         const int t1 = t1_of(axis), t2 = t2_of(axis);
@@ -222,8 +239,17 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
           const PatchDev &d = pl->host[i];
           const int64_t w1 = (tm & 1) ? d.n[t1] : d.n[t1] + 2 * d.ghost;
           const int64_t w2 = (tm & 2) ? d.n[t2] : d.n[t2] + 2 * d.ghost;
+          // work items: pencils (marching), or waves of pencils (lane-parallel:
+          // one long pencil, or 64/n short ones side by side)
+          int64_t items = w1 * w2, per_block = pl->block;
+          if (kind == 1) {
+            const int64_t n = d.n[axis] + 2 * d.ghost;
+            const int64_t ppw = n <= 64 ? 64 / n : 1;
+            items = (items + ppw - 1) / ppw;
+            per_block = pl->lanes_block / 64;
+          }
           c[i] = int32_t(acc);
-          acc += (w1 * w2 + per_block - 1) / per_block;
+          acc += (items + per_block - 1) / per_block;
           if (acc > std::numeric_limits<int32_t>::max() / 2) {
             delete pl;
             return fail(PPM_EINVAL, "too many pencils for one launch");
@@ -248,9 +274,29 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     c[npatch] = int32_t(acc);
     pl->cfl_blocks = int32_t(acc);
   }
+  // persistent queue order: descending cost (cell-sweeps of a step)
+  std::vector<int32_t> order(npatch);
+  {
+    std::vector<std::pair<double, int32_t>> cost(npatch);
+    for (int i = 0; i < npatch; ++i) {
+      const PatchDev &d = pl->host[i];
+      const double a = d.n[0], b = d.n[1], c = d.n[2], g2 = 2.0 * d.ghost;
+      cost[i] = {-(a * (b + g2) * (c + g2) + a * b * (c + g2) + a * b * c), i};
+    }
+    std::stable_sort(cost.begin(), cost.end());
+    for (int i = 0; i < npatch; ++i) order[i] = cost[i].second;
+  }
+  if (pl->batch_blocks == 0) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess || cus <= 0)
+      cus = 256;
+    pl->batch_blocks = std::min<int64_t>(int64_t(cus) * (512 / pl->batch_block), npatch);
+  }
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipError_t e;
-  if ((e = hipMalloc(&pl->d_patches, sizeof(PatchDev) * npatch)) != hipSuccess ||
+  if ((e = hipMalloc(&pl->d_order, sizeof(int32_t) * npatch)) != hipSuccess ||
+      (e = hipMalloc(&pl->d_queue, 2 * sizeof(unsigned int))) != hipSuccess ||
+      (e = hipMalloc(&pl->d_patches, sizeof(PatchDev) * npatch)) != hipSuccess ||
       (e = hipMalloc(&pl->d_chunks, sizeof(int32_t) * chunks.size())) != hipSuccess ||
       (e = hipMalloc(&pl->d_counters, 2 * sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMalloc(&pl->d_smax, nlevels * sizeof(unsigned long long))) != hipSuccess) {
@@ -258,7 +304,11 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     return fail(PPM_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
   }
   std::vector<unsigned long long> zeros(size_t(nlevels) + 2, 0ull);
-  if ((e = hipMemcpyAsync(pl->d_patches, pl->host.data(), sizeof(PatchDev) * npatch,
+  if ((e = hipMemcpyAsync(pl->d_order, order.data(), sizeof(int32_t) * npatch,
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(pl->d_queue, zeros.data(), 2 * sizeof(unsigned int),
+                          hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (e = hipMemcpyAsync(pl->d_patches, pl->host.data(), sizeof(PatchDev) * npatch,
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(pl->d_chunks, chunks.data(), sizeof(int32_t) * chunks.size(),
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -324,6 +374,19 @@ ppm_status ppm_step(ppm_plan *plan, const double *dt_dev, int32_t sweep_order,
   if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
   if (sweep_order < 0 || sweep_order > 5) return fail(PPM_EINVAL, "sweep_order must be in 0..5");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (plan->persistent) {
+    hipError_t e = plan->prec == PPM_FP64
+        ? ppm::launch_batch<ppm::PrecF64>(plan->d_patches, plan->d_order, plan->npatch,
+                                          plan->batch_blocks, plan->batch_block, sweep_order,
+                                          plan->lanes_mask, dt_dev, plan->P, plan->d_counters,
+                                          plan->d_queue, s)
+        : ppm::launch_batch<ppm::PrecMixed>(plan->d_patches, plan->d_order, plan->npatch,
+                                            plan->batch_blocks, plan->batch_block, sweep_order,
+                                            plan->lanes_mask, dt_dev, plan->P, plan->d_counters,
+                                            plan->d_queue, s);
+    if (e != hipSuccess) return hip_fail(e, "persistent step launch");
+    return PPM_OK;
+  }
   int mask = 0;
   for (int k = 0; k < 3; ++k) {
     const int axis = kOrders[sweep_order][k];
@@ -350,6 +413,70 @@ ppm_status ppm_event_counts(ppm_plan *plan, int64_t *fallback_faces, int64_t *fl
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "event counter reset");
   }
+  return PPM_OK;
+}
+
+struct ppm_graph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+ppm_status ppm_graph_create(ppm_graph **out, ppm_plan *plan, double *dt_dev,
+                            int32_t sweep_order, uint32_t parts, void *hip_stream) {
+  (void)hip_stream;
+  if (!out) return fail(PPM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
+  if (parts == 0 || (parts & ~7u)) return fail(PPM_EINVAL, "parts must be a non-empty subset of FILL|CFL|STEP");
+  if ((parts & PPM_GRAPH_STEP) && (sweep_order < 0 || sweep_order > 5))
+    return fail(PPM_EINVAL, "sweep_order must be in 0..5");
+  ppm_graph *g = new (std::nothrow) ppm_graph();
+  if (!g) return fail(PPM_ENOMEM, "host allocation failed");
+  hipStream_t cs = nullptr;  // capture on a private stream (the null stream cannot be captured)
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete g;
+    return hip_fail(e, "capture stream");
+  }
+  ppm_status st = PPM_OK;
+  e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    if (parts & PPM_GRAPH_FILL) st = ppm_fill_periodic(plan, cs);
+    if (st == PPM_OK && (parts & PPM_GRAPH_CFL)) st = ppm_cfl_dt(plan, dt_dev, cs);
+    if (st == PPM_OK && (parts & PPM_GRAPH_STEP)) st = ppm_step(plan, dt_dev, sweep_order, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+    if (st == PPM_OK && e2 != hipSuccess) st = hip_fail(e2, "end capture");
+    if (st == PPM_OK) {
+      e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = hip_fail(e, "graph instantiate");
+    }
+  } else {
+    st = hip_fail(e, "begin capture");
+  }
+  (void)hipStreamDestroy(cs);
+  if (st != PPM_OK) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return st;
+  }
+  *out = g;
+  return PPM_OK;
+}
+
+ppm_status ppm_graph_launch(ppm_graph *graph, void *hip_stream) {
+  if (!graph || !graph->exec) return fail(PPM_EINVAL, "graph is NULL");
+  hipError_t e = hipGraphLaunch(graph->exec, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "graph launch");
+  return PPM_OK;
+}
+
+ppm_status ppm_graph_destroy(ppm_graph *graph) {
+  if (!graph) return PPM_OK;
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
   return PPM_OK;
 }
 

@@ -114,7 +114,12 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
 }
 
-// One wavefront walks one pencil with its cells across the lanes.
+// Pencils of a wave in the lane-parallel kernel: one long pencil walked in
+// segments, or floor(64 / n) short ones side by side.
+__device__ __forceinline__ int pencils_per_wave(int n) { return n <= 64 ? 64 / n : 1; }
+
+// One wavefront takes one long pencil, or several short ones, with the cells
+// across its lanes.
 template <class Prec>
 __global__ void __launch_bounds__(kMaxBlock)
 sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
@@ -124,15 +129,105 @@ sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restri
   const int p = find_patch(chunk_start, npatch, blockIdx.x);
   const PatchDev pd = patches[p];
   const int waves = blockDim.x >> 6;
-  const int idx = (blockIdx.x - chunk_start[p]) * waves + (threadIdx.x >> 6);
-  int i1, i2;
-  if (!pencil_index(pd, axis, mask, idx, i1, i2)) return;  // the whole wave leaves
-  const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+  const int item = (blockIdx.x - chunk_start[p]) * waves + (threadIdx.x >> 6);
+  const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * pd.ghost;
+  const int ppw = pencils_per_wave(n);
   const double dt = dt_dev[pd.level];
   uint32_t nfb = 0, nfl = 0;
-  sweep_pencil_lanes<Prec>(P, pc, dt, nfb, nfl);
+  int i1, i2;
+  if (ppw == 1) {
+    if (!pencil_index(pd, axis, mask, item, i1, i2)) return;  // the whole wave leaves
+    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+    sweep_pencil_lanes<Prec>(P, pc, dt, nfb, nfl);
+  } else {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / n;
+    bool active = sub < ppw && pencil_index(pd, axis, mask, item * ppw + sub, i1, i2);
+    if (!__any(active)) return;
+    if (!active) i1 = i2 = pd.ghost;  // a valid pencil; nothing of it is written
+    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+    PencilRef<S> pcl = pc;
+    if (!active) pcl.reg_lo = pcl.reg_hi = nullptr;
+    sweep_pencils_packed<Prec>(P, pcl, dt, active, nfb, nfl);
+  }
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
+}
+
+// ---------------------------------------------------------------------------
+// Persistent batch kernel: one launch advances every patch by a full step.
+// Workgroups take patches from a queue (an atomic counter over the patches
+// in descending order of cost) and run the three sweeps of each patch one
+// after the other, separated by workgroup barriers; the workgroup's threads
+// share the pencils of each sweep (x sweeps of pencils of at most 64 cells go
+// to the lane-parallel form, packed 64/n per wave, the rest march).  No
+// workgroup ever waits for another, and every workgroup leaves once the queue
+// is empty; the last one to leave rewinds the queue for the next launch.
+
+__constant__ int kStepOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1},
+                                      {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
+
+template <class Prec>
+__global__ void __launch_bounds__(kMaxBlock, 2)
+batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ order,
+                        int32_t npatch, int32_t sweep_order, int32_t lanes_mask,
+                        const double *__restrict__ dt_dev, Params P,
+                        unsigned long long *__restrict__ counters, unsigned int *queue) {
+  using S = typename Prec::S;
+  extern __shared__ double lds[];
+  __shared__ int s_item;
+  uint32_t nfb = 0, nfl = 0;
+  const int wave = threadIdx.x >> 6, waves = blockDim.x >> 6;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = int(atomicAdd(&queue[0], 1u));
+    __syncthreads();
+    const int item = s_item;
+    __syncthreads();
+    if (item >= npatch) break;
+    const PatchDev pd = patches[order[item]];
+    const double dt = dt_dev[pd.level];
+    int mask = 0;
+    for (int k = 0; k < 3; ++k) {
+      const int axis = kStepOrders[sweep_order][k];
+      const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+      const int g = pd.ghost;
+      const int Nt1 = pick3(t1, pd.n[0], pd.n[1], pd.n[2]);
+      const int Nt2 = pick3(t2, pd.n[0], pd.n[1], pd.n[2]);
+      const int w1 = ((mask >> t1) & 1) ? Nt1 : Nt1 + 2 * g;
+      const int w2 = ((mask >> t2) & 1) ? Nt2 : Nt2 + 2 * g;
+      const int np = w1 * w2;
+      const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * g;
+      int i1, i2;
+      if (((lanes_mask >> axis) & 1) && n <= 64) {
+        const int ppw = 64 / n;
+        const int lane = threadIdx.x & 63, sub = lane / n;
+        for (int it = wave; it * ppw < np; it += waves) {
+          bool active = sub < ppw && pencil_index(pd, axis, mask, it * ppw + sub, i1, i2);
+          if (!active) i1 = i2 = g;
+          PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+          if (!active) pc.reg_lo = pc.reg_hi = nullptr;
+          sweep_pencils_packed<Prec>(P, pc, dt, active, nfb, nfl);
+        }
+      } else {
+        for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
+          pencil_index(pd, axis, mask, idx, i1, i2);
+          const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+          march_pencil<Prec>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl);
+        }
+      }
+      __syncthreads();  // this sweep of the patch is complete before the next reads it
+      mask |= 1 << axis;
+    }
+  }
+  if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
+  if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&queue[1], 1u) == gridDim.x - 1) {  // last workgroup out
+      atomicExch(&queue[0], 0u);
+      atomicExch(&queue[1], 0u);
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -272,6 +367,17 @@ hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_star
 }
 
 template <class Prec>
+hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t npatch,
+                        int32_t nblocks, int32_t block, int32_t sweep_order, int32_t lanes_mask,
+                        const double *dt_dev, const Params &P, unsigned long long *counters,
+                        unsigned int *queue, hipStream_t s) {
+  const size_t lds = (P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block * sizeof(double) : 0;
+  hipLaunchKernelGGL(batch_persistent_kernel<Prec>, dim3(nblocks), dim3(block), lds, s, patches,
+                     order, npatch, sweep_order, lanes_mask, dt_dev, P, counters, queue);
+  return hipGetLastError();
+}
+
+template <class Prec>
 hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                       int32_t nblocks, int32_t cells_per_block, int32_t nlevels, const Params &P,
                       unsigned long long *smax_bits, double *dt_dev, hipStream_t s) {
@@ -309,6 +415,14 @@ template hipError_t launch_sweep_lanes<PrecMixed>(const PatchDev *, const int32_
                                                   int32_t, int32_t, int32_t, int32_t,
                                                   const double *, const Params &,
                                                   unsigned long long *, hipStream_t);
+template hipError_t launch_batch<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
+                                          int32_t, int32_t, int32_t, const double *,
+                                          const Params &, unsigned long long *, unsigned int *,
+                                          hipStream_t);
+template hipError_t launch_batch<PrecMixed>(const PatchDev *, const int32_t *, int32_t, int32_t,
+                                            int32_t, int32_t, int32_t, const double *,
+                                            const Params &, unsigned long long *, unsigned int *,
+                                            hipStream_t);
 template hipError_t launch_cfl<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
                                         int32_t, int32_t, const Params &, unsigned long long *,
                                         double *, hipStream_t);

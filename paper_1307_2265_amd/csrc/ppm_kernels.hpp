@@ -22,6 +22,13 @@ hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_star
                               const double *dt_dev, const Params &P,
                               unsigned long long *counters, hipStream_t s);
 
+// Persistent batch kernel: the whole step of every patch in one launch.
+template <class Prec>
+hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t npatch,
+                        int32_t nblocks, int32_t block, int32_t sweep_order, int32_t lanes_mask,
+                        const double *dt_dev, const Params &P, unsigned long long *counters,
+                        unsigned int *queue, hipStream_t s);
+
 template <class Prec>
 hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                       int32_t nblocks, int32_t cells_per_block, int32_t nlevels, const Params &P,

@@ -51,14 +51,12 @@ struct CellLoad {
 // uses).  `in` is this lane's input cell; writes cells [out_lo, out_hi).
 template <class Prec>
 __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
-                              int j0, int out_lo, int out_hi, const CellLoad &in,
+                              int j, int out_lo, int out_hi, const CellLoad &in,
                               uint32_t &n_fallback, uint32_t &n_floor) {
   using S = typename Prec::S;
   using T = typename Prec::T;
-  const int lane = threadIdx.x & 63;
   const int n = pc.n, g = pc.g;
   const int a0 = g, a1 = n - g - 1;
-  const int j = j0 + lane;
   const double lam = dt / pc.dx;
   const T tlam = T(lam);
   const double gam = P.gamma;
@@ -237,8 +235,30 @@ __device__ void sweep_pencil_lanes(const Params &P, const PencilRef<typename Pre
     }
     const int out_lo = g + s * kLaneOut;
     const int out_hi = min(out_lo + kLaneOut, n - g);
-    sweep_segment<Prec>(P, pc, dt, j0, out_lo, out_hi, cur, n_fallback, n_floor);
+    sweep_segment<Prec>(P, pc, dt, j, out_lo, out_hi, cur, n_fallback, n_floor);
   }
+}
+
+// Pencils of at most 64 cells: `per_wave` of them side by side across the
+// lanes (lane = i*n + j holds cell j of the wave's i-th pencil), one pass.
+// A lane next to a pencil boundary reads a neighbouring pencil's cell where
+// the sweep would read a cell outside its pencil; no stage that a valid
+// result uses does so, exactly as with the placeholders of the long form.
+template <class Prec>
+__device__ void sweep_pencils_packed(const Params &P, const PencilRef<typename Prec::S> &pc,
+                                     double dt, bool active, uint32_t &n_fallback,
+                                     uint32_t &n_floor) {
+  const int lane = threadIdx.x & 63;
+  const int n = pc.n, g = pc.g;
+  const int j = active ? lane % n : -1;
+  CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
+  if (active) {
+    const int64_t o = pc.base + int64_t(j) * pc.stride;
+    cur.r = double(pc.rho[o]); cur.u = double(pc.u[o]);
+    cur.v1 = double(pc.v1[o]); cur.v2 = double(pc.v2[o]);
+    cur.E = pc.E[o]; cur.e = pc.e[o];
+  }
+  sweep_segment<Prec>(P, pc, dt, j, g, n - g, cur, n_fallback, n_floor);
 }
 
 }  // namespace ppm

@@ -19,6 +19,7 @@ PPM_FP64, PPM_MIXED = 0, 1
 PPM_STEEPEN, PPM_FLATTEN, PPM_DUAL_ENERGY, PPM_FALLBACK_HLL = 1, 2, 4, 8
 PPM_ALL_FLAGS = 15
 ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
+PPM_GRAPH_FILL, PPM_GRAPH_CFL, PPM_GRAPH_STEP = 1, 2, 4
 
 # Every function the header declares, with (restype, argtypes).
 _vp = C.c_void_p
@@ -50,6 +51,9 @@ SIGNATURES = {
     "ppm_sweep": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, _vp]),
     "ppm_event_counts": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32,
                                    _vp]),
+    "ppm_graph_create": (C.c_int, [C.POINTER(_vp), _vp, _vp, C.c_int32, C.c_uint32, _vp]),
+    "ppm_graph_launch": (C.c_int, [_vp, _vp]),
+    "ppm_graph_destroy": (C.c_int, [_vp]),
     "ppm_status_str": (C.c_char_p, [C.c_int]),
     "ppm_last_error": (C.c_char_p, []),
 }
@@ -187,6 +191,33 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib().ppm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """A captured step (ppm_graph_create); launch() replays it."""
+
+    def __init__(self, plan: Plan, dt_dev, sweep_order=0, parts=PPM_GRAPH_CFL | PPM_GRAPH_STEP,
+                 stream=None):
+        sweep_order = ORDERS.get(sweep_order, sweep_order)
+        self._plan, self._dt = plan, dt_dev  # keep alive
+        h = _vp()
+        _check(lib().ppm_graph_create(C.byref(h), plan._h, dt_dev.data_ptr(), int(sweep_order),
+                                      int(parts), _stream_handle(stream)), "ppm_graph_create")
+        self._h = h
+
+    def ppm_graph_launch(self, stream=None):
+        _check(lib().ppm_graph_launch(self._h, _stream_handle(stream)), "ppm_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ppm_graph_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -244,3 +244,159 @@ def test_both_sweep_kernels_on_every_axis(P, O, tiles, prec):
         for f in FIELDS:
             l1 = np.abs(g[f][sl] - o[f][sl]).sum() / np.abs(o[f][sl]).sum()
             assert l1 <= 1e-5, (f, l1)
+
+
+def test_full_size_512_step_in_bench_configuration(P, O):
+    # The benchmark's workload (512^3, strongly shocked, seed 1002) and launch
+    # configuration (default tiles: lane-parallel x sweeps, marching y and z),
+    # one full step from the same stored input: FP64 compared with the oracle
+    # cell by cell, mixed precision by per-field relative L1.
+    import torch
+    n = 512
+    cfg = W.CONFIGS[2]
+    print("generating 512^3 input", flush=True)
+    d = stored_inputs(W.random_grid(n, n, n, cfg["seed"], cfg["recipe"]), P.PPM_MIXED)
+    print("oracle step", flush=True)
+    G = oracle_grid(O, d)
+    prm = O.params()
+    O.fill_periodic(G)
+    dt_ref = O.cfl_dt(G, prm)
+    ocnt = O.step(G, prm, dt_ref, 0)
+    sl = (slice(3, -3),) * 3
+    for prec in (P.PPM_FP64, P.PPM_MIXED):
+        print(f"gpu step, precision {prec}", flush=True)
+        patch = to_device(d, prec)
+        plan = P.Plan([patch], 1, prec, P.params())
+        dt = _dt_tensor()
+        plan.ppm_fill_periodic()
+        plan.ppm_cfl_dt(dt)
+        plan.ppm_step(dt, 0)
+        torch.cuda.synchronize()
+        assert float(dt.item()) == dt_ref
+        counts = plan.ppm_event_counts()
+        for f in FIELDS:
+            a = getattr(patch, f)[3:-3, 3:-3, 3:-3].double().cpu().numpy()
+            b = getattr(G, f)[sl]
+            if prec == P.PPM_FP64:
+                differ = int(np.count_nonzero(a != b))
+                scale = np.maximum(np.abs(b), np.abs(b).mean())
+                worst = float(np.max(np.abs(a - b) / scale))
+                print(f"fp64 {f}: worst {worst:.2e}, cells not bitwise equal {differ}")
+                assert worst <= TOL64
+            else:
+                l1 = float(np.abs(a - b).sum() / np.abs(b).sum())
+                print(f"mixed {f}: relative L1 {l1:.2e}")
+                assert l1 <= 1e-5
+            del a
+        if prec == P.PPM_FP64:
+            assert counts == (ocnt.fallback_faces, ocnt.floored_cells)
+        plan.close()
+        del patch
+        torch.cuda.empty_cache()
+
+
+def _batch(P, O, npatch, seed, prec, tiles=None, steps=1):
+    """Run a batch of uneven patches on the GPU and patch by patch on the oracle."""
+    import torch
+    specs = W.patch_specs(npatch, seed)
+    nlev = 7
+    fields = [stored_inputs(W.patch_fields(sp), prec) for sp in specs]
+    patches = [to_device(f, prec, dx=(sp.dx,) * 3, level=sp.level, with_reg=True)
+               for f, sp in zip(fields, specs)]
+    plan = P.Plan(patches, nlev, prec, P.params(), tile_config=tiles)
+    dt = _dt_tensor(nlev)
+    prm = O.params()
+    grids = [oracle_grid(O, f, dx=(sp.dx,) * 3, with_reg=True) for f, sp in zip(fields, specs)]
+    ocnt = [0, 0]
+    dts_g, dts_o = [], []
+    for s in range(steps):
+        plan.ppm_cfl_dt(dt)
+        plan.ppm_step(dt, s % 2)
+        torch.cuda.synchronize()
+        dts_g.append(dt.cpu().numpy().copy())
+        smax = np.zeros(nlev)
+        for G, sp in zip(grids, specs):
+            smax[sp.level] = max(smax[sp.level], O.cfl_signal_max(G, prm))
+        dto = np.where(smax > 0, prm.cfl / np.where(smax > 0, smax, 1.0), np.inf)
+        dts_o.append(dto)
+        for G, sp in zip(grids, specs):
+            c = O.step(G, prm, float(dto[sp.level]), s % 2)
+            ocnt[0] += c.fallback_faces
+            ocnt[1] += c.floored_cells
+    gcnt = plan.ppm_event_counts()
+    outs = [(from_device(p), p.flux_reg.cpu().numpy()) for p in patches]
+    plan.close()
+    return specs, outs, grids, dts_g, dts_o, gcnt, tuple(ocnt)
+
+
+@pytest.mark.parametrize("tiles", [None, "lanes=0", "lanes=7", "persistent=0",
+                                   "persistent=0 lanes=0", "persistent=1 batch_block=64"])
+def test_batch_of_uneven_patches_fp64(P, O, tiles):
+    specs, outs, grids, dg, do, gcnt, ocnt = _batch(P, O, 48, 1003, P.PPM_FP64, tiles, steps=2)
+    for a, b in zip(dg, do):
+        assert np.array_equal(a, b), (a, b)
+    differ = 0
+    for (g, greg), G in zip(outs, grids):
+        sl = (slice(3, -3),) * 3
+        _, d = compare_fields({f: g[f][sl] for f in FIELDS},
+                              {f: getattr(G, f)[sl] for f in FIELDS}, TOL64)
+        differ += d
+        scale = np.maximum(np.abs(G.flux_reg), np.abs(G.flux_reg).mean())
+        assert np.max(np.abs(greg - G.flux_reg) / scale) <= TOL64
+    print(f"{tiles}: 48 patches, active cells not bitwise equal: {differ}, counts {gcnt} {ocnt}")
+    assert gcnt == ocnt
+
+
+def test_batch_of_uneven_patches_mixed(P, O):
+    specs, outs, grids, dg, do, _, _ = _batch(P, O, 32, 2003, P.PPM_MIXED)
+    num = {f: 0.0 for f in FIELDS}
+    den = {f: 0.0 for f in FIELDS}
+    for (g, _), G in zip(outs, grids):
+        sl = (slice(3, -3),) * 3
+        for f in FIELDS:
+            num[f] += np.abs(g[f][sl] - getattr(G, f)[sl]).sum()
+            den[f] += np.abs(getattr(G, f)[sl]).sum()
+    for f in FIELDS:
+        print(f"batch mixed {f}: relative L1 {num[f] / den[f]:.2e}")
+        assert num[f] / den[f] <= 1e-5
+
+
+@pytest.mark.parametrize("batch", [False, True])
+def test_graph_replays_match_eager_steps(P, O, batch):
+    # Capture fill (single grid) + CFL + step into a HIP graph, replay it
+    # several times with eager work and synchronisations in between, and
+    # check every replay against the same steps run eagerly.
+    import torch
+    if batch:
+        specs = W.patch_specs(24, 77)
+        fields = [W.patch_fields(sp) for sp in specs]
+        mk = lambda: [to_device(f, P.PPM_FP64, dx=(sp.dx,) * 3, level=sp.level)
+                      for f, sp in zip(fields, specs)]
+        nlev, parts = 7, P.PPM_GRAPH_CFL | P.PPM_GRAPH_STEP
+    else:
+        d = W.random_grid(40, 24, 16, 5, W.SHOCKED)
+        mk = lambda: [to_device(d, P.PPM_FP64)]
+        nlev, parts = 1, P.PPM_GRAPH_FILL | P.PPM_GRAPH_CFL | P.PPM_GRAPH_STEP
+    A, B = mk(), mk()
+    pa = P.Plan(A, nlev, P.PPM_FP64, P.params())
+    pb = P.Plan(B, nlev, P.PPM_FP64, P.params())
+    dta, dtb = _dt_tensor(nlev), _dt_tensor(nlev)
+    graphs = [P.Graph(pb, dtb, order, parts) for order in (0, 1)]
+    for s in range(4):
+        if not batch:
+            pa.ppm_fill_periodic()
+        pa.ppm_cfl_dt(dta)
+        pa.ppm_step(dta, s % 2)
+        graphs[s % 2].ppm_graph_launch()
+        torch.cuda.synchronize()
+        junk = torch.ones(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(dta, dtb)
+        for pA, pB in zip(A, B):
+            for f in FIELDS:
+                assert torch.equal(getattr(pA, f), getattr(pB, f)), (s, f)
+    del junk
+    for g in graphs:
+        g.close()
+    pa.close()
+    pb.close()
