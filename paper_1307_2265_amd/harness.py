@@ -1,0 +1,192 @@
+"""Device-side workload setup and timing shared by bench.py and the autotuner.
+
+Builds the seeded workloads of workloads.py on the GPU (a single periodic
+grid, or a batch of uneven patches stored as views into one flat buffer per
+field), runs steps through the C ABI (fill -> CFL -> step, directly or as
+captured HIP graphs) and times them with HIP events on the launch stream.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import ppm
+from . import workloads as W
+
+FIELDS = ("rho", "vx", "vy", "vz", "etot", "eint")
+ORDERS = ((0, 1, 2), (2, 1, 0))  # xyz on even steps, zyx on odd ones
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def lanes_mask_of(tiles: str | None) -> int:
+    if tiles and "lanes=" in tiles:
+        return int(tiles.split("lanes=")[1].split()[0])
+    return 1
+
+
+class Run:
+    """Patches, plan and per-level dt array of one workload on the device."""
+
+    def __init__(self, host_fields: list, specs: list, prec: int, nlevels: int, periodic: bool,
+                 tiles: str | None = None, with_reg: bool = False, ghost: int = W.GHOST):
+        torch = _torch()
+        low = torch.float32 if prec == ppm.PPM_MIXED else torch.float64
+        self.prec, self.periodic, self.tiles, self.nlevels = prec, periodic, tiles, nlevels
+        sizes = [f["rho"].size for f in host_fields]
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        self.flat = {}
+        for name in FIELDS:
+            dt = torch.float64 if name in ("etot", "eint") else low
+            host = np.concatenate([f[name].ravel() for f in host_fields])
+            self.flat[name] = torch.from_numpy(host).to("cuda", dtype=dt)
+        self.init = {k: v.clone() for k, v in self.flat.items()}
+        self.reg = None
+        if with_reg:
+            rs = [ppm.ppm_flux_reg_size(*s[:3]) for s in specs]
+            self.reg = torch.zeros(int(sum(rs)), dtype=torch.float64, device="cuda")
+            roffs = np.concatenate([[0], np.cumsum(rs)])
+        self.patches = []
+        for i, (f, sp) in enumerate(zip(host_fields, specs)):
+            shape = f["rho"].shape
+            views = {k: v[offs[i]:offs[i + 1]].view(shape) for k, v in self.flat.items()}
+            reg = None if self.reg is None else self.reg[roffs[i]:roffs[i + 1]]
+            nx, ny, nz, level, dx = sp
+            self.patches.append(ppm.Patch(**views, dx=dx, dy=dx, dz=dx, ghost=ghost,
+                                          level=level, flux_reg=reg))
+        self.cells = int(sum(s[0] * s[1] * s[2] for s in specs))
+        self.plan = ppm.Plan(self.patches, nlevels, prec, ppm.params(), tile_config=tiles)
+        self.dt = torch.zeros(nlevels, dtype=torch.float64, device="cuda")
+        self.graphs = None
+
+    # -- construction helpers -------------------------------------------------
+    @classmethod
+    def single(cls, d: dict, n: int, prec: int, tiles=None):
+        return cls([d], [(n, n, n, 0, 1.0 / n)], prec, 1, True, tiles)
+
+    @classmethod
+    def batch(cls, specs: list, fields: list, prec: int, tiles=None, nlevels=7):
+        sp = [(s.nx, s.ny, s.nz, s.level, s.dx) for s in specs]
+        return cls(fields, sp, prec, nlevels, False, tiles, with_reg=True)
+
+    def replan(self, tiles: str | None):
+        """Replace the plan by one with other launch shapes (same patches)."""
+        if self.graphs:
+            for g in self.graphs:
+                g.close()
+            self.graphs = None
+        self.plan.close()
+        self.tiles = tiles
+        self.plan = ppm.Plan(self.patches, self.nlevels, self.prec, ppm.params(), tile_config=tiles)
+
+    # -- stepping -------------------------------------------------------------
+    def reset(self):
+        for k, v in self.flat.items():
+            v.copy_(self.init[k])
+
+    def step(self, s: int):
+        if self.periodic:
+            self.plan.ppm_fill_periodic()
+        self.plan.ppm_cfl_dt(self.dt)
+        self.plan.ppm_step(self.dt, s % 2)
+
+    def make_graphs(self):
+        parts = ppm.PPM_GRAPH_CFL | ppm.PPM_GRAPH_STEP
+        if self.periodic:
+            parts |= ppm.PPM_GRAPH_FILL
+        self.graphs = [ppm.Graph(self.plan, self.dt, o, parts) for o in (0, 1)]
+
+    def timed(self, steps: int, graphs: bool = False, per_sweep: bool = False):
+        """Time `steps` steps from the current state.
+
+        graphs: replay the captured step graphs.  per_sweep: issue the three
+        sweeps as ppm_sweep calls bracketed by HIP events (the same kernels
+        and extents ppm_step launches when it is not persistent) and return
+        the mean duration per kernel kind.  Returns (seconds, {kind: s})."""
+        torch = _torch()
+        E = lambda: torch.cuda.Event(enable_timing=True)
+        if graphs and self.graphs is None:
+            self.make_graphs()
+        lm = lanes_mask_of(self.tiles)
+        ev = []
+        torch.cuda.synchronize()
+        t0, t1 = E(), E()
+        t0.record()
+        for s in range(steps):
+            if graphs:
+                self.graphs[s % 2].ppm_graph_launch()
+                continue
+            if not per_sweep:
+                self.step(s)
+                continue
+            if self.periodic:
+                self.plan.ppm_fill_periodic()
+            self.plan.ppm_cfl_dt(self.dt)
+            mask = 0
+            for axis in ORDERS[s % 2]:
+                a, b = E(), E()
+                a.record()
+                self.plan.ppm_sweep(self.dt, axis, mask)
+                b.record()
+                ev.append(("lanes" if (lm >> axis) & 1 else "march", a, b))
+                mask |= 1 << axis
+        t1.record()
+        torch.cuda.synchronize()
+        per = {}
+        for kind, a, b in ev:
+            per.setdefault(kind, []).append(a.elapsed_time(b) / 1e3)
+        return t0.elapsed_time(t1) / 1e3, {k: sum(v) / len(v) for k, v in per.items()}
+
+    def close(self):
+        if self.graphs:
+            for g in self.graphs:
+                g.close()
+        self.plan.close()
+
+
+def active_mask(run: Run):
+    """Boolean mask of the active cells in the flat field buffers of a run."""
+    torch = _torch()
+    m = torch.zeros(run.flat["rho"].numel(), dtype=torch.bool, device="cuda")
+    off = 0
+    for p in run.patches:
+        g = p.ghost
+        v = m[off:off + p.rho.numel()].view(p.rho.shape)
+        v[g:-g, g:-g, g:-g] = True
+        off += p.rho.numel()
+    return m
+
+
+def l1_per_field(a: Run, b: Run) -> dict:
+    """sum |a - b| / sum |b| over the active cells of every patch, per field."""
+    m = active_mask(b)
+    out = {}
+    for f in FIELDS:
+        x = a.flat[f][m].double()
+        y = b.flat[f][m].double()
+        out[f] = float((x - y).abs().sum() / y.abs().sum())
+    return out
+
+
+def single_grid_input(n: int, config: int = 2) -> dict:
+    """The seeded single-grid input of a named config, with rho and v rounded
+    to float32 so that both precisions start from the same stored values."""
+    cfg = W.CONFIGS[config]
+    d = W.random_grid(n, n, n, cfg["seed"], cfg["recipe"])
+    for f in ("rho", "vx", "vy", "vz"):
+        d[f] = d[f].astype(np.float32).astype(np.float64)
+    return d
+
+
+def batch_input(npatch: int, seed: int = 1003):
+    """Uneven patches (dims from {8,12,16,24,32}, levels 0..6) with seeded ghosts."""
+    specs = W.patch_specs(npatch, seed)
+    fields = []
+    for sp in specs:
+        f = W.patch_fields(sp)
+        for k in ("rho", "vx", "vy", "vz"):
+            f[k] = f[k].astype(np.float32).astype(np.float64)
+        fields.append(f)
+    return specs, fields
