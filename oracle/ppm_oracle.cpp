@@ -67,6 +67,12 @@ template <class R> R clamp01(R x) { return x < 0.0 ? R(0.0) : (x > 1.0 ? R(1.0) 
 using std::fabs;
 using std::sqrt;
 
+// The ratio test a/b > t of the paper's selection rules, taken as a > t*b
+// when b > 0 (the case of every physical state) and as written otherwise.
+template <class R> bool ratio_above(R a, R b, double t) {
+  return b > 0.0 ? a > t * b : a / b > t;
+}
+
 // Average of the parabola over the part of the cell next to its right edge
 // that a wave travelling right at Courant number y sweeps through in dt.
 template <class R> R avg_right(R qr, R dq, R q6, R y) {
@@ -104,7 +110,7 @@ void eos(const ppmo_params &P, R rho, R u, R v1, R v2, R E, R e, R *p_out, R *c_
   const double g = P.gamma;
   R ke = 0.5 * (u * u + v1 * v1 + v2 * v2);
   R eps = E - ke;
-  if ((P.flags & PPMO_DUAL_ENERGY) && !(eps / E > P.eta1)) eps = e;
+  if ((P.flags & PPMO_DUAL_ENERGY) && !ratio_above(eps, E, P.eta1)) eps = e;
   R p = (g - 1.0) * rho * eps;
   if (p < P.p_floor) p = R(P.p_floor);
   *p_out = p;
@@ -134,28 +140,29 @@ RiemannOut<R> two_shock(const ppmo_params &P, R rl, R ul, R pl, R rr, R ur, R pr
   // linearised (acoustic) first guess
   R ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) / (cl + cr);
   if (ps < P.p_floor) ps = R(P.p_floor);
+  // Iterate until the Newton correction falls below rtol; the star state is
+  // that last iterate, with its shock speeds and contact velocities.
   int it = 0;
-  for (; it < P.riemann_max_iter;) {
-    R wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
-    R wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
-    R iwl = 1.0 / wl, iwr = 1.0 / wr;
-    R usl = ul - (ps - pl) * iwl;
-    R usr = ur + (ps - pr) * iwr;
+  bool capped = false;
+  R wl, wr, iwl, iwr, usl, usr;
+  for (;;) {
+    wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
+    wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
+    iwl = 1.0 / wl;
+    iwr = 1.0 / wr;
+    usl = ul - (ps - pl) * iwl;
+    usr = ur + (ps - pr) * iwr;
+    if (capped || it == P.riemann_max_iter) break;
     // 1/Z_s = (W_s^2 + C_s^2) / (2 W_s^3)
     R izl = (wl * wl + cl * cl) * (0.5 * iwl * iwl * iwl);
     R izr = (wr * wr + cr * cr) * (0.5 * iwr * iwr * iwr);
     R pn = ps - (usr - usl) / (izl + izr);
     if (pn < P.p_floor) pn = R(P.p_floor);
     ++it;
-    bool done = fabs(pn - ps) <= P.riemann_rtol * pn;
+    if (fabs(pn - ps) <= P.riemann_rtol * pn) break;  // ps is the answer
     ps = pn;
-    if (done) break;
+    if (it == P.riemann_max_iter) capped = true;  // evaluate at the last iterate
   }
-  R wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
-  R wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
-  R iwl = 1.0 / wl, iwr = 1.0 / wr;
-  R usl = ul - (ps - pl) * iwl;
-  R usr = ur + (ps - pr) * iwr;
   R us = 0.5 * (usl + usr);
   o.ps = ps; o.us = us; o.iters = it;
   // Sample the solution at x/t = 0.
@@ -283,10 +290,10 @@ bool update_cell(const ppmo_params &P, R dtdx, const CellIn<R> &c, const R *Fm, 
   R epsE = En - ke;
   bool bad = !(rn > P.rho_floor);
   R sel = epsE;
-  if (dual && !(epsE / En > P.eta1)) sel = eraw;
+  if (dual && !ratio_above(epsE, En, P.eta1)) sel = eraw;
   if (!(sel > 0.0)) bad = true;
   R en = eraw < P.e_floor ? R(P.e_floor) : eraw;
-  if (dual && rn * epsE / c.rhoEmax > P.eta2) en = epsE;
+  if (dual && ratio_above(rn * epsE, c.rhoEmax, P.eta2)) en = epsE;
   out[0] = rn; out[1] = un; out[2] = v1n; out[3] = v2n; out[4] = En; out[5] = en;
   return bad;
 }
@@ -360,8 +367,8 @@ void pencil_sweep(const ppmo_params &P, int n, int gh, R dt, R dx, R *rho, R *u,
       R eta = 0.0;
       if (d2p * d2m < 0.0 &&
           fabs(drho) - STEEP_EPS * rmin<R>(fabs(r[j + 1]), fabs(r[j - 1])) > 0.0 &&
-          g * STEEP_K0 * fabs(drho) / rmin<R>(r[j + 1], r[j - 1]) >=
-              fabs(p[j + 1] - p[j - 1]) / rmin<R>(p[j + 1], p[j - 1])) {
+          g * STEEP_K0 * fabs(drho) * rmin<R>(p[j + 1], p[j - 1]) >=
+              fabs(p[j + 1] - p[j - 1]) * rmin<R>(r[j + 1], r[j - 1])) {
         R etat = -(d2p - d2m) / (6.0 * drho);
         eta = clamp01<R>(STEEP_ETA1 * (etat - STEEP_ETA2));
       }
@@ -377,7 +384,7 @@ void pencil_sweep(const ppmo_params &P, int n, int gh, R dt, R dx, R *rho, R *u,
     for (int j = 2; j <= n - 3; ++j) {
       R dp = p[j + 1] - p[j - 1];
       R f = 0.0;
-      if (fabs(dp) / rmin<R>(p[j + 1], p[j - 1]) > FLAT_EPS && uu[j - 1] - uu[j + 1] > 0.0) {
+      if (fabs(dp) > FLAT_EPS * rmin<R>(p[j + 1], p[j - 1]) && uu[j - 1] - uu[j + 1] > 0.0) {
         R den = p[j + 2] - p[j - 2];
         if (den == 0.0) f = 1.0;
         else f = clamp01<R>(FLAT_OMEGA2 * (dp / den - FLAT_OMEGA1));
