@@ -42,6 +42,29 @@ template <class T> __device__ __forceinline__ T clamp01(T x) {
   return x < T(0) ? T(0) : (x > T(1) ? T(1) : x);
 }
 
+// Quotient, reciprocal and square root of the reconstruction and tracing
+// stages: IEEE (correctly rounded) in double; in the float stages of the
+// mixed precision the hardware reciprocal and square root (1 ulp), well
+// inside that path's error budget.
+template <class T> __device__ __forceinline__ T rdiv(T a, T b) { return a / b; }
+template <> __device__ __forceinline__ float rdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
+}
+template <class T> __device__ __forceinline__ T rrcp(T a) { return T(1) / a; }
+template <> __device__ __forceinline__ float rrcp<float>(float a) {
+  return __builtin_amdgcn_rcpf(a);
+}
+template <class T> __device__ __forceinline__ T rsqrt_exact(T a) { return sqrt(a); }
+template <> __device__ __forceinline__ float rsqrt_exact<float>(float a) {
+  return __builtin_amdgcn_sqrtf(a);
+}
+
+// The ratio test a/b > t of the selection rules, as a > t*b when b > 0 (every
+// physical state) and as written otherwise.
+__device__ __forceinline__ bool ratio_above(double a, double b, double t) {
+  return b > 0.0 ? a > t * b : a / b > t;
+}
+
 // ---------------------------------------------------------------------------
 // Pressure from the dual-energy selection rule (eta1) and the sound speed.
 // Velocities in pencil order: normal u, then the two transverse components.
@@ -50,7 +73,7 @@ __device__ __forceinline__ void eos(const Params &P, double rho, double u, doubl
   const double g = P.gamma;
   double ke = 0.5 * (u * u + v1 * v1 + v2 * v2);
   double eps = E - ke;
-  if ((P.flags & kDualEnergy) && !(eps / E > P.eta1)) eps = e;
+  if ((P.flags & kDualEnergy) && !ratio_above(eps, E, P.eta1)) eps = e;
   double pp = (g - 1.0) * rho * eps;
   if (pp < P.p_floor) pp = P.p_floor;
   p = pp;
@@ -89,8 +112,8 @@ __device__ __forceinline__ T steepen_eta(double g, T rm, T rp, T pm, T pp, T d2m
   T drho = rp - rm;
   T eta = T(0);
   if (d2p * d2m < T(0) && fabs(drho) - T(kSteepEps) * vmin<T>(fabs(rp), fabs(rm)) > T(0) &&
-      T(g * kSteepK0) * fabs(drho) / vmin<T>(rp, rm) >= fabs(pp - pm) / vmin<T>(pp, pm)) {
-    T etat = -(d2p - d2m) / (T(6) * drho);
+      T(g * kSteepK0) * fabs(drho) * vmin<T>(pp, pm) >= fabs(pp - pm) * vmin<T>(rp, rm)) {
+    T etat = rdiv<T>(-(d2p - d2m), T(6) * drho);
     eta = clamp01<T>(T(kSteepEta1) * (etat - T(kSteepEta2)));
   }
   return eta;
@@ -102,10 +125,10 @@ template <class T>
 __device__ __forceinline__ T flatten_indicator(T pm2, T pm1, T pp1, T pp2, T um1, T up1) {
   T dp = pp1 - pm1;
   T f = T(0);
-  if (fabs(dp) / vmin<T>(pp1, pm1) > T(kFlatEps) && um1 - up1 > T(0)) {
+  if (fabs(dp) > T(kFlatEps) * vmin<T>(pp1, pm1) && um1 - up1 > T(0)) {
     T den = pp2 - pm2;
     if (den == T(0)) f = T(1);
-    else f = clamp01<T>(T(kFlatOmega2) * (dp / den - T(kFlatOmega1)));
+    else f = clamp01<T>(T(kFlatOmega2) * (rdiv<T>(dp, den) - T(kFlatOmega1)));
   }
   return f;
 }
@@ -171,8 +194,8 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
     return RightEdge ? avg_right<T>(qrr[k], dq[k], q6[k], y) : avg_left<T>(ql[k], dq[k], q6[k], y);
   };
   T rt = avg(0, yref), ut = avg(1, yref), pt = avg(4, yref);
-  T C = sqrt(T(g) * pt * rt);
-  T iC = T(1) / C;
+  T C = rsqrt_exact<T>(T(g) * pt * rt);
+  T iC = rrcp<T>(C);
   // b_fast: correction of the other acoustic wave; b0: entropy wave.  The
   // reference wave's own correction is exactly zero.
   T bslow = T(0), b0 = T(0);
@@ -185,15 +208,15 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
   }
   if (zero_on) {
     T r0 = avg(0, y0), p0 = avg(4, y0);
-    b0 = (pt - p0) * iC * iC + T(1) / rt - T(1) / r0;
+    b0 = (pt - p0) * iC * iC + rrcp<T>(rt) - rrcp<T>(r0);
   }
   // With the reference wave's beta at zero: bp + bm = bslow, bp - bm = -+bslow.
   T bp = RightEdge ? T(0) : bslow;
   T bm = RightEdge ? bslow : T(0);
   T ps = pt + C * C * (bp + bm);
   T us = ut + C * (bp - bm);
-  T tau = T(1) / rt - (bp + bm + b0);
-  T rs = tau > T(0) ? T(1) / tau : rt;
+  T tau = rrcp<T>(rt) - (bp + bm + b0);
+  T rs = tau > T(0) ? rrcp<T>(tau) : rt;
   s.r = vmax<T>(rs, rho_floor);
   s.u = us;
   s.p = vmax<T>(ps, p_floor);
@@ -220,28 +243,29 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   double ipl = 1.0 / pl, ipr = 1.0 / pr;
   double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) / (cl + cr);
   if (ps < P.p_floor) ps = P.p_floor;
+  // Newton until the correction falls below rtol*p; the star state is that
+  // last iterate, whose shock speeds are already at hand.
   int it = 0;
-  for (; it < P.riemann_max_iter;) {
-    double wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
-    double wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
-    double iwl = 1.0 / wl, iwr = 1.0 / wr;
-    double usl = ul - (ps - pl) * iwl;
-    double usr = ur + (ps - pr) * iwr;
+  bool capped = false;
+  double wl, wr, iwl, iwr, usl, usr;
+  for (;;) {
+    wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
+    wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
+    iwl = 1.0 / wl;
+    iwr = 1.0 / wr;
+    usl = ul - (ps - pl) * iwl;
+    usr = ur + (ps - pr) * iwr;
+    if (capped || it == P.riemann_max_iter) break;
     double izl = (wl * wl + cl * cl) * (0.5 * iwl * iwl * iwl);
     double izr = (wr * wr + cr * cr) * (0.5 * iwr * iwr * iwr);
     double pn = ps - (usr - usl) / (izl + izr);
     if (pn < P.p_floor) pn = P.p_floor;
     ++it;
-    bool done = fabs(pn - ps) <= P.riemann_rtol * pn;
+    if (fabs(pn - ps) <= P.riemann_rtol * pn) break;
     ps = pn;
-    if (done) break;
+    if (it == P.riemann_max_iter) capped = true;
   }
   iters = it;
-  double wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
-  double wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
-  double iwl = 1.0 / wl, iwr = 1.0 / wr;
-  double usl = ul - (ps - pl) * iwl;
-  double usr = ur + (ps - pr) * iwr;
   double us = 0.5 * (usl + usr);
   // sample the upwind side of the contact at x/t = 0
   const bool left = us >= 0.0;
@@ -346,10 +370,10 @@ __device__ __forceinline__ bool update_cell(const Params &P, double lam, const C
   double epsE = En - ke;
   bool bad = !(rn > P.rho_floor);
   double sel = epsE;
-  if (dual && !(epsE / En > P.eta1)) sel = eraw;
+  if (dual && !ratio_above(epsE, En, P.eta1)) sel = eraw;
   if (!(sel > 0.0)) bad = true;
   double en = eraw < P.e_floor ? P.e_floor : eraw;
-  if (dual && rn * epsE / c.rhoEmax > P.eta2) en = epsE;
+  if (dual && ratio_above(rn * epsE, c.rhoEmax, P.eta2)) en = epsE;
   out[0] = rn; out[1] = un; out[2] = v1n; out[3] = v2n; out[4] = En; out[5] = en;
   return bad;
 }
