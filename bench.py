@@ -33,7 +33,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0         # MI355X HBM3E, GB/s
-FP64_VECTOR_PEAK_TF = 78.6    # MI355X FP64 vector, TFLOP/s
+# FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz = 39.3 T
+# operations/s; the published 78.6 TFLOP/s counts a fused multiply-add as two.
+# The sweep's operations are separate adds, multiplies, divides and square
+# roots (the FP64 path is built without contraction so that it reproduces the
+# oracle bit for bit), so 39.3 T op/s is the ceiling of its arithmetic.
+FP64_OP_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def log(msg):
@@ -49,30 +54,50 @@ def parse():
     ap.add_argument("--npatch", type=int, default=4096, help="patches of the batch (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--cpu-sample-planes", type=int, default=64,
-                    help="z-planes of the grid the CPU oracle advances (its sample)")
+    ap.add_argument("--cpu-sample-planes", type=int, default=0,
+                    help="z-planes of the grid the CPU oracle advances (0: all)")
+    ap.add_argument("--cpu-sample-steps", type=int, default=2,
+                    help="steps the CPU oracle advances")
     ap.add_argument("--tiles", default=None, help="tile_config of the single-grid plans")
     return ap.parse_args()
 
 
-def cpu_baseline(d, n, planes):
-    """The oracle (all host threads) on a slab of the same grid: `planes`
-    z-planes treated as a periodic box of their own, one step."""
+def cpu_baseline(d, n, planes, steps):
+    """The oracle (all host threads) on the same grid, or on a slab of its
+    first `planes` z-planes treated as a periodic box of its own: `steps`
+    steps (fill + CFL + xyz/zyx sweeps), only the sweeps timed."""
     import numpy as np
     import oracle as O
     g = 3
-    sub = {f: np.ascontiguousarray(a[:planes + 2 * g]) for f, a in d.items()}
+    sub = {f: np.array(a[:planes + 2 * g], dtype=np.float64, copy=True) for f, a in d.items()}
     G = O.Grid(**sub, dx=1.0 / n, dy=1.0 / n, dz=1.0 / n)
-    O.fill_periodic(G)
     prm = O.params()
-    dt = O.cfl_dt(G, prm)
-    t0 = time.perf_counter()
-    O.step(G, prm, dt, 0)
-    el = time.perf_counter() - t0
-    cells = n * n * planes
+    el = 0.0
+    for s in range(steps):
+        O.fill_periodic(G)
+        dt = O.cfl_dt(G, prm)
+        t0 = time.perf_counter()
+        O.step(G, prm, dt, s % 2)
+        el += time.perf_counter() - t0
+    cells = n * n * planes * steps
+    what = f"the full {n}^3 grid" if planes == n else f"a {n}x{n}x{planes} periodic slab of the grid"
     return dict(value=cells / el, unit="cell-updates/s", cores=O.num_threads(), kind="oracle",
-                sample=f"one step of a {n}x{n}x{planes} slab of the same seeded grid "
-                       f"(periodic), FP64, {el:.1f}s wall")
+                sample=f"{steps} steps of {what} (same seeded input), FP64, sweeps {el:.1f}s wall")
+
+
+def measured_traffic(kernel: str):
+    """Calibrated HBM bytes per dispatch of `kernel` from the committed
+    FETCH_SIZE / WRITE_SIZE summary, or None if the kernel sources changed
+    since those counters were taken."""
+    from paper_1307_2265_amd import profsummary
+    path = os.path.join(ROOT, "paper_1307_2265_amd", "data", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_digest") != profsummary.kernel_source_digest() or kernel not in t["kernels"]:
+        return None
+    return t["kernels"][kernel]
 
 
 def main():
@@ -166,7 +191,9 @@ def main():
     # the FP64 single-grid run (y sweeps, and the z sweeps first or last).
     # Algorithmic work of one launch: every pencil reads its n+6 cells and
     # writes its n active cells (6 fields of 8 B), and performs the
-    # oracle-counted FP64 operations for each of its n updated cells.
+    # oracle-counted FP64 operations (add, mul, div, sqrt) for each of its n
+    # updated cells.  The bound is the roof the kernel's arithmetic intensity
+    # meets first: ops per byte above FP64_OP_PEAK / HBM peak -> "alu".
     g = 3
     nf = n + 2 * g
     kern = results["fp64"]["kern"]
@@ -179,18 +206,26 @@ def main():
     flops_launch = mean_pencils * n * ops["flops"]
     sw = kern[dom]
     kname = "sweep_kernel<PrecF64>" if dom == "march" else "sweep_lanes_kernel<PrecF64>"
+    tr = measured_traffic(kname)
+    traffic = None if tr is None else tr["bytes"]
     hbm = dict(bound="hbm", achieved=bytes_launch / sw / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-               kernel=kname, traffic=None)
+               frac=0.0, traffic=traffic, kernel=kname, algorithmic_bytes=bytes_launch,
+               launch_ms=sw * 1e3)
     hbm["frac"] = hbm["achieved"] / hbm["peak"]
-    alu = dict(bound="alu", achieved=flops_launch / sw / 1e12, peak=FP64_VECTOR_PEAK_TF,
-               unit="TFLOP/s", kernel=kname, traffic=None)
+    alu = dict(bound="alu", achieved=flops_launch / sw / 1e12, peak=FP64_OP_PEAK_T,
+               unit="TFLOP/s", frac=0.0, traffic=traffic, kernel=kname,
+               algorithmic_flops=flops_launch, launch_ms=sw * 1e3,
+               peak_note="FP64 add/mul/div/sqrt issue rate, 256 CU x 64 lanes x 2.4 GHz")
     alu["frac"] = alu["achieved"] / alu["peak"]
-    roofline, other = (alu, hbm) if alu["frac"] >= hbm["frac"] else (hbm, alu)
+    intensity = flops_launch / bytes_launch
+    ridge = FP64_OP_PEAK_T * 1e12 / (HBM_PEAK_GBS * 1e9)
+    roofline, other = (alu, hbm) if intensity > ridge else (hbm, alu)
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(d, n, min(args.cpu_sample_planes, n))
+        planes = n if args.cpu_sample_planes <= 0 else min(args.cpu_sample_planes, n)
+        cpu = cpu_baseline(d, n, planes, args.cpu_sample_steps)
         log(f"cpu baseline: {cpu['value'] / 1e6:.2f} M cell-updates/s on {cpu['cores']} threads")
 
     fp = results["fp64"]

@@ -1,0 +1,179 @@
+"""Short text summaries of rocprofv3 runs of bench.py, for profiles/.
+
+kernels  -- from a `rocprofv3 --kernel-trace --stats --output-format csv`
+            run: per kernel (and per launch grid of the sweep kernels) the
+            number of dispatches and their mean / total duration.
+traffic  -- from two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs:
+            HBM bytes per dispatch of every kernel, each counter scaled by
+            what it reads for a device-to-device copy of known size that the
+            same run performs (bench.py copies every (n+2g)^3 double field of
+            the grid when it resets it).  Also writes data/traffic.json, which
+            bench.py reports beside its roofline as long as the kernel sources
+            hash to the digest stored there.
+
+Usage:
+  python -m paper_1307_2265_amd.profsummary kernels DIR/run_kernel_stats.csv \
+      DIR/run_kernel_trace.csv --cmd "..." --out profiles/x.md
+  python -m paper_1307_2265_amd.profsummary traffic FETCH.csv WRITE.csv --n 512 \
+      --cmd-fetch "..." --cmd-write "..." --out profiles/y.md [--json data/traffic.json]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+
+
+def kernel_source_digest() -> str:
+    """sha256 over the HIP sources and the build script (sorted by name)."""
+    h = hashlib.sha256()
+    names = sorted(os.listdir(CSRC)) + ["../build.py"]
+    for name in names:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def short(name: str) -> str:
+    base = name.split("(")[0]
+    return base.replace("void ", "").replace("ppm::", "")
+
+
+def kernels(stats_csv: str, trace_csv: str, cmd: str, out: str):
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = [f"# Kernel durations: {os.path.basename(out)[:-3]}", "",
+             "Command (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```", cmd, "```", "",
+             "## rocprofv3 --stats summary", "",
+             "| kernel | calls | mean ms | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    agg = collections.defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        if "sweep" not in r["Kernel_Name"] and "batch" not in r["Kernel_Name"]:
+            continue
+        key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]),
+               int(r["VGPR_Count"]), int(r["Scratch_Size"]), int(r["LDS_Block_Size"]))
+        agg[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    lines += ["", "## Sweep kernels by launch grid (from the kernel trace)", "",
+              "| kernel | grid threads | block | VGPRs | scratch B | LDS B | calls | mean ms |",
+              "|---|---:|---:|---:|---:|---:|---:|---:|"]
+    for k, d in sorted(agg.items(), key=lambda kv: (kv[0][0], -kv[0][1])):
+        lines.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {k[3]} | {k[4]} | {k[5]} | {len(d)} | "
+                     f"{sum(d) / len(d):.3f} |")
+    # the single-grid and the batch launches of one kernel differ in block size
+    byblock = collections.defaultdict(list)
+    for k, d in agg.items():
+        byblock[(k[0], k[2])] += d
+    lines += ["", "## Mean duration per kernel and block size", "",
+              "| kernel | block | calls | mean ms |", "|---|---:|---:|---:|"]
+    for k, d in sorted(byblock.items()):
+        lines.append(f"| `{k[0]}` | {k[1]} | {len(d)} | {sum(d) / len(d):.3f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(path: str, counter: str):
+    out = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        out.append((r["Kernel_Name"], int(r["Grid_Size"]),
+                    float(r["Counter_Value"]) * 1024.0))  # KiB -> bytes
+    return out
+
+
+def traffic(fetch_csv: str, write_csv: str, n: int, ghost: int, cmd_fetch: str, cmd_write: str,
+            out: str, json_out: str | None):
+    copy_bytes = float((n + 2 * ghost) ** 3 * 8)
+    F = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    Wr = _per_dispatch(write_csv, "WRITE_SIZE")
+
+    def calib(rows):
+        # the device-to-device copies of one whole field: the largest copies
+        big = [v for name, g, v in rows if "copyBuffer" in name]
+        top = max(big)
+        sel = [v for v in big if v > 0.9 * top]
+        return copy_bytes / (sum(sel) / len(sel)), len(sel)
+
+    cf, nf = calib(F)
+    cw, nw = calib(Wr)
+
+    def table(rows, scale):
+        agg = collections.defaultdict(list)
+        for name, g, v in rows:
+            if "ppm::" in name:
+                agg[(short(name), g)].append(v * scale)
+        return agg
+
+    TF, TW = table(F, cf), table(Wr, cw)
+    lines = [f"# HBM bytes per dispatch: {os.path.basename(out)[:-3]}", "",
+             "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```", cmd_fetch, cmd_write, "```", "",
+             f"Calibration: the run copies whole fields of (n+2g)^3 = {(n + 2 * ghost) ** 3} doubles "
+             f"({copy_bytes / 1e9:.4f} GB) device to device; FETCH_SIZE reads "
+             f"{copy_bytes / cf / 1e9:.4f} GB for such a copy ({nf} copies), WRITE_SIZE "
+             f"{copy_bytes / cw / 1e9:.4f} GB ({nw} copies).  Scale factors: fetch x{cf:.4f}, "
+             f"write x{cw:.4f}.", "",
+             "| kernel | grid threads | dispatches | fetch GB | write GB | total GB |",
+             "|---|---:|---:|---:|---:|---:|"]
+    summary = {}
+    for key in sorted(TF, key=lambda k: (k[0], -k[1])):
+        f = sum(TF[key]) / len(TF[key])
+        w = sum(TW.get(key, [0.0])) / max(1, len(TW.get(key, [])))
+        lines.append(f"| `{key[0]}` | {key[1]} | {len(TF[key])} | {f / 1e9:.3f} | {w / 1e9:.3f} | "
+                     f"{(f + w) / 1e9:.3f} |")
+        s = summary.setdefault(key[0], {"fetch": [], "write": []})
+        s["fetch"] += TF[key]
+        s["write"] += TW.get(key, [])
+    lines += ["", "Mean over all dispatches of a kernel:", "",
+              "| kernel | fetch GB | write GB | total GB |", "|---|---:|---:|---:|"]
+    per_kernel = {}
+    for k, s in sorted(summary.items()):
+        f = sum(s["fetch"]) / len(s["fetch"])
+        w = sum(s["write"]) / max(1, len(s["write"]))
+        per_kernel[k] = {"fetch_bytes": f, "write_bytes": w, "bytes": f + w,
+                         "dispatches": len(s["fetch"])}
+        lines.append(f"| `{k}` | {f / 1e9:.3f} | {w / 1e9:.3f} | {(f + w) / 1e9:.3f} |")
+    with open(out, "w") as fo:
+        fo.write("\n".join(lines) + "\n")
+    if json_out:
+        with open(json_out, "w") as fo:
+            json.dump({"source_digest": kernel_source_digest(), "workload_n": n, "ghost": ghost,
+                       "fetch_scale": cf, "write_scale": cw, "profile": os.path.basename(out),
+                       "kernels": per_kernel}, fo, indent=1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("stats")
+    k.add_argument("trace")
+    k.add_argument("--cmd", required=True)
+    k.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch")
+    t.add_argument("write")
+    t.add_argument("--n", type=int, default=512)
+    t.add_argument("--ghost", type=int, default=3)
+    t.add_argument("--cmd-fetch", required=True)
+    t.add_argument("--cmd-write", required=True)
+    t.add_argument("--out", required=True)
+    t.add_argument("--json", default=None)
+    a = ap.parse_args()
+    if a.mode == "kernels":
+        kernels(a.stats, a.trace, a.cmd, a.out)
+    else:
+        traffic(a.fetch, a.write, a.n, a.ghost, a.cmd_fetch, a.cmd_write, a.out, a.json)
+
+
+if __name__ == "__main__":
+    main()
