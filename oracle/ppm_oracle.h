@@ -14,6 +14,24 @@
  * Only tests, the smoke check and the benchmark's CPU-baseline leg may call
  * this library.  It shares no code with the HIP path.
  *
+ * What pins it (tests/test_oracle_*.py): the exact Riemann solution (Sod star
+ * state, jump conditions, shock-shock problems where two-shock is exact), exact
+ * translation of a quadratic profile and the flux it carries (reconstruction
+ * and domain averages), second-order convergence of smooth and acoustic waves,
+ * Sod E1 convergence, no new extrema, conservation, uniform state, mirror
+ * symmetry, 1-D embedded in 3-D, flux-register identity, the CFL definition,
+ * the steepening and flattening thresholds, the dual-energy selection rules
+ * (eta1 cold flow, eta2 neighbourhood maximum), the flux of a flattened shock
+ * face, and the HLL fallback on a vacuum-forming rarefaction.
+ *
+ * Parity unpinned (pinned only by these readings and by GPU == oracle):
+ *   - the CW84 flattening slope omega_2 = 10 (f~ rises from 0 at a pressure
+ *     ratio of omega_1 = 0.75 to 1 at 0.85; only the end points are pinned);
+ *   - the HLL fallback's details: Davis wave-speed estimates, the face
+ *     velocity of the HLL intermediate state in the p div v term, and the
+ *     state given to a cell still non-positive after the fallback;
+ *   - the Newton tolerance and iteration cap of the two-shock solver.
+ *
  * Conventions (all host pointers, owned by the caller):
  *   - A grid has nx*ny*nz active cells and `ghost` ghost layers per side (3, as
  *     the paper's PPM stencil needs; 3..6 accepted).  With 3 layers the CW84

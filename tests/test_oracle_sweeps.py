@@ -481,3 +481,195 @@ def test_flattening_suppresses_post_shock_oscillations(O):
         excess[name] = np.abs(np.diff(r[G3:-G3])).sum() - tv_exact
     assert excess["on"] < 0.01, excess
     assert excess["off"] > 0.05, excess
+
+
+# ---------------------------------------------------------------------------
+# Closed-form pins of the reconstruction, tracing and flattening stages
+
+def _quad_avgs(a, b, c, x, h):
+    """Cell averages of a + b x + c x^2 over cells of width h centred at x."""
+    return a + b * x + c * (x * x + h * h / 12.0)
+
+
+@pytest.mark.parametrize("which", ["density", "transverse"])
+def test_quadratic_profile_is_translated_exactly(O, which):
+    # The fourth-order interface formula (CW84 Eq. 1.6 on a uniform grid)
+    # reproduces the point values of a quadratic from its cell averages, so
+    # the parabolas of a monotone quadratic profile are the profile itself
+    # (no limiting, no steepening since d^2 rho is constant, no flattening
+    # since p is uniform).  The left state at each face is then the exact
+    # average over the domain the entropy wave sweeps in dt (CW84 Eq. 1.12),
+    # and one sweep with uniform u and p translates the profile exactly: the
+    # new cell averages are those of q(x - u dt).  A density quadratic checks
+    # the mass flux, a transverse-velocity quadratic (uniform density) the
+    # passively advected state.
+    g, N = 5.0 / 3.0, 24
+    h = 1.0 / N
+    x = (np.arange(N + 6) - G3 + 0.5) * h
+    u0, p0 = 0.7, 1.0
+    rho = np.ones_like(x)
+    v1 = np.zeros_like(x)
+    if which == "density":
+        A = (1.0, 0.3, 0.1)
+        rho = _quad_avgs(*A, x, h)
+    else:
+        A = (0.2, 0.5, 0.3)
+        v1 = _quad_avgs(*A, x, h)
+    u = np.full_like(x, u0)
+    v2 = np.zeros_like(x)
+    e = p0 / ((g - 1.0) * rho)
+    E = e + 0.5 * (u * u + v1 * v1 + v2 * v2)
+    prm = O.params(gamma=g)
+    cmax = np.sqrt(g * p0 / rho.min())
+    dt = 0.5 * h / (u0 + cmax)
+    _, lo, _ = O.pencil(prm, dt, h, rho, u, v1, v2, E, e, want_reg=True)
+    xa = x[G3:-G3]
+    want = _quad_avgs(*A, xa - u0 * dt, h)
+    got = rho[G3:-G3] if which == "density" else v1[G3:-G3]
+    assert np.max(np.abs(got - want) / np.abs(want)) < 1e-12
+    # the low register holds dt*F through the face at x = 0: the mass (or
+    # transverse momentum) that the translation carries across it, the
+    # integral of q over [-u dt, 0]
+    s = u0 * dt
+    flux = A[0] * s - A[1] * s * s / 2.0 + A[2] * s ** 3 / 3.0
+    k = 0 if which == "density" else 2
+    assert abs(lo[k] - flux) / abs(flux) < 1e-12, (lo[k], flux)
+    assert np.max(np.abs(u[G3:-G3] - u0)) < 1e-12
+    if which == "transverse":
+        assert np.max(np.abs(rho[G3:-G3] - 1.0)) < 1e-12
+
+
+def _pencil_state(g, p, u, rho=None):
+    n = len(p)
+    rho = np.ones(n) if rho is None else rho
+    v1 = np.full(n, 0.25)
+    v2 = np.full(n, -0.15)
+    e = p / ((g - 1.0) * rho)
+    E = e + 0.5 * (u * u + v1 * v1 + v2 * v2)
+    return [a.astype(float).copy() for a in (rho, u, v1, v2, E, e)]
+
+
+def _shock_pencil(p_hi, p_mid):
+    # pressure falls from p_hi (cells 0-2) through p_mid (cell 3) to 1 while
+    # the flow converges, so the flattening stencil of cell 3 sees the whole
+    # jump: (p_4 - p_2) / (p_5 - p_1) = 1
+    n = 12
+    p = np.array([p_hi] * 3 + [p_mid] + [1.0] * (n - 4))
+    u = np.array([0.3] * 3 + [0.1] + [-0.1] * (n - 4))
+    return p, u
+
+
+def test_flattened_shock_face_carries_the_riemann_flux_of_the_cell_values(O):
+    # CW84 appendix flattening: a converging jump with
+    # |p_4 - p_2| / min(p_4, p_2) = 0.4 above the shock threshold 0.33 and
+    # (p_4 - p_2)/(p_5 - p_1) = 1 gives f~_3 = 1; cell 2 takes the larger
+    # coefficient of its upstream neighbour (pressure falls to the right), so
+    # both cells at the first active face are flat.  Their traced states are
+    # the cell values themselves, and the flux through that face -- recorded
+    # in the low flux register -- is the flux of the two-shock solution
+    # between cells 2 and 3 (Sec. "Riemann Solvers and Fallback"): mass
+    # rho u, momentum rho u^2 + p, transverse rho u v, total energy
+    # u (rho E + p) with E from the interface pressure, internal energy
+    # rho u e.
+    g = 5.0 / 3.0
+    prm = O.params(gamma=g)
+    p, u = _shock_pencil(1.4, 1.2)
+    st = _pencil_state(g, p, u)
+    rho, uu, v1, v2, E, e = [a.copy() for a in st]
+    h, dt = 0.1, 0.01
+    _, lo, _ = O.pencil(prm, dt, h, *st, want_reg=True)
+    pc = (g - 1.0) * rho * e
+    rs = O.two_shock(prm, [rho[2], uu[2], pc[2]], [rho[3], uu[3], pc[3]])
+    up = 2 if rs["u_star"] >= 0.0 else 3
+    rb, ub, pb = rs["rho"], rs["u"], rs["p"]
+    eb = pb / ((g - 1.0) * rb)
+    fr = rb * ub
+    want = dt * np.array([fr, fr * ub + pb, fr * v1[up], fr * v2[up],
+                          fr * (eb + 0.5 * (ub * ub + v1[up] ** 2 + v2[up] ** 2)) + ub * pb,
+                          fr * eb])
+    assert np.max(np.abs(lo - want) / np.abs(want)) < 1e-12, (lo, want)
+    # without flattening the same face differs
+    _, lo_off, _ = O.pencil(O.params(gamma=g, flags=O.ALL_FLAGS & ~O.FLATTEN), dt, h,
+                            *[a.copy() for a in (rho, uu, v1, v2, E, e)], want_reg=True)
+    assert np.max(np.abs(lo_off - want) / np.abs(want)) > 1e-6
+
+
+@pytest.mark.parametrize("p_hi,p_mid", [(1.3, 1.15),    # jump 0.3, below the 0.33 threshold
+                                        (2.0, 1.3)])    # ratio 0.7, below omega_1 = 0.75
+def test_flattening_stays_off_below_its_thresholds(O, p_hi, p_mid):
+    # CW84 appendix: no flattening unless the relative pressure jump across
+    # the cell exceeds 0.33 and (p_{j+1}-p_{j-1})/(p_{j+2}-p_{j-2}) exceeds
+    # omega_1 = 0.75; below both, the sweep equals the one without
+    # flattening bit for bit.
+    g = 5.0 / 3.0
+    p, u = _shock_pencil(p_hi, p_mid)
+    if p_hi == 2.0:
+        p[2] = 1.7  # (p_3 - p_1)/(p_4 - p_0) = (p_4 - p_2)/(p_5 - p_1) = 0.7
+    jumps = np.abs(p[2:] - p[:-2]) / np.minimum(p[2:], p[:-2])
+    ratios = [(p[j + 1] - p[j - 1]) / (p[j + 2] - p[j - 2]) if p[j + 2] != p[j - 2] else 0.0
+              for j in range(2, len(p) - 2)]
+    assert max(jumps) < 0.33 or max(ratios) < 0.75
+    h, dt = 0.1, 0.01
+    outs = []
+    for flags in (O.ALL_FLAGS, O.ALL_FLAGS & ~O.FLATTEN):
+        st = _pencil_state(g, p, u)
+        O.pencil(O.params(gamma=g, flags=flags), dt, h, *st)
+        outs.append(st)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("drho,dp,steepened", [
+    (1.0, 0.1, True),     # gamma K0 drho = 1/6 >= dp: a contact
+    (1.0, 0.2, False),    # pressure jump too large for a contact
+    (0.05, 0.0, True),    # density jump above eps = 0.01
+    (0.005, 0.0, False),  # density jump below eps
+])
+def test_steepening_detection_thresholds(O, drho, dp, steepened):
+    # CW84 Eqs. 1.16-1.17 and 3.2 on a two-cell ramp in density (and in
+    # pressure): the middle cell j has d^2 rho of opposite signs on its two
+    # sides and eta~_j = 1/6, so eta_j = min(1, 20 (1/6 - 0.05)) = 1 whenever
+    # the detection tests pass: |rho_{j+1} - rho_{j-1}| above 0.01 min(rho),
+    # and gamma K0 |d rho|/min(rho) >= |d p|/min(p) with K0 = 0.1.  Steepening
+    # then changes the result; otherwise the sweep equals the one without
+    # steepening bit for bit.
+    g = 5.0 / 3.0
+    n = 14
+    ramp = np.array([0.0] * 6 + [0.5] + [1.0] * (n - 7))
+    rho = 1.0 + drho * ramp
+    p = 1.0 + dp * ramp
+    u = np.full(n, 0.3)  # a moving contact, so the face densities enter the fluxes
+    h, dt = 0.1, 0.01
+    outs = []
+    for flags in (O.ALL_FLAGS, O.ALL_FLAGS & ~O.STEEPEN):
+        st = _pencil_state(g, p, u, rho)
+        O.pencil(O.params(gamma=g, flags=flags), dt, h, *st)
+        outs.append(st)
+    same = all(np.array_equal(a, b) for a, b in zip(*outs))
+    assert same != steepened
+
+
+def test_eta2_resync_looks_at_the_neighbourhood_maximum(O):
+    # Eq. dualselect: e is reset to E - v^2/2 only where rho (E - v^2/2)
+    # exceeds eta2 times the largest rho E among the cell and its two
+    # neighbours along the sweep.  Cells 4 and 8 start with an internal
+    # energy half of E - v^2/2; cell 4 sits in uniform gas (ratio ~1 > 0.1:
+    # resynced, as with eta2 = 0), cell 8 between two hot cells whose rho E
+    # is 20 times its thermal energy (ratio ~0.05 < 0.1: not resynced, as
+    # with an eta2 no cell reaches).
+    g = 5.0 / 3.0
+    n = 16
+    p = np.ones(n)
+    p[[7, 9]] = 20.0
+    u = np.full(n, 0.2)
+    h, dt = 0.1, 1e-4
+
+    def run(eta2):
+        st = _pencil_state(g, p, u)
+        st[5][[4, 8]] *= 0.5  # contaminated internal energy
+        O.pencil(O.params(gamma=g, eta2=eta2), dt, h, *st)
+        return st[5]
+
+    e_paper, e_always, e_never = run(0.1), run(0.0), run(1e30)
+    assert e_paper[4] == e_always[4] and e_paper[4] != e_never[4]
+    assert e_paper[8] == e_never[8] and e_paper[8] != e_always[8]
