@@ -68,6 +68,13 @@ typedef enum {
 
 typedef enum { PPM_FP64 = 0, PPM_MIXED = 1 } ppm_precision;
 
+/* Where a patch's ghost values come from. */
+enum {
+  PPM_BC_PERIODIC = 0, /* ppm_fill_periodic fills them from the patch's own active cells */
+  PPM_BC_SUPPLIED = 1  /* the caller fills them (e.g. from a parent or sibling grid);
+                          ppm_fill_periodic leaves the patch untouched */
+};
+
 enum {
   PPM_STEEPEN = 1u,      /* contact steepening of the density parabola */
   PPM_FLATTEN = 2u,      /* shock flattening of all parabolas */
@@ -81,7 +88,7 @@ typedef struct {
   int32_t nx, ny, nz; /* active cells per axis, >= 1 */
   int32_t ghost;      /* ghost layers per side, 3..6 (3 in the paper) */
   int32_t level;      /* index into the per-level dt array, 0 <= level < nlevels */
-  int32_t reserved;   /* must be 0 */
+  int32_t bc;         /* PPM_BC_PERIODIC or PPM_BC_SUPPLIED */
   double dx, dy, dz;  /* cell widths, > 0 */
   void *rho, *vx, *vy, *vz; /* double (PPM_FP64) or float (PPM_MIXED) */
   double *etot, *eint;      /* double in both precisions */
@@ -119,8 +126,11 @@ int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
  *   cfl_cells=C    active cells per block of the CFL reduction.
  *   persistent=0|1 ppm_step as one persistent launch: workgroups take whole
  *                  patches from a queue (largest first) and run their three
- *                  sweeps back to back (default 1 for several patches, 0 for
- *                  one); with 0, one launch per sweep over all patches.
+ *                  sweeps back to back; with 0, one launch per sweep over all
+ *                  patches.  A workgroup owns a whole patch, so persistent=1
+ *                  needs every patch to hold at most 2^21 active cells
+ *                  (PPM_EINVAL otherwise).  Default: 1 for several patches
+ *                  that all satisfy this, else 0.
  *   batch_block=B  threads per workgroup of the persistent launch (64..256).
  *   batch_blocks=W workgroups of the persistent launch (default: 512/B per CU).
  * Results do not depend on the launch shapes.  Uploads the patch table to
@@ -134,9 +144,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
  * enqueued work still uses it).  NULL is accepted. */
 ppm_status ppm_plan_destroy(ppm_plan *plan);
 
-/* Periodic ghost fill of every patch of the plan (each patch is treated as a
- * periodic box of its own): ghost cell i takes the value of the active cell
- * g + ((i - g) mod N) along every axis. */
+/* Periodic ghost fill of every PPM_BC_PERIODIC patch of the plan (each is
+ * treated as a periodic box of its own): ghost cell i takes the value of the
+ * active cell g + ((i - g) mod N) along every axis.  PPM_BC_SUPPLIED patches
+ * are not touched. */
 ppm_status ppm_fill_periodic(ppm_plan *plan, void *hip_stream);
 
 /* Hydro CFL timestep per level (Sec. "Timestepping"):

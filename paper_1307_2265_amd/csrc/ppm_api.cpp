@@ -35,6 +35,7 @@ struct ppm_plan {
   int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
   unsigned int *d_queue = nullptr;  // persistent queue head and exit count
   std::vector<PatchDev> host;
+  std::vector<int32_t> bc;        // boundary kind of each patch
   PatchDev *d_patches = nullptr;
   int32_t *d_chunks = nullptr;    // 12 marching, 12 lane-parallel prefix arrays, then CFL
   int32_t nblocks[24] = {};
@@ -63,6 +64,8 @@ ppm_status hip_fail(hipError_t e, const char *what) {
 }
 
 const int kOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
+// Largest patch (active cells) that one workgroup of the persistent launch owns.
+const int64_t kPersistentMaxCells = int64_t(1) << 21;
 
 inline int t1_of(int axis) { return axis == 0 ? 1 : 0; }
 inline int t2_of(int axis) { return axis == 2 ? 1 : 2; }
@@ -90,7 +93,8 @@ ppm_status check_patch(const ppm_patch &q, int i, int32_t nlevels) {
   if (q.ghost < 3 || q.ghost > 6) return fail(PPM_EINVAL, "patch %d: ghost must be in 3..6", i);
   if (q.level < 0 || q.level >= nlevels)
     return fail(PPM_EINVAL, "patch %d: level %d outside [0, %d)", i, q.level, nlevels);
-  if (q.reserved != 0) return fail(PPM_EINVAL, "patch %d: reserved must be 0", i);
+  if (q.bc != PPM_BC_PERIODIC && q.bc != PPM_BC_SUPPLIED)
+    return fail(PPM_EINVAL, "patch %d: bc must be PPM_BC_PERIODIC or PPM_BC_SUPPLIED", i);
   if (!(q.dx > 0.0) || !(q.dy > 0.0) || !(q.dz > 0.0) || !std::isfinite(q.dx) ||
       !std::isfinite(q.dy) || !std::isfinite(q.dz))
     return fail(PPM_EINVAL, "patch %d: cell widths must be finite and > 0", i);
@@ -205,17 +209,27 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   pl->prec = prec;
   std::memcpy(&pl->P, params, sizeof(ppm::Params));
   static_assert(sizeof(ppm::Params) == sizeof(ppm_params), "params layout");
-  if (npatch > 1) {  // uneven small patches: finer chunks, one persistent launch
+  int64_t max_cells = 0;
+  for (int i = 0; i < npatch; ++i)
+    max_cells = std::max(max_cells, int64_t(patches[i].nx) * patches[i].ny * patches[i].nz);
+  if (npatch > 1) {  // uneven patches: finer chunks, one persistent launch if they are small
     pl->block = 64;
     pl->lanes_block = 64;
-    pl->persistent = 1;
+    pl->persistent = max_cells <= kPersistentMaxCells ? 1 : 0;
   }
   if ((st = parse_tiles(pl, tile_config)) != PPM_OK) {
     delete pl;
     return st;
   }
+  if (pl->persistent && max_cells > kPersistentMaxCells) {
+    delete pl;
+    return fail(PPM_EINVAL, "persistent=1 needs every patch to hold at most %lld active cells",
+                (long long)kPersistentMaxCells);
+  }
   (void)hipGetDevice(&pl->device);
   pl->host.resize(npatch);
+  pl->bc.resize(npatch);
+  for (int i = 0; i < npatch; ++i) pl->bc[i] = patches[i].bc;
   for (int i = 0; i < npatch; ++i) {
     const ppm_patch &q = patches[i];
     PatchDev &d = pl->host[i];
@@ -333,6 +347,7 @@ ppm_status ppm_fill_periodic(ppm_plan *plan, void *hip_stream) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   for (int i = 0; i < plan->npatch; ++i) {
+    if (plan->bc[i] != PPM_BC_PERIODIC) continue;
     hipError_t e = plan->prec == PPM_FP64 ? ppm::launch_fill<ppm::PrecF64>(plan->host[i], s)
                                           : ppm::launch_fill<ppm::PrecMixed>(plan->host[i], s);
     if (e != hipSuccess) return hip_fail(e, "fill_periodic launch");

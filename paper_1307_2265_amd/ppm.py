@@ -20,6 +20,7 @@ PPM_STEEPEN, PPM_FLATTEN, PPM_DUAL_ENERGY, PPM_FALLBACK_HLL = 1, 2, 4, 8
 PPM_ALL_FLAGS = 15
 ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
 PPM_GRAPH_FILL, PPM_GRAPH_CFL, PPM_GRAPH_STEP = 1, 2, 4
+PPM_BC_PERIODIC, PPM_BC_SUPPLIED = 0, 1
 
 # Every function the header declares, with (restype, argtypes).
 _vp = C.c_void_p
@@ -27,7 +28,7 @@ _vp = C.c_void_p
 
 class ppm_patch(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("ghost", C.c_int32),
-                ("level", C.c_int32), ("reserved", C.c_int32),
+                ("level", C.c_int32), ("bc", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("rho", _vp), ("vx", _vp), ("vy", _vp), ("vz", _vp),
                 ("etot", _vp), ("eint", _vp), ("flux_reg", _vp)]
@@ -115,7 +116,8 @@ class Patch:
 
     rho, vx, vy, vz are float64 (PPM_FP64) or float32 (PPM_MIXED); etot and
     eint are float64.  flux_reg is an optional float64 tensor of
-    ppm_flux_reg_size(nx, ny, nz) elements.
+    ppm_flux_reg_size(nx, ny, nz) elements.  bc: PPM_BC_PERIODIC (ghosts filled
+    by ppm_fill_periodic) or PPM_BC_SUPPLIED (ghosts filled by the caller).
     """
     rho: object
     vx: object
@@ -129,6 +131,7 @@ class Patch:
     ghost: int = 3
     level: int = 0
     flux_reg: object = None
+    bc: int = PPM_BC_PERIODIC
 
     @property
     def dims(self):
@@ -146,7 +149,7 @@ class Patch:
             if tuple(t.shape) != shp or not t.is_contiguous() or t.device.type != "cuda":
                 raise ValueError("patch fields must be contiguous CUDA tensors of one shape")
         ptr = lambda t: None if t is None else t.data_ptr()
-        return ppm_patch(nx, ny, nz, self.ghost, self.level, 0, self.dx, self.dy, self.dz,
+        return ppm_patch(nx, ny, nz, self.ghost, self.level, self.bc, self.dx, self.dy, self.dz,
                          *[ptr(t) for t in self.fields()], ptr(self.flux_reg))
 
 

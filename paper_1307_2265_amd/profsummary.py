@@ -31,9 +31,9 @@ CSRC = os.path.join(HERE, "csrc")
 
 
 def kernel_source_digest() -> str:
-    """sha256 over the HIP sources and the build script (sorted by name)."""
+    """sha256 over the device code (.hip, .hpp) and the build script."""
     h = hashlib.sha256()
-    names = sorted(os.listdir(CSRC)) + ["../build.py"]
+    names = sorted(n for n in os.listdir(CSRC) if n.endswith((".hip", ".hpp"))) + ["../build.py"]
     for name in names:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())

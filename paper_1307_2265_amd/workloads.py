@@ -129,3 +129,114 @@ CONFIGS = {
     1: dict(n=256, recipe=GENTLE, seed=1001, steps=10),
     2: dict(n=512, recipe=SHOCKED, seed=1002, steps=20),
 }
+
+
+# ---------------------------------------------------------------------------
+# Cosmology-shaped hierarchy: a periodic root grid holding a log-normal
+# Gaussian random field density and cold bulk flows, plus nested patches on
+# levels 1-8 whose fields (ghosts included) are injected piecewise constant
+# from the root at random positions.  The root is generated on the GPU with
+# torch (white noise filtered in Fourier space), so these inputs exist only
+# where a GPU does; the CPU oracle receives copies of the generated arrays.
+
+# Grids per level in the paper's AMR scaling run (Sec. "AMR scaling"),
+# levels 1-6, extended to levels 7 and 8 by the ratio 0.7 per level.
+HIER_LEVEL_WEIGHTS = (61868.0, 91182.0, 59932.0, 40700.0, 28346.0, 19771.0,
+                      19771.0 * 0.7, 19771.0 * 0.49)
+HIER_DIMS = tuple(range(16, 49, 2))   # per-axis active dims of a patch
+HIER_RHO_SIGMA = 1.5                  # sigma of ln(rho)
+HIER_KE_OVER_TE_MAX = 1e6             # largest kinetic / thermal energy ratio
+
+
+@dataclass
+class HierPatch:
+    nx: int
+    ny: int
+    nz: int
+    level: int
+    dx: float
+    origin: tuple   # root cell (x, y, z) of the patch's first active cell
+
+
+def hierarchy_specs(npatch: int, n_root: int, seed: int) -> list:
+    """Patch dims i.i.d. from HIER_DIMS, levels 1-8 drawn with the weights
+    above, dx = 2^-level / n_root, origin uniform over the root's cells."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = np.asarray(HIER_LEVEL_WEIGHTS)
+    lev = rng.choice(np.arange(1, 9), size=npatch, p=w / w.sum())
+    d = rng.choice(np.asarray(HIER_DIMS), size=(npatch, 3))
+    org = rng.integers(0, n_root, size=(npatch, 3))
+    return [HierPatch(int(a), int(b), int(c), int(l), 2.0 ** -int(l) / n_root,
+                      (int(o[0]), int(o[1]), int(o[2])))
+            for (a, b, c), l, o in zip(d, lev, org)]
+
+
+def _grf(n: int, gen, device):
+    """Unit-variance Gaussian random field on an n^3 periodic grid with power
+    spectrum P(k) ~ k^-2 (white noise times 1/|k| in Fourier space, k = 0
+    removed)."""
+    import torch
+    w = torch.randn((n, n, n), generator=gen, dtype=torch.float64, device=device)
+    F = torch.fft.rfftn(w)
+    del w
+    k = torch.fft.fftfreq(n, d=1.0 / n, dtype=torch.float64, device=device)
+    kr = torch.fft.rfftfreq(n, d=1.0 / n, dtype=torch.float64, device=device)
+    k2 = k[:, None, None] ** 2 + k[None, :, None] ** 2 + kr[None, None, :] ** 2
+    k2[0, 0, 0] = 1.0
+    F *= k2.rsqrt_()
+    F[0, 0, 0] = 0.0
+    del k2
+    d = torch.fft.irfftn(F, s=(n, n, n))
+    del F
+    d -= d.mean()
+    d /= d.std()
+    return d
+
+
+def hierarchy_root(n: int, seed: int, gamma: float = GAMMA, device="cuda",
+                   ghost: int = GHOST) -> dict:
+    """Root fields as float64 device tensors of shape (n+2g)^3 with zero ghosts:
+    rho = exp(1.5 delta - 1.125) (mean one), three velocity components that
+    are independent unit-variance fields of the same spectrum, and a cold
+    adiabatic gas e = e_c rho^(gamma-1) with e_c such that the largest
+    kinetic / thermal energy ratio over the grid is 1e6."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    s = HIER_RHO_SIGMA
+    full = (n + 2 * ghost,) * 3
+    inner = (slice(ghost, ghost + n),) * 3
+    out = {}
+    rho = torch.exp(s * _grf(n, gen, device) - 0.5 * s * s)
+    ke = torch.zeros((n, n, n), dtype=torch.float64, device=device)
+    for name in ("vx", "vy", "vz"):
+        v = _grf(n, gen, device)
+        ke += 0.5 * v * v
+        out[name] = torch.zeros(full, dtype=torch.float64, device=device)
+        out[name][inner] = v
+        del v
+    rg = rho ** (gamma - 1.0)
+    ec = float((ke / rg).max()) / HIER_KE_OVER_TE_MAX
+    e = ec * rg
+    del rg
+    for name, a in (("rho", rho), ("eint", e), ("etot", e + ke)):
+        out[name] = torch.zeros(full, dtype=torch.float64, device=device)
+        out[name][inner] = a
+    return out
+
+
+def inject_patch(root: dict, spec: HierPatch, n_root: int, ghost: int = GHOST) -> dict:
+    """A patch's fields (ghosts included) injected piecewise constant from the
+    root's active cells: patch cell i along an axis lies in root cell
+    origin + floor((i - g) / 2^level), wrapped periodically."""
+    import torch
+    dev = root["rho"].device
+    r = 2 ** spec.level
+
+    def idx(n, o):
+        i = torch.arange(n + 2 * ghost, device=dev) - ghost
+        return (o + torch.div(i, r, rounding_mode="floor")) % n_root + ghost
+
+    ix, iy, iz = idx(spec.nx, spec.origin[0]), idx(spec.ny, spec.origin[1]), idx(spec.nz, spec.origin[2])
+    sel = (iz[:, None, None], iy[None, :, None], ix[None, None, :])
+    return {k: v[sel] for k, v in root.items()}

@@ -33,7 +33,7 @@ def test_status_strings_and_reg_size():
 
 
 def _patch(**kw):
-    base = dict(nx=8, ny=8, nz=8, ghost=3, level=0, reserved=0, dx=0.1, dy=0.1, dz=0.1,
+    base = dict(nx=8, ny=8, nz=8, ghost=3, level=0, bc=0, dx=0.1, dy=0.1, dz=0.1,
                 rho=1, vx=1, vy=1, vz=1, etot=1, eint=1, flux_reg=None)
     base.update(kw)
     return ppm.ppm_patch(**base)
@@ -45,7 +45,7 @@ def _patch(**kw):
     (dict(level=3), {}, "level"),
     (dict(dx=0.0), {}, "cell widths"),
     (dict(rho=None), {}, "NULL field"),
-    (dict(reserved=1), {}, "reserved"),
+    (dict(bc=2), {}, "bc must be"),
     ({}, dict(gamma=1.0), "gamma"),
     ({}, dict(cfl=1.5), "cfl"),
     ({}, dict(riemann_max_iter=0), "riemann_max_iter"),
@@ -82,3 +82,16 @@ def test_bad_tile_config_is_rejected():
     assert st == ppm.PPM_EINVAL and "block" in L.ppm_last_error().decode()
     st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"warp=3", None)
     assert st == ppm.PPM_EINVAL and "unknown key" in L.ppm_last_error().decode()
+
+
+def test_persistent_launch_rejects_patches_too_large_for_one_workgroup():
+    # a workgroup of the persistent launch owns a whole patch; 2^21 active
+    # cells is the limit (the check runs before anything touches the device)
+    L = ppm.lib()
+    arr = (ppm.ppm_patch * 2)(_patch(), _patch(nx=128, ny=128, nz=129))
+    prm = ppm.params()
+    h = C.c_void_p()
+    st = L.ppm_plan_create(C.byref(h), arr, 2, 1, ppm.PPM_FP64, C.byref(prm), b"persistent=1",
+                           None)
+    assert st == ppm.PPM_EINVAL and "persistent=1" in L.ppm_last_error().decode()
+    assert not h.value

@@ -252,6 +252,7 @@ def test_full_size_512_step_in_bench_configuration(P, O):
     # one full step from the same stored input: FP64 compared with the oracle
     # cell by cell, mixed precision by per-field relative L1.
     import torch
+    from paper_1307_2265_amd import autotune
     n = 512
     cfg = W.CONFIGS[2]
     print("generating 512^3 input", flush=True)
@@ -266,7 +267,8 @@ def test_full_size_512_step_in_bench_configuration(P, O):
     for prec in (P.PPM_FP64, P.PPM_MIXED):
         print(f"gpu step, precision {prec}", flush=True)
         patch = to_device(d, prec)
-        plan = P.Plan([patch], 1, prec, P.params())
+        name = "fp64" if prec == P.PPM_FP64 else "mixed"
+        plan = P.Plan([patch], 1, prec, P.params(), tile_config=autotune.best_tiles(f"single/{name}"))
         dt = _dt_tensor()
         plan.ppm_fill_periodic()
         plan.ppm_cfl_dt(dt)
@@ -293,6 +295,94 @@ def test_full_size_512_step_in_bench_configuration(P, O):
         plan.close()
         del patch
         torch.cuda.empty_cache()
+
+
+def test_config1_256_ten_steps_fp64(P, O):
+    # The 256^3 workload (gentle white noise, seed 1001): ten steps with the
+    # device CFL dt each step, in the single-grid launch configuration of the
+    # benchmark, against ten oracle steps with the oracle's own dt.
+    from paper_1307_2265_amd import autotune
+    cfg = W.CONFIGS[1]
+    n = cfg["n"]
+    print("generating 256^3 input", flush=True)
+    d = W.random_grid(n, n, n, cfg["seed"], cfg["recipe"])
+    g, dg, cg, _ = _run_gpu_steps(P, d, cfg["steps"], P.PPM_FP64,
+                                  tiles=autotune.best_tiles("single/fp64"))
+    print("oracle steps", flush=True)
+    o, do, co, _ = _run_oracle_steps(O, d, cfg["steps"])
+    assert dg == do
+    worst, differ = compare_fields(g, o, TOL64, region=(slice(3, -3),) * 3)
+    print(f"256^3 x 10 steps: worst {worst:.2e}, cells not bitwise equal {differ}, "
+          f"counts {cg} {co}")
+    assert cg == co
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config3_full_batch_in_bench_configuration(P, O, prec):
+    # The full 4096-patch batch (seed 1003) exactly as the benchmark runs it:
+    # flat field buffers, autotuned launch shapes, one captured graph per step
+    # (CFL + step, xyz then zyx), registers on.  Two steps; the oracle
+    # advances every patch with its level's dt from its own CFL reduction.
+    import torch
+    from paper_1307_2265_amd import autotune
+    from paper_1307_2265_amd import harness as H
+    print("generating 4096 patches", flush=True)
+    specs, fields = H.batch_input(4096)
+    pr = P.PPM_FP64 if prec == "fp64" else P.PPM_MIXED
+    run = H.Run.batch(specs, fields, pr, autotune.best_tiles(f"batch/{prec}"))
+    run.make_graphs()
+    dts_g = []
+    for s in range(2):
+        run.graphs[s].ppm_graph_launch()
+        torch.cuda.synchronize()
+        dts_g.append(run.dt.cpu().numpy().copy())
+    counts_g = run.plan.ppm_event_counts()
+    print("oracle", flush=True)
+    prm = O.params()
+    nlev = run.nlevels
+    grids = [oracle_grid(O, stored_inputs(f, pr), dx=(sp.dx,) * 3, with_reg=True)
+             for f, sp in zip(fields, specs)]
+    counts_o = [0, 0]
+    for s in range(2):
+        smax = np.zeros(nlev)
+        for G, sp in zip(grids, specs):
+            smax[sp.level] = max(smax[sp.level], O.cfl_signal_max(G, prm))
+        dto = np.where(smax > 0, prm.cfl / np.where(smax > 0, smax, 1.0), np.inf)
+        if prec == "fp64":
+            assert np.array_equal(dts_g[s], dto), (s, dts_g[s], dto)
+        else:
+            assert np.allclose(dts_g[s], dto, rtol=1e-5), (s, dts_g[s], dto)
+        for G, sp in zip(grids, specs):
+            c = O.step(G, prm, float(dts_g[s][sp.level] if prec == "mixed" else dto[sp.level]),
+                       s)
+            counts_o[0] += c.fallback_faces
+            counts_o[1] += c.floored_cells
+    num = {f: 0.0 for f in FIELDS}
+    den = {f: 0.0 for f in FIELDS}
+    differ, worst = 0, 0.0
+    sl = (slice(3, -3),) * 3
+    for i, (p, G) in enumerate(zip(run.patches, grids)):
+        g = from_device(p)
+        if prec == "fp64":
+            w, d = compare_fields({f: g[f][sl] for f in FIELDS},
+                                  {f: getattr(G, f)[sl] for f in FIELDS}, TOL64)
+            worst, differ = max(worst, w), differ + d
+            reg = p.flux_reg.cpu().numpy()
+            scale = np.maximum(np.abs(G.flux_reg), np.abs(G.flux_reg).mean())
+            assert np.max(np.abs(reg - G.flux_reg) / scale) <= TOL64, i
+        else:
+            for f in FIELDS:
+                num[f] += np.abs(g[f][sl] - getattr(G, f)[sl]).sum()
+                den[f] += np.abs(getattr(G, f)[sl]).sum()
+    run.close()
+    if prec == "fp64":
+        print(f"4096 patches x 2 steps: worst {worst:.2e}, cells not bitwise equal {differ}, "
+              f"counts {counts_g} {tuple(counts_o)}")
+        assert counts_g == tuple(counts_o)
+    else:
+        for f in FIELDS:
+            print(f"4096 patches mixed, {f}: relative L1 after 2 steps {num[f] / den[f]:.2e}")
+            assert num[f] / den[f] <= 1e-5
 
 
 def _batch(P, O, npatch, seed, prec, tiles=None, steps=1):

@@ -673,3 +673,46 @@ def test_eta2_resync_looks_at_the_neighbourhood_maximum(O):
     e_paper, e_always, e_never = run(0.1), run(0.0), run(1e30)
     assert e_paper[4] == e_always[4] and e_paper[4] != e_never[4]
     assert e_paper[8] == e_never[8] and e_paper[8] != e_always[8]
+
+
+def test_update_of_a_cell_depends_only_on_cells_within_six(O):
+    # Locality of one step (the basis of the sampled full-size checks): the
+    # new state of a cell depends on the old states within six cells along
+    # each axis.  A face's states come from the parabolas of its two cells,
+    # whose flattening reaches three cells further; the HLL fallback re-solves
+    # the faces of a neighbouring cell whose provisional update went
+    # non-positive, so the neighbours' own updates (five cells out) count too.
+    # A 13^3 box around a cell -- the cell and its neighbours active, five
+    # ghost layers -- advanced by the oracle reproduces the full periodic
+    # grid's result there bit for bit; the box of one active cell does not
+    # once the fallback fires next to it.  Cold, Mach ~100 flows (the
+    # cosmology-shaped recipe) make the fallback and the floors frequent.
+    n = 32
+    r = W.hierarchy_root(n, 1004, device="cpu")
+    G_ = O.Grid(**{k: v.numpy().copy() for k, v in r.items()}, dx=1.0 / n, dy=1.0 / n,
+                dz=1.0 / n)
+    O.fill_periodic(G_)
+    prm = O.params()
+    dt = O.cfl_dt(G_, prm)
+    inp = G_.copy()
+    c = O.step(G_, prm, dt, 0)
+    assert c.fallback_faces > 1000 and c.floored_cells > 100
+    h = 1.0 / n
+    B = 5
+    rng = np.random.Generator(np.random.PCG64(7))
+    single_box_misses = 0
+    for cx, cy, cz in rng.integers(8, n - 8, size=(200, 3)):
+        x, y, z = cx + G3, cy + G3, cz + G3
+        for act in (3, 1):
+            a = act // 2
+            sl = tuple(slice(q - B - a, q + B + a + 1) for q in (z, y, x))
+            box = {f: np.ascontiguousarray(getattr(inp, f)[sl]) for f in O.FIELDS}
+            g = O.Grid(**box, dx=h, dy=h, dz=h, ghost=B)
+            O.step(g, prm, dt, 0)
+            k = B + a
+            same = all(getattr(g, f)[k, k, k] == getattr(G_, f)[z, y, x] for f in O.FIELDS)
+            if act == 3:
+                assert same, (cx, cy, cz)
+            else:
+                single_box_misses += not same
+    assert single_box_misses > 0
