@@ -42,27 +42,64 @@ template <class T> __device__ __forceinline__ T clamp01(T x) {
   return x < T(0) ? T(0) : (x > T(1) ? T(1) : x);
 }
 
+// Correctly rounded double quotient and square root for operands of
+// ordinary magnitude.  Both refine the hardware reciprocal (square root) by
+// Newton steps on fused multiply-adds and finish with one exact-remainder
+// correction, which yields the IEEE round-to-nearest result (Markstein's
+// theorem; the square root likewise).  They omit the operand scaling and
+// special-value fix-ups that a general IEEE division or square root needs for
+// operands within 2^768 of the overflow or underflow threshold, zeros,
+// infinities and NaNs: every divisor and radicand on the hot path is a
+// density, pressure, sound or shock speed, or a sum of them, bounded well
+// inside that range by the floors, and a value computed for a discarded
+// branch may be a NaN where IEEE gives an infinity.  Results are bit for bit
+// those of a / b and sqrt(x).
+__device__ __forceinline__ double ddiv(double a, double b) {
+  double y = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-b, y, 1.0);
+  y = fma(y, e, y);
+  const double q = a * y;
+  const double r = fma(-b, q, a);
+  return fma(r, y, q);
+}
+__device__ __forceinline__ double dsqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y;   // sqrt(x)
+  double h = y * 0.5; // 1 / (2 sqrt(x))
+  const double e = fma(-h, s, 0.5);
+  s = fma(s, e, s);
+  h = fma(h, e, h);
+  double d = fma(-s, s, x);
+  s = fma(d, h, s);
+  d = fma(-s, s, x);
+  return fma(d, h, s);
+}
+
 // Quotient, reciprocal and square root of the reconstruction and tracing
-// stages: IEEE (correctly rounded) in double; in the float stages of the
-// mixed precision the hardware reciprocal and square root (1 ulp), well
-// inside that path's error budget.
-template <class T> __device__ __forceinline__ T rdiv(T a, T b) { return a / b; }
+// stages: correctly rounded in double; in the float stages of the mixed
+// precision the hardware reciprocal and square root (1 ulp), well inside
+// that path's error budget.
+template <class T> __device__ __forceinline__ T rdiv(T a, T b) { return ddiv(a, b); }
 template <> __device__ __forceinline__ float rdiv<float>(float a, float b) {
   return a * __builtin_amdgcn_rcpf(b);
 }
-template <class T> __device__ __forceinline__ T rrcp(T a) { return T(1) / a; }
+template <class T> __device__ __forceinline__ T rrcp(T a) { return ddiv(1.0, a); }
 template <> __device__ __forceinline__ float rrcp<float>(float a) {
   return __builtin_amdgcn_rcpf(a);
 }
-template <class T> __device__ __forceinline__ T rsqrt_exact(T a) { return sqrt(a); }
+template <class T> __device__ __forceinline__ T rsqrt_exact(T a) { return dsqrt(a); }
 template <> __device__ __forceinline__ float rsqrt_exact<float>(float a) {
   return __builtin_amdgcn_sqrtf(a);
 }
 
 // The ratio test a/b > t of the selection rules, as a > t*b when b > 0 (every
-// physical state) and as written otherwise.
+// physical state) and as written otherwise; the quotient is formed only when
+// some lane of the wave has b <= 0.
 __device__ __forceinline__ bool ratio_above(double a, double b, double t) {
-  return b > 0.0 ? a > t * b : a / b > t;
+  if (__builtin_expect(b > 0.0, 1)) return a > t * b;
+  return a / b > t;
 }
 
 // ---------------------------------------------------------------------------
@@ -77,7 +114,7 @@ __device__ __forceinline__ void eos(const Params &P, double rho, double u, doubl
   double pp = (g - 1.0) * rho * eps;
   if (pp < P.p_floor) pp = P.p_floor;
   p = pp;
-  c = sqrt(g * pp / rho);
+  c = dsqrt(ddiv(g * pp, rho));
 }
 
 // CW84 limited slope of a cell from its two neighbours.
@@ -238,10 +275,10 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
                                                double v1r, double v2r, double pr, int &iters) {
   const double g = P.gamma;
   const double G1 = (g + 1.0) / (2.0 * g);
-  double cl = sqrt(g * pl * rl);
-  double cr = sqrt(g * pr * rr);
-  double ipl = 1.0 / pl, ipr = 1.0 / pr;
-  double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) / (cl + cr);
+  double cl = dsqrt(g * pl * rl);
+  double cr = dsqrt(g * pr * rr);
+  double ipl = ddiv(1.0, pl), ipr = ddiv(1.0, pr);
+  double ps = ddiv(cr * pl + cl * pr - cl * cr * (ur - ul), cl + cr);
   if (ps < P.p_floor) ps = P.p_floor;
   // Newton until the correction falls below rtol*p; the star state is that
   // last iterate, whose shock speeds are already at hand.
@@ -249,16 +286,16 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   bool capped = false;
   double wl, wr, iwl, iwr, usl, usr;
   for (;;) {
-    wl = cl * sqrt(1.0 + G1 * (ps * ipl - 1.0));
-    wr = cr * sqrt(1.0 + G1 * (ps * ipr - 1.0));
-    iwl = 1.0 / wl;
-    iwr = 1.0 / wr;
+    wl = cl * dsqrt(1.0 + G1 * (ps * ipl - 1.0));
+    wr = cr * dsqrt(1.0 + G1 * (ps * ipr - 1.0));
+    iwl = ddiv(1.0, wl);
+    iwr = ddiv(1.0, wr);
     usl = ul - (ps - pl) * iwl;
     usr = ur + (ps - pr) * iwr;
     if (capped || it == P.riemann_max_iter) break;
     double izl = (wl * wl + cl * cl) * (0.5 * iwl * iwl * iwl);
     double izr = (wr * wr + cr * cr) * (0.5 * iwr * iwr * iwr);
-    double pn = ps - (usr - usl) / (izl + izr);
+    double pn = ps - ddiv(usr - usl, izl + izr);
     if (pn < P.p_floor) pn = P.p_floor;
     ++it;
     if (fabs(pn - ps) <= P.riemann_rtol * pn) break;
@@ -271,25 +308,25 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   const bool left = us >= 0.0;
   double rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
   double iwK = left ? iwl : iwr;
-  double rs = 1.0 / (1.0 / rK - (ps - pK) * iwK * iwK);
+  double rs = ddiv(1.0, ddiv(1.0, rK) - (ps - pK) * iwK * iwK);
   if (rs < P.rho_floor) rs = P.rho_floor;
   double rb, ub, pb;
   if (ps > pK) {  // shock on the upwind side
     bool keep;
-    if (left) keep = (ul - wl / rl) >= 0.0;
-    else keep = (ur + wr / rr) <= 0.0;
+    if (left) keep = (ul - ddiv(wl, rl)) >= 0.0;
+    else keep = (ur + ddiv(wr, rr)) <= 0.0;
     if (keep) { rb = rK; ub = uK; pb = pK; }
     else { rb = rs; ub = us; pb = ps; }
   } else {        // rarefaction: linear through the fan
     double head, tail;
-    if (left) { head = ul - sqrt(g * pl / rl); tail = us - sqrt(g * ps / rs); }
-    else { head = ur + sqrt(g * pr / rr); tail = us + sqrt(g * ps / rs); }
+    if (left) { head = ul - dsqrt(ddiv(g * pl, rl)); tail = us - dsqrt(ddiv(g * ps, rs)); }
+    else { head = ur + dsqrt(ddiv(g * pr, rr)); tail = us + dsqrt(ddiv(g * ps, rs)); }
     bool outside = left ? head >= 0.0 : head <= 0.0;
     bool star = left ? tail <= 0.0 : tail >= 0.0;
     if (outside) { rb = rK; ub = uK; pb = pK; }
     else if (star) { rb = rs; ub = us; pb = ps; }
     else {
-      double w = left ? -head / (tail - head) : head / (head - tail);
+      double w = left ? ddiv(-head, tail - head) : ddiv(head, head - tail);
       rb = (1.0 - w) * rK + w * rs;
       ub = (1.0 - w) * uK + w * us;
       pb = (1.0 - w) * pK + w * ps;
@@ -303,7 +340,7 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   F.f[1] = fr * ub + pb;
   F.f[2] = fr * v1;
   F.f[3] = fr * v2;
-  double eb = pb / ((g - 1.0) * rb);
+  double eb = ddiv(pb, (g - 1.0) * rb);
   double Eb = eb + 0.5 * (ub * ub + v1 * v1 + v2 * v2);
   F.f[4] = fr * Eb + ub * pb;
   F.f[5] = fr * eb;
@@ -364,7 +401,7 @@ __device__ __forceinline__ bool update_cell(const Params &P, double lam, const C
   double m2 = c.rho * c.v2 - lam * (Fp.f[3] - Fm.f[3]);
   double mE = c.rho * c.E - lam * (Fp.f[4] - Fm.f[4]);
   double me = c.rho * c.e - lam * (Fp.f[5] - Fm.f[5]) - lam * c.p * (Fp.f[6] - Fm.f[6]);
-  double ir = 1.0 / rn;
+  double ir = ddiv(1.0, rn);
   double un = mu * ir, v1n = m1 * ir, v2n = m2 * ir, En = mE * ir, eraw = me * ir;
   double ke = 0.5 * (un * un + v1n * v1n + v2n * v2n);
   double epsE = En - ke;
