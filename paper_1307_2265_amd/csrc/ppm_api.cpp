@@ -253,13 +253,12 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
           const PatchDev &d = pl->host[i];
           const int64_t w1 = (tm & 1) ? d.n[t1] : d.n[t1] + 2 * d.ghost;
           const int64_t w2 = (tm & 2) ? d.n[t2] : d.n[t2] + 2 * d.ghost;
-          // work items: pencils (marching), or waves of pencils (lane-parallel:
-          // one long pencil, or 64/n short ones side by side)
+          // work items: pencils (marching), or waves streaming runs of pencils
+          // (lane-parallel)
           int64_t items = w1 * w2, per_block = pl->block;
-          if (kind == 1) {
-            const int64_t n = d.n[axis] + 2 * d.ghost;
-            const int64_t ppw = n <= 64 ? 64 / n : 1;
-            items = (items + ppw - 1) / ppw;
+          if (kind == 1) {  // a wave streams rows_per_wave(n) pencils
+            const int64_t rpw = ppm::rows_per_wave(int(d.n[axis] + 2 * d.ghost));
+            items = (items + rpw - 1) / rpw;
             per_block = pl->lanes_block / 64;
           }
           c[i] = int32_t(acc);

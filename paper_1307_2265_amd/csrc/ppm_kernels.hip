@@ -27,72 +27,6 @@ __device__ __forceinline__ int find_patch(const int32_t *start, int32_t npatch, 
   return lo;
 }
 
-// Select one of three values by a (wave-uniform) axis index without
-// indexing a private array, which would live in scratch memory.
-template <class V> __device__ __forceinline__ V pick3(int i, V a, V b, V c) {
-  return i == 0 ? a : (i == 1 ? b : c);
-}
-
-// Offset of the block of face (2*axis + hi) in a patch's flux register.
-__device__ __forceinline__ int64_t reg_face_offset(int64_t nx, int64_t ny, int64_t nz, int axis,
-                                                   int hi) {
-  const int64_t ax = ny * nz, ay = nx * nz, az = nx * ny;
-  const int64_t before = axis == 0 ? 0 : (axis == 1 ? 2 * ax : 2 * (ax + ay));
-  return 6 * (before + (hi ? pick3<int64_t>(axis, ax, ay, az) : 0));
-}
-
-// The pencil (i1, i2) of a sweep along `axis` of one patch.
-template <class S>
-__device__ __forceinline__ PencilRef<S> make_pencil(const PatchDev &pd, int axis, int i1, int i2) {
-  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
-  const int g = pd.ghost;
-  const int N0 = pd.n[0], N1 = pd.n[1], N2 = pd.n[2];
-  const int nf0 = N0 + 2 * g, nf1 = N1 + 2 * g;
-  const int Na = pick3(axis, N0, N1, N2), Nt1 = pick3(t1, N0, N1, N2), Nt2 = pick3(t2, N0, N1, N2);
-  const int64_t sx = 1, sy = nf0, sz = int64_t(nf0) * nf1;
-  PencilRef<S> pc;
-  pc.rho = static_cast<S *>(pd.rho);
-  pc.u = static_cast<S *>(pick3(axis, pd.vel[0], pd.vel[1], pd.vel[2]));
-  pc.v1 = static_cast<S *>(pick3(t1, pd.vel[0], pd.vel[1], pd.vel[2]));
-  pc.v2 = static_cast<S *>(pick3(t2, pd.vel[0], pd.vel[1], pd.vel[2]));
-  pc.E = pd.etot;
-  pc.e = pd.eint;
-  pc.base = i1 * pick3(t1, sx, sy, sz) + i2 * pick3(t2, sx, sy, sz);
-  pc.stride = pick3(axis, sx, sy, sz);
-  pc.n = Na + 2 * g;
-  pc.g = g;
-  pc.dx = pick3(axis, pd.dx[0], pd.dx[1], pd.dx[2]);
-  pc.reg_lo = pc.reg_hi = nullptr;
-  pc.reg_stride = 0;
-  pc.lab[0] = 0; pc.lab[1] = 1 + axis; pc.lab[2] = 1 + t1; pc.lab[3] = 1 + t2;
-  pc.lab[4] = 4; pc.lab[5] = 5;
-  if (pd.flux_reg && i1 >= g && i1 < g + Nt1 && i2 >= g && i2 < g + Nt2) {
-    const int64_t ro = int64_t(i2 - g) * Nt1 + (i1 - g);
-    pc.reg_lo = pd.flux_reg + reg_face_offset(N0, N1, N2, axis, 0) + ro;
-    pc.reg_hi = pd.flux_reg + reg_face_offset(N0, N1, N2, axis, 1) + ro;
-    pc.reg_stride = int64_t(Nt1) * Nt2;
-  }
-  return pc;
-}
-
-// Pencil `idx` of the sweep's pencil set in one patch: transverse axes
-// restricted to their active range where `mask` says so.  False if idx is
-// past the end.
-__device__ __forceinline__ bool pencil_index(const PatchDev &pd, int axis, int mask, int idx,
-                                             int &i1, int &i2) {
-  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
-  const int g = pd.ghost;
-  const int Nt1 = pick3(t1, pd.n[0], pd.n[1], pd.n[2]);
-  const int Nt2 = pick3(t2, pd.n[0], pd.n[1], pd.n[2]);
-  const bool r1 = (mask >> t1) & 1, r2 = (mask >> t2) & 1;
-  const int lo1 = r1 ? g : 0, w1 = r1 ? Nt1 : Nt1 + 2 * g;
-  const int lo2 = r2 ? g : 0, w2 = r2 ? Nt2 : Nt2 + 2 * g;
-  if (idx >= w1 * w2) return false;
-  i1 = lo1 + idx % w1;
-  i2 = lo2 + idx / w1;
-  return true;
-}
-
 // One thread marches one pencil.
 template <class Prec>
 __global__ void __launch_bounds__(kMaxBlock, 2)
@@ -114,42 +48,25 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
 }
 
-// Pencils of a wave in the lane-parallel kernel: one long pencil walked in
-// segments, or floor(64 / n) short ones side by side.
-__device__ __forceinline__ int pencils_per_wave(int n) { return n <= 64 ? 64 / n : 1; }
-
-// One wavefront takes one long pencil, or several short ones, with the cells
-// across its lanes.
+// One wavefront streams a run of rows_per_wave(n) consecutive pencils with
+// the cells across its lanes.
 template <class Prec>
-__global__ void __launch_bounds__(kMaxBlock)
+__global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
                    int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
                    Params P, unsigned long long *__restrict__ counters) {
-  using S = typename Prec::S;
   const int p = find_patch(chunk_start, npatch, blockIdx.x);
   const PatchDev pd = patches[p];
   const int waves = blockDim.x >> 6;
   const int item = (blockIdx.x - chunk_start[p]) * waves + (threadIdx.x >> 6);
   const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * pd.ghost;
-  const int ppw = pencils_per_wave(n);
+  const int K = rows_per_wave(n);
+  const int np = pencil_count(pd, axis, mask);
+  const int first = item * K;
+  if (first >= np) return;  // the whole wave leaves
   const double dt = dt_dev[pd.level];
   uint32_t nfb = 0, nfl = 0;
-  int i1, i2;
-  if (ppw == 1) {
-    if (!pencil_index(pd, axis, mask, item, i1, i2)) return;  // the whole wave leaves
-    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
-    sweep_pencil_lanes<Prec>(P, pc, dt, nfb, nfl);
-  } else {
-    const int lane = threadIdx.x & 63;
-    const int sub = lane / n;
-    bool active = sub < ppw && pencil_index(pd, axis, mask, item * ppw + sub, i1, i2);
-    if (!__any(active)) return;
-    if (!active) i1 = i2 = pd.ghost;  // a valid pencil; nothing of it is written
-    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
-    PencilRef<S> pcl = pc;
-    if (!active) pcl.reg_lo = pcl.reg_hi = nullptr;
-    sweep_pencils_packed<Prec>(P, pcl, dt, active, nfb, nfl);
-  }
+  sweep_rows_lanes<Prec>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl);
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
 }
@@ -198,16 +115,10 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
       const int np = w1 * w2;
       const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * g;
       int i1, i2;
-      if (((lanes_mask >> axis) & 1) && n <= 64) {
-        const int ppw = 64 / n;
-        const int lane = threadIdx.x & 63, sub = lane / n;
-        for (int it = wave; it * ppw < np; it += waves) {
-          bool active = sub < ppw && pencil_index(pd, axis, mask, it * ppw + sub, i1, i2);
-          if (!active) i1 = i2 = g;
-          PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
-          if (!active) pc.reg_lo = pc.reg_hi = nullptr;
-          sweep_pencils_packed<Prec>(P, pc, dt, active, nfb, nfl);
-        }
+      if ((lanes_mask >> axis) & 1) {
+        const int K = rows_per_wave(n);
+        for (int first = wave * K; first < np; first += waves * K)
+          sweep_rows_lanes<Prec>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl);
       } else {
         for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
           pencil_index(pd, axis, mask, idx, i1, i2);

@@ -1,28 +1,31 @@
 // ppm_lanes.hpp -- the 1-D PPM sweep with the cells of a pencil across the
 // lanes of a wave (device).
 //
-// Used for sweeps along x, the contiguous axis: a wavefront owns one pencil
-// and walks it in segments of 64 consecutive cells, so every load and store
-// is one fully coalesced 512-byte access per field, and every stage of the
-// update is evaluated for 64 cells at once, reading its neighbours' values
-// from the adjacent lanes with cross-lane shuffles.  The update of a cell
-// depends on the five cells either side of it (the flattening of its
-// neighbours' parabolas reaches three cells out, the HLL fallback of a
-// neighbouring face two more), so a segment writes its 54 middle cells and
-// the 5 lanes at each end only supply halo values.  Segments overlap by 10
-// cells; since the pencil is updated in place, the next segment takes those
-// cells' inputs from the registers of the previous one (a lane permute)
-// rather than from memory, where some were already overwritten.  Every stage
-// tests the global index of its cell against the same ranges the
-// pencil-marching sweep uses, so both give the same result bit for bit.
+// A wavefront streams a run of consecutive pencils (rows) of one patch,
+// concatenated, through segments of 64 consecutive cells, so every load and
+// store of a sweep along x is one coalesced access per field, and every stage
+// of the update is evaluated for 64 cells at once, reading its neighbours'
+// values from the adjacent lanes with cross-lane shuffles.  The update of a
+// cell depends on the five cells either side of it in its own pencil (the
+// flattening of its neighbours' parabolas reaches three cells out, the HLL
+// fallback of a neighbouring face two more), so a segment writes its 54
+// middle cells and the 5 lanes at each end only supply halo values.
+// Segments overlap by 10 cells; since the pencils are updated in place, the
+// next segment takes those cells' inputs from the registers of the previous
+// one (a lane permute) rather than from memory, where some were already
+// overwritten.  Where a segment spans the end of one pencil and the start of
+// the next, a lane reads its neighbour pencil's cell where the sweep would
+// read a cell outside its own pencil; every stage tests the position of its
+// cell within its pencil against the same ranges the pencil-marching sweep
+// uses, so no valid result uses such a value and both sweeps give the same
+// result bit for bit.  Streaming many short pencils back to back keeps 54 of
+// 64 lanes productive whatever the pencil length.
 #pragma once
 
 #include "ppm_sweep.hpp"
 
 namespace ppm {
 
-constexpr int kLaneHalo = 5;
-constexpr int kLaneOut = 64 - 2 * kLaneHalo;  // cells written per wave
 
 template <class V> __device__ __forceinline__ V from_left(V v) { return __shfl_up(v, 1, 64); }
 template <class V> __device__ __forceinline__ V from_right(V v) { return __shfl_down(v, 1, 64); }
@@ -46,13 +49,13 @@ struct CellLoad {
   double r, u, v1, v2, E, e;
 };
 
-// One segment: cells j0 .. j0+63 of the pencil (j0 may be negative or run
-// past the end; such lanes hold a benign placeholder that no valid result
-// uses).  `in` is this lane's input cell; writes cells [out_lo, out_hi).
+// One segment: lane holds cell j of pencil pc (j = -1 for a placeholder
+// lane beyond the stream, which no valid result uses).  `in` is this lane's
+// input cell; the lane writes its cell (and counts its events) if `mine`.
 template <class Prec>
 __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
-                              int j, int out_lo, int out_hi, const CellLoad &in,
-                              uint32_t &n_fallback, uint32_t &n_floor) {
+                              int j, bool mine, const CellLoad &in, uint32_t &n_fallback,
+                              uint32_t &n_floor) {
   using S = typename Prec::S;
   using T = typename Prec::T;
   const int n = pc.n, g = pc.g;
@@ -160,7 +163,9 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
   Flux Fm = flux_from_left(F);
   bool bad = false;
   if (cell_ok) bad = update_cell(P, lam, cin, Fm, F, out);
-  const bool mine = j >= out_lo && j < out_hi;
+  // the lane to the right holds cell j+1 of the same pencil whenever j+1 is
+  // a cell this lane's results are needed for
+  const bool mine_next = from_right(int(mine)) != 0;
 
   // ---- HLL fallback on faces next to a non-positive cell, then redo
   if (fallback) {
@@ -172,7 +177,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
         const double R5[5] = {double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p)};
         F = hll_flux(P, L5, R5);
         // face j+1/2 is counted by the wave that writes cell j (or cell a0 for the first face)
-        if (mine || (j == a0 - 1 && a0 >= out_lo && a0 < out_hi)) ++n_fallback;
+        if (mine || (j == a0 - 1 && mine_next)) ++n_fallback;
       }
       const bool hll_prev = from_left(int(hll)) != 0;
       Fm = flux_from_left(F);
@@ -185,7 +190,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
   }
 
   // ---- boundary flux registers and write-back
-  if (pc.reg_lo && j == a0 - 1 && a0 >= out_lo && a0 < out_hi) {
+  if (pc.reg_lo && j == a0 - 1 && mine_next) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) pc.reg_lo[pc.lab[k] * pc.reg_stride] = dt * F.f[k];
   }
@@ -203,18 +208,26 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
   }
 }
 
-// One wave walks one pencil segment by segment.
+// One wave streams pencils first .. first+nrows-1 of a sweep's pencil set,
+// concatenated, segment by segment.
 template <class Prec>
-__device__ void sweep_pencil_lanes(const Params &P, const PencilRef<typename Prec::S> &pc,
-                                   double dt, uint32_t &n_fallback, uint32_t &n_floor) {
+__device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, int mask,
+                                 int first, int nrows, double dt, uint32_t &n_fallback,
+                                 uint32_t &n_floor) {
+  using S = typename Prec::S;
   const int lane = threadIdx.x & 63;
-  const int n = pc.n, g = pc.g;
-  const int N = n - 2 * g;
-  const int nseg = (N + kLaneOut - 1) / kLaneOut;
+  const int n = (axis == 0 ? pd.n[0] : (axis == 1 ? pd.n[1] : pd.n[2])) + 2 * pd.ghost;
+  const int L = nrows * n;
+  const int nseg = (L + kLaneOut - 1) / kLaneOut;
   CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
   for (int s = 0; s < nseg; ++s) {
-    const int j0 = g - kLaneHalo + s * kLaneOut;
-    const int j = j0 + lane;
+    const int t = s * kLaneOut - kLaneHalo + lane;  // stream position of this lane
+    const bool in = t >= 0 && t < L;
+    const int row = in ? t / n : 0;
+    const int j = in ? t - row * n : -1;
+    int i1 = pd.ghost, i2 = pd.ghost;
+    pencil_index(pd, axis, mask, first + row, i1, i2);
+    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
     // the first 2*halo lanes overlap the previous segment's last lanes
     CellLoad prev;
     prev.r = __shfl(cur.r, lane + kLaneOut, 64);
@@ -225,7 +238,7 @@ __device__ void sweep_pencil_lanes(const Params &P, const PencilRef<typename Pre
     prev.e = __shfl(cur.e, lane + kLaneOut, 64);
     if (s > 0 && lane < 2 * kLaneHalo) {
       cur = prev;
-    } else if (j >= 0 && j < n) {
+    } else if (in) {
       const int64_t o = pc.base + int64_t(j) * pc.stride;
       cur.r = double(pc.rho[o]); cur.u = double(pc.u[o]);
       cur.v1 = double(pc.v1[o]); cur.v2 = double(pc.v2[o]);
@@ -233,32 +246,9 @@ __device__ void sweep_pencil_lanes(const Params &P, const PencilRef<typename Pre
     } else {
       cur = CellLoad{1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
     }
-    const int out_lo = g + s * kLaneOut;
-    const int out_hi = min(out_lo + kLaneOut, n - g);
-    sweep_segment<Prec>(P, pc, dt, j, out_lo, out_hi, cur, n_fallback, n_floor);
+    const bool mine = in && lane >= kLaneHalo && lane < kLaneHalo + kLaneOut;
+    sweep_segment<Prec>(P, pc, dt, j, mine, cur, n_fallback, n_floor);
   }
-}
-
-// Pencils of at most 64 cells: `per_wave` of them side by side across the
-// lanes (lane = i*n + j holds cell j of the wave's i-th pencil), one pass.
-// A lane next to a pencil boundary reads a neighbouring pencil's cell where
-// the sweep would read a cell outside its pencil; no stage that a valid
-// result uses does so, exactly as with the placeholders of the long form.
-template <class Prec>
-__device__ void sweep_pencils_packed(const Params &P, const PencilRef<typename Prec::S> &pc,
-                                     double dt, bool active, uint32_t &n_fallback,
-                                     uint32_t &n_floor) {
-  const int lane = threadIdx.x & 63;
-  const int n = pc.n, g = pc.g;
-  const int j = active ? lane % n : -1;
-  CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
-  if (active) {
-    const int64_t o = pc.base + int64_t(j) * pc.stride;
-    cur.r = double(pc.rho[o]); cur.u = double(pc.u[o]);
-    cur.v1 = double(pc.v1[o]); cur.v2 = double(pc.v2[o]);
-    cur.E = pc.E[o]; cur.e = pc.e[o];
-  }
-  sweep_segment<Prec>(P, pc, dt, j, g, n - g, cur, n_fallback, n_floor);
 }
 
 }  // namespace ppm

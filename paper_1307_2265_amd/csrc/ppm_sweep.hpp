@@ -63,6 +63,95 @@ template <class S> struct PencilRef {
 
 constexpr int kSlotDoubles = 10;  // traced L and R states of one face
 
+// Lane-parallel sweep: halo lanes at each end of a 64-lane segment, cells a
+// segment writes, and the pencils a wave streams in one run (about
+// kStreamCells cells).
+constexpr int kLaneHalo = 5;
+constexpr int kLaneOut = 64 - 2 * kLaneHalo;
+constexpr int kStreamCells = 32 * kLaneOut;
+__host__ __device__ __forceinline__ int rows_per_wave(int n) {
+  return n >= kStreamCells ? 1 : (kStreamCells + n - 1) / n;
+}
+
+// Select one of three values by a (wave-uniform) axis index without
+// indexing a private array, which would live in scratch memory.
+template <class V> __device__ __forceinline__ V pick3(int i, V a, V b, V c) {
+  return i == 0 ? a : (i == 1 ? b : c);
+}
+
+// Offset of the block of face (2*axis + hi) in a patch's flux register.
+__device__ __forceinline__ int64_t reg_face_offset(int64_t nx, int64_t ny, int64_t nz, int axis,
+                                                   int hi) {
+  const int64_t ax = ny * nz, ay = nx * nz, az = nx * ny;
+  const int64_t before = axis == 0 ? 0 : (axis == 1 ? 2 * ax : 2 * (ax + ay));
+  return 6 * (before + (hi ? pick3<int64_t>(axis, ax, ay, az) : 0));
+}
+
+// The pencil (i1, i2) of a sweep along `axis` of one patch.
+template <class S>
+__device__ __forceinline__ PencilRef<S> make_pencil(const PatchDev &pd, int axis, int i1, int i2) {
+  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+  const int g = pd.ghost;
+  const int N0 = pd.n[0], N1 = pd.n[1], N2 = pd.n[2];
+  const int nf0 = N0 + 2 * g, nf1 = N1 + 2 * g;
+  const int Na = pick3(axis, N0, N1, N2), Nt1 = pick3(t1, N0, N1, N2), Nt2 = pick3(t2, N0, N1, N2);
+  const int64_t sx = 1, sy = nf0, sz = int64_t(nf0) * nf1;
+  PencilRef<S> pc;
+  pc.rho = static_cast<S *>(pd.rho);
+  pc.u = static_cast<S *>(pick3(axis, pd.vel[0], pd.vel[1], pd.vel[2]));
+  pc.v1 = static_cast<S *>(pick3(t1, pd.vel[0], pd.vel[1], pd.vel[2]));
+  pc.v2 = static_cast<S *>(pick3(t2, pd.vel[0], pd.vel[1], pd.vel[2]));
+  pc.E = pd.etot;
+  pc.e = pd.eint;
+  pc.base = i1 * pick3(t1, sx, sy, sz) + i2 * pick3(t2, sx, sy, sz);
+  pc.stride = pick3(axis, sx, sy, sz);
+  pc.n = Na + 2 * g;
+  pc.g = g;
+  pc.dx = pick3(axis, pd.dx[0], pd.dx[1], pd.dx[2]);
+  pc.reg_lo = pc.reg_hi = nullptr;
+  pc.reg_stride = 0;
+  pc.lab[0] = 0; pc.lab[1] = 1 + axis; pc.lab[2] = 1 + t1; pc.lab[3] = 1 + t2;
+  pc.lab[4] = 4; pc.lab[5] = 5;
+  if (pd.flux_reg && i1 >= g && i1 < g + Nt1 && i2 >= g && i2 < g + Nt2) {
+    const int64_t ro = int64_t(i2 - g) * Nt1 + (i1 - g);
+    pc.reg_lo = pd.flux_reg + reg_face_offset(N0, N1, N2, axis, 0) + ro;
+    pc.reg_hi = pd.flux_reg + reg_face_offset(N0, N1, N2, axis, 1) + ro;
+    pc.reg_stride = int64_t(Nt1) * Nt2;
+  }
+  return pc;
+}
+
+// Number of pencils of a sweep along `axis` of one patch: transverse axes
+// restricted to their active range where `mask` says so.
+__device__ __forceinline__ int pencil_count(const PatchDev &pd, int axis, int mask) {
+  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+  const int g = pd.ghost;
+  const int Nt1 = pick3(t1, pd.n[0], pd.n[1], pd.n[2]);
+  const int Nt2 = pick3(t2, pd.n[0], pd.n[1], pd.n[2]);
+  const int w1 = ((mask >> t1) & 1) ? Nt1 : Nt1 + 2 * g;
+  const int w2 = ((mask >> t2) & 1) ? Nt2 : Nt2 + 2 * g;
+  return w1 * w2;
+}
+
+// Pencil `idx` of the sweep's pencil set in one patch: transverse axes
+// restricted to their active range where `mask` says so.  False if idx is
+// past the end.
+__device__ __forceinline__ bool pencil_index(const PatchDev &pd, int axis, int mask, int idx,
+                                             int &i1, int &i2) {
+  const int t1 = axis == 0 ? 1 : 0, t2 = axis == 2 ? 1 : 2;
+  const int g = pd.ghost;
+  const int Nt1 = pick3(t1, pd.n[0], pd.n[1], pd.n[2]);
+  const int Nt2 = pick3(t2, pd.n[0], pd.n[1], pd.n[2]);
+  const bool r1 = (mask >> t1) & 1, r2 = (mask >> t2) & 1;
+  const int lo1 = r1 ? g : 0, w1 = r1 ? Nt1 : Nt1 + 2 * g;
+  const int lo2 = r2 ? g : 0, w2 = r2 ? Nt2 : Nt2 + 2 * g;
+  if (idx >= w1 * w2) return false;
+  i1 = lo1 + idx % w1;
+  i2 = lo2 + idx / w1;
+  return true;
+}
+
+
 template <class Prec>
 __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                              double *lds_slots, int slot_stride, uint32_t &n_fallback,
