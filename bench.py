@@ -4,15 +4,16 @@ Headline workload: the strongly shocked 512^3 periodic grid (density
 lognormal sigma_ln = 2, Gaussian velocities of rms Mach 5, lognormal pressure
 sigma_ln = 1, gamma = 5/3, 3 ghost layers, CFL 0.4, seed 1002), advanced K
 steps in FP64 and in mixed precision side by side from the same stored input.
-One step = periodic ghost fill + device CFL reduction + the three sweeps
-(xyz on even steps, zyx on odd ones).  Inputs are synthetic and resident in
-HBM when the timed region starts; launch shapes come from the autotuner's
-table (data/tiles.json) when it exists.
+One step = periodic ghost fill + the three sweeps (xyz on even steps, zyx on
+odd ones), the last of which also yields the next step's CFL timestep; the
+first step's timestep is reduced before the timed region.  Inputs are
+synthetic and resident in HBM when the timed region starts; launch shapes
+come from the autotuner's table (data/tiles.json) when it exists.
 
 Also measured: the batched form -- 4096 uneven AMR patches (dims from
 {8,12,16,24,32}, levels 0-6 with their own dt, seeded ghosts, flux registers
-on) advanced by replaying one captured HIP graph per step -- and its rate
-relative to the single grid.
+on) advanced by replaying one captured HIP graph per step (the three sweeps
+and the next timestep) -- and its rate relative to the single grid.
 
 Prints ONE JSON line: FP64 cell-updates/s of the single grid as `value` (one
 cell-update = one active cell through the x, y and z sweeps of one step), the
@@ -161,7 +162,7 @@ def main():
         batch = {"workload": f"{args.npatch} patches, dims iid from {{8,12,16,24,32}}, levels "
                              "0-6 (dx = 2^-level, own dt per level), strongly shocked fields "
                              "with seeded ghosts, flux registers on, one HIP graph per step "
-                             "(CFL + step)"}
+                             "(three sweeps + next dt)"}
         bruns = {}
         for name, prec in (("fp64", ppm.PPM_FP64), ("mixed", ppm.PPM_MIXED)):
             if name == "mixed" and args.no_mixed:
@@ -169,6 +170,7 @@ def main():
             tiles = autotune.best_tiles(f"batch/{name}")
             r = H.Run.batch(specs, fields, prec, tiles)
             r.make_graphs()
+            r.ensure_dt()
             for s in range(Wm):
                 r.graphs[s % 2].ppm_graph_launch()
             torch.cuda.synchronize()
@@ -188,7 +190,9 @@ def main():
         torch.cuda.empty_cache()
 
     # ---- roofline of the dominant kernel: the pencil-marching sweep kernel of
-    # the FP64 single-grid run (y sweeps, and the z sweeps first or last).
+    # the FP64 single-grid run, in its plain form (the y sweeps, and the z
+    # sweeps that open a zyx step; the z sweeps that close an xyz step run the
+    # variant that also takes the next timestep).
     # Algorithmic work of one launch: every pencil reads its n+6 cells and
     # writes its n active cells (6 fields of 8 B), and performs the
     # oracle-counted FP64 operations (add, mul, div, sqrt) for each of its n
@@ -199,13 +203,13 @@ def main():
     kern = results["fp64"]["kern"]
     dom = "march" if "march" in kern else "lanes"
     if dom == "march" and "lanes" in kern:  # x sweeps go to the lane kernel
-        mean_pencils = (n * nf + (nf * nf + n * n) / 2.0) / 2.0
+        mean_pencils = (n * nf + nf * nf + n * nf) / 3.0
     else:
-        mean_pencils = (nf * nf + n * nf + n * n) / 3.0
+        mean_pencils = (nf * nf + n * nf) / 2.0
     bytes_launch = mean_pencils * (nf + n) * 48.0
     flops_launch = mean_pencils * n * ops["flops"]
     sw = kern[dom]
-    kname = "sweep_kernel<PrecF64>" if dom == "march" else "sweep_lanes_kernel<PrecF64>"
+    kname = "sweep_kernel<PrecF64, false>" if dom == "march" else "sweep_lanes_kernel<PrecF64, false>"
     tr = measured_traffic(kname)
     traffic = None if tr is None else tr["bytes"]
     hbm = dict(bound="hbm", achieved=bytes_launch / sw / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
@@ -245,7 +249,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single {n}^3 periodic grid, strongly shocked (rho lognormal "
                                "sigma 2, rms Mach 5, p lognormal sigma 1), gamma 5/3, ghost 3, "
-                               "CFL 0.4, fill+cfl+xyz/zyx sweeps per step",
+                               "CFL 0.4, fill + xyz/zyx sweeps per step, the last sweep also yielding "
+                               "the next CFL dt",
                    "cells": cells, "precision_of_value": "fp64", "tiles": fp["tiles"]},
         "roofline": roofline,
         "roofline_other": other,

@@ -167,10 +167,28 @@ ppm_status ppm_cfl_dt(ppm_plan *plan, double *dt_dev, void *hip_stream);
 ppm_status ppm_step(ppm_plan *plan, const double *dt_dev, int32_t sweep_order,
                     void *hip_stream);
 
+/* One step as ppm_step with the per-level dt in dt_dev, after which dt_dev
+ * holds the hydro CFL timestep of the new state -- the values ppm_cfl_dt
+ * would return if called next, bit for bit.  The signal speeds are taken by
+ * the step's last sweep from the values it stores, so no extra pass reads
+ * the fields.  A loop calls ppm_cfl_dt once, then ppm_step_cfl every step
+ * (ppm_fill_periodic before each, for periodic patches). */
+ppm_status ppm_step_cfl(ppm_plan *plan, double *dt_dev, int32_t sweep_order, void *hip_stream);
+
 /* One sweep along `axis` (0,1,2) of every patch; bit a of active_mask
  * restricts transverse axis a to its active range (else all indices). */
 ppm_status ppm_sweep(ppm_plan *plan, const double *dt_dev, int32_t axis, int32_t active_mask,
                      void *hip_stream);
+
+/* ppm_sweep that also folds the CFL signal speed of every cell it writes
+ * into the plan's per-level maxima (the last sweep of a step, whose cells
+ * are exactly the active ones); ppm_cfl_finalize then turns the maxima into
+ * dt_dev[l] = cfl / max (+inf for a level without patches) and clears them.
+ * ppm_cfl_dt is the same maxima over the current state followed by
+ * ppm_cfl_finalize. */
+ppm_status ppm_sweep_cfl(ppm_plan *plan, const double *dt_dev, int32_t axis,
+                         int32_t active_mask, void *hip_stream);
+ppm_status ppm_cfl_finalize(ppm_plan *plan, double *dt_dev, void *hip_stream);
 
 /* Read (synchronising `hip_stream`) and optionally reset the plan's event
  * counters: faces re-solved with HLL, cells floored after the fallback. */
@@ -179,12 +197,14 @@ ppm_status ppm_event_counts(ppm_plan *plan, int64_t *fallback_faces, int64_t *fl
 
 /* HIP graph of one step, for callers that launch the same step repeatedly
  * (and for capture-friendly batching): the parts selected by `parts`, in the
- * order fill -> CFL -> step, with the given dt array and sweep order, are
+ * order fill -> CFL -> step (or step with the next dt), with the given dt
+ * array and sweep order, are
  * captured once into an executable graph (on a private stream; nothing is
  * executed).  The graph records only kernel launches.  It refers to the
  * plan, its patches and dt_dev, which must outlive it. */
 typedef struct ppm_graph ppm_graph;
-enum { PPM_GRAPH_FILL = 1u, PPM_GRAPH_CFL = 2u, PPM_GRAPH_STEP = 4u };
+enum { PPM_GRAPH_FILL = 1u, PPM_GRAPH_CFL = 2u, PPM_GRAPH_STEP = 4u,
+       PPM_GRAPH_STEP_CFL = 8u /* ppm_step_cfl; excludes PPM_GRAPH_STEP */ };
 ppm_status ppm_graph_create(ppm_graph **out, ppm_plan *plan, double *dt_dev,
                             int32_t sweep_order, uint32_t parts, void *hip_stream);
 ppm_status ppm_graph_launch(ppm_graph *graph, void *hip_stream);

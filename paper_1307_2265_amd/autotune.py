@@ -26,21 +26,20 @@ TILES_JSON = os.path.join(HERE, "data", "tiles.json")
 CANDIDATES = {
     "single": [
         "lanes=1 block=256 lanes_block=256",
-        "lanes=1 block=128 lanes_block=256",
-        "lanes=1 block=64 lanes_block=256",
         "lanes=1 block=256 lanes_block=128",
         "lanes=1 block=256 lanes_block=64",
+        "lanes=1 block=128 lanes_block=256",
+        "lanes=1 block=128 lanes_block=64",
         "lanes=0 block=256",
-        "lanes=7 lanes_block=256",
     ],
     "batch": [
         "persistent=1 lanes=1 batch_block=256",
         "persistent=1 lanes=1 batch_block=128",
-        "persistent=1 lanes=1 batch_block=64",
-        "persistent=1 lanes=0 batch_block=256",
         "persistent=0 lanes=1 block=64 lanes_block=64",
+        "persistent=0 lanes=1 block=64 lanes_block=128",
+        "persistent=0 lanes=1 block=64 lanes_block=256",
         "persistent=0 lanes=1 block=128 lanes_block=128",
-        "persistent=0 lanes=1 block=256 lanes_block=256",
+        "persistent=0 lanes=1 block=128 lanes_block=256",
         "persistent=0 lanes=0 block=64",
     ],
 }

@@ -158,26 +158,30 @@ void free_plan(ppm_plan *p) {
   delete p;
 }
 
+// One sweep over every patch; smax (nullable): also take the max signal
+// speed per level of the cells written.
 template <class Prec>
-hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, hipStream_t s) {
+hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, unsigned long long *smax,
+                    hipStream_t s) {
   const int tm = tmask_of(axis, mask);
   if ((pl->lanes_mask >> axis) & 1) {
     const int slot = 12 + axis * 4 + tm;
     if (pl->nblocks[slot] == 0) return hipSuccess;
     return ppm::launch_sweep_lanes<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
                                          pl->npatch, pl->nblocks[slot], pl->lanes_block, axis,
-                                         mask, dt, pl->P, pl->d_counters, s);
+                                         mask, dt, pl->P, pl->d_counters, smax, s);
   }
   const int slot = axis * 4 + tm;
   if (pl->nblocks[slot] == 0) return hipSuccess;
   return ppm::launch_sweep<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
                                  pl->npatch, pl->nblocks[slot], pl->block, axis, mask, dt, pl->P,
-                                 pl->d_counters, s);
+                                 pl->d_counters, smax, s);
 }
 
-hipError_t sweep_any(ppm_plan *pl, const double *dt, int axis, int mask, hipStream_t s) {
-  return pl->prec == PPM_FP64 ? do_sweep<ppm::PrecF64>(pl, dt, axis, mask, s)
-                              : do_sweep<ppm::PrecMixed>(pl, dt, axis, mask, s);
+hipError_t sweep_any(ppm_plan *pl, const double *dt, int axis, int mask, unsigned long long *smax,
+                     hipStream_t s) {
+  return pl->prec == PPM_FP64 ? do_sweep<ppm::PrecF64>(pl, dt, axis, mask, smax, s)
+                              : do_sweep<ppm::PrecMixed>(pl, dt, axis, mask, smax, s);
 }
 
 }  // namespace
@@ -370,15 +374,60 @@ ppm_status ppm_cfl_dt(ppm_plan *plan, double *dt_dev, void *hip_stream) {
   return PPM_OK;
 }
 
-ppm_status ppm_sweep(ppm_plan *plan, const double *dt_dev, int32_t axis, int32_t active_mask,
-                     void *hip_stream) {
+ppm_status sweep_checked(ppm_plan *plan, const double *dt_dev, int32_t axis, int32_t active_mask,
+                         bool cfl, void *hip_stream) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
   if (axis < 0 || axis > 2) return fail(PPM_EINVAL, "axis must be 0, 1 or 2");
   if (active_mask < 0 || active_mask > 7) return fail(PPM_EINVAL, "active_mask must be in 0..7");
   hipError_t e = sweep_any(plan, dt_dev, axis, active_mask & ~(1 << axis),
-                           static_cast<hipStream_t>(hip_stream));
+                           cfl ? plan->d_smax : nullptr, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "sweep launch");
+  return PPM_OK;
+}
+
+ppm_status step_any(ppm_plan *plan, const double *dt_dev, int32_t sweep_order, bool cfl,
+                    hipStream_t s) {
+  unsigned long long *smax = cfl ? plan->d_smax : nullptr;
+  if (plan->persistent) {
+    hipError_t e = plan->prec == PPM_FP64
+        ? ppm::launch_batch<ppm::PrecF64>(plan->d_patches, plan->d_order, plan->npatch,
+                                          plan->batch_blocks, plan->batch_block, sweep_order,
+                                          plan->lanes_mask, dt_dev, plan->P, plan->d_counters,
+                                          plan->d_queue, smax, s)
+        : ppm::launch_batch<ppm::PrecMixed>(plan->d_patches, plan->d_order, plan->npatch,
+                                            plan->batch_blocks, plan->batch_block, sweep_order,
+                                            plan->lanes_mask, dt_dev, plan->P, plan->d_counters,
+                                            plan->d_queue, smax, s);
+    if (e != hipSuccess) return hip_fail(e, "persistent step launch");
+    return PPM_OK;
+  }
+  int mask = 0;
+  for (int k = 0; k < 3; ++k) {
+    const int axis = kOrders[sweep_order][k];
+    hipError_t e = sweep_any(plan, dt_dev, axis, mask, k == 2 ? smax : nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "sweep launch");
+    mask |= 1 << axis;
+  }
+  return PPM_OK;
+}
+
+ppm_status ppm_sweep(ppm_plan *plan, const double *dt_dev, int32_t axis, int32_t active_mask,
+                     void *hip_stream) {
+  return sweep_checked(plan, dt_dev, axis, active_mask, false, hip_stream);
+}
+
+ppm_status ppm_sweep_cfl(ppm_plan *plan, const double *dt_dev, int32_t axis,
+                         int32_t active_mask, void *hip_stream) {
+  return sweep_checked(plan, dt_dev, axis, active_mask, true, hip_stream);
+}
+
+ppm_status ppm_cfl_finalize(ppm_plan *plan, double *dt_dev, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
+  hipError_t e = ppm::launch_cfl_finalize(plan->nlevels, plan->P.cfl, plan->d_smax, dt_dev,
+                                          static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "cfl finalize launch");
   return PPM_OK;
 }
 
@@ -387,28 +436,17 @@ ppm_status ppm_step(ppm_plan *plan, const double *dt_dev, int32_t sweep_order,
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
   if (sweep_order < 0 || sweep_order > 5) return fail(PPM_EINVAL, "sweep_order must be in 0..5");
+  return step_any(plan, dt_dev, sweep_order, false, static_cast<hipStream_t>(hip_stream));
+}
+
+ppm_status ppm_step_cfl(ppm_plan *plan, double *dt_dev, int32_t sweep_order, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
+  if (sweep_order < 0 || sweep_order > 5) return fail(PPM_EINVAL, "sweep_order must be in 0..5");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (plan->persistent) {
-    hipError_t e = plan->prec == PPM_FP64
-        ? ppm::launch_batch<ppm::PrecF64>(plan->d_patches, plan->d_order, plan->npatch,
-                                          plan->batch_blocks, plan->batch_block, sweep_order,
-                                          plan->lanes_mask, dt_dev, plan->P, plan->d_counters,
-                                          plan->d_queue, s)
-        : ppm::launch_batch<ppm::PrecMixed>(plan->d_patches, plan->d_order, plan->npatch,
-                                            plan->batch_blocks, plan->batch_block, sweep_order,
-                                            plan->lanes_mask, dt_dev, plan->P, plan->d_counters,
-                                            plan->d_queue, s);
-    if (e != hipSuccess) return hip_fail(e, "persistent step launch");
-    return PPM_OK;
-  }
-  int mask = 0;
-  for (int k = 0; k < 3; ++k) {
-    const int axis = kOrders[sweep_order][k];
-    hipError_t e = sweep_any(plan, dt_dev, axis, mask, s);
-    if (e != hipSuccess) return hip_fail(e, "sweep launch");
-    mask |= 1 << axis;
-  }
-  return PPM_OK;
+  ppm_status st = step_any(plan, dt_dev, sweep_order, true, s);
+  if (st != PPM_OK) return st;
+  return ppm_cfl_finalize(plan, dt_dev, s);
 }
 
 ppm_status ppm_event_counts(ppm_plan *plan, int64_t *fallback_faces, int64_t *floored_cells,
@@ -442,8 +480,11 @@ ppm_status ppm_graph_create(ppm_graph **out, ppm_plan *plan, double *dt_dev,
   *out = nullptr;
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
-  if (parts == 0 || (parts & ~7u)) return fail(PPM_EINVAL, "parts must be a non-empty subset of FILL|CFL|STEP");
-  if ((parts & PPM_GRAPH_STEP) && (sweep_order < 0 || sweep_order > 5))
+  if (parts == 0 || (parts & ~15u))
+    return fail(PPM_EINVAL, "parts must be a non-empty subset of FILL|CFL|STEP|STEP_CFL");
+  if ((parts & PPM_GRAPH_STEP) && (parts & PPM_GRAPH_STEP_CFL))
+    return fail(PPM_EINVAL, "parts: STEP and STEP_CFL exclude each other");
+  if ((parts & (PPM_GRAPH_STEP | PPM_GRAPH_STEP_CFL)) && (sweep_order < 0 || sweep_order > 5))
     return fail(PPM_EINVAL, "sweep_order must be in 0..5");
   ppm_graph *g = new (std::nothrow) ppm_graph();
   if (!g) return fail(PPM_ENOMEM, "host allocation failed");
@@ -459,6 +500,8 @@ ppm_status ppm_graph_create(ppm_graph **out, ppm_plan *plan, double *dt_dev,
     if (parts & PPM_GRAPH_FILL) st = ppm_fill_periodic(plan, cs);
     if (st == PPM_OK && (parts & PPM_GRAPH_CFL)) st = ppm_cfl_dt(plan, dt_dev, cs);
     if (st == PPM_OK && (parts & PPM_GRAPH_STEP)) st = ppm_step(plan, dt_dev, sweep_order, cs);
+    if (st == PPM_OK && (parts & PPM_GRAPH_STEP_CFL))
+      st = ppm_step_cfl(plan, dt_dev, sweep_order, cs);
     hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
     if (st == PPM_OK && e2 != hipSuccess) st = hip_fail(e2, "end capture");
     if (st == PPM_OK) {

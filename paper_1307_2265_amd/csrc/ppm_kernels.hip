@@ -5,6 +5,13 @@
 //     patch by binary search in a prefix array of chunk counts, and each
 //     thread of the block marches one pencil (ppm_sweep.hpp).  A single big
 //     grid is the one-patch case of the same kernel.
+//   * sweep_lanes_kernel: the same sweep with the cells of a pencil across
+//     the lanes of a wave (ppm_lanes.hpp), for x sweeps.
+//   * batch_persistent_kernel: a whole step of every patch in one launch.
+//   * Each sweep kernel has a variant for the last sweep of a step that also
+//     takes the max signal speed of the cells it writes, so the next step's
+//     timestep needs no pass of its own (cfl_finalize_kernel turns the max
+//     into dt).
 //   * cfl_reduce_kernel / cfl_finalize_kernel: the hydro CFL timestep of
 //     every level (Sec. "Timestepping"): a wave-level max of the per-cell
 //     signal speed sum_d (c_s + |v_d|)/dx_d, a block max through LDS, and a
@@ -27,34 +34,56 @@ __device__ __forceinline__ int find_patch(const int32_t *start, int32_t npatch, 
   return lo;
 }
 
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Fold a wave's signal-speed maxima into the level's device-wide max: a
+// wave-level max, then atomicMax on the bit pattern of the non-negative
+// double (which orders like the value).
+__device__ __forceinline__ void cfl_commit(double smax, unsigned long long *slot) {
+  smax = wave_max(smax);
+  if ((threadIdx.x & 63) == 0 && smax > 0.0)
+    atomicMax(slot, (unsigned long long)__double_as_longlong(smax));
+}
+
 // One thread marches one pencil.
-template <class Prec>
+template <class Prec, bool kCFL>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
              int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
-             Params P, unsigned long long *__restrict__ counters) {
+             Params P, unsigned long long *__restrict__ counters,
+             unsigned long long *__restrict__ smax_bits) {
   using S = typename Prec::S;
   extern __shared__ double lds[];
   const int p = find_patch(chunk_start, npatch, blockIdx.x);
   const PatchDev pd = patches[p];
   const int idx = (blockIdx.x - chunk_start[p]) * blockDim.x + threadIdx.x;
-  int i1, i2;
-  if (!pencil_index(pd, axis, mask, idx, i1, i2)) return;
-  const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
-  const double dt = dt_dev[pd.level];
+  int i1 = pd.ghost, i2 = pd.ghost;
+  const bool has = pencil_index(pd, axis, mask, idx, i1, i2);
+  if (!kCFL && !has) return;
+  CflAcc cfl = cfl_acc(pd, axis);
   uint32_t nfb = 0, nfl = 0;
-  march_pencil<Prec>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl);
+  if (has) {
+    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+    const double dt = dt_dev[pd.level];
+    march_pencil<Prec, kCFL>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
+  }
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
+  if (kCFL) cfl_commit(cfl.smax, &smax_bits[pd.level]);  // every lane of the wave takes part
 }
 
 // One wavefront streams a run of rows_per_wave(n) consecutive pencils with
 // the cells across its lanes.
-template <class Prec>
+template <class Prec, bool kCFL>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
                    int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
-                   Params P, unsigned long long *__restrict__ counters) {
+                   Params P, unsigned long long *__restrict__ counters,
+                   unsigned long long *__restrict__ smax_bits) {
   const int p = find_patch(chunk_start, npatch, blockIdx.x);
   const PatchDev pd = patches[p];
   const int waves = blockDim.x >> 6;
@@ -66,9 +95,11 @@ sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restri
   if (first >= np) return;  // the whole wave leaves
   const double dt = dt_dev[pd.level];
   uint32_t nfb = 0, nfl = 0;
-  sweep_rows_lanes<Prec>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl);
+  CflAcc cfl = cfl_acc(pd, axis);
+  sweep_rows_lanes<Prec, kCFL>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl, cfl);
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
+  if (kCFL) cfl_commit(cfl.smax, &smax_bits[pd.level]);
 }
 
 // ---------------------------------------------------------------------------
@@ -76,20 +107,21 @@ sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restri
 // Workgroups take patches from a queue (an atomic counter over the patches
 // in descending order of cost) and run the three sweeps of each patch one
 // after the other, separated by workgroup barriers; the workgroup's threads
-// share the pencils of each sweep (x sweeps of pencils of at most 64 cells go
-// to the lane-parallel form, packed 64/n per wave, the rest march).  No
+// share the pencils of each sweep (sweeps along the lane-parallel axes are
+// streamed by the waves, the rest marched by the threads).  No
 // workgroup ever waits for another, and every workgroup leaves once the queue
 // is empty; the last one to leave rewinds the queue for the next launch.
 
 __constant__ int kStepOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1},
                                       {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
 
-template <class Prec>
+template <class Prec, bool kCFL>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ order,
                         int32_t npatch, int32_t sweep_order, int32_t lanes_mask,
                         const double *__restrict__ dt_dev, Params P,
-                        unsigned long long *__restrict__ counters, unsigned int *queue) {
+                        unsigned long long *__restrict__ counters, unsigned int *queue,
+                        unsigned long long *__restrict__ smax_bits) {
   using S = typename Prec::S;
   extern __shared__ double lds[];
   __shared__ int s_item;
@@ -115,17 +147,28 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
       const int np = w1 * w2;
       const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * g;
       int i1, i2;
+      CflAcc cfl = cfl_acc(pd, axis);
       if ((lanes_mask >> axis) & 1) {
         const int K = rows_per_wave(n);
-        for (int first = wave * K; first < np; first += waves * K)
-          sweep_rows_lanes<Prec>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl);
+        for (int first = wave * K; first < np; first += waves * K) {
+          if (kCFL && k == 2)
+            sweep_rows_lanes<Prec, true>(P, pd, axis, mask, first, min(K, np - first), dt, nfb,
+                                         nfl, cfl);
+          else
+            sweep_rows_lanes<Prec, false>(P, pd, axis, mask, first, min(K, np - first), dt, nfb,
+                                          nfl, cfl);
+        }
       } else {
         for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
           pencil_index(pd, axis, mask, idx, i1, i2);
           const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
-          march_pencil<Prec>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl);
+          if (kCFL && k == 2)
+            march_pencil<Prec, true>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
+          else
+            march_pencil<Prec, false>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
         }
       }
+      if (kCFL && k == 2) cfl_commit(cfl.smax, &smax_bits[pd.level]);
       __syncthreads();  // this sweep of the patch is complete before the next reads it
       mask |= 1 << axis;
     }
@@ -143,12 +186,6 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
 
 // ---------------------------------------------------------------------------
 // CFL reduction
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
 
 template <class Prec>
 __global__ void __launch_bounds__(256)
@@ -174,10 +211,8 @@ cfl_reduce_kernel(const PatchDev *__restrict__ patches, const int32_t *__restric
     const int64_t x = c % nx, yz = c / nx;
     const int64_t y = yz % ny, z = yz / ny;
     const int64_t o = ((z + g) * nfy + (y + g)) * nfx + (x + g);
-    const double r = double(rho[o]), u = double(vx[o]), v = double(vy[o]), w = double(vz[o]);
-    double pp, cs;
-    eos(P, r, u, v, w, pd.etot[o], pd.eint[o], pp, cs);
-    const double s = (cs + fabs(u)) / pd.dx[0] + (cs + fabs(v)) / pd.dx[1] + (cs + fabs(w)) / pd.dx[2];
+    const double s = cell_signal<S>(P, 0, pd.dx, rho[o], vx[o], vy[o], vz[o], pd.etot[o],
+                                    pd.eint[o]);
     smax = s > smax ? s : smax;
   }
   smax = wave_max(smax);
@@ -260,10 +295,14 @@ template <class Prec>
 hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
-                        hipStream_t s) {
+                        unsigned long long *smax_bits, hipStream_t s) {
   const size_t lds = (P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block * sizeof(double) : 0;
-  hipLaunchKernelGGL(sweep_kernel<Prec>, dim3(nblocks), dim3(block), lds, s, patches,
-                     chunk_start, npatch, axis, mask, dt_dev, P, counters);
+  if (smax_bits)
+    hipLaunchKernelGGL((sweep_kernel<Prec, true>), dim3(nblocks), dim3(block), lds, s, patches,
+                       chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
+  else
+    hipLaunchKernelGGL((sweep_kernel<Prec, false>), dim3(nblocks), dim3(block), lds, s, patches,
+                       chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
   return hipGetLastError();
 }
 
@@ -271,9 +310,14 @@ template <class Prec>
 hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                               int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                               const double *dt_dev, const Params &P,
-                              unsigned long long *counters, hipStream_t s) {
-  hipLaunchKernelGGL(sweep_lanes_kernel<Prec>, dim3(nblocks), dim3(block), 0, s, patches,
-                     chunk_start, npatch, axis, mask, dt_dev, P, counters);
+                              unsigned long long *counters, unsigned long long *smax_bits,
+                              hipStream_t s) {
+  if (smax_bits)
+    hipLaunchKernelGGL((sweep_lanes_kernel<Prec, true>), dim3(nblocks), dim3(block), 0, s,
+                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
+  else
+    hipLaunchKernelGGL((sweep_lanes_kernel<Prec, false>), dim3(nblocks), dim3(block), 0, s,
+                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
   return hipGetLastError();
 }
 
@@ -281,10 +325,23 @@ template <class Prec>
 hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t npatch,
                         int32_t nblocks, int32_t block, int32_t sweep_order, int32_t lanes_mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
-                        unsigned int *queue, hipStream_t s) {
+                        unsigned int *queue, unsigned long long *smax_bits, hipStream_t s) {
   const size_t lds = (P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block * sizeof(double) : 0;
-  hipLaunchKernelGGL(batch_persistent_kernel<Prec>, dim3(nblocks), dim3(block), lds, s, patches,
-                     order, npatch, sweep_order, lanes_mask, dt_dev, P, counters, queue);
+  if (smax_bits)
+    hipLaunchKernelGGL((batch_persistent_kernel<Prec, true>), dim3(nblocks), dim3(block), lds, s,
+                       patches, order, npatch, sweep_order, lanes_mask, dt_dev, P, counters,
+                       queue, smax_bits);
+  else
+    hipLaunchKernelGGL((batch_persistent_kernel<Prec, false>), dim3(nblocks), dim3(block), lds,
+                       s, patches, order, npatch, sweep_order, lanes_mask, dt_dev, P, counters,
+                       queue, smax_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_finalize(int32_t nlevels, double cfl, unsigned long long *smax_bits,
+                               double *dt_dev, hipStream_t s) {
+  hipLaunchKernelGGL(cfl_finalize_kernel, dim3((nlevels + 63) / 64), dim3(64), 0, s, nlevels,
+                     cfl, smax_bits, dt_dev);
   return hipGetLastError();
 }
 
@@ -296,9 +353,7 @@ hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32
                      chunk_start, npatch, cells_per_block, P, smax_bits);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cfl_finalize_kernel, dim3((nlevels + 63) / 64), dim3(64), 0, s, nlevels,
-                     P.cfl, smax_bits, dt_dev);
-  return hipGetLastError();
+  return launch_cfl_finalize(nlevels, P.cfl, smax_bits, dt_dev, s);
 }
 
 template <class Prec>
@@ -312,28 +367,23 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
   return hipGetLastError();
 }
 
-template hipError_t launch_sweep<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
-                                          int32_t, int32_t, int32_t, const double *,
-                                          const Params &, unsigned long long *, hipStream_t);
-template hipError_t launch_sweep<PrecMixed>(const PatchDev *, const int32_t *, int32_t, int32_t,
-                                            int32_t, int32_t, int32_t, const double *,
-                                            const Params &, unsigned long long *, hipStream_t);
-template hipError_t launch_sweep_lanes<PrecF64>(const PatchDev *, const int32_t *, int32_t,
-                                                int32_t, int32_t, int32_t, int32_t,
-                                                const double *, const Params &,
-                                                unsigned long long *, hipStream_t);
-template hipError_t launch_sweep_lanes<PrecMixed>(const PatchDev *, const int32_t *, int32_t,
-                                                  int32_t, int32_t, int32_t, int32_t,
-                                                  const double *, const Params &,
-                                                  unsigned long long *, hipStream_t);
-template hipError_t launch_batch<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
-                                          int32_t, int32_t, int32_t, const double *,
-                                          const Params &, unsigned long long *, unsigned int *,
-                                          hipStream_t);
-template hipError_t launch_batch<PrecMixed>(const PatchDev *, const int32_t *, int32_t, int32_t,
-                                            int32_t, int32_t, int32_t, const double *,
-                                            const Params &, unsigned long long *, unsigned int *,
-                                            hipStream_t);
+#define PPM_INSTANTIATE(Prec)                                                                  \
+  template hipError_t launch_sweep<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
+                                         int32_t, int32_t, int32_t, const double *,               \
+                                         const Params &, unsigned long long *,                    \
+                                         unsigned long long *, hipStream_t);                       \
+  template hipError_t launch_sweep_lanes<Prec>(const PatchDev *, const int32_t *, int32_t,        \
+                                               int32_t, int32_t, int32_t, int32_t,                \
+                                               const double *, const Params &,                    \
+                                               unsigned long long *, unsigned long long *,        \
+                                               hipStream_t);                                       \
+  template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
+                                         int32_t, int32_t, int32_t, const double *,               \
+                                         const Params &, unsigned long long *, unsigned int *,    \
+                                         unsigned long long *, hipStream_t);
+PPM_INSTANTIATE(PrecF64)
+PPM_INSTANTIATE(PrecMixed)
+#undef PPM_INSTANTIATE
 template hipError_t launch_cfl<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
                                         int32_t, int32_t, const Params &, unsigned long long *,
                                         double *, hipStream_t);

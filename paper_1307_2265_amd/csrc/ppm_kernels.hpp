@@ -13,21 +13,28 @@ template <class Prec>
 hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
-                        hipStream_t s);
+                        unsigned long long *smax_bits, hipStream_t s);
 
-// Lane-parallel variant (one wavefront per pencil); block = 64 * pencils per block.
+// Lane-parallel variant (a wavefront streams a run of pencils); block = 64 * waves.
+// smax_bits (nullable) of a sweep launch: the sweep is the last of its step and
+// also takes the max signal speed per level of the cells it writes.
 template <class Prec>
 hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                               int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                               const double *dt_dev, const Params &P,
-                              unsigned long long *counters, hipStream_t s);
+                              unsigned long long *counters, unsigned long long *smax_bits,
+                              hipStream_t s);
 
 // Persistent batch kernel: the whole step of every patch in one launch.
 template <class Prec>
 hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t npatch,
                         int32_t nblocks, int32_t block, int32_t sweep_order, int32_t lanes_mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
-                        unsigned int *queue, hipStream_t s);
+                        unsigned int *queue, unsigned long long *smax_bits, hipStream_t s);
+
+// dt_dev[l] = cfl / max signal speed of level l (+inf if none); clears the maxima.
+hipError_t launch_cfl_finalize(int32_t nlevels, double cfl, unsigned long long *smax_bits,
+                               double *dt_dev, hipStream_t s);
 
 template <class Prec>
 hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,

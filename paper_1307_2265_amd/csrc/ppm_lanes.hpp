@@ -52,10 +52,10 @@ struct CellLoad {
 // One segment: lane holds cell j of pencil pc (j = -1 for a placeholder
 // lane beyond the stream, which no valid result uses).  `in` is this lane's
 // input cell; the lane writes its cell (and counts its events) if `mine`.
-template <class Prec>
+template <class Prec, bool kCFL>
 __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                               int j, bool mine, const CellLoad &in, uint32_t &n_fallback,
-                              uint32_t &n_floor) {
+                              uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
   using T = typename Prec::T;
   const int n = pc.n, g = pc.g;
@@ -205,15 +205,16 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
     pc.v2[o] = S(out[3]);
     pc.E[o] = out[4];
     pc.e[o] = out[5];
+    if (kCFL) cfl_take<S>(P, cfl, S(out[0]), S(out[1]), S(out[2]), S(out[3]), out[4], out[5]);
   }
 }
 
 // One wave streams pencils first .. first+nrows-1 of a sweep's pencil set,
 // concatenated, segment by segment.
-template <class Prec>
+template <class Prec, bool kCFL>
 __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, int mask,
                                  int first, int nrows, double dt, uint32_t &n_fallback,
-                                 uint32_t &n_floor) {
+                                 uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
   const int lane = threadIdx.x & 63;
   const int n = (axis == 0 ? pd.n[0] : (axis == 1 ? pd.n[1] : pd.n[2])) + 2 * pd.ghost;
@@ -247,7 +248,7 @@ __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, 
       cur = CellLoad{1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
     }
     const bool mine = in && lane >= kLaneHalo && lane < kLaneHalo + kLaneOut;
-    sweep_segment<Prec>(P, pc, dt, j, mine, cur, n_fallback, n_floor);
+    sweep_segment<Prec, kCFL>(P, pc, dt, j, mine, cur, n_fallback, n_floor, cfl);
   }
 }
 

@@ -151,11 +151,50 @@ __device__ __forceinline__ bool pencil_index(const PatchDev &pd, int axis, int m
   return true;
 }
 
+// Hydro CFL signal speed of one cell (Sec. "Timestepping", the harmonic
+// multi-D form): sum over the axes of (c_s + |v_d|) / dx_d, with c_s from the
+// dual-energy pressure.  Takes the cell as stored (rho and the velocity in
+// storage precision) and its velocity in pencil order (u along `axis`, then
+// the two transverse components), and evaluates everything in lab axis order,
+// so the CFL reduction and the last sweep of a step that accumulates the next
+// step's timestep give the same value bit for bit.
+template <class S>
+__device__ __forceinline__ double cell_signal(const Params &P, int axis, const double (&dx)[3],
+                                              S r, S u, S v1, S v2, double E, double e) {
+  const double uu = double(u), a = double(v1), b = double(v2);
+  const double vx = axis == 0 ? uu : a;
+  const double vy = axis == 1 ? uu : (axis == 0 ? a : b);
+  const double vz = axis == 2 ? uu : b;
+  double p, c;
+  eos(P, double(r), vx, vy, vz, E, e, p, c);
+  return ddiv(c + fabs(vx), dx[0]) + ddiv(c + fabs(vy), dx[1]) + ddiv(c + fabs(vz), dx[2]);
+}
 
-template <class Prec>
+// Running maximum of the signal speed over the cells a thread writes, for a
+// sweep that also yields the next step's timestep.
+struct CflAcc {
+  int axis;
+  double dx[3];
+  double smax;
+};
+
+__device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis) {
+  return CflAcc{axis, {pd.dx[0], pd.dx[1], pd.dx[2]}, 0.0};
+}
+
+template <class S>
+__device__ __forceinline__ void cfl_take(const Params &P, CflAcc &acc, S r, S u, S v1, S v2,
+                                         double E, double e) {
+  const double s = cell_signal<S>(P, acc.axis, acc.dx, r, u, v1, v2, E, e);
+  acc.smax = s > acc.smax ? s : acc.smax;
+}
+
+// One thread marches one pencil.  kCFL: also take the signal speed of every
+// cell written (the sweep must then be the last of its step).
+template <class Prec, bool kCFL>
 __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                              double *lds_slots, int slot_stride, uint32_t &n_fallback,
-                             uint32_t &n_floor) {
+                             uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
   using T = typename Prec::T;
   // with T = double the window already holds the exact pressure
@@ -404,6 +443,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       pc.v2[o] = S(out[3]);
       pc.E[o] = out[4];
       pc.e[o] = out[5];
+      if (kCFL) cfl_take<S>(P, cfl, S(out[0]), S(out[1]), S(out[2]), S(out[3]), out[4], out[5]);
     }
 
     // ---- 10. carry the face and cell state one step

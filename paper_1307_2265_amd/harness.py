@@ -2,8 +2,11 @@
 
 Builds the seeded workloads of workloads.py on the GPU (a single periodic
 grid, or a batch of uneven patches stored as views into one flat buffer per
-field), runs steps through the C ABI (fill -> CFL -> step, directly or as
-captured HIP graphs) and times them with HIP events on the launch stream.
+field), runs steps through the C ABI and times them with HIP events on the
+launch stream.  A step is fill (periodic grids) -> the three sweeps, the last
+of which also yields the next step's CFL timestep (ppm_step_cfl, directly or
+as a captured HIP graph); the first step's timestep comes from a plain CFL
+reduction (ppm_cfl_dt), issued whenever the state was reset.
 """
 from __future__ import annotations
 
@@ -60,6 +63,7 @@ class Run:
         self.plan = ppm.Plan(self.patches, nlevels, prec, ppm.params(), tile_config=tiles)
         self.dt = torch.zeros(nlevels, dtype=torch.float64, device="cuda")
         self.graphs = None
+        self.dt_valid = False
 
     # -- construction helpers -------------------------------------------------
     @classmethod
@@ -85,32 +89,46 @@ class Run:
     def reset(self):
         for k, v in self.flat.items():
             v.copy_(self.init[k])
+        self.dt_valid = False
+
+    def ensure_dt(self):
+        """The current state's CFL timestep in self.dt (a reduction pass),
+        unless the last step already left it there."""
+        if not self.dt_valid:
+            if self.periodic:
+                self.plan.ppm_fill_periodic()
+            self.plan.ppm_cfl_dt(self.dt)
+            self.dt_valid = True
 
     def step(self, s: int):
+        self.ensure_dt()
         if self.periodic:
             self.plan.ppm_fill_periodic()
-        self.plan.ppm_cfl_dt(self.dt)
-        self.plan.ppm_step(self.dt, s % 2)
+        self.plan.ppm_step_cfl(self.dt, s % 2)
 
     def make_graphs(self):
-        parts = ppm.PPM_GRAPH_CFL | ppm.PPM_GRAPH_STEP
+        parts = ppm.PPM_GRAPH_STEP_CFL
         if self.periodic:
             parts |= ppm.PPM_GRAPH_FILL
         self.graphs = [ppm.Graph(self.plan, self.dt, o, parts) for o in (0, 1)]
 
     def timed(self, steps: int, graphs: bool = False, per_sweep: bool = False):
-        """Time `steps` steps from the current state.
+        """Time `steps` steps from the current state (its timestep, if not
+        known, is reduced before the timed region).
 
-        graphs: replay the captured step graphs.  per_sweep: issue the three
-        sweeps as ppm_sweep calls bracketed by HIP events (the same kernels
-        and extents ppm_step launches when it is not persistent) and return
-        the mean duration per kernel kind.  Returns (seconds, {kind: s})."""
+        graphs: replay the captured step graphs.  per_sweep: issue the sweeps
+        as ppm_sweep, ppm_sweep, ppm_sweep_cfl + ppm_cfl_finalize bracketed by
+        HIP events (the same kernels and extents ppm_step_cfl launches when it
+        is not persistent) and return the mean duration per kernel kind
+        ("march", "lanes", and "+cfl" for the last sweep's variant).
+        Returns (seconds, {kind: s})."""
         torch = _torch()
         E = lambda: torch.cuda.Event(enable_timing=True)
         if graphs and self.graphs is None:
             self.make_graphs()
         lm = lanes_mask_of(self.tiles)
         ev = []
+        self.ensure_dt()
         torch.cuda.synchronize()
         t0, t1 = E(), E()
         t0.record()
@@ -123,15 +141,19 @@ class Run:
                 continue
             if self.periodic:
                 self.plan.ppm_fill_periodic()
-            self.plan.ppm_cfl_dt(self.dt)
             mask = 0
-            for axis in ORDERS[s % 2]:
+            for k, axis in enumerate(ORDERS[s % 2]):
                 a, b = E(), E()
                 a.record()
-                self.plan.ppm_sweep(self.dt, axis, mask)
+                if k < 2:
+                    self.plan.ppm_sweep(self.dt, axis, mask)
+                else:
+                    self.plan.ppm_sweep_cfl(self.dt, axis, mask)
                 b.record()
-                ev.append(("lanes" if (lm >> axis) & 1 else "march", a, b))
+                kind = "lanes" if (lm >> axis) & 1 else "march"
+                ev.append((kind if k < 2 else kind + "+cfl", a, b))
                 mask |= 1 << axis
+            self.plan.ppm_cfl_finalize(self.dt)
         t1.record()
         torch.cuda.synchronize()
         per = {}

@@ -19,7 +19,7 @@ PPM_FP64, PPM_MIXED = 0, 1
 PPM_STEEPEN, PPM_FLATTEN, PPM_DUAL_ENERGY, PPM_FALLBACK_HLL = 1, 2, 4, 8
 PPM_ALL_FLAGS = 15
 ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
-PPM_GRAPH_FILL, PPM_GRAPH_CFL, PPM_GRAPH_STEP = 1, 2, 4
+PPM_GRAPH_FILL, PPM_GRAPH_CFL, PPM_GRAPH_STEP, PPM_GRAPH_STEP_CFL = 1, 2, 4, 8
 PPM_BC_PERIODIC, PPM_BC_SUPPLIED = 0, 1
 
 # Every function the header declares, with (restype, argtypes).
@@ -49,7 +49,10 @@ SIGNATURES = {
     "ppm_fill_periodic": (C.c_int, [_vp, _vp]),
     "ppm_cfl_dt": (C.c_int, [_vp, _vp, _vp]),
     "ppm_step": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
+    "ppm_step_cfl": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
     "ppm_sweep": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, _vp]),
+    "ppm_sweep_cfl": (C.c_int, [_vp, _vp, C.c_int32, C.c_int32, _vp]),
+    "ppm_cfl_finalize": (C.c_int, [_vp, _vp, _vp]),
     "ppm_event_counts": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_int32,
                                    _vp]),
     "ppm_graph_create": (C.c_int, [C.POINTER(_vp), _vp, _vp, C.c_int32, C.c_uint32, _vp]),
@@ -181,9 +184,22 @@ class Plan:
         _check(lib().ppm_step(self._h, dt_dev.data_ptr(), int(sweep_order),
                               _stream_handle(stream)), "ppm_step")
 
+    def ppm_step_cfl(self, dt_dev, sweep_order=0, stream=None):
+        sweep_order = ORDERS.get(sweep_order, sweep_order)
+        _check(lib().ppm_step_cfl(self._h, dt_dev.data_ptr(), int(sweep_order),
+                                  _stream_handle(stream)), "ppm_step_cfl")
+
     def ppm_sweep(self, dt_dev, axis: int, active_mask: int, stream=None):
         _check(lib().ppm_sweep(self._h, dt_dev.data_ptr(), axis, active_mask,
                                _stream_handle(stream)), "ppm_sweep")
+
+    def ppm_sweep_cfl(self, dt_dev, axis: int, active_mask: int, stream=None):
+        _check(lib().ppm_sweep_cfl(self._h, dt_dev.data_ptr(), axis, active_mask,
+                                   _stream_handle(stream)), "ppm_sweep_cfl")
+
+    def ppm_cfl_finalize(self, dt_dev, stream=None):
+        _check(lib().ppm_cfl_finalize(self._h, dt_dev.data_ptr(), _stream_handle(stream)),
+               "ppm_cfl_finalize")
 
     def ppm_event_counts(self, reset=False, stream=None):
         a, b = C.c_int64(0), C.c_int64(0)

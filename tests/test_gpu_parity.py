@@ -321,8 +321,9 @@ def test_config1_256_ten_steps_fp64(P, O):
 def test_config3_full_batch_in_bench_configuration(P, O, prec):
     # The full 4096-patch batch (seed 1003) exactly as the benchmark runs it:
     # flat field buffers, autotuned launch shapes, one captured graph per step
-    # (CFL + step, xyz then zyx), registers on.  Two steps; the oracle
-    # advances every patch with its level's dt from its own CFL reduction.
+    # (the three sweeps and the next step's dt, xyz then zyx; the first dt
+    # from a CFL reduction), registers on.  Two steps; the oracle advances
+    # every patch with its level's dt from its own CFL reduction.
     import torch
     from paper_1307_2265_amd import autotune
     from paper_1307_2265_amd import harness as H
@@ -331,11 +332,13 @@ def test_config3_full_batch_in_bench_configuration(P, O, prec):
     pr = P.PPM_FP64 if prec == "fp64" else P.PPM_MIXED
     run = H.Run.batch(specs, fields, pr, autotune.best_tiles(f"batch/{prec}"))
     run.make_graphs()
+    run.ensure_dt()
     dts_g = []
     for s in range(2):
-        run.graphs[s].ppm_graph_launch()
         torch.cuda.synchronize()
-        dts_g.append(run.dt.cpu().numpy().copy())
+        dts_g.append(run.dt.cpu().numpy().copy())  # the dt step s advances with
+        run.graphs[s].ppm_graph_launch()
+    torch.cuda.synchronize()
     counts_g = run.plan.ppm_event_counts()
     print("oracle", flush=True)
     prm = O.params()
@@ -451,42 +454,104 @@ def test_batch_of_uneven_patches_mixed(P, O):
         assert num[f] / den[f] <= 1e-5
 
 
-@pytest.mark.parametrize("batch", [False, True])
-def test_graph_replays_match_eager_steps(P, O, batch):
-    # Capture fill (single grid) + CFL + step into a HIP graph, replay it
-    # several times with eager work and synchronisations in between, and
-    # check every replay against the same steps run eagerly.
+@pytest.mark.parametrize("batch,fused", [(False, False), (True, False), (False, True),
+                                         (True, True)])
+def test_graph_replays_match_eager_steps(P, O, batch, fused):
+    # Capture fill (single grid) + CFL + step -- or fill + step with the next
+    # dt (fused) -- into a HIP graph, replay it several times with eager work
+    # and synchronisations in between, and check every replay against the
+    # same steps run eagerly.
     import torch
+    step = P.PPM_GRAPH_STEP_CFL if fused else P.PPM_GRAPH_CFL | P.PPM_GRAPH_STEP
     if batch:
         specs = W.patch_specs(24, 77)
         fields = [W.patch_fields(sp) for sp in specs]
         mk = lambda: [to_device(f, P.PPM_FP64, dx=(sp.dx,) * 3, level=sp.level)
                       for f, sp in zip(fields, specs)]
-        nlev, parts = 7, P.PPM_GRAPH_CFL | P.PPM_GRAPH_STEP
+        nlev, parts = 7, step
     else:
         d = W.random_grid(40, 24, 16, 5, W.SHOCKED)
         mk = lambda: [to_device(d, P.PPM_FP64)]
-        nlev, parts = 1, P.PPM_GRAPH_FILL | P.PPM_GRAPH_CFL | P.PPM_GRAPH_STEP
+        nlev, parts = 1, P.PPM_GRAPH_FILL | step
     A, B = mk(), mk()
     pa = P.Plan(A, nlev, P.PPM_FP64, P.params())
     pb = P.Plan(B, nlev, P.PPM_FP64, P.params())
     dta, dtb = _dt_tensor(nlev), _dt_tensor(nlev)
     graphs = [P.Graph(pb, dtb, order, parts) for order in (0, 1)]
+    if fused:  # the first step's dt comes from a plain reduction
+        if not batch:
+            pb.ppm_fill_periodic()
+        pb.ppm_cfl_dt(dtb)
     for s in range(4):
         if not batch:
             pa.ppm_fill_periodic()
         pa.ppm_cfl_dt(dta)
+        if fused:
+            torch.cuda.synchronize()
+            assert torch.equal(dta, dtb)
         pa.ppm_step(dta, s % 2)
         graphs[s % 2].ppm_graph_launch()
         torch.cuda.synchronize()
         junk = torch.ones(1000, device="cuda").sum()  # eager work between replays
         torch.cuda.synchronize()
-        assert torch.equal(dta, dtb)
+        if not fused:
+            assert torch.equal(dta, dtb)
         for pA, pB in zip(A, B):
             for f in FIELDS:
                 assert torch.equal(getattr(pA, f), getattr(pB, f)), (s, f)
     del junk
     for g in graphs:
         g.close()
+    pa.close()
+    pb.close()
+
+
+@pytest.mark.parametrize("case", ["single-fp64", "single-mixed", "single-lanes7", "batch-fp64",
+                                  "batch-mixed", "batch-persistent", "batch-march"])
+def test_step_with_next_dt_equals_step_then_cfl(P, case):
+    # ppm_step_cfl takes the next step's CFL timestep from the values its last
+    # sweep stores; it must leave the same fields as ppm_step and the same dt
+    # as a separate ppm_cfl_dt, bit for bit, step after step (both orders).
+    import torch
+    prec = P.PPM_MIXED if "mixed" in case else P.PPM_FP64
+    tiles = {"single-lanes7": "lanes=7", "batch-persistent": "persistent=1",
+             "batch-march": "persistent=0 lanes=0"}.get(case)
+    if case.startswith("single"):
+        d = W.random_grid(40, 28, 20, 11, W.SHOCKED)
+        mk = lambda: [to_device(stored_inputs(d, prec), prec)]
+        nlev, periodic = 1, True
+    else:
+        specs = W.patch_specs(40, 21)
+        fields = [stored_inputs(W.patch_fields(sp), prec) for sp in specs]
+        mk = lambda: [to_device(f, prec, dx=(sp.dx,) * 3, level=sp.level, with_reg=True)
+                      for f, sp in zip(fields, specs)]
+        nlev, periodic = 7, False
+    A, B = mk(), mk()
+    pa = P.Plan(A, nlev, prec, P.params(), tile_config=tiles)
+    pb = P.Plan(B, nlev, prec, P.params(), tile_config=tiles)
+    dta, dtb = _dt_tensor(nlev), _dt_tensor(nlev)
+    if periodic:
+        pb.ppm_fill_periodic()
+    pb.ppm_cfl_dt(dtb)
+    for s in range(4):
+        if periodic:
+            pa.ppm_fill_periodic()
+            pb.ppm_fill_periodic()
+        pa.ppm_cfl_dt(dta)
+        assert torch.equal(dta, dtb), (s, dta, dtb)
+        pa.ppm_step(dta, s % 2)
+        pb.ppm_step_cfl(dtb, s % 2)
+        torch.cuda.synchronize()
+        for pA, pB in zip(A, B):
+            for f in FIELDS:
+                assert torch.equal(getattr(pA, f), getattr(pB, f)), (s, f)
+            if pA.flux_reg is not None:
+                assert torch.equal(pA.flux_reg, pB.flux_reg), s
+    if periodic:
+        pa.ppm_fill_periodic()
+    pa.ppm_cfl_dt(dta)
+    torch.cuda.synchronize()
+    assert torch.equal(dta, dtb)
+    assert pa.ppm_event_counts() == pb.ppm_event_counts()
     pa.close()
     pb.close()
