@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=2,
                     help="steps the CPU oracle advances")
     ap.add_argument("--tiles", default=None, help="tile_config of the single-grid plans")
+    ap.add_argument("--batch-tiles", default=None, help="tile_config of the batch plans")
     return ap.parse_args()
 
 
@@ -167,7 +168,7 @@ def main():
         for name, prec in (("fp64", ppm.PPM_FP64), ("mixed", ppm.PPM_MIXED)):
             if name == "mixed" and args.no_mixed:
                 continue
-            tiles = autotune.best_tiles(f"batch/{name}")
+            tiles = args.batch_tiles or autotune.best_tiles(f"batch/{name}")
             r = H.Run.batch(specs, fields, prec, tiles)
             r.make_graphs()
             r.ensure_dt()

@@ -34,12 +34,6 @@ __device__ __forceinline__ int find_patch(const int32_t *start, int32_t npatch, 
   return lo;
 }
 
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-  return v;
-}
-
 // Fold a wave's signal-speed maxima into the level's device-wide max: a
 // wave-level max, then atomicMax on the bit pattern of the non-negative
 // double (which orders like the value).
@@ -64,7 +58,10 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
   int i1 = pd.ghost, i2 = pd.ghost;
   const bool has = pencil_index(pd, axis, mask, idx, i1, i2);
   if (!kCFL && !has) return;
-  CflAcc cfl = cfl_acc(pd, axis);
+  // LDS: the fallback's traced-state slots, then one CFL maximum per thread
+  const int nslot = (P.flags & kFallbackHLL) ? 2 * kSlotDoubles * int(blockDim.x) : 0;
+  CflAcc cfl = cfl_acc(pd, axis, lds + nslot + threadIdx.x);
+  if (kCFL) *cfl.lds = 0.0;
   uint32_t nfb = 0, nfl = 0;
   if (has) {
     const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
@@ -73,7 +70,7 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
   }
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
-  if (kCFL) cfl_commit(cfl.smax, &smax_bits[pd.level]);  // every lane of the wave takes part
+  if (kCFL) cfl_commit(*cfl.lds, &smax_bits[pd.level]);  // every lane of the wave takes part
 }
 
 // One wavefront streams a run of rows_per_wave(n) consecutive pencils with
@@ -95,7 +92,7 @@ sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restri
   if (first >= np) return;  // the whole wave leaves
   const double dt = dt_dev[pd.level];
   uint32_t nfb = 0, nfl = 0;
-  CflAcc cfl = cfl_acc(pd, axis);
+  CflAcc cfl = cfl_acc(pd, axis, nullptr);
   sweep_rows_lanes<Prec, kCFL>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl, cfl);
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
@@ -147,7 +144,9 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
       const int np = w1 * w2;
       const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * g;
       int i1, i2;
-      CflAcc cfl = cfl_acc(pd, axis);
+      const int nslot = (P.flags & kFallbackHLL) ? 2 * kSlotDoubles * int(blockDim.x) : 0;
+      CflAcc cfl = cfl_acc(pd, axis, lds + nslot + threadIdx.x);
+      if (kCFL && k == 2) *cfl.lds = 0.0;
       if ((lanes_mask >> axis) & 1) {
         const int K = rows_per_wave(n);
         for (int first = wave * K; first < np; first += waves * K) {
@@ -168,7 +167,8 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
             march_pencil<Prec, false>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
         }
       }
-      if (kCFL && k == 2) cfl_commit(cfl.smax, &smax_bits[pd.level]);
+      if (kCFL && k == 2)
+        cfl_commit(((lanes_mask >> axis) & 1) ? cfl.smax : *cfl.lds, &smax_bits[pd.level]);
       __syncthreads();  // this sweep of the patch is complete before the next reads it
       mask |= 1 << axis;
     }
@@ -296,7 +296,8 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned long long *smax_bits, hipStream_t s) {
-  const size_t lds = (P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block * sizeof(double) : 0;
+  const size_t lds = ((P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block : 0) *
+                        sizeof(double) + (smax_bits ? size_t(block) * sizeof(double) : 0);
   if (smax_bits)
     hipLaunchKernelGGL((sweep_kernel<Prec, true>), dim3(nblocks), dim3(block), lds, s, patches,
                        chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
@@ -326,7 +327,8 @@ hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t n
                         int32_t nblocks, int32_t block, int32_t sweep_order, int32_t lanes_mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned int *queue, unsigned long long *smax_bits, hipStream_t s) {
-  const size_t lds = (P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block * sizeof(double) : 0;
+  const size_t lds = ((P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block : 0) *
+                        sizeof(double) + (smax_bits ? size_t(block) * sizeof(double) : 0);
   if (smax_bits)
     hipLaunchKernelGGL((batch_persistent_kernel<Prec, true>), dim3(nblocks), dim3(block), lds, s,
                        patches, order, npatch, sweep_order, lanes_mask, dt_dev, P, counters,

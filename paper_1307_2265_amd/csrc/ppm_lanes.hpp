@@ -198,6 +198,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
 #pragma unroll
     for (int k = 0; k < 6; ++k) pc.reg_hi[pc.lab[k] * pc.reg_stride] = dt * F.f[k];
   }
+  double sig = 0.0;
   if (cell_ok && mine) {
     pc.rho[o] = S(out[0]);
     pc.u[o] = S(out[1]);
@@ -205,7 +206,13 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
     pc.v2[o] = S(out[3]);
     pc.E[o] = out[4];
     pc.e[o] = out[5];
-    if (kCFL) cfl_take<S>(P, cfl, S(out[0]), S(out[1]), S(out[2]), S(out[3]), out[4], out[5]);
+    if (kCFL)
+      sig = cell_signal<S>(P, cfl.axis, cfl.dx, S(out[0]), S(out[1]), S(out[2]), S(out[3]),
+                           out[4], out[5]);
+  }
+  if (kCFL) {
+    const double m = wave_uniform(wave_max(sig));
+    cfl.smax = m > cfl.smax ? m : cfl.smax;
   }
 }
 

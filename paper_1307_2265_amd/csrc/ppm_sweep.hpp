@@ -170,23 +170,34 @@ __device__ __forceinline__ double cell_signal(const Params &P, int axis, const d
   return ddiv(c + fabs(vx), dx[0]) + ddiv(c + fabs(vy), dx[1]) + ddiv(c + fabs(vz), dx[2]);
 }
 
-// Running maximum of the signal speed over the cells a thread writes, for a
-// sweep that also yields the next step's timestep.
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// A wave-uniform double, kept in scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b)));
+  const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(b >> 32)));
+  return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
+}
+
+// Maximum signal speed over the cells a sweep writes, for a sweep that also
+// yields the next step's timestep.  The marching sweep keeps each thread's
+// running maximum in LDS (`lds`, one double per thread), the lane-parallel
+// sweep a wave maximum in scalar registers (`smax`): neither costs the
+// sweep a vector register.
 struct CflAcc {
   int axis;
   double dx[3];
   double smax;
+  double *lds;
 };
 
-__device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis) {
-  return CflAcc{axis, {pd.dx[0], pd.dx[1], pd.dx[2]}, 0.0};
-}
-
-template <class S>
-__device__ __forceinline__ void cfl_take(const Params &P, CflAcc &acc, S r, S u, S v1, S v2,
-                                         double E, double e) {
-  const double s = cell_signal<S>(P, acc.axis, acc.dx, r, u, v1, v2, E, e);
-  acc.smax = s > acc.smax ? s : acc.smax;
+__device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis, double *lds) {
+  return CflAcc{axis, {pd.dx[0], pd.dx[1], pd.dx[2]}, 0.0, lds};
 }
 
 // One thread marches one pencil.  kCFL: also take the signal speed of every
@@ -443,7 +454,12 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       pc.v2[o] = S(out[3]);
       pc.E[o] = out[4];
       pc.e[o] = out[5];
-      if (kCFL) cfl_take<S>(P, cfl, S(out[0]), S(out[1]), S(out[2]), S(out[3]), out[4], out[5]);
+      if (kCFL) {
+        const double s = cell_signal<S>(P, cfl.axis, cfl.dx, S(out[0]), S(out[1]), S(out[2]),
+                                        S(out[3]), out[4], out[5]);
+        const double m = *cfl.lds;
+        *cfl.lds = s > m ? s : m;
+      }
     }
 
     // ---- 10. carry the face and cell state one step
