@@ -124,6 +124,10 @@ int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
  *   lanes_block=B  threads per block of the lane-parallel kernel (64..256;
  *                  default 256 for one patch, 64 for several).
  *   cfl_cells=C    active cells per block of the CFL reduction.
+ *   group=0|1      marching sweeps number the pencils of patches of equal
+ *                  pencil length consecutively, so a wavefront may span
+ *                  patches and none is left partly empty at a patch's end
+ *                  (default 1 for several patches, 0 for one).
  *   persistent=0|1 ppm_step as one persistent launch: workgroups take whole
  *                  patches from a queue (largest first) and run their three
  *                  sweeps back to back; with 0, one launch per sweep over all

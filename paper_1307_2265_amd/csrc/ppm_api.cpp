@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdint>
 #include <cstring>
 #include <limits>
 #include <sstream>
@@ -32,6 +33,9 @@ struct ppm_plan {
   int32_t persistent = 0;         // ppm_step as one persistent launch over all patches
   int32_t batch_block = 256;      // threads per workgroup of the persistent kernel
   int32_t batch_blocks = 0;       // workgroups of the persistent kernel
+  int32_t group = 0;              // marching sweeps number pencils across equal-length patches
+  bool group_set = false;         // group given in the tile config
+  int64_t *d_eoff = nullptr;      // element offset of each patch from patch 0 (grouped)
   int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
   unsigned int *d_queue = nullptr;  // persistent queue head and exit count
   std::vector<PatchDev> host;
@@ -39,6 +43,9 @@ struct ppm_plan {
   PatchDev *d_patches = nullptr;
   int32_t *d_chunks = nullptr;    // 12 marching, 12 lane-parallel prefix arrays, then CFL
   int32_t nblocks[24] = {};
+  int32_t *d_groups = nullptr;    // grouped marching maps of the 12 (axis, extent) slots
+  int64_t gofs[12] = {};          // offset of each slot's map in d_groups
+  int32_t ngroups[12] = {};
   int32_t cfl_blocks = 0;
   unsigned long long *d_counters = nullptr;  // fallback faces, floored cells
   unsigned long long *d_smax = nullptr;      // per-level max signal speed bits
@@ -128,6 +135,10 @@ ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
     } else if (k == "lanes_block") {
       if (v < 64 || v > ppm::kMaxBlock || v % 64) return fail(PPM_EINVAL, "tile_config: lanes_block must be 64..256, a multiple of 64");
       pl->lanes_block = int32_t(v);
+    } else if (k == "group") {
+      if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: group must be 0 or 1");
+      pl->group = int32_t(v);
+      pl->group_set = true;
     } else if (k == "persistent") {
       if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: persistent must be 0 or 1");
       pl->persistent = int32_t(v);
@@ -155,6 +166,8 @@ void free_plan(ppm_plan *p) {
   if (p->d_smax) (void)hipFree(p->d_smax);
   if (p->d_order) (void)hipFree(p->d_order);
   if (p->d_queue) (void)hipFree(p->d_queue);
+  if (p->d_groups) (void)hipFree(p->d_groups);
+  if (p->d_eoff) (void)hipFree(p->d_eoff);
   delete p;
 }
 
@@ -173,9 +186,10 @@ hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, unsigned
   }
   const int slot = axis * 4 + tm;
   if (pl->nblocks[slot] == 0) return hipSuccess;
+  const int32_t *groups = pl->group ? pl->d_groups + pl->gofs[slot] : nullptr;
   return ppm::launch_sweep<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
                                  pl->npatch, pl->nblocks[slot], pl->block, axis, mask, dt, pl->P,
-                                 pl->d_counters, smax, s);
+                                 pl->d_counters, smax, groups, pl->ngroups[slot], pl->d_eoff, s);
 }
 
 hipError_t sweep_any(ppm_plan *pl, const double *dt, int axis, int mask, unsigned long long *smax,
@@ -220,6 +234,7 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     pl->block = 64;
     pl->lanes_block = 64;
     pl->persistent = max_cells <= kPersistentMaxCells ? 1 : 0;
+    pl->group = 1;
   }
   if ((st = parse_tiles(pl, tile_config)) != PPM_OK) {
     delete pl;
@@ -275,6 +290,77 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
         c[npatch] = int32_t(acc);
         pl->nblocks[slot] = int32_t(acc);
       }
+  // grouping needs the patches to be views into six shared arrays at equal
+  // element offsets, so that one set of field pointers serves a whole wave
+  std::vector<int64_t> eoff(npatch, 0);
+  if (pl->group) {
+    const int64_t sS = prec == PPM_FP64 ? 8 : 4;
+    bool ok = true;
+    for (int i = 0; i < npatch && ok; ++i) {
+      const ppm_patch &q = patches[i], &r = patches[0];
+      auto d = [](const void *a, const void *b) {
+        return int64_t(reinterpret_cast<uintptr_t>(a)) - int64_t(reinterpret_cast<uintptr_t>(b));
+      };
+      const int64_t dr = d(q.rho, r.rho);
+      ok = dr % sS == 0 && d(q.vx, r.vx) == dr && d(q.vy, r.vy) == dr && d(q.vz, r.vz) == dr &&
+           d(q.etot, r.etot) == dr / sS * 8 && d(q.eint, r.eint) == dr / sS * 8;
+      eoff[i] = dr / sS;
+    }
+    if (!ok) {
+      if (pl->group_set) {
+        delete pl;
+        return fail(PPM_EINVAL, "tile_config: group=1 needs every patch's six fields to be views "
+                                "at one element offset into six shared arrays");
+      }
+      pl->group = 0;
+    }
+  }
+  // grouped marching maps: per (axis, extent) slot, the patches sorted by
+  // pencil length, runs of equal length, the first block of each run, the
+  // first sorted patch of each run, the pencil prefix over the sorted patches
+  // and the sorted patch indices
+  std::vector<int32_t> gmap;
+  if (pl->group) {
+    for (int axis = 0; axis < 3; ++axis)
+      for (int tm = 0; tm < 4; ++tm) {
+        const int slot = axis * 4 + tm;
+        const int t1 = t1_of(axis), t2 = t2_of(axis);
+        std::vector<int32_t> sorted(npatch);
+        for (int i = 0; i < npatch; ++i) sorted[i] = i;
+        auto len = [&](int i) { return pl->host[i].n[axis] + 2 * pl->host[i].ghost; };
+        std::stable_sort(sorted.begin(), sorted.end(),
+                         [&](int a, int b) { return len(a) < len(b); });
+        std::vector<int32_t> pp(size_t(npatch) + 1, 0), gfirst, gbs;
+        int64_t acc = 0, blocks = 0;
+        for (int j = 0; j < npatch; ++j) {
+          const PatchDev &d = pl->host[sorted[j]];
+          const int64_t w1 = (tm & 1) ? d.n[t1] : d.n[t1] + 2 * d.ghost;
+          const int64_t w2 = (tm & 2) ? d.n[t2] : d.n[t2] + 2 * d.ghost;
+          if (j == 0 || len(sorted[j]) != len(sorted[j - 1])) {
+            if (j > 0) blocks += (acc - pp[gfirst.back()] + pl->block - 1) / pl->block;
+            gfirst.push_back(j);
+            gbs.push_back(int32_t(blocks));
+          }
+          pp[j] = int32_t(acc);
+          acc += w1 * w2;
+          if (acc > std::numeric_limits<int32_t>::max() / 2) {
+            delete pl;
+            return fail(PPM_EINVAL, "too many pencils for one launch");
+          }
+        }
+        pp[npatch] = int32_t(acc);
+        blocks += (acc - pp[gfirst.back()] + pl->block - 1) / pl->block;
+        gfirst.push_back(npatch);
+        gbs.push_back(int32_t(blocks));
+        pl->ngroups[slot] = int32_t(gfirst.size()) - 1;
+        pl->nblocks[slot] = int32_t(blocks);
+        pl->gofs[slot] = int64_t(gmap.size());
+        gmap.insert(gmap.end(), gbs.begin(), gbs.end());
+        gmap.insert(gmap.end(), gfirst.begin(), gfirst.end());
+        gmap.insert(gmap.end(), pp.begin(), pp.end());
+        gmap.insert(gmap.end(), sorted.begin(), sorted.end());
+      }
+  }
   {
     int64_t acc = 0;
     int32_t *c = &chunks[size_t(24) * stride];
@@ -316,7 +402,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
       (e = hipMalloc(&pl->d_patches, sizeof(PatchDev) * npatch)) != hipSuccess ||
       (e = hipMalloc(&pl->d_chunks, sizeof(int32_t) * chunks.size())) != hipSuccess ||
       (e = hipMalloc(&pl->d_counters, 2 * sizeof(unsigned long long))) != hipSuccess ||
-      (e = hipMalloc(&pl->d_smax, nlevels * sizeof(unsigned long long))) != hipSuccess) {
+      (e = hipMalloc(&pl->d_smax, nlevels * sizeof(unsigned long long))) != hipSuccess ||
+      (!gmap.empty() &&
+       (e = hipMalloc(&pl->d_groups, sizeof(int32_t) * gmap.size())) != hipSuccess) ||
+      (pl->group && (e = hipMalloc(&pl->d_eoff, sizeof(int64_t) * npatch)) != hipSuccess)) {
     free_plan(pl);
     return fail(PPM_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
   }
@@ -333,6 +422,11 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipMemcpyAsync(pl->d_smax, zeros.data(), nlevels * sizeof(unsigned long long),
                           hipMemcpyHostToDevice, s)) != hipSuccess ||
+      (!gmap.empty() &&
+       (e = hipMemcpyAsync(pl->d_groups, gmap.data(), sizeof(int32_t) * gmap.size(),
+                           hipMemcpyHostToDevice, s)) != hipSuccess) ||
+      (pl->group && (e = hipMemcpyAsync(pl->d_eoff, eoff.data(), sizeof(int64_t) * npatch,
+                                        hipMemcpyHostToDevice, s)) != hipSuccess) ||
       (e = hipStreamSynchronize(s)) != hipSuccess) {
     free_plan(pl);
     return hip_fail(e, "plan upload");

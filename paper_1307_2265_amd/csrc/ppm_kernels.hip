@@ -43,34 +43,96 @@ __device__ __forceinline__ void cfl_commit(double smax, unsigned long long *slot
     atomicMax(slot, (unsigned long long)__double_as_longlong(smax));
 }
 
-// One thread marches one pencil.
-template <class Prec, bool kCFL>
+// Largest i in [lo, hi) with a[i] <= x (a non-decreasing, a[lo] <= x).
+__device__ __forceinline__ int last_at_most(const int32_t *a, int lo, int hi, int32_t x) {
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Fold each lane's signal-speed maximum into its own level's maximum, for
+// waves whose lanes may belong to patches of different levels.
+__device__ __forceinline__ void cfl_commit_levels(double smax, int level,
+                                                  unsigned long long *smax_bits) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(smax > 0.0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int L = __shfl(level, leader, 64);
+    const bool take = smax > 0.0 && level == L;
+    const double m = wave_max(take ? smax : 0.0);
+    if (lane == leader) atomicMax(&smax_bits[L], (unsigned long long)__double_as_longlong(m));
+    pending &= ~__ballot(take);
+  }
+}
+
+// One thread marches one pencil.  Ungrouped: each block takes `blockDim.x`
+// consecutive pencils of one patch (block -> patch by the prefix array
+// chunk_start).  Grouped (several patches): patches are sorted by pencil
+// length and the pencils of a run of equal-length patches are numbered
+// consecutively, so a block's threads may belong to several patches and no
+// wave is left partly empty at a patch's end; `groups` holds, for this
+// sweep, the first block and the first sorted patch of every run, the
+// pencil prefix over the sorted patches, and the sorted patch indices.  The
+// patches of a grouped plan are views into six shared arrays at equal
+// element offsets (`eoff`, relative to patch 0), so the field pointers stay
+// wave-uniform and only the offset, strides and cell width vary per lane.
+template <class Prec, bool kCFL, bool kGrouped>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
              int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
              Params P, unsigned long long *__restrict__ counters,
-             unsigned long long *__restrict__ smax_bits) {
+             unsigned long long *__restrict__ smax_bits, const int32_t *__restrict__ groups,
+             int32_t ngroups, const int64_t *__restrict__ eoff) {
   using S = typename Prec::S;
   extern __shared__ double lds[];
-  const int p = find_patch(chunk_start, npatch, blockIdx.x);
+  int p, idx;
+  bool has;
+  if (kGrouped) {
+    const int32_t *gbs = groups, *gfirst = groups + ngroups + 1;
+    const int32_t *pp = gfirst + ngroups + 1, *sorted = pp + npatch + 1;
+    const int grp = last_at_most(gbs, 0, ngroups, int32_t(blockIdx.x));
+    const int j0 = gfirst[grp], j1 = gfirst[grp + 1];
+    const int q = pp[j0] + (int(blockIdx.x) - gbs[grp]) * int(blockDim.x) + int(threadIdx.x);
+    has = q < pp[j1];
+    const int j = has ? last_at_most(pp, j0, j1, q) : j0;
+    p = sorted[j];
+    idx = has ? q - pp[j] : 0;
+  } else {
+    p = find_patch(chunk_start, npatch, blockIdx.x);
+    idx = (blockIdx.x - chunk_start[p]) * blockDim.x + threadIdx.x;
+    has = true;
+  }
   const PatchDev pd = patches[p];
-  const int idx = (blockIdx.x - chunk_start[p]) * blockDim.x + threadIdx.x;
   int i1 = pd.ghost, i2 = pd.ghost;
-  const bool has = pencil_index(pd, axis, mask, idx, i1, i2);
+  has = has && pencil_index(pd, axis, mask, idx, i1, i2);
   if (!kCFL && !has) return;
-  // LDS: the fallback's traced-state slots, then one CFL maximum per thread
-  const int nslot = (P.flags & kFallbackHLL) ? 2 * kSlotDoubles * int(blockDim.x) : 0;
-  CflAcc cfl = cfl_acc(pd, axis, lds + nslot + threadIdx.x);
+  CflAcc cfl = cfl_acc(pd, axis, lds + kLdsCfl * int(blockDim.x) + threadIdx.x);
   if (kCFL) *cfl.lds = 0.0;
   uint32_t nfb = 0, nfl = 0;
   if (has) {
-    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+    PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+    if (kGrouped) {
+      // equal within a run of patches: keep the loop bounds scalar; address
+      // through patch 0's (uniform) field pointers
+      pc.n = __builtin_amdgcn_readfirstlane(pc.n);
+      pc.g = __builtin_amdgcn_readfirstlane(pc.g);
+      const PencilRef<S> ref = make_pencil<S>(patches[0], axis, 0, 0);
+      pc.rho = ref.rho; pc.u = ref.u; pc.v1 = ref.v1; pc.v2 = ref.v2; pc.E = ref.E; pc.e = ref.e;
+      pc.base += eoff[p];
+    }
     const double dt = dt_dev[pd.level];
     march_pencil<Prec, kCFL>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
   }
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
-  if (kCFL) cfl_commit(*cfl.lds, &smax_bits[pd.level]);  // every lane of the wave takes part
+  if (kCFL) {  // every lane of the wave takes part
+    if (kGrouped) cfl_commit_levels(*cfl.lds, pd.level, smax_bits);
+    else cfl_commit(*cfl.lds, &smax_bits[pd.level]);
+  }
 }
 
 // One wavefront streams a run of rows_per_wave(n) consecutive pencils with
@@ -144,8 +206,7 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
       const int np = w1 * w2;
       const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * g;
       int i1, i2;
-      const int nslot = (P.flags & kFallbackHLL) ? 2 * kSlotDoubles * int(blockDim.x) : 0;
-      CflAcc cfl = cfl_acc(pd, axis, lds + nslot + threadIdx.x);
+      CflAcc cfl = cfl_acc(pd, axis, lds + kLdsCfl * int(blockDim.x) + threadIdx.x);
       if (kCFL && k == 2) *cfl.lds = 0.0;
       if ((lanes_mask >> axis) & 1) {
         const int K = rows_per_wave(n);
@@ -295,15 +356,21 @@ template <class Prec>
 hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
-                        unsigned long long *smax_bits, hipStream_t s) {
-  const size_t lds = ((P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block : 0) *
-                        sizeof(double) + (smax_bits ? size_t(block) * sizeof(double) : 0);
-  if (smax_bits)
-    hipLaunchKernelGGL((sweep_kernel<Prec, true>), dim3(nblocks), dim3(block), lds, s, patches,
-                       chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
-  else
-    hipLaunchKernelGGL((sweep_kernel<Prec, false>), dim3(nblocks), dim3(block), lds, s, patches,
-                       chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
+                        unsigned long long *smax_bits, const int32_t *groups, int32_t ngroups,
+                        const int64_t *eoff, hipStream_t s) {
+  const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
+#define PPM_LAUNCH_MARCH(CFL, GRP)                                                           \
+  hipLaunchKernelGGL((sweep_kernel<Prec, CFL, GRP>), dim3(nblocks), dim3(block), lds, s,      \
+                     patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits, \
+                     groups, ngroups, eoff)
+  if (groups) {
+    if (smax_bits) PPM_LAUNCH_MARCH(true, true);
+    else PPM_LAUNCH_MARCH(false, true);
+  } else {
+    if (smax_bits) PPM_LAUNCH_MARCH(true, false);
+    else PPM_LAUNCH_MARCH(false, false);
+  }
+#undef PPM_LAUNCH_MARCH
   return hipGetLastError();
 }
 
@@ -327,8 +394,7 @@ hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t n
                         int32_t nblocks, int32_t block, int32_t sweep_order, int32_t lanes_mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned int *queue, unsigned long long *smax_bits, hipStream_t s) {
-  const size_t lds = ((P.flags & kFallbackHLL) ? size_t(2) * kSlotDoubles * block : 0) *
-                        sizeof(double) + (smax_bits ? size_t(block) * sizeof(double) : 0);
+  const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
   if (smax_bits)
     hipLaunchKernelGGL((batch_persistent_kernel<Prec, true>), dim3(nblocks), dim3(block), lds, s,
                        patches, order, npatch, sweep_order, lanes_mask, dt_dev, P, counters,
@@ -373,7 +439,8 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
   template hipError_t launch_sweep<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *,                    \
-                                         unsigned long long *, hipStream_t);                       \
+                                         unsigned long long *, const int32_t *, int32_t,          \
+                                         const int64_t *, hipStream_t);                            \
   template hipError_t launch_sweep_lanes<Prec>(const PatchDev *, const int32_t *, int32_t,        \
                                                int32_t, int32_t, int32_t, int32_t,                \
                                                const double *, const Params &,                    \

@@ -61,7 +61,16 @@ template <class S> struct PencilRef {
   int lab[6];               // lab field index of each pencil-order flux slot
 };
 
-constexpr int kSlotDoubles = 10;  // traced L and R states of one face
+// LDS of a marching thread, in doubles (strided by the block size): two
+// slots of the traced L and R states of a face (for the fallback), the final
+// flux of the face behind the cell about to be written (read only by the
+// fallback) and that cell's provisional update, then the running CFL maximum
+// of the sweeps that take one.
+constexpr int kSlotDoubles = 10;
+constexpr int kLdsFluxA = 2 * kSlotDoubles;
+constexpr int kLdsProvA = kLdsFluxA + 7;
+constexpr int kLdsMarch = kLdsProvA + 6;
+constexpr int kLdsCfl = kLdsMarch;
 
 // Lane-parallel sweep: halo lanes at each end of a 64-lane segment, cells a
 // segment writes, and the pencils a wave streams in one run (about
@@ -234,9 +243,11 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   T fc[3][5];      // faces (k-4)+1/2 .. (k-2)+1/2: interface values
   State<T> lcarry; // left state of face r+1/2 from the previous iteration
   Flux ft_b;       // two-shock flux at face (r-2)+1/2
-  Flux ff_a;       // final flux at face (r-3)+1/2
+  // final flux at face (r-3)+1/2 and provisional update of cell A = r-2 live
+  // in LDS (written every step; the flux is read only by the fallback)
+  double *ff_a = lds_slots + kLdsFluxA * slot_stride;
+  double *prov_a = lds_slots + kLdsProvA * slot_stride;
   bool hll_a = false;
-  double prov_a[6];
   bool bad_a = false;
 #pragma unroll
   for (int i = 0; i < 5; ++i) {
@@ -262,9 +273,12 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   c_head = c_km1 = 0.0;
   lcarry = State<T>{T(0), T(0), T(0), T(0), T(0)};
 #pragma unroll
-  for (int j = 0; j < 7; ++j) ft_b.f[j] = ff_a.f[j] = 0.0;
+  for (int j = 0; j < 7; ++j) {
+    ft_b.f[j] = 0.0;
+    ff_a[j * slot_stride] = 0.0;
+  }
 #pragma unroll
-  for (int j = 0; j < 6; ++j) prov_a[j] = 0.0;
+  for (int j = 0; j < 6; ++j) prov_a[j * slot_stride] = 0.0;
 
   // prefetch of the head cell
   S nr = S(0), nu = S(0), nv1 = S(0), nv2 = S(0);
@@ -426,7 +440,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       const int64_t o = pc.base + int64_t(A) * pc.stride;
       double out[6];
 #pragma unroll
-      for (int j = 0; j < 6; ++j) out[j] = prov_a[j];
+      for (int j = 0; j < 6; ++j) out[j] = prov_a[j * slot_stride];
       bool bad = bad_a;
       if (hll_a || hll_b) {
         // redo the update with the final fluxes (input of A is still in memory)
@@ -438,7 +452,10 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
         eos(P, cin.rho, cin.u, cin.v1, cin.v2, cin.E, cin.e, pp, cc);
         cin.p = pp;
         cin.rhoEmax = m3[0];
-        bad = update_cell(P, lam, cin, ff_a, ff_b, out);
+        Flux fa;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) fa.f[j] = ff_a[j * slot_stride];
+        bad = update_cell(P, lam, cin, fa, ff_b, out);
       }
       if (bad) {
         CellIn cin;
@@ -463,11 +480,12 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     }
 
     // ---- 10. carry the face and cell state one step
-    ff_a = ff_b;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) ff_a[j * slot_stride] = ff_b.f[j];
     hll_a = hll_b;
     ft_b = ft_c;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) prov_a[j] = prov_b[j];
+    for (int j = 0; j < 6; ++j) prov_a[j * slot_stride] = prov_b[j];
     bad_a = bad_b;
     lcarry = lnew;
 

@@ -26,6 +26,34 @@ def to_device(d: dict, precision: int, ghost: int = 3, dx=None, level: int = 0,
     return ppm.Patch(**t, dx=dx[0], dy=dx[1], dz=dx[2], ghost=ghost, level=level, flux_reg=reg)
 
 
+def to_device_flat(fields: list, precision: int, dxs: list, levels: list,
+                   with_reg: bool = False, ghost: int = 3) -> list:
+    """Patches as views into one device array per field (patches back to back),
+    the layout a batched caller keeps its patches in."""
+    import torch
+    from paper_1307_2265_amd import ppm
+    low = torch.float32 if precision == ppm.PPM_MIXED else torch.float64
+    flat = {}
+    for f in FIELDS:
+        dt = torch.float64 if f in ("etot", "eint") else low
+        host = np.concatenate([np.ascontiguousarray(d[f]).ravel() for d in fields])
+        flat[f] = torch.from_numpy(host).to("cuda", dtype=dt)
+    out, off = [], 0
+    for d, dx, lev in zip(fields, dxs, levels):
+        shape = d["rho"].shape
+        size = int(np.prod(shape))
+        views = {f: flat[f][off:off + size].view(shape) for f in FIELDS}
+        nz, ny, nx = (s - 2 * ghost for s in shape)
+        reg = None
+        if with_reg:
+            reg = torch.zeros(ppm.ppm_flux_reg_size(nx, ny, nz), dtype=torch.float64,
+                              device="cuda")
+        out.append(ppm.Patch(**views, dx=dx[0], dy=dx[1], dz=dx[2], ghost=ghost, level=lev,
+                             flux_reg=reg))
+        off += size
+    return out
+
+
 def from_device(p) -> dict:
     return {f: getattr(p, f).double().cpu().numpy() for f in FIELDS}
 

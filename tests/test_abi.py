@@ -98,3 +98,16 @@ def test_persistent_launch_rejects_patches_too_large_for_one_workgroup():
                            None)
     assert st == ppm.PPM_EINVAL and "persistent=1" in L.ppm_last_error().decode()
     assert not h.value
+
+
+def test_grouping_needs_patches_in_shared_arrays():
+    # explicit group=1 with patches whose fields are separate allocations
+    L = ppm.lib()
+    arr = (ppm.ppm_patch * 2)(_patch(), _patch(rho=1024, vx=2048, vy=4096, vz=8192, etot=16384,
+                                               eint=32768))
+    prm = ppm.params()
+    h = C.c_void_p()
+    st = L.ppm_plan_create(C.byref(h), arr, 2, 1, ppm.PPM_FP64, C.byref(prm),
+                           b"group=1 persistent=0", None)
+    assert st == ppm.PPM_EINVAL and "group=1" in L.ppm_last_error().decode()
+    assert not h.value

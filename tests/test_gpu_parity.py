@@ -11,7 +11,7 @@ import pytest
 
 from paper_1307_2265_amd import workloads as W
 from tests.helpers import (FIELDS, compare_fields, from_device, oracle_grid, stored_inputs,
-                           to_device)
+                           to_device, to_device_flat)
 
 pytestmark = pytest.mark.gpu
 
@@ -388,14 +388,20 @@ def test_config3_full_batch_in_bench_configuration(P, O, prec):
             assert num[f] / den[f] <= 1e-5
 
 
-def _batch(P, O, npatch, seed, prec, tiles=None, steps=1):
-    """Run a batch of uneven patches on the GPU and patch by patch on the oracle."""
+def _batch(P, O, npatch, seed, prec, tiles=None, steps=1, flat=True):
+    """Run a batch of uneven patches on the GPU and patch by patch on the oracle.
+    flat: patches as views into shared field arrays (the marching sweeps may
+    then span patches), else one allocation per patch field."""
     import torch
     specs = W.patch_specs(npatch, seed)
     nlev = 7
     fields = [stored_inputs(W.patch_fields(sp), prec) for sp in specs]
-    patches = [to_device(f, prec, dx=(sp.dx,) * 3, level=sp.level, with_reg=True)
-               for f, sp in zip(fields, specs)]
+    if flat:
+        patches = to_device_flat(fields, prec, [(sp.dx,) * 3 for sp in specs],
+                                 [sp.level for sp in specs], with_reg=True)
+    else:
+        patches = [to_device(f, prec, dx=(sp.dx,) * 3, level=sp.level, with_reg=True)
+                   for f, sp in zip(fields, specs)]
     plan = P.Plan(patches, nlev, prec, P.params(), tile_config=tiles)
     dt = _dt_tensor(nlev)
     prm = O.params()
@@ -422,10 +428,15 @@ def _batch(P, O, npatch, seed, prec, tiles=None, steps=1):
     return specs, outs, grids, dts_g, dts_o, gcnt, tuple(ocnt)
 
 
-@pytest.mark.parametrize("tiles", [None, "lanes=0", "lanes=7", "persistent=0",
-                                   "persistent=0 lanes=0", "persistent=1 batch_block=64"])
-def test_batch_of_uneven_patches_fp64(P, O, tiles):
-    specs, outs, grids, dg, do, gcnt, ocnt = _batch(P, O, 48, 1003, P.PPM_FP64, tiles, steps=2)
+@pytest.mark.parametrize("tiles,flat", [(None, True), ("lanes=0", True), ("lanes=7", True),
+                                        ("persistent=0", True), ("persistent=0 lanes=0", True),
+                                        ("persistent=0 lanes=0 group=1 block=128", True),
+                                        ("persistent=0 lanes=0", False),
+                                        ("persistent=0 lanes=0 group=0", True),
+                                        ("persistent=1 batch_block=64", True)])
+def test_batch_of_uneven_patches_fp64(P, O, tiles, flat):
+    specs, outs, grids, dg, do, gcnt, ocnt = _batch(P, O, 48, 1003, P.PPM_FP64, tiles, steps=2,
+                                                    flat=flat)
     for a, b in zip(dg, do):
         assert np.array_equal(a, b), (a, b)
     differ = 0
@@ -436,12 +447,14 @@ def test_batch_of_uneven_patches_fp64(P, O, tiles):
         differ += d
         scale = np.maximum(np.abs(G.flux_reg), np.abs(G.flux_reg).mean())
         assert np.max(np.abs(greg - G.flux_reg) / scale) <= TOL64
-    print(f"{tiles}: 48 patches, active cells not bitwise equal: {differ}, counts {gcnt} {ocnt}")
+    print(f"{tiles} (flat {flat}): 48 patches, active cells not bitwise equal: {differ}, "
+          f"counts {gcnt} {ocnt}")
     assert gcnt == ocnt
 
 
-def test_batch_of_uneven_patches_mixed(P, O):
-    specs, outs, grids, dg, do, _, _ = _batch(P, O, 32, 2003, P.PPM_MIXED)
+@pytest.mark.parametrize("tiles", [None, "persistent=0 lanes=0"])
+def test_batch_of_uneven_patches_mixed(P, O, tiles):
+    specs, outs, grids, dg, do, _, _ = _batch(P, O, 32, 2003, P.PPM_MIXED, tiles)
     num = {f: 0.0 for f in FIELDS}
     den = {f: 0.0 for f in FIELDS}
     for (g, _), G in zip(outs, grids):
@@ -507,7 +520,8 @@ def test_graph_replays_match_eager_steps(P, O, batch, fused):
 
 
 @pytest.mark.parametrize("case", ["single-fp64", "single-mixed", "single-lanes7", "batch-fp64",
-                                  "batch-mixed", "batch-persistent", "batch-march"])
+                                  "batch-mixed", "batch-persistent", "batch-march",
+                                  "batch-march-ungrouped"])
 def test_step_with_next_dt_equals_step_then_cfl(P, case):
     # ppm_step_cfl takes the next step's CFL timestep from the values its last
     # sweep stores; it must leave the same fields as ppm_step and the same dt
@@ -515,7 +529,8 @@ def test_step_with_next_dt_equals_step_then_cfl(P, case):
     import torch
     prec = P.PPM_MIXED if "mixed" in case else P.PPM_FP64
     tiles = {"single-lanes7": "lanes=7", "batch-persistent": "persistent=1",
-             "batch-march": "persistent=0 lanes=0"}.get(case)
+             "batch-march": "persistent=0 lanes=0",
+             "batch-march-ungrouped": "persistent=0 lanes=0 group=0"}.get(case)
     if case.startswith("single"):
         d = W.random_grid(40, 28, 20, 11, W.SHOCKED)
         mk = lambda: [to_device(stored_inputs(d, prec), prec)]
@@ -523,8 +538,8 @@ def test_step_with_next_dt_equals_step_then_cfl(P, case):
     else:
         specs = W.patch_specs(40, 21)
         fields = [stored_inputs(W.patch_fields(sp), prec) for sp in specs]
-        mk = lambda: [to_device(f, prec, dx=(sp.dx,) * 3, level=sp.level, with_reg=True)
-                      for f, sp in zip(fields, specs)]
+        mk = lambda: to_device_flat(fields, prec, [(sp.dx,) * 3 for sp in specs],
+                                    [sp.level for sp in specs], with_reg=True)
         nlev, periodic = 7, False
     A, B = mk(), mk()
     pa = P.Plan(A, nlev, prec, P.params(), tile_config=tiles)
