@@ -37,9 +37,10 @@ CANDIDATES = {
         "persistent=1 lanes=1 batch_block=128",
         "persistent=0 lanes=1 block=64 lanes_block=64",
         "persistent=0 lanes=1 block=64 lanes_block=128",
-        "persistent=0 lanes=1 block=64 lanes_block=256",
+        "persistent=0 lanes=1 block=128 lanes_block=64",
         "persistent=0 lanes=1 block=128 lanes_block=128",
-        "persistent=0 lanes=1 block=128 lanes_block=256",
+        "persistent=0 lanes=1 block=256 lanes_block=64",
+        "persistent=0 lanes=1 block=64 lanes_block=64 group=0",
         "persistent=0 lanes=0 block=64",
     ],
 }
