@@ -210,7 +210,10 @@ def main():
     bytes_launch = mean_pencils * (nf + n) * 48.0
     flops_launch = mean_pencils * n * ops["flops"]
     sw = kern[dom]
-    kname = "sweep_kernel<PrecF64, false>" if dom == "march" else "sweep_lanes_kernel<PrecF64, false>"
+    # kernel names as the profiler reports them (template arguments: precision,
+    # takes the next dt, spans patches)
+    kname = ("sweep_kernel<PrecF64, false, false>" if dom == "march"
+             else "sweep_lanes_kernel<PrecF64, false>")
     tr = measured_traffic(kname)
     traffic = None if tr is None else tr["bytes"]
     hbm = dict(bound="hbm", achieved=bytes_launch / sw / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
