@@ -35,7 +35,6 @@ struct ppm_plan {
   int32_t batch_blocks = 0;       // workgroups of the persistent kernel
   int32_t group = 0;              // marching sweeps number pencils across equal-length patches
   bool group_set = false;         // group given in the tile config
-  int64_t *d_eoff = nullptr;      // element offset of each patch from patch 0 (grouped)
   int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
   unsigned int *d_queue = nullptr;  // persistent queue head and exit count
   std::vector<PatchDev> host;
@@ -167,7 +166,6 @@ void free_plan(ppm_plan *p) {
   if (p->d_order) (void)hipFree(p->d_order);
   if (p->d_queue) (void)hipFree(p->d_queue);
   if (p->d_groups) (void)hipFree(p->d_groups);
-  if (p->d_eoff) (void)hipFree(p->d_eoff);
   delete p;
 }
 
@@ -189,7 +187,7 @@ hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, unsigned
   const int32_t *groups = pl->group ? pl->d_groups + pl->gofs[slot] : nullptr;
   return ppm::launch_sweep<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
                                  pl->npatch, pl->nblocks[slot], pl->block, axis, mask, dt, pl->P,
-                                 pl->d_counters, smax, groups, pl->ngroups[slot], pl->d_eoff, s);
+                                 pl->d_counters, smax, groups, pl->ngroups[slot], s);
 }
 
 hipError_t sweep_any(ppm_plan *pl, const double *dt, int axis, int mask, unsigned long long *smax,
@@ -290,36 +288,25 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
         c[npatch] = int32_t(acc);
         pl->nblocks[slot] = int32_t(acc);
       }
-  // grouping needs the patches to be views into six shared arrays at equal
-  // element offsets, so that one set of field pointers serves a whole wave
-  std::vector<int64_t> eoff(npatch, 0);
-  if (pl->group) {
-    const int64_t sS = prec == PPM_FP64 ? 8 : 4;
-    bool ok = true;
-    for (int i = 0; i < npatch && ok; ++i) {
-      const ppm_patch &q = patches[i], &r = patches[0];
-      auto d = [](const void *a, const void *b) {
-        return int64_t(reinterpret_cast<uintptr_t>(a)) - int64_t(reinterpret_cast<uintptr_t>(b));
-      };
-      const int64_t dr = d(q.rho, r.rho);
-      ok = dr % sS == 0 && d(q.vx, r.vx) == dr && d(q.vy, r.vy) == dr && d(q.vz, r.vz) == dr &&
-           d(q.etot, r.etot) == dr / sS * 8 && d(q.eint, r.eint) == dr / sS * 8;
-      eoff[i] = dr / sS;
-    }
-    if (!ok) {
-      if (pl->group_set) {
-        delete pl;
-        return fail(PPM_EINVAL, "tile_config: group=1 needs every patch's six fields to be views "
-                                "at one element offset into six shared arrays");
-      }
-      pl->group = 0;
-    }
-  }
   // grouped marching maps: per (axis, extent) slot, the patches sorted by
   // pencil length, runs of equal length, the first block of each run, the
   // first sorted patch of each run, the pencil prefix over the sorted patches
   // and the sorted patch indices
+  // A run's patches must be views into six shared arrays at one element
+  // offset per patch (the run's first patch lends its field pointers to the
+  // whole wave).
+  auto aligned = [&](int i, int r) {
+    const ppm_patch &q = patches[i], &b = patches[r];
+    const int64_t sS = prec == PPM_FP64 ? 8 : 4;
+    auto d = [](const void *x, const void *y) {
+      return int64_t(reinterpret_cast<uintptr_t>(x)) - int64_t(reinterpret_cast<uintptr_t>(y));
+    };
+    const int64_t dr = d(q.rho, b.rho);
+    return dr % sS == 0 && d(q.vx, b.vx) == dr && d(q.vy, b.vy) == dr && d(q.vz, b.vz) == dr &&
+           d(q.etot, b.etot) == dr / sS * 8 && d(q.eint, b.eint) == dr / sS * 8;
+  };
   std::vector<int32_t> gmap;
+  bool runs_aligned = true;
   if (pl->group) {
     for (int axis = 0; axis < 3; ++axis)
       for (int tm = 0; tm < 4; ++tm) {
@@ -341,6 +328,7 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
             gfirst.push_back(j);
             gbs.push_back(int32_t(blocks));
           }
+          runs_aligned = runs_aligned && aligned(sorted[j], sorted[gfirst.back()]);
           pp[j] = int32_t(acc);
           acc += w1 * w2;
           if (acc > std::numeric_limits<int32_t>::max() / 2) {
@@ -360,6 +348,17 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
         gmap.insert(gmap.end(), pp.begin(), pp.end());
         gmap.insert(gmap.end(), sorted.begin(), sorted.end());
       }
+    if (!runs_aligned) {
+      if (pl->group_set) {
+        delete pl;
+        return fail(PPM_EINVAL, "tile_config: group=1 needs the patches of equal pencil length to "
+                                "be views at one element offset into six shared arrays");
+      }
+      pl->group = 0;  // per-patch launch maps (the marching block counts above)
+      gmap.clear();
+      for (int slot = 0; slot < 12; ++slot)
+        pl->nblocks[slot] = chunks[size_t(slot + 1) * stride - 1];
+    }
   }
   {
     int64_t acc = 0;
@@ -404,8 +403,7 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
       (e = hipMalloc(&pl->d_counters, 2 * sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMalloc(&pl->d_smax, nlevels * sizeof(unsigned long long))) != hipSuccess ||
       (!gmap.empty() &&
-       (e = hipMalloc(&pl->d_groups, sizeof(int32_t) * gmap.size())) != hipSuccess) ||
-      (pl->group && (e = hipMalloc(&pl->d_eoff, sizeof(int64_t) * npatch)) != hipSuccess)) {
+       (e = hipMalloc(&pl->d_groups, sizeof(int32_t) * gmap.size())) != hipSuccess)) {
     free_plan(pl);
     return fail(PPM_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
   }
@@ -425,8 +423,6 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
       (!gmap.empty() &&
        (e = hipMemcpyAsync(pl->d_groups, gmap.data(), sizeof(int32_t) * gmap.size(),
                            hipMemcpyHostToDevice, s)) != hipSuccess) ||
-      (pl->group && (e = hipMemcpyAsync(pl->d_eoff, eoff.data(), sizeof(int64_t) * npatch,
-                                        hipMemcpyHostToDevice, s)) != hipSuccess) ||
       (e = hipStreamSynchronize(s)) != hipSuccess) {
     free_plan(pl);
     return hip_fail(e, "plan upload");

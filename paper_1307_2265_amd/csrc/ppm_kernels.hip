@@ -77,19 +77,19 @@ __device__ __forceinline__ void cfl_commit_levels(double smax, int level,
 // wave is left partly empty at a patch's end; `groups` holds, for this
 // sweep, the first block and the first sorted patch of every run, the
 // pencil prefix over the sorted patches, and the sorted patch indices.  The
-// patches of a grouped plan are views into six shared arrays at equal
-// element offsets (`eoff`, relative to patch 0), so the field pointers stay
-// wave-uniform and only the offset, strides and cell width vary per lane.
+// patches of a run are views into six shared arrays at one element offset
+// per patch, so the field pointers of the run's first patch serve the whole
+// wave and only the offset, strides and cell width vary per lane.
 template <class Prec, bool kCFL, bool kGrouped>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
              int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
              Params P, unsigned long long *__restrict__ counters,
              unsigned long long *__restrict__ smax_bits, const int32_t *__restrict__ groups,
-             int32_t ngroups, const int64_t *__restrict__ eoff) {
+             int32_t ngroups) {
   using S = typename Prec::S;
   extern __shared__ double lds[];
-  int p, idx;
+  int p, idx, pref = 0;
   bool has;
   if (kGrouped) {
     const int32_t *gbs = groups, *gfirst = groups + ngroups + 1;
@@ -100,6 +100,7 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
     has = q < pp[j1];
     const int j = has ? last_at_most(pp, j0, j1, q) : j0;
     p = sorted[j];
+    pref = sorted[j0];
     idx = has ? q - pp[j] : 0;
   } else {
     p = find_patch(chunk_start, npatch, blockIdx.x);
@@ -117,12 +118,13 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
     PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
     if (kGrouped) {
       // equal within a run of patches: keep the loop bounds scalar; address
-      // through patch 0's (uniform) field pointers
+      // through the (wave-uniform) field pointers of the run's first patch
       pc.n = __builtin_amdgcn_readfirstlane(pc.n);
       pc.g = __builtin_amdgcn_readfirstlane(pc.g);
-      const PencilRef<S> ref = make_pencil<S>(patches[0], axis, 0, 0);
+      const PencilRef<S> ref = make_pencil<S>(patches[__builtin_amdgcn_readfirstlane(pref)],
+                                              axis, 0, 0);
+      pc.base += pc.rho - ref.rho;
       pc.rho = ref.rho; pc.u = ref.u; pc.v1 = ref.v1; pc.v2 = ref.v2; pc.E = ref.E; pc.e = ref.e;
-      pc.base += eoff[p];
     }
     const double dt = dt_dev[pd.level];
     march_pencil<Prec, kCFL>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
@@ -357,12 +359,12 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned long long *smax_bits, const int32_t *groups, int32_t ngroups,
-                        const int64_t *eoff, hipStream_t s) {
+                        hipStream_t s) {
   const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
 #define PPM_LAUNCH_MARCH(CFL, GRP)                                                           \
   hipLaunchKernelGGL((sweep_kernel<Prec, CFL, GRP>), dim3(nblocks), dim3(block), lds, s,      \
                      patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits, \
-                     groups, ngroups, eoff)
+                     groups, ngroups)
   if (groups) {
     if (smax_bits) PPM_LAUNCH_MARCH(true, true);
     else PPM_LAUNCH_MARCH(false, true);
@@ -440,7 +442,7 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *,                    \
                                          unsigned long long *, const int32_t *, int32_t,          \
-                                         const int64_t *, hipStream_t);                            \
+                                         hipStream_t);                                             \
   template hipError_t launch_sweep_lanes<Prec>(const PatchDev *, const int32_t *, int32_t,        \
                                                int32_t, int32_t, int32_t, int32_t,                \
                                                const double *, const Params &,                    \
