@@ -570,3 +570,39 @@ def test_step_with_next_dt_equals_step_then_cfl(P, case):
     assert pa.ppm_event_counts() == pb.ppm_event_counts()
     pa.close()
     pb.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_sweeps_with_cfl_finalize_equal_fused_step(P, prec):
+    # ppm_sweep, ppm_sweep, ppm_sweep_cfl + ppm_cfl_finalize (the form the
+    # benchmark times sweep by sweep) against ppm_step_cfl: same fields, same
+    # next dt, both sweep orders.
+    import torch
+    pr = P.PPM_FP64 if prec == "fp64" else P.PPM_MIXED
+    d = stored_inputs(W.random_grid(36, 30, 22, 17, W.SHOCKED), pr)
+    A, B = [to_device(d, pr)], [to_device(d, pr)]
+    pa = P.Plan(A, 1, pr, P.params())
+    pb = P.Plan(B, 1, pr, P.params())
+    dta, dtb = _dt_tensor(), _dt_tensor()
+    for p_, dt in ((pa, dta), (pb, dtb)):
+        p_.ppm_fill_periodic()
+        p_.ppm_cfl_dt(dt)
+    orders = ((0, 1, 2), (2, 1, 0))
+    for s in range(4):
+        pa.ppm_fill_periodic()
+        pb.ppm_fill_periodic()
+        mask = 0
+        for k, axis in enumerate(orders[s % 2]):
+            if k < 2:
+                pa.ppm_sweep(dta, axis, mask)
+            else:
+                pa.ppm_sweep_cfl(dta, axis, mask)
+            mask |= 1 << axis
+        pa.ppm_cfl_finalize(dta)
+        pb.ppm_step_cfl(dtb, s % 2)
+        torch.cuda.synchronize()
+        assert torch.equal(dta, dtb), s
+        for f in FIELDS:
+            assert torch.equal(getattr(A[0], f), getattr(B[0], f)), (s, f)
+    pa.close()
+    pb.close()
