@@ -137,6 +137,13 @@ int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
  *                  that all satisfy this, else 0.
  *   batch_block=B  threads per workgroup of the persistent launch (64..256).
  *   batch_blocks=W workgroups of the persistent launch (default: 512/B per CU).
+ *   tail=0|1       one ungrouped patch: when a marching sweep's pencils
+ *                  exceed a whole number of rounds of resident marching
+ *                  threads by at most an eighth of a round, march the whole
+ *                  rounds and stream the rest with the lane-parallel kernel,
+ *                  one pencil per wavefront, in a second launch (default 1).
+ *   tail_round=R   take R pencils (a multiple of block) as the round and give
+ *                  any rest to the lane-parallel launch (for tests and tuning).
  * Results do not depend on the launch shapes.  Uploads the patch table to
  * the device on `hip_stream` (0 = default stream) and allocates the event
  * counters.  On success *out owns the plan. */

@@ -35,6 +35,11 @@ struct ppm_plan {
   int32_t batch_blocks = 0;       // workgroups of the persistent kernel
   int32_t group = 0;              // marching sweeps number pencils across equal-length patches
   bool group_set = false;         // group given in the tile config
+  int32_t tail = 1;               // one patch: lanes launch for a marching sweep's last round
+  int32_t tail_round = 0;         // pencils per marching round (0: from the occupancy)
+  int32_t tail_pencil0[2][12] = {};  // [cfl][slot]: first pencil of the lanes tail
+  int32_t tail_main[2][12] = {};     // marching blocks before it
+  int32_t tail_blocks[2][12] = {};   // lane-parallel blocks of the tail (0: no tail)
   int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
   unsigned int *d_queue = nullptr;  // persistent queue head and exit count
   std::vector<PatchDev> host;
@@ -138,6 +143,12 @@ ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
       if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: group must be 0 or 1");
       pl->group = int32_t(v);
       pl->group_set = true;
+    } else if (k == "tail") {
+      if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: tail must be 0 or 1");
+      pl->tail = int32_t(v);
+    } else if (k == "tail_round") {
+      if (v < 64 || v > (1 << 26) || v % 64) return fail(PPM_EINVAL, "tile_config: tail_round must be a multiple of 64 in 64..2^26");
+      pl->tail_round = int32_t(v);
     } else if (k == "persistent") {
       if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: persistent must be 0 or 1");
       pl->persistent = int32_t(v);
@@ -180,14 +191,26 @@ hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, unsigned
     if (pl->nblocks[slot] == 0) return hipSuccess;
     return ppm::launch_sweep_lanes<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
                                          pl->npatch, pl->nblocks[slot], pl->lanes_block, axis,
-                                         mask, dt, pl->P, pl->d_counters, smax, s);
+                                         mask, 0, 0, dt, pl->P, pl->d_counters, smax, s);
   }
   const int slot = axis * 4 + tm;
   if (pl->nblocks[slot] == 0) return hipSuccess;
   const int32_t *groups = pl->group ? pl->d_groups + pl->gofs[slot] : nullptr;
-  return ppm::launch_sweep<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
-                                 pl->npatch, pl->nblocks[slot], pl->block, axis, mask, dt, pl->P,
-                                 pl->d_counters, smax, groups, pl->ngroups[slot], s);
+  const int c = smax ? 1 : 0;
+  const int32_t *chunks = pl->d_chunks + slot * (pl->npatch + 1);
+  if (pl->tail_blocks[c][slot] > 0) {  // whole rounds marched, the rest one pencil per wave
+    hipError_t e = ppm::launch_sweep<Prec>(pl->d_patches, chunks, pl->npatch,
+                                           pl->tail_main[c][slot], pl->block, axis, mask, dt,
+                                           pl->P, pl->d_counters, smax, nullptr, 0, s);
+    if (e != hipSuccess) return e;
+    return ppm::launch_sweep_lanes<Prec>(pl->d_patches, chunks, pl->npatch,
+                                         pl->tail_blocks[c][slot], pl->lanes_block, axis, mask,
+                                         pl->tail_pencil0[c][slot], 1, dt, pl->P,
+                                         pl->d_counters, smax, s);
+  }
+  return ppm::launch_sweep<Prec>(pl->d_patches, chunks, pl->npatch, pl->nblocks[slot], pl->block,
+                                 axis, mask, dt, pl->P, pl->d_counters, smax, groups,
+                                 pl->ngroups[slot], s);
 }
 
 hipError_t sweep_any(ppm_plan *pl, const double *dt, int axis, int mask, unsigned long long *smax,
@@ -237,6 +260,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   if ((st = parse_tiles(pl, tile_config)) != PPM_OK) {
     delete pl;
     return st;
+  }
+  if (pl->tail_round % pl->block) {
+    delete pl;
+    return fail(PPM_EINVAL, "tile_config: tail_round must be a multiple of block");
   }
   if (pl->persistent && max_cells > kPersistentMaxCells) {
     delete pl;
@@ -360,6 +387,37 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
         pl->nblocks[slot] = chunks[size_t(slot + 1) * stride - 1];
     }
   }
+  // One patch, marched pencils just over a whole number of resident rounds:
+  // march the whole rounds and give the few pencils left (at most an eighth
+  // of a round) to the lane-parallel kernel, one pencil per wave, instead of
+  // a last round of whole-pencil marches on an almost idle device.  A given
+  // tail_round replaces the resident round and the eighth rule (any rest).
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess)
+    cus = 0;
+  if (npatch == 1 && !pl->group && pl->tail && (cus > 0 || pl->tail_round > 0)) {
+    for (int c = 0; c < 2; ++c) {
+      int64_t cap = pl->tail_round;  // marching threads resident at once
+      if (cap == 0) {
+        const int bpc = prec == PPM_FP64 ? ppm::march_blocks_per_cu<ppm::PrecF64>(pl->block, c)
+                                         : ppm::march_blocks_per_cu<ppm::PrecMixed>(pl->block, c);
+        cap = int64_t(cus) * bpc * pl->block;
+      }
+      if (cap <= 0) continue;
+      for (int slot = 0; slot < 12; ++slot) {
+        const int axis = slot / 4, tm = slot % 4;
+        const PatchDev &d = pl->host[0];
+        const int64_t w1 = (tm & 1) ? d.n[t1_of(axis)] : d.n[t1_of(axis)] + 2 * d.ghost;
+        const int64_t w2 = (tm & 2) ? d.n[t2_of(axis)] : d.n[t2_of(axis)] + 2 * d.ghost;
+        const int64_t np = w1 * w2, rest = np % cap;
+        if (np < cap || rest == 0 || (pl->tail_round == 0 && rest * 8 > cap)) continue;
+        const int64_t waves = pl->lanes_block / 64;
+        pl->tail_pencil0[c][slot] = int32_t(np - rest);
+        pl->tail_main[c][slot] = int32_t((np - rest) / pl->block);
+        pl->tail_blocks[c][slot] = int32_t((rest + waves - 1) / waves);
+      }
+    }
+  }
   {
     int64_t acc = 0;
     int32_t *c = &chunks[size_t(24) * stride];
@@ -388,12 +446,9 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     std::stable_sort(cost.begin(), cost.end());
     for (int i = 0; i < npatch; ++i) order[i] = cost[i].second;
   }
-  if (pl->batch_blocks == 0) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess || cus <= 0)
-      cus = 256;
-    pl->batch_blocks = std::min<int64_t>(int64_t(cus) * (512 / pl->batch_block), npatch);
-  }
+  if (pl->batch_blocks == 0)
+    pl->batch_blocks = std::min<int64_t>(int64_t(cus > 0 ? cus : 256) * (512 / pl->batch_block),
+                                         npatch);
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   hipError_t e;
   if ((e = hipMalloc(&pl->d_order, sizeof(int32_t) * npatch)) != hipSuccess ||

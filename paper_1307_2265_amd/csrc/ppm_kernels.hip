@@ -137,22 +137,25 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
   }
 }
 
-// One wavefront streams a run of rows_per_wave(n) consecutive pencils with
-// the cells across its lanes.
+// One wavefront streams a run of `rows` consecutive pencils (rows_per_wave(n)
+// if rows is 0) with the cells across its lanes, from pencil `pencil0` of the
+// patch on (a run of whole pencils per wave, so a launch can take over any
+// trailing range of a patch's pencils).
 template <class Prec, bool kCFL>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
-                   int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
-                   Params P, unsigned long long *__restrict__ counters,
+                   int32_t npatch, int32_t axis, int32_t mask, int32_t pencil0, int32_t rows,
+                   const double *__restrict__ dt_dev, Params P,
+                   unsigned long long *__restrict__ counters,
                    unsigned long long *__restrict__ smax_bits) {
   const int p = find_patch(chunk_start, npatch, blockIdx.x);
   const PatchDev pd = patches[p];
   const int waves = blockDim.x >> 6;
   const int item = (blockIdx.x - chunk_start[p]) * waves + (threadIdx.x >> 6);
   const int n = pick3(axis, pd.n[0], pd.n[1], pd.n[2]) + 2 * pd.ghost;
-  const int K = rows_per_wave(n);
+  const int K = rows > 0 ? rows : rows_per_wave(n);
   const int np = pencil_count(pd, axis, mask);
-  const int first = item * K;
+  const int first = pencil0 + item * K;
   if (first >= np) return;  // the whole wave leaves
   const double dt = dt_dev[pd.level];
   uint32_t nfb = 0, nfl = 0;
@@ -379,16 +382,31 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
 template <class Prec>
 hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                               int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
-                              const double *dt_dev, const Params &P,
-                              unsigned long long *counters, unsigned long long *smax_bits,
-                              hipStream_t s) {
+                              int32_t pencil0, int32_t rows, const double *dt_dev,
+                              const Params &P, unsigned long long *counters,
+                              unsigned long long *smax_bits, hipStream_t s) {
   if (smax_bits)
     hipLaunchKernelGGL((sweep_lanes_kernel<Prec, true>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
+                       patches, chunk_start, npatch, axis, mask, pencil0, rows, dt_dev, P,
+                       counters, smax_bits);
   else
     hipLaunchKernelGGL((sweep_lanes_kernel<Prec, false>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
+                       patches, chunk_start, npatch, axis, mask, pencil0, rows, dt_dev, P,
+                       counters, smax_bits);
   return hipGetLastError();
+}
+
+template <class Prec>
+int march_blocks_per_cu(int32_t block, bool cfl) {
+  const size_t lds = size_t(kLdsMarch + (cfl ? 1 : 0)) * block * sizeof(double);
+  int nb = 0;
+  hipError_t e = cfl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &nb, reinterpret_cast<const void *>(sweep_kernel<Prec, true, false>),
+                           block, lds)
+                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                           &nb, reinterpret_cast<const void *>(sweep_kernel<Prec, false, false>),
+                           block, lds);
+  return e == hipSuccess ? nb : 0;
 }
 
 template <class Prec>
@@ -444,10 +462,11 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                          unsigned long long *, const int32_t *, int32_t,          \
                                          hipStream_t);                                             \
   template hipError_t launch_sweep_lanes<Prec>(const PatchDev *, const int32_t *, int32_t,        \
-                                               int32_t, int32_t, int32_t, int32_t,                \
-                                               const double *, const Params &,                    \
+                                               int32_t, int32_t, int32_t, int32_t, int32_t,       \
+                                               int32_t, const double *, const Params &,           \
                                                unsigned long long *, unsigned long long *,        \
                                                hipStream_t);                                       \
+  template int march_blocks_per_cu<Prec>(int32_t, bool);                                          \
   template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *, unsigned int *,    \

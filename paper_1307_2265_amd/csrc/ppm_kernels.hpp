@@ -19,14 +19,21 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
 // groups (nullable): the marching sweep numbers the pencils of runs of
 // equal-length patches consecutively (layout in ppm_kernels.hip).
 // Lane-parallel variant (a wavefront streams a run of pencils); block = 64 * waves.
+// Each wave takes `rows` pencils (0: rows_per_wave of the pencil length),
+// counted from pencil `pencil0` of its patch.
 // smax_bits (nullable) of a sweep launch: the sweep is the last of its step and
 // also takes the max signal speed per level of the cells it writes.
 template <class Prec>
 hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                               int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
-                              const double *dt_dev, const Params &P,
-                              unsigned long long *counters, unsigned long long *smax_bits,
-                              hipStream_t s);
+                              int32_t pencil0, int32_t rows, const double *dt_dev,
+                              const Params &P, unsigned long long *counters,
+                              unsigned long long *smax_bits, hipStream_t s);
+
+// Resident workgroups per compute unit of the (ungrouped) marching sweep
+// with `block` threads, with or without the CFL maximum; 0 if unknown.
+template <class Prec>
+int march_blocks_per_cu(int32_t block, bool cfl);
 
 // Persistent batch kernel: the whole step of every patch in one launch.
 template <class Prec>

@@ -210,10 +210,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
       sig = cell_signal<S>(P, cfl.axis, cfl.dx, S(out[0]), S(out[1]), S(out[2]), S(out[3]),
                            out[4], out[5]);
   }
-  if (kCFL) {
-    const double m = wave_uniform(wave_max(sig));
-    cfl.smax = m > cfl.smax ? m : cfl.smax;
-  }
+  if (kCFL) cfl.smax = sig > cfl.smax ? sig : cfl.smax;  // per lane; reduced at the end
 }
 
 // One wave streams pencils first .. first+nrows-1 of a sweep's pencil set,

@@ -185,19 +185,11 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
-// A wave-uniform double, kept in scalar registers.
-__device__ __forceinline__ double wave_uniform(double v) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = unsigned(__builtin_amdgcn_readfirstlane(int(b)));
-  const unsigned hi = unsigned(__builtin_amdgcn_readfirstlane(int(b >> 32)));
-  return __longlong_as_double((long long)((unsigned long long)hi << 32 | lo));
-}
-
 // Maximum signal speed over the cells a sweep writes, for a sweep that also
 // yields the next step's timestep.  The marching sweep keeps each thread's
-// running maximum in LDS (`lds`, one double per thread), the lane-parallel
-// sweep a wave maximum in scalar registers (`smax`): neither costs the
-// sweep a vector register.
+// running maximum in LDS (`lds`, one double per thread) to spare its vector
+// registers; the lane-parallel sweep keeps each lane's in `smax`, and the
+// wave maximum is taken once, when the kernel commits it.
 struct CflAcc {
   int axis;
   double dx[3];

@@ -85,6 +85,12 @@ def test_bad_tile_config_is_rejected():
     assert st == ppm.PPM_EINVAL and "block" in L.ppm_last_error().decode()
     st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"warp=3", None)
     assert st == ppm.PPM_EINVAL and "unknown key" in L.ppm_last_error().decode()
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"tail=2", None)
+    assert st == ppm.PPM_EINVAL and "tail" in L.ppm_last_error().decode()
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm),
+                           b"block=128 tail_round=320", None)
+    assert st == ppm.PPM_EINVAL and "multiple of block" in L.ppm_last_error().decode()
+    assert not h.value
 
 
 def test_persistent_launch_rejects_patches_too_large_for_one_workgroup():

@@ -223,12 +223,14 @@ def test_sweep_extents_on_gpu(P, O):
 
 
 @pytest.mark.parametrize("tiles", ["lanes=0", "lanes=7", "lanes=7 lanes_block=64",
-                                   "block=64"])
+                                   "block=64", "lanes=0 block=64 tail_round=640",
+                                   "block=128 lanes_block=64 tail_round=1024"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_both_sweep_kernels_on_every_axis(P, O, tiles, prec):
     # The pencil-marching kernel and the lane-parallel kernel must agree with
     # the oracle along every axis, on grids long enough for several 54-cell
-    # lane segments and with ragged tails.
+    # lane segments and with ragged tails; tail_round: each marching sweep
+    # marches whole rounds of pencils and streams the rest one per wave.
     d = W.random_grid(131, 37, 61, 31337, W.SHOCKED)
     pr = P.PPM_FP64 if prec == "fp64" else P.PPM_MIXED
     d = stored_inputs(d, pr)
@@ -519,8 +521,8 @@ def test_graph_replays_match_eager_steps(P, O, batch, fused):
     pb.close()
 
 
-@pytest.mark.parametrize("case", ["single-fp64", "single-mixed", "single-lanes7", "batch-fp64",
-                                  "batch-mixed", "batch-persistent", "batch-march",
+@pytest.mark.parametrize("case", ["single-fp64", "single-mixed", "single-lanes7", "single-tail",
+                                  "batch-fp64", "batch-mixed", "batch-persistent", "batch-march",
                                   "batch-march-ungrouped"])
 def test_step_with_next_dt_equals_step_then_cfl(P, case):
     # ppm_step_cfl takes the next step's CFL timestep from the values its last
@@ -528,7 +530,8 @@ def test_step_with_next_dt_equals_step_then_cfl(P, case):
     # as a separate ppm_cfl_dt, bit for bit, step after step (both orders).
     import torch
     prec = P.PPM_MIXED if "mixed" in case else P.PPM_FP64
-    tiles = {"single-lanes7": "lanes=7", "batch-persistent": "persistent=1",
+    tiles = {"single-lanes7": "lanes=7", "single-tail": "block=64 lanes_block=64 tail_round=320",
+             "batch-persistent": "persistent=1",
              "batch-march": "persistent=0 lanes=0",
              "batch-march-ungrouped": "persistent=0 lanes=0 group=0"}.get(case)
     if case.startswith("single"):
