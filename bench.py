@@ -193,8 +193,11 @@ def main():
     # ---- roofline of the dominant kernel: the pencil-marching sweep kernel of
     # the FP64 single-grid run, in its plain form (the y sweeps, and the z
     # sweeps that open a zyx step; the z sweeps that close an xyz step run the
-    # variant that also takes the next timestep).
-    # Algorithmic work of one launch: every pencil reads its n+6 cells and
+    # variant that also takes the next timestep).  Such a sweep is one
+    # marching launch over whole rounds of resident threads plus, when
+    # pencils are left over, a tail launch (sweep_tail_kernel) that streams
+    # them; the unit measured is the sweep, both launches.
+    # Algorithmic work of one sweep: every pencil reads its n+6 cells and
     # writes its n active cells (6 fields of 8 B), and performs the
     # oracle-counted FP64 operations (add, mul, div, sqrt) for each of its n
     # updated cells.  The bound is the roof the kernel's arithmetic intensity
@@ -216,6 +219,12 @@ def main():
              else "sweep_lanes_kernel<PrecF64, false>")
     tr = measured_traffic(kname)
     traffic = None if tr is None else tr["bytes"]
+    if dom == "march" and traffic is not None:
+        tt = measured_traffic("sweep_tail_kernel<PrecF64, false>")
+        if tt is not None:  # mean bytes of the tail launches of the same sweeps
+            traffic += tt["bytes"]
+            kname += " + sweep_tail_kernel<PrecF64, false>"
+
     hbm = dict(bound="hbm", achieved=bytes_launch / sw / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                frac=0.0, traffic=traffic, kernel=kname, algorithmic_bytes=bytes_launch,
                launch_ms=sw * 1e3)

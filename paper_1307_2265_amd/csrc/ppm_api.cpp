@@ -191,7 +191,7 @@ hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, unsigned
     if (pl->nblocks[slot] == 0) return hipSuccess;
     return ppm::launch_sweep_lanes<Prec>(pl->d_patches, pl->d_chunks + slot * (pl->npatch + 1),
                                          pl->npatch, pl->nblocks[slot], pl->lanes_block, axis,
-                                         mask, 0, 0, dt, pl->P, pl->d_counters, smax, s);
+                                         mask, dt, pl->P, pl->d_counters, smax, s);
   }
   const int slot = axis * 4 + tm;
   if (pl->nblocks[slot] == 0) return hipSuccess;
@@ -203,10 +203,9 @@ hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, unsigned
                                            pl->tail_main[c][slot], pl->block, axis, mask, dt,
                                            pl->P, pl->d_counters, smax, nullptr, 0, s);
     if (e != hipSuccess) return e;
-    return ppm::launch_sweep_lanes<Prec>(pl->d_patches, chunks, pl->npatch,
-                                         pl->tail_blocks[c][slot], pl->lanes_block, axis, mask,
-                                         pl->tail_pencil0[c][slot], 1, dt, pl->P,
-                                         pl->d_counters, smax, s);
+    return ppm::launch_sweep_tail<Prec>(pl->d_patches, chunks, pl->tail_blocks[c][slot],
+                                        pl->lanes_block, axis, mask, pl->tail_pencil0[c][slot],
+                                        dt, pl->P, pl->d_counters, smax, s);
   }
   return ppm::launch_sweep<Prec>(pl->d_patches, chunks, pl->npatch, pl->nblocks[slot], pl->block,
                                  axis, mask, dt, pl->P, pl->d_counters, smax, groups,
@@ -316,7 +315,8 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
         pl->nblocks[slot] = int32_t(acc);
       }
   // grouped marching maps: per (axis, extent) slot, the patches sorted by
-  // pencil length, runs of equal length, the first block of each run, the
+  // pencil length, longest first (the last blocks to start then hold the
+  // shortest pencils), runs of equal length, the first block of each run, the
   // first sorted patch of each run, the pencil prefix over the sorted patches
   // and the sorted patch indices
   // A run's patches must be views into six shared arrays at one element
@@ -343,7 +343,7 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
         for (int i = 0; i < npatch; ++i) sorted[i] = i;
         auto len = [&](int i) { return pl->host[i].n[axis] + 2 * pl->host[i].ghost; };
         std::stable_sort(sorted.begin(), sorted.end(),
-                         [&](int a, int b) { return len(a) < len(b); });
+                         [&](int a, int b) { return len(a) > len(b); });
         std::vector<int32_t> pp(size_t(npatch) + 1, 0), gfirst, gbs;
         int64_t acc = 0, blocks = 0;
         for (int j = 0; j < npatch; ++j) {

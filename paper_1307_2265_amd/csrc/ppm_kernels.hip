@@ -7,6 +7,9 @@
 //     grid is the one-patch case of the same kernel.
 //   * sweep_lanes_kernel: the same sweep with the cells of a pencil across
 //     the lanes of a wave (ppm_lanes.hpp), for x sweeps.
+//   * sweep_tail_kernel: the same lane-parallel code over the last pencils of
+//     a big patch's marching sweep, one pencil per wave, after the marching
+//     launch has taken whole rounds of resident threads.
 //   * batch_persistent_kernel: a whole step of every patch in one launch.
 //   * Each sweep kernel has a variant for the last sweep of a step that also
 //     takes the max signal speed of the cells it writes, so the next step's
@@ -72,7 +75,7 @@ __device__ __forceinline__ void cfl_commit_levels(double smax, int level,
 // One thread marches one pencil.  Ungrouped: each block takes `blockDim.x`
 // consecutive pencils of one patch (block -> patch by the prefix array
 // chunk_start).  Grouped (several patches): patches are sorted by pencil
-// length and the pencils of a run of equal-length patches are numbered
+// length (longest first) and the pencils of a run of equal-length patches are numbered
 // consecutively, so a block's threads may belong to several patches and no
 // wave is left partly empty at a patch's end; `groups` holds, for this
 // sweep, the first block and the first sorted patch of every run, the
@@ -139,15 +142,15 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
 
 // One wavefront streams a run of `rows` consecutive pencils (rows_per_wave(n)
 // if rows is 0) with the cells across its lanes, from pencil `pencil0` of the
-// patch on (a run of whole pencils per wave, so a launch can take over any
-// trailing range of a patch's pencils).
+// patch on.
 template <class Prec, bool kCFL>
-__global__ void __launch_bounds__(kMaxBlock, 4)
-sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
-                   int32_t npatch, int32_t axis, int32_t mask, int32_t pencil0, int32_t rows,
-                   const double *__restrict__ dt_dev, Params P,
-                   unsigned long long *__restrict__ counters,
-                   unsigned long long *__restrict__ smax_bits) {
+__device__ __forceinline__ void stream_pencils(const PatchDev *__restrict__ patches,
+                                               const int32_t *__restrict__ chunk_start,
+                                               int32_t npatch, int32_t axis, int32_t mask,
+                                               int32_t pencil0, int32_t rows,
+                                               const double *__restrict__ dt_dev, const Params &P,
+                                               unsigned long long *__restrict__ counters,
+                                               unsigned long long *__restrict__ smax_bits) {
   const int p = find_patch(chunk_start, npatch, blockIdx.x);
   const PatchDev pd = patches[p];
   const int waves = blockDim.x >> 6;
@@ -164,6 +167,29 @@ sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restri
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
   if (kCFL) cfl_commit(cfl.smax, &smax_bits[pd.level]);
+}
+
+// Lane-parallel sweep: each wavefront streams rows_per_wave(n) pencils.
+template <class Prec, bool kCFL>
+__global__ void __launch_bounds__(kMaxBlock, 4)
+sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
+                   int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
+                   Params P, unsigned long long *__restrict__ counters,
+                   unsigned long long *__restrict__ smax_bits) {
+  stream_pencils<Prec, kCFL>(patches, chunk_start, npatch, axis, mask, 0, 0, dt_dev, P, counters,
+                             smax_bits);
+}
+
+// The pencils of one patch from `pencil0` on, one per wavefront: what is
+// left of a marching sweep after whole rounds of resident marching threads.
+template <class Prec, bool kCFL>
+__global__ void __launch_bounds__(kMaxBlock, 4)
+sweep_tail_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
+                  int32_t axis, int32_t mask, int32_t pencil0, const double *__restrict__ dt_dev,
+                  Params P, unsigned long long *__restrict__ counters,
+                  unsigned long long *__restrict__ smax_bits) {
+  stream_pencils<Prec, kCFL>(patches, chunk_start, 1, axis, mask, pencil0, 1, dt_dev, P, counters,
+                             smax_bits);
 }
 
 // ---------------------------------------------------------------------------
@@ -382,17 +408,29 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
 template <class Prec>
 hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                               int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
-                              int32_t pencil0, int32_t rows, const double *dt_dev,
-                              const Params &P, unsigned long long *counters,
-                              unsigned long long *smax_bits, hipStream_t s) {
+                              const double *dt_dev, const Params &P,
+                              unsigned long long *counters, unsigned long long *smax_bits,
+                              hipStream_t s) {
   if (smax_bits)
     hipLaunchKernelGGL((sweep_lanes_kernel<Prec, true>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, npatch, axis, mask, pencil0, rows, dt_dev, P,
-                       counters, smax_bits);
+                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
   else
     hipLaunchKernelGGL((sweep_lanes_kernel<Prec, false>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, npatch, axis, mask, pencil0, rows, dt_dev, P,
-                       counters, smax_bits);
+                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start, int32_t nblocks,
+                             int32_t block, int32_t axis, int32_t mask, int32_t pencil0,
+                             const double *dt_dev, const Params &P, unsigned long long *counters,
+                             unsigned long long *smax_bits, hipStream_t s) {
+  if (smax_bits)
+    hipLaunchKernelGGL((sweep_tail_kernel<Prec, true>), dim3(nblocks), dim3(block), 0, s,
+                       patches, chunk_start, axis, mask, pencil0, dt_dev, P, counters, smax_bits);
+  else
+    hipLaunchKernelGGL((sweep_tail_kernel<Prec, false>), dim3(nblocks), dim3(block), 0, s,
+                       patches, chunk_start, axis, mask, pencil0, dt_dev, P, counters, smax_bits);
   return hipGetLastError();
 }
 
@@ -462,10 +500,14 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                          unsigned long long *, const int32_t *, int32_t,          \
                                          hipStream_t);                                             \
   template hipError_t launch_sweep_lanes<Prec>(const PatchDev *, const int32_t *, int32_t,        \
-                                               int32_t, int32_t, int32_t, int32_t, int32_t,       \
-                                               int32_t, const double *, const Params &,           \
+                                               int32_t, int32_t, int32_t, int32_t,                \
+                                               const double *, const Params &,                    \
                                                unsigned long long *, unsigned long long *,        \
                                                hipStream_t);                                       \
+  template hipError_t launch_sweep_tail<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t, \
+                                              int32_t, int32_t, int32_t, const double *,          \
+                                              const Params &, unsigned long long *,               \
+                                              unsigned long long *, hipStream_t);                  \
   template int march_blocks_per_cu<Prec>(int32_t, bool);                                          \
   template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
                                          int32_t, int32_t, int32_t, const double *,               \

@@ -19,16 +19,22 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
 // groups (nullable): the marching sweep numbers the pencils of runs of
 // equal-length patches consecutively (layout in ppm_kernels.hip).
 // Lane-parallel variant (a wavefront streams a run of pencils); block = 64 * waves.
-// Each wave takes `rows` pencils (0: rows_per_wave of the pencil length),
-// counted from pencil `pencil0` of its patch.
 // smax_bits (nullable) of a sweep launch: the sweep is the last of its step and
 // also takes the max signal speed per level of the cells it writes.
 template <class Prec>
 hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                               int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
-                              int32_t pencil0, int32_t rows, const double *dt_dev,
-                              const Params &P, unsigned long long *counters,
-                              unsigned long long *smax_bits, hipStream_t s);
+                              const double *dt_dev, const Params &P,
+                              unsigned long long *counters, unsigned long long *smax_bits,
+                              hipStream_t s);
+
+// The pencils of one patch from `pencil0` on, one per wavefront of the
+// lane-parallel code (block = 64 * waves): the rest of a marching sweep.
+template <class Prec>
+hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start, int32_t nblocks,
+                             int32_t block, int32_t axis, int32_t mask, int32_t pencil0,
+                             const double *dt_dev, const Params &P, unsigned long long *counters,
+                             unsigned long long *smax_bits, hipStream_t s);
 
 // Resident workgroups per compute unit of the (ungrouped) marching sweep
 // with `block` threads, with or without the CFL maximum; 0 if unknown.

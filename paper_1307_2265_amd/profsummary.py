@@ -57,7 +57,7 @@ def kernels(stats_csv: str, trace_csv: str, cmd: str, out: str):
                      f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
     agg = collections.defaultdict(list)
     for r in csv.DictReader(open(trace_csv)):
-        if "sweep" not in r["Kernel_Name"] and "batch" not in r["Kernel_Name"]:
+        if "sweep" not in r["Kernel_Name"] and "batch" not in r["Kernel_Name"]:  # incl. tails
             continue
         key = (short(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]),
                int(r["VGPR_Count"]), int(r["Scratch_Size"]), int(r["LDS_Block_Size"]))
@@ -76,6 +76,22 @@ def kernels(stats_csv: str, trace_csv: str, cmd: str, out: str):
               "| kernel | block | calls | mean ms |", "|---|---:|---:|---:|"]
     for k, d in sorted(byblock.items()):
         lines.append(f"| `{k[0]}` | {k[1]} | {len(d)} | {sum(d) / len(d):.3f} |")
+    # a marching sweep of the big grid is its marching launch plus, when
+    # pencils are left over after whole rounds, a tail launch
+    means = {k: sum(d) / len(d) for k, d in
+             ((name, [x for kk, dd in agg.items() if kk[0] == name for x in dd])
+              for name in {kk[0] for kk in agg})}
+    sweeps = []
+    for prec in ("PrecF64", "PrecMixed"):
+        for cfl in ("false", "true"):
+            m, t = f"sweep_kernel<{prec}, {cfl}, false>", f"sweep_tail_kernel<{prec}, {cfl}>"
+            if m in means and t in means:
+                sweeps.append(f"| `{m}` + `{t}` | {means[m]:.3f} | {means[t]:.3f} | "
+                              f"{means[m] + means[t]:.3f} |")
+    if sweeps:
+        lines += ["", "## Marching sweeps of the single grid (marching launch + tail launch)", "",
+                  "| launches | marching ms | tail ms | sweep ms |", "|---|---:|---:|---:|"]
+        lines += sweeps
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
