@@ -27,10 +27,32 @@
 namespace ppm {
 
 
-template <class V> __device__ __forceinline__ V from_left(V v) { return __shfl_up(v, 1, 64); }
-template <class V> __device__ __forceinline__ V from_right(V v) { return __shfl_down(v, 1, 64); }
-template <class V> __device__ __forceinline__ V from_left2(V v) { return __shfl_up(v, 2, 64); }
-template <class V> __device__ __forceinline__ V from_right2(V v) { return __shfl_down(v, 2, 64); }
+// Neighbour values by whole-wave DPP shifts (a VALU move per 32 bits, no LDS
+// round trip): wave_shr:1 gives lane i the value of lane i-1, wave_shl:1 that
+// of lane i+1; the lane with no source (0, resp. 63) keeps its own value.
+constexpr int kDppWaveShl1 = 0x130;
+constexpr int kDppWaveShr1 = 0x138;
+
+template <int kCtrl> __device__ __forceinline__ int dpp_shift32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, kCtrl, 0xf, 0xf, false);
+}
+
+template <int kCtrl, class V> __device__ __forceinline__ V dpp_shift(V v) {
+  static_assert(sizeof(V) == 4 || sizeof(V) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(V) == 8) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = unsigned(dpp_shift32<kCtrl>(int(unsigned(b))));
+    const unsigned hi = unsigned(dpp_shift32<kCtrl>(int(unsigned(b >> 32))));
+    return __builtin_bit_cast(V, (unsigned long long)hi << 32 | lo);
+  } else {
+    return __builtin_bit_cast(V, dpp_shift32<kCtrl>(__builtin_bit_cast(int, v)));
+  }
+}
+
+template <class V> __device__ __forceinline__ V from_left(V v) { return dpp_shift<kDppWaveShr1>(v); }
+template <class V> __device__ __forceinline__ V from_right(V v) { return dpp_shift<kDppWaveShl1>(v); }
+template <class V> __device__ __forceinline__ V from_left2(V v) { return from_left(from_left(v)); }
+template <class V> __device__ __forceinline__ V from_right2(V v) { return from_right(from_right(v)); }
 
 __device__ __forceinline__ Flux flux_from_left(const Flux &F) {
   Flux o;
@@ -52,15 +74,15 @@ struct CellLoad {
 // One segment: lane holds cell j of pencil pc (j = -1 for a placeholder
 // lane beyond the stream, which no valid result uses).  `in` is this lane's
 // input cell; the lane writes its cell (and counts its events) if `mine`.
+// lam = dt / pc.dx (the same for every pencil of the patch).
 template <class Prec, bool kCFL>
 __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
-                              int j, bool mine, const CellLoad &in, uint32_t &n_fallback,
-                              uint32_t &n_floor, CflAcc &cfl) {
+                              double lam, int j, bool mine, const CellLoad &in,
+                              uint32_t &n_fallback, uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
   using T = typename Prec::T;
   const int n = pc.n, g = pc.g;
   const int a0 = g, a1 = n - g - 1;
-  const double lam = dt / pc.dx;
   const T tlam = T(lam);
   const double gam = P.gamma;
   const bool steepen = (P.flags & kSteepen) != 0;
@@ -224,6 +246,7 @@ __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, 
   const int n = (axis == 0 ? pd.n[0] : (axis == 1 ? pd.n[1] : pd.n[2])) + 2 * pd.ghost;
   const int L = nrows * n;
   const int nseg = (L + kLaneOut - 1) / kLaneOut;
+  const double lam = dt / pick3(axis, pd.dx[0], pd.dx[1], pd.dx[2]);
   CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
   for (int s = 0; s < nseg; ++s) {
     const int t = s * kLaneOut - kLaneHalo + lane;  // stream position of this lane
@@ -252,7 +275,7 @@ __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, 
       cur = CellLoad{1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
     }
     const bool mine = in && lane >= kLaneHalo && lane < kLaneHalo + kLaneOut;
-    sweep_segment<Prec, kCFL>(P, pc, dt, j, mine, cur, n_fallback, n_floor, cfl);
+    sweep_segment<Prec, kCFL>(P, pc, dt, lam, j, mine, cur, n_fallback, n_floor, cfl);
   }
 }
 
