@@ -30,6 +30,7 @@ CANDIDATES = {
         "lanes=1 block=256 lanes_block=64",
         "lanes=1 block=128 lanes_block=256",
         "lanes=1 block=128 lanes_block=64",
+        "lanes=1 block=256 lanes_block=128 tail=0",
         "lanes=0 block=256",
     ],
     "batch": [
