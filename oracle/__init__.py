@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SOURCES = ["ppm_oracle.cpp", "exact_riemann.cpp"]
 
 STEEPEN, FLATTEN, DUAL_ENERGY, FALLBACK_HLL = 1, 2, 4, 8
+HLLC = 16  # HLLC face fluxes instead of the two-shock solver
 ALL_FLAGS = STEEPEN | FLATTEN | DUAL_ENERGY | FALLBACK_HLL
 ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
 
@@ -90,6 +91,7 @@ def lib():
         L.ppmo_fill_periodic.argtypes = [C.POINTER(_Grid)]
         L.ppmo_two_shock.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.ppmo_hll_flux.argtypes = [C.POINTER(Params), dp, dp, dp]
+        L.ppmo_hllc_flux.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.ppmo_exact_riemann.argtypes = [C.c_double, dp, dp, C.c_int32, dp, dp, dp, dp, dp]
         L.ppmo_count_ops.argtypes = [C.POINTER(_Grid), C.POINTER(Params), C.c_double, C.c_int32,
                                      C.POINTER(C.c_int64)]
@@ -212,6 +214,16 @@ def hll_flux(prm: Params, left6, right6) -> np.ndarray:
     r = np.ascontiguousarray(right6, dtype=np.float64)
     out = np.zeros(7)
     lib().ppmo_hll_flux(C.byref(prm), _ptr(l), _ptr(r), _ptr(out))
+    return out
+
+
+def hllc_flux(prm: Params, left6, right6) -> np.ndarray:
+    """HLLC flux on traced states (rho, u, v1, v2, p): F_rho, F_u, F_v1, F_v2,
+    F_E, F_e and the face velocity (S* inside the fan)."""
+    l = np.ascontiguousarray(left6, dtype=np.float64)
+    r = np.ascontiguousarray(right6, dtype=np.float64)
+    out = np.zeros(7)
+    lib().ppmo_hllc_flux(C.byref(prm), _ptr(l), _ptr(r), _ptr(out))
     return out
 
 

@@ -11,7 +11,7 @@
 //      the paper's Eq. for q_{L}, Delta q, q_6),
 //   6. characteristic tracing over the u-c, u, u+c domains (CW84 Eqs. 3.5-3.7),
 //   7. two-shock Riemann solver and sampling at x/t = 0 (Sec. "Riemann
-//      Solvers and Fallback"),
+//      Solvers and Fallback"), or the HLLC flux when PPMO_HLLC is set,
 //   8. fluxes and the conservative update of mass, momentum and total energy
 //      (Eqs. mass_diff, momentum_diff, energy_diff, with the flux-difference
 //      sign read as minus, i.e. the conservative upwind form) and of the
@@ -216,7 +216,14 @@ RiemannOut<R> two_shock(const ppmo_params &P, R rl, R ul, R pl, R rr, R ur, R pr
 // transverse velocities come from the upwind side.  Slot FUB keeps the face
 // velocity for the p div v term of the internal-energy equation.
 template <class R>
+void hllc_flux(const ppmo_params &P, const R *sl, const R *sr, R *F);
+
+template <class R>
 void godunov_flux(const ppmo_params &P, const R *sl, const R *sr, R *F) {
+  if (P.flags & PPMO_HLLC) {
+    hllc_flux<R>(P, sl, sr, F);
+    return;
+  }
   const double g = P.gamma;
   RiemannOut<R> o = two_shock<R>(P, sl[QR], sl[QU], sl[QP], sr[QR], sr[QU], sr[QP]);
   R v1 = o.left ? sl[QV1] : sr[QV1];
@@ -265,6 +272,58 @@ void hll_flux(const ppmo_params &P, const R *sl, const R *sr, R *F) {
     R um_m = (sR * Ur[1] - sL * Ul[1] - (Fr[1] - Fl[1])) * id;
     F[FUB] = um_m / um_r;
   }
+}
+
+// HLLC flux (Sec. "Riemann Solvers and Fallback": HLL with the contact wave
+// restored), selected by PPMO_HLLC in place of the two-shock solver.  Outer
+// wave speeds as in hll_flux (Davis estimates); the contact speed S* follows
+// from the Rankine-Hugoniot conditions across the two outer waves with equal
+// pressure and normal velocity on both sides of the contact; the state
+// between an outer wave s_K and the contact is
+//   rho*_K = rho_K (s_K - u_K) / (s_K - S*),  u* = S*,  v*_t = v_t,K,
+//   E*_K = E_K + (S* - u_K) (S* + p_K / (rho_K (s_K - u_K))),
+// the internal energy riding with the density (e*_K = e_K); the flux at
+// x/t = 0 is that of the upwind side, F_K + s_K (U*_K - U_K) inside the fan.
+// The face velocity slot carries S*.
+template <class R>
+void hllc_flux(const ppmo_params &P, const R *sl, const R *sr, R *F) {
+  const double g = P.gamma;
+  R rl = sl[QR], ul = sl[QU], pl = sl[QP];
+  R rr = sr[QR], ur = sr[QU], pr = sr[QP];
+  R cl = sqrt(g * pl / rl), cr = sqrt(g * pr / rr);
+  R el = pl / ((g - 1.0) * rl), er = pr / ((g - 1.0) * rr);
+  R El = el + 0.5 * (ul * ul + sl[QV1] * sl[QV1] + sl[QV2] * sl[QV2]);
+  R Er = er + 0.5 * (ur * ur + sr[QV1] * sr[QV1] + sr[QV2] * sr[QV2]);
+  R sL = rmin<R>(ul - cl, ur - cr);
+  R sR = rmax<R>(ul + cl, ur + cr);
+  // the side whose state (or star state) sits at x/t = 0
+  R S = 0.0;
+  bool left;
+  if (sL >= 0.0) {
+    left = true;
+  } else if (sR <= 0.0) {
+    left = false;
+  } else {
+    R ml = rl * (sL - ul), mr = rr * (sR - ur);
+    S = (pr - pl + ml * ul - mr * ur) / (ml - mr);
+    left = S >= 0.0;
+  }
+  R rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
+  R v1K = left ? sl[QV1] : sr[QV1], v2K = left ? sl[QV2] : sr[QV2];
+  R EK = left ? El : Er, eK = left ? el : er, sK = left ? sL : sR;
+  R fr = rK * uK;
+  R Fk[6] = {fr, fr * uK + pK, fr * v1K, fr * v2K, uK * (rK * EK + pK), fr * eK};
+  if (sL >= 0.0 || sR <= 0.0) {
+    for (int k = 0; k < 6; ++k) F[k] = Fk[k];
+    F[FUB] = uK;
+    return;
+  }
+  R mK = rK * (sK - uK);
+  R rs = mK / (sK - S);
+  R Us[6] = {rs, rs * S, rs * v1K, rs * v2K, rs * (EK + (S - uK) * (S + pK / mK)), rs * eK};
+  R Uk[6] = {rK, rK * uK, rK * v1K, rK * v2K, rK * EK, rK * eK};
+  for (int k = 0; k < 6; ++k) F[k] = Fk[k] + sK * (Us[k] - Uk[k]);
+  F[FUB] = S;
 }
 
 // ---------------------------------------------------------------------------
@@ -760,6 +819,10 @@ void ppmo_two_shock(const ppmo_params *p, const double l[3], const double r[3], 
 
 void ppmo_hll_flux(const ppmo_params *p, const double l[5], const double r[5], double out[7]) {
   hll_flux<double>(*p, l, r, out);
+}
+
+void ppmo_hllc_flux(const ppmo_params *p, const double l[5], const double r[5], double out[7]) {
+  hllc_flux<double>(*p, l, r, out);
 }
 
 int ppmo_count_ops(ppmo_grid *G, const ppmo_params *P, double dt, int32_t order,

@@ -22,7 +22,13 @@
  * symmetry, 1-D embedded in 3-D, flux-register identity, the CFL definition,
  * the steepening and flattening thresholds, the dual-energy selection rules
  * (eta1 cold flow, eta2 neighbourhood maximum), the flux of a flattened shock
- * face, and the HLL fallback on a vacuum-forming rarefaction.
+ * face, and the HLL fallback on a vacuum-forming rarefaction.  The HLLC
+ * solver (flag PPMO_HLLC, in place of two-shock) is pinned by the
+ * Rankine-Hugoniot conditions across its outer waves and contact, exact
+ * isolated contacts (stationary and moving), consistency, supersonic
+ * upwinding, mirror symmetry, second-order agreement with the exact solution
+ * for weak waves and with two-shock on smooth flow, Sod E1 convergence, a
+ * stationary contact held to round-off and conservation.
  *
  * Parity unpinned (pinned only by these readings and by GPU == oracle):
  *   - the CW84 flattening slope omega_2 = 10 (f~ rises from 0 at a pressure
@@ -30,7 +36,10 @@
  *   - the HLL fallback's details: Davis wave-speed estimates, the face
  *     velocity of the HLL intermediate state in the p div v term, and the
  *     state given to a cell still non-positive after the fallback;
- *   - the Newton tolerance and iteration cap of the two-shock solver.
+ *   - the Newton tolerance and iteration cap of the two-shock solver;
+ *   - HLLC's outer wave speeds (the Davis estimates of the HLL fallback; the
+ *     paper names none) and the internal energy carried with the density
+ *     across its star states.
  *
  * Conventions (all host pointers, owned by the caller):
  *   - A grid has nx*ny*nz active cells and `ghost` ghost layers per side (3, as
@@ -60,7 +69,8 @@ enum {
   PPMO_STEEPEN = 1u,      /* CW84 contact steepening of the density parabola */
   PPMO_FLATTEN = 2u,      /* CW84 appendix shock flattening */
   PPMO_DUAL_ENERGY = 4u,  /* eta1 pressure selection and eta2 resync */
-  PPMO_FALLBACK_HLL = 8u  /* re-solve faces of non-positive cells with HLL */
+  PPMO_FALLBACK_HLL = 8u, /* re-solve faces of non-positive cells with HLL */
+  PPMO_HLLC = 16u         /* HLLC face fluxes instead of the two-shock solver */
 };
 
 typedef struct {
@@ -127,6 +137,13 @@ void ppmo_two_shock(const ppmo_params *p, const double left[3], const double rig
  * out = F_rho, F_u, F_v1, F_v2, F_E, F_e, face velocity. */
 void ppmo_hll_flux(const ppmo_params *p, const double left[5], const double right[5],
                    double out[7]);
+
+/* HLLC flux (Davis outer wave speeds, contact speed from the Rankine-Hugoniot
+ * conditions of the outer waves) on the same traced states and with the same
+ * output layout as ppmo_hll_flux; out[6] is the contact speed S* inside the
+ * wave fan, else the upwind normal velocity. */
+void ppmo_hllc_flux(const ppmo_params *p, const double left[5], const double right[5],
+                    double out[7]);
 
 /* Exact Riemann solution of the Euler equations (ideal gas) by bisection on
  * the pressure function; samples rho,u,p at x/t = xi[k].  star[0]=p*,
