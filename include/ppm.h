@@ -80,7 +80,11 @@ enum {
   PPM_FLATTEN = 2u,      /* shock flattening of all parabolas */
   PPM_DUAL_ENERGY = 4u,  /* eta1 pressure selection and eta2 resync of e */
   PPM_FALLBACK_HLL = 8u, /* re-solve the faces of non-positive cells with HLL */
-  PPM_ALL_FLAGS = 15u
+  PPM_ALL_FLAGS = 15u,   /* the four above: the paper's PPM with two-shock */
+  PPM_HLLC = 16u         /* face fluxes by the HLLC solver (Sec. "Riemann Solvers
+                            and Fallback"; Davis outer wave speeds, contact speed
+                            from the outer waves' jump conditions) instead of
+                            two-shock; the HLL fallback still applies */
 };
 
 /* One grid patch.  All pointers are device pointers owned by the caller. */

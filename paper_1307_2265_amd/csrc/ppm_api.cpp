@@ -94,7 +94,8 @@ ppm_status check_params(const ppm_params *p) {
   if (!(p->riemann_rtol > 0.0)) return fail(PPM_EINVAL, "riemann_rtol must be > 0");
   if (p->riemann_max_iter < 1 || p->riemann_max_iter > 1000)
     return fail(PPM_EINVAL, "riemann_max_iter must be in [1, 1000]");
-  if (p->flags & ~uint32_t(PPM_ALL_FLAGS)) return fail(PPM_EINVAL, "unknown flag bits 0x%x", p->flags);
+  if (p->flags & ~uint32_t(PPM_ALL_FLAGS | PPM_HLLC))
+    return fail(PPM_EINVAL, "unknown flag bits 0x%x", p->flags);
   return PPM_OK;
 }
 

@@ -170,10 +170,8 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
 #pragma unroll
   for (int k = 0; k < 7; ++k) F.f[k] = 0.0;
   if (face_ok) {
-    int iters;
-    F = two_shock_flux(P, double(sl.r), double(sl.u), double(sl.v1), double(sl.v2),
-                       double(sl.p), double(sr.r), double(sr.u), double(sr.v1), double(sr.v2),
-                       double(sr.p), iters);
+    F = riemann_flux(P, double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p),
+                     double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p));
   }
 
   // ---- provisional update of cell j (a0..a1)

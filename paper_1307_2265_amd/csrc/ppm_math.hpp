@@ -28,7 +28,7 @@ constexpr double kFlatOmega1 = 0.75;
 constexpr double kFlatOmega2 = 10.0;
 constexpr double kFlatEps = 0.33;
 
-enum : uint32_t { kSteepen = 1u, kFlatten = 2u, kDualEnergy = 4u, kFallbackHLL = 8u };
+enum : uint32_t { kSteepen = 1u, kFlatten = 2u, kDualEnergy = 4u, kFallbackHLL = 8u, kHLLC = 16u };
 
 struct Params {
   double gamma, cfl, eta1, eta2, rho_floor, p_floor, e_floor, riemann_rtol;
@@ -346,6 +346,68 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   F.f[5] = fr * eb;
   F.f[6] = ub;
   return F;
+}
+
+// HLLC flux (Sec. "Riemann Solvers and Fallback": HLL with the contact wave
+// restored), the solver kHLLC selects in place of two-shock.  Outer wave
+// speeds are the Davis estimates of the HLL fallback; the contact speed S*
+// follows from the Rankine-Hugoniot conditions across the two outer waves
+// with a common pressure and normal velocity at the contact; between outer
+// wave s_K and the contact the state is rho*_K = rho_K (s_K - u_K)/(s_K - S*),
+// u = S*, the transverse velocities and internal energy of side K, and
+// E*_K = E_K + (S* - u_K)(S* + p_K / (rho_K (s_K - u_K))).  The flux at
+// x/t = 0 is that of the upwind side, F_K + s_K (U*_K - U_K) inside the fan;
+// the face velocity slot carries S*.
+__device__ __forceinline__ Flux hllc_flux(const Params &P, double rl, double ul, double v1l,
+                                          double v2l, double pl, double rr, double ur,
+                                          double v1r, double v2r, double pr) {
+  const double g = P.gamma;
+  const double cl = dsqrt(ddiv(g * pl, rl)), cr = dsqrt(ddiv(g * pr, rr));
+  const double el = ddiv(pl, (g - 1.0) * rl), er = ddiv(pr, (g - 1.0) * rr);
+  const double El = el + 0.5 * (ul * ul + v1l * v1l + v2l * v2l);
+  const double Er = er + 0.5 * (ur * ur + v1r * v1r + v2r * v2r);
+  const double sL = vmin<double>(ul - cl, ur - cr);
+  const double sR = vmax<double>(ul + cl, ur + cr);
+  const bool fan = !(sL >= 0.0) && !(sR <= 0.0);
+  double S = 0.0;
+  bool left = sL >= 0.0;
+  if (fan) {
+    const double ml = rl * (sL - ul), mr = rr * (sR - ur);
+    S = ddiv(pr - pl + ml * ul - mr * ur, ml - mr);
+    left = S >= 0.0;
+  }
+  const double rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
+  const double v1K = left ? v1l : v1r, v2K = left ? v2l : v2r;
+  const double EK = left ? El : Er, eK = left ? el : er, sK = left ? sL : sR;
+  const double fr = rK * uK;
+  Flux F;
+  F.f[0] = fr;
+  F.f[1] = fr * uK + pK;
+  F.f[2] = fr * v1K;
+  F.f[3] = fr * v2K;
+  F.f[4] = uK * (rK * EK + pK);
+  F.f[5] = fr * eK;
+  F.f[6] = uK;
+  if (!fan) return F;
+  const double mK = rK * (sK - uK);
+  const double rs = ddiv(mK, sK - S);
+  F.f[0] = F.f[0] + sK * (rs - rK);
+  F.f[1] = F.f[1] + sK * (rs * S - rK * uK);
+  F.f[2] = F.f[2] + sK * (rs * v1K - rK * v1K);
+  F.f[3] = F.f[3] + sK * (rs * v2K - rK * v2K);
+  F.f[4] = F.f[4] + sK * (rs * (EK + (S - uK) * (S + ddiv(pK, mK))) - rK * EK);
+  F.f[5] = F.f[5] + sK * (rs * eK - rK * eK);
+  F.f[6] = S;
+  return F;
+}
+
+// The face flux of the selected solver: two-shock, or HLLC with kHLLC.
+__device__ __forceinline__ Flux riemann_flux(const Params &P, double rl, double ul, double v1l,
+                                             double v2l, double pl, double rr, double ur,
+                                             double v1r, double v2r, double pr) {
+  if (P.flags & kHLLC) return hllc_flux(P, rl, ul, v1l, v2l, pl, rr, ur, v1r, v2r, pr);
+  int iters;
+  return two_shock_flux(P, rl, ul, v1l, v2l, pl, rr, ur, v1r, v2r, pr, iters);
 }
 
 // HLL flux with Davis wave speeds (the fallback solver).

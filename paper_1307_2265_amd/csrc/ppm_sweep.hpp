@@ -366,11 +366,10 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     for (int j = 0; j < 7; ++j) ft_c.f[j] = 0.0;
     double *slot_c = lds_slots + (k & 1) * kSlotDoubles * slot_stride;
     if (r - 1 >= a0 - 1 && r - 1 <= a1) {
-      int iters;
-      ft_c = two_shock_flux(P, double(lcarry.r), double(lcarry.u), double(lcarry.v1),
-                            double(lcarry.v2), double(lcarry.p), double(rstate.r),
-                            double(rstate.u), double(rstate.v1), double(rstate.v2),
-                            double(rstate.p), iters);
+      ft_c = riemann_flux(P, double(lcarry.r), double(lcarry.u), double(lcarry.v1),
+                          double(lcarry.v2), double(lcarry.p), double(rstate.r),
+                          double(rstate.u), double(rstate.v1), double(rstate.v2),
+                          double(rstate.p));
       if (fallback) {
         slot_c[0 * slot_stride] = double(lcarry.r);
         slot_c[1 * slot_stride] = double(lcarry.u);

@@ -390,7 +390,7 @@ def test_config3_full_batch_in_bench_configuration(P, O, prec):
             assert num[f] / den[f] <= 1e-5
 
 
-def _batch(P, O, npatch, seed, prec, tiles=None, steps=1, flat=True):
+def _batch(P, O, npatch, seed, prec, tiles=None, steps=1, flat=True, flags=None):
     """Run a batch of uneven patches on the GPU and patch by patch on the oracle.
     flat: patches as views into shared field arrays (the marching sweeps may
     then span patches), else one allocation per patch field."""
@@ -404,9 +404,10 @@ def _batch(P, O, npatch, seed, prec, tiles=None, steps=1, flat=True):
     else:
         patches = [to_device(f, prec, dx=(sp.dx,) * 3, level=sp.level, with_reg=True)
                    for f, sp in zip(fields, specs)]
-    plan = P.Plan(patches, nlev, prec, P.params(), tile_config=tiles)
+    gprm = P.params() if flags is None else P.params(flags=flags)
+    plan = P.Plan(patches, nlev, prec, gprm, tile_config=tiles)
     dt = _dt_tensor(nlev)
-    prm = O.params()
+    prm = O.params() if flags is None else O.params(flags=flags)
     grids = [oracle_grid(O, f, dx=(sp.dx,) * 3, with_reg=True) for f, sp in zip(fields, specs)]
     ocnt = [0, 0]
     dts_g, dts_o = [], []

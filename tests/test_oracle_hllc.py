@@ -243,3 +243,33 @@ def test_hllc_and_two_shock_agree_on_smooth_flow(O):
         diffs.append(np.max(np.abs(out["ts"] - out["hllc"])))
     assert 0.0 < diffs[1] < 1e-9, diffs
     assert diffs[0] / diffs[1] > 50, diffs
+
+
+@pytest.mark.parametrize("v,p0,dt", [(4.0, 0.4, 0.0015), (20.0, 0.01, 0.0004)])
+def test_hllc_keeps_vacuum_forming_rarefactions_positive(O, v, p0, dt):
+    # HLL-type fluxes with outer speeds that bound the waves keep density and
+    # pressure positive; on a double rarefaction strong enough that the
+    # two-shock update goes non-positive (and needs the HLL fallback), HLLC
+    # needs no fallback.
+    from tests.helpers import FIELDS, oracle_grid
+    nx, ny, nz = 4, 100, 3
+    shape = (nz + 6, ny + 6, nx + 6)
+    y = (np.arange(ny + 6) - G3 + 0.5) / ny
+    vy = np.broadcast_to(np.where(y < 0.5, -v, v)[None, :, None], shape).copy()
+    z = np.zeros(shape)
+    st = W.stored_from_primitive(np.ones(shape), z, vy, z.copy(), np.full(shape, p0), G)
+    d = dict(zip(FIELDS, [np.ascontiguousarray(a) for a in st]))
+    counts = {}
+    for name, fl in (("two-shock", O.ALL_FLAGS), ("hllc", O.ALL_FLAGS | O.HLLC)):
+        Gr = oracle_grid(O, d, dx=(0.25, 0.01, 1.0 / 3.0))
+        prm = O.params(gamma=G, flags=fl)
+        tot = [0, 0]
+        for _ in range(16):
+            c = O.step(Gr, prm, dt, 0)
+            tot[0] += c.fallback_faces
+            tot[1] += c.floored_cells
+        counts[name] = tot
+        if name == "hllc":
+            assert np.all(Gr.rho > 0) and np.all(Gr.eint > 0)
+    assert counts["two-shock"][0] > 0, counts
+    assert counts["hllc"] == [0, 0], counts
