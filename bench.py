@@ -10,7 +10,8 @@ first step's timestep is reduced before the timed region.  Inputs are
 synthetic and resident in HBM when the timed region starts; launch shapes
 come from the autotuner's table (data/tiles.json) when it exists.
 
-Also measured: the batched form -- 4096 uneven AMR patches (dims from
+Also measured: the same grid and steps with the HLLC solver in place of
+two-shock (FP64 and mixed); the batched form -- 4096 uneven AMR patches (dims from
 {8,12,16,24,32}, levels 0-6 with their own dt, seeded ghosts, flux registers
 on) advanced by replaying one captured HIP graph per step (the three sweeps
 and the next timestep) -- and its rate relative to the single grid.
@@ -61,6 +62,7 @@ def parse():
                     help="steps the CPU oracle advances")
     ap.add_argument("--tiles", default=None, help="tile_config of the single-grid plans")
     ap.add_argument("--batch-tiles", default=None, help="tile_config of the batch plans")
+    ap.add_argument("--no-hllc", action="store_true", help="skip the HLLC-solver runs")
     return ap.parse_args()
 
 
@@ -119,7 +121,8 @@ def main():
     d = H.single_grid_input(n)
     log(f"generated {n}^3 input in {time.time() - t0:.1f}s")
     with open(os.path.join(ROOT, "paper_1307_2265_amd", "data", "algorithmic_ops.json")) as f:
-        ops = json.load(f)["shocked"]["per_cell_sweep"]
+        all_ops = json.load(f)
+    ops = all_ops["shocked"]["per_cell_sweep"]
 
     # ---- single grid, FP64 and mixed
     results, runs = {}, {}
@@ -153,6 +156,31 @@ def main():
         r.close()
     del runs
     torch.cuda.empty_cache()
+
+    # ---- the same grid and steps with the HLLC solver in place of two-shock
+    hllc = None
+    if not args.no_hllc:
+        hllc = {"flags": "PPM_ALL_FLAGS | PPM_HLLC"}
+        for name, prec in (("fp64", ppm.PPM_FP64), ("mixed", ppm.PPM_MIXED)):
+            if name == "mixed" and args.no_mixed:
+                continue
+            tiles = args.tiles or autotune.best_tiles(f"single/{name}")
+            r = H.Run.single(d, n, prec, tiles, flags=ppm.PPM_ALL_FLAGS | ppm.PPM_HLLC)
+            for s in range(Wm):
+                r.step(s)
+            torch.cuda.synchronize()
+            r.reset()
+            r.plan.ppm_event_counts(reset=True)
+            total, hk = r.timed(K, per_sweep=True)
+            fb, fl = r.plan.ppm_event_counts()
+            hllc[name] = {"value": cells * K / total, "unit": "cell-updates/s",
+                          "ms_per_step": total / K * 1e3, "tiles": tiles,
+                          "sweep_kernel_ms": {k: v * 1e3 for k, v in hk.items()},
+                          "speedup_vs_two_shock": results[name]["seconds"] / total,
+                          "events": {"fallback_faces": fb, "floored_cells": fl}}
+            log(f"hllc {name}: {cells * K / total / 1e9:.3f} G cell-updates/s")
+            r.close()
+        torch.cuda.empty_cache()
 
     # ---- batch of uneven patches, one captured graph per step
     batch = None
@@ -237,6 +265,15 @@ def main():
     intensity = flops_launch / bytes_launch
     ridge = FP64_OP_PEAK_T * 1e12 / (HBM_PEAK_GBS * 1e9)
     roofline, other = (alu, hbm) if intensity > ridge else (hbm, alu)
+    if hllc is not None and "march" in hllc["fp64"]["sweep_kernel_ms"]:
+        # the same marching sweeps with the HLLC flux: their own operation count
+        hops = all_ops["shocked_hllc"]["per_cell_sweep"]["flops"]
+        sw_h = hllc["fp64"]["sweep_kernel_ms"]["march"] / 1e3
+        fl_h = mean_pencils * n * hops
+        hllc["fp64"]["roofline"] = dict(
+            bound="alu", achieved=fl_h / sw_h / 1e12, peak=FP64_OP_PEAK_T, unit="TFLOP/s",
+            frac=fl_h / sw_h / 1e12 / FP64_OP_PEAK_T, kernel=kname.split(" + ")[0],
+            algorithmic_flops=fl_h, launch_ms=sw_h * 1e3, ops_per_cell_sweep=hops)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -277,6 +314,8 @@ def main():
                          "sweep_kernel_ms": {k: v * 1e3 for k, v in mx["kern"].items()},
                          "l1_rel_vs_fp64": l1, "speedup_vs_fp64": mx["rate"] / fp["rate"],
                          "tiles": mx["tiles"]}
+    if hllc is not None:
+        line["hllc"] = hllc
     if batch is not None:
         line["batch"] = batch
     if cpu is not None:

@@ -23,11 +23,11 @@ from paper_1307_2265_amd import workloads as W  # noqa: E402
 OUT = os.path.join(ROOT, "paper_1307_2265_amd", "data", "algorithmic_ops.json")
 
 
-def count(recipe, n, seed):
+def count(recipe, n, seed, flags=O.ALL_FLAGS):
     d = W.random_grid(n, n, n, seed, recipe)
     G = O.Grid(**d, dx=1.0 / n, dy=1.0 / n, dz=1.0 / n)
     O.fill_periodic(G)
-    prm = O.params()
+    prm = O.params(flags=flags)
     dt = O.cfl_dt(G, prm)
     ops = O.count_ops(G, prm, dt, 0)
     cs = ops["cell_sweeps"]
@@ -39,9 +39,11 @@ def count(recipe, n, seed):
 def main():
     res = {
         "note": "FP64 operations per cell-sweep of one step, from the oracle's counting "
-                "scalar; flops = add + mul + div + sqrt",
+                "scalar; flops = add + mul + div + sqrt; shocked_hllc: the HLLC solver in "
+                "place of two-shock",
         "gentle": count(W.GENTLE, 48, 1000),
         "shocked": count(W.SHOCKED, 48, 1002),
+        "shocked_hllc": count(W.SHOCKED, 48, 1002, O.ALL_FLAGS | O.HLLC),
     }
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     with open(OUT, "w") as f:

@@ -34,10 +34,12 @@ class Run:
     """Patches, plan and per-level dt array of one workload on the device."""
 
     def __init__(self, host_fields: list, specs: list, prec: int, nlevels: int, periodic: bool,
-                 tiles: str | None = None, with_reg: bool = False, ghost: int = W.GHOST):
+                 tiles: str | None = None, with_reg: bool = False, ghost: int = W.GHOST,
+                 flags: int | None = None):
         torch = _torch()
         low = torch.float32 if prec == ppm.PPM_MIXED else torch.float64
         self.prec, self.periodic, self.tiles, self.nlevels = prec, periodic, tiles, nlevels
+        self.params = ppm.params() if flags is None else ppm.params(flags=flags)
         sizes = [f["rho"].size for f in host_fields]
         offs = np.concatenate([[0], np.cumsum(sizes)])
         self.flat = {}
@@ -60,15 +62,15 @@ class Run:
             self.patches.append(ppm.Patch(**views, dx=dx, dy=dx, dz=dx, ghost=ghost,
                                           level=level, flux_reg=reg))
         self.cells = int(sum(s[0] * s[1] * s[2] for s in specs))
-        self.plan = ppm.Plan(self.patches, nlevels, prec, ppm.params(), tile_config=tiles)
+        self.plan = ppm.Plan(self.patches, nlevels, prec, self.params, tile_config=tiles)
         self.dt = torch.zeros(nlevels, dtype=torch.float64, device="cuda")
         self.graphs = None
         self.dt_valid = False
 
     # -- construction helpers -------------------------------------------------
     @classmethod
-    def single(cls, d: dict, n: int, prec: int, tiles=None):
-        return cls([d], [(n, n, n, 0, 1.0 / n)], prec, 1, True, tiles)
+    def single(cls, d: dict, n: int, prec: int, tiles=None, flags=None):
+        return cls([d], [(n, n, n, 0, 1.0 / n)], prec, 1, True, tiles, flags=flags)
 
     @classmethod
     def batch(cls, specs: list, fields: list, prec: int, tiles=None, nlevels=7):
@@ -83,7 +85,8 @@ class Run:
             self.graphs = None
         self.plan.close()
         self.tiles = tiles
-        self.plan = ppm.Plan(self.patches, self.nlevels, self.prec, ppm.params(), tile_config=tiles)
+        self.plan = ppm.Plan(self.patches, self.nlevels, self.prec, self.params,
+                             tile_config=tiles)
 
     # -- stepping -------------------------------------------------------------
     def reset(self):
