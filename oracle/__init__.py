@@ -89,6 +89,7 @@ def lib():
         L.ppmo_cfl_dt.restype = C.c_double
         L.ppmo_cfl_dt.argtypes = [C.POINTER(_Grid), C.POINTER(Params)]
         L.ppmo_fill_periodic.argtypes = [C.POINTER(_Grid)]
+        L.ppmo_fill_boundary.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32), dp]
         L.ppmo_two_shock.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.ppmo_hll_flux.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.ppmo_hllc_flux.argtypes = [C.POINTER(Params), dp, dp, dp]
@@ -192,6 +193,21 @@ def cfl_signal_max(grid: Grid, prm: Params) -> float:
 def cfl_dt(grid: Grid, prm: Params) -> float:
     g = grid._c()
     return float(lib().ppmo_cfl_dt(C.byref(g), C.byref(prm)))
+
+
+FACE_PERIODIC, FACE_REFLECTING, FACE_OUTFLOW, FACE_INFLOW = 0, 1, 2, 3
+
+
+def fill_boundary(grid: Grid, kinds, inflow=None) -> None:
+    """Ghost fill by per-face boundary conditions (faces -x,+x,-y,+y,-z,+z);
+    inflow: [6 faces][rho, vx, vy, vz, etot, eint] for INFLOW faces."""
+    k = (C.c_int32 * 6)(*[int(v) for v in kinds])
+    inf = None
+    if inflow is not None:
+        inf = np.ascontiguousarray(inflow, dtype=np.float64).reshape(36)
+    g = grid._c()
+    if lib().ppmo_fill_boundary(C.byref(g), k, None if inf is None else _ptr(inf)) != 0:
+        raise ValueError("ppmo_fill_boundary: invalid argument")
 
 
 def fill_periodic(grid: Grid) -> None:

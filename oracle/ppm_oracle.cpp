@@ -811,6 +811,58 @@ int ppmo_fill_periodic(ppmo_grid *G) {
   return 0;
 }
 
+int ppmo_fill_boundary(ppmo_grid *G, const int32_t kinds[6], const double *inflow) {
+  if (!G || !kinds || G->nx < 1 || G->ny < 1 || G->nz < 1 || G->ghost < 0) return -1;
+  const int g = G->ghost;
+  const int N[3] = {G->nx, G->ny, G->nz};
+  for (int a = 0; a < 3; ++a) {
+    for (int s = 0; s < 2; ++s) {
+      const int k = kinds[2 * a + s];
+      if (k < PPMO_FACE_PERIODIC || k > PPMO_FACE_INFLOW) return -1;
+      if (k == PPMO_FACE_INFLOW && !inflow) return -1;
+      if (k == PPMO_FACE_REFLECTING && N[a] < g) return -1;
+    }
+    if ((kinds[2 * a] == PPMO_FACE_PERIODIC) != (kinds[2 * a + 1] == PPMO_FACE_PERIODIC)) return -1;
+  }
+  const int64_t n[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
+  double *f[6] = {G->rho, G->vx, G->vy, G->vz, G->etot, G->eint};
+  // Axis by axis: axis a over its ghost layers, the axes before it over
+  // their whole extent (ghosts already filled), the axes after it over their
+  // active range.
+  for (int a = 0; a < 3; ++a) {
+    int lo[3], hi[3];
+    for (int b = 0; b < 3; ++b) {
+      lo[b] = b < a ? 0 : g;
+      hi[b] = b < a ? int(n[b]) : g + N[b];
+    }
+    lo[a] = 0;
+    hi[a] = int(n[a]);
+    for (int z = lo[2]; z < hi[2]; ++z)
+      for (int y = lo[1]; y < hi[1]; ++y)
+        for (int x = lo[0]; x < hi[0]; ++x) {
+          int c[3] = {x, y, z};
+          const int ca = c[a];
+          if (ca >= g && ca < g + N[a]) continue;  // active along a
+          const int side = ca < g ? 0 : 1;
+          const int kind = kinds[2 * a + side];
+          const int64_t dst = (int64_t(z) * n[1] + y) * n[0] + x;
+          if (kind == PPMO_FACE_INFLOW) {
+            for (int q = 0; q < 6; ++q) f[q][dst] = inflow[(2 * a + side) * 6 + q];
+            continue;
+          }
+          int sc;
+          if (kind == PPMO_FACE_PERIODIC) sc = g + (((ca - g) % N[a]) + N[a]) % N[a];
+          else if (kind == PPMO_FACE_REFLECTING) sc = side == 0 ? 2 * g - 1 - ca : 2 * (g + N[a]) - 1 - ca;
+          else sc = side == 0 ? g : g + N[a] - 1;  // outflow: the edge cell
+          c[a] = sc;
+          const int64_t src = (int64_t(c[2]) * n[1] + c[1]) * n[0] + c[0];
+          for (int q = 0; q < 6; ++q) f[q][dst] = f[q][src];
+          if (kind == PPMO_FACE_REFLECTING) f[1 + a][dst] = -f[1 + a][src];
+        }
+  }
+  return 0;
+}
+
 void ppmo_two_shock(const ppmo_params *p, const double l[3], const double r[3], double out[7]) {
   RiemannOut<double> o = two_shock<double>(*p, l[0], l[1], l[2], r[0], r[1], r[2]);
   out[0] = o.ps; out[1] = o.us; out[2] = o.rho; out[3] = o.u; out[4] = o.p;

@@ -28,7 +28,11 @@
  * isolated contacts (stationary and moving), consistency, supersonic
  * upwinding, mirror symmetry, second-order agreement with the exact solution
  * for weak waves and with two-shock on smooth flow, Sod E1 convergence, a
- * stationary contact held to round-off and conservation.
+ * stationary contact held to round-off and conservation.  The domain
+ * boundary fill (ppmo_fill_boundary) is pinned by: periodic faces equal to
+ * the periodic fill; reflecting walls evolving bit for bit as half of the
+ * mirrored periodic box of twice the size; Sod between outflow faces against
+ * the exact solution; uniform inflow-to-outflow flow staying uniform.
  *
  * Parity unpinned (pinned only by these readings and by GPU == oracle):
  *   - the CW84 flattening slope omega_2 = 10 (f~ rises from 0 at a pressure
@@ -125,6 +129,23 @@ double ppmo_cfl_dt(const ppmo_grid *g, const ppmo_params *p);
 
 /* Periodic ghost fill of all six fields: q(ghost i) = q(active image of i). */
 int ppmo_fill_periodic(ppmo_grid *g);
+
+/* Domain boundary conditions of a grid face (Sec. "Boundary conditions"). */
+enum {
+  PPMO_FACE_PERIODIC = 0,   /* the image across the domain */
+  PPMO_FACE_REFLECTING = 1, /* mirror image, normal velocity reversed */
+  PPMO_FACE_OUTFLOW = 2,    /* copy of the edge cell */
+  PPMO_FACE_INFLOW = 3      /* fixed values */
+};
+
+/* Ghost fill by per-face boundary conditions, faces -x,+x,-y,+y,-z,+z.
+ * Axes are filled in order x, y, z; axis a covers its ghost layers, the axes
+ * filled before it over their whole extent and the later axes over their
+ * active range, so edges and corners compose the faces' rules.  inflow
+ * (nullable unless a face is INFLOW): [face][rho, vx, vy, vz, etot, eint].
+ * Periodic faces come in pairs; a reflecting axis needs at least `ghost`
+ * active cells.  Returns -1 on an invalid argument. */
+int ppmo_fill_boundary(ppmo_grid *g, const int32_t kinds[6], const double *inflow);
 
 /* Two-shock Riemann solver on (rho,u,p) left/right states.
  * out[0]=p*, out[1]=u*, out[2..4] = sampled (rho,u,p) at x/t=0,
