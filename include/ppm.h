@@ -165,6 +165,27 @@ ppm_status ppm_plan_destroy(ppm_plan *plan);
  * are not touched. */
 ppm_status ppm_fill_periodic(ppm_plan *plan, void *hip_stream);
 
+/* Domain boundary conditions of a face (Sec. "Boundary conditions"). */
+typedef enum {
+  PPM_FACE_PERIODIC = 0,   /* q(ghost) = q(the image across the patch) */
+  PPM_FACE_REFLECTING = 1, /* mirror image about the face, normal velocity reversed */
+  PPM_FACE_OUTFLOW = 2,    /* copy of the edge cell */
+  PPM_FACE_INFLOW = 3      /* fixed values */
+} ppm_face_kind;
+
+/* Ghost fill of patch `patch` of the plan (any bc) by per-face domain
+ * boundary conditions: kinds[6] (host) for the faces -x,+x,-y,+y,-z,+z;
+ * inflow (host, nullable unless a face is PPM_FACE_INFLOW) holds
+ * [face][rho, vx, vy, vz, etot, eint] (copied at the call; narrowed to the
+ * field precision).  The result is that of filling the axes in order x, y,
+ * z, each over the whole extent of the axes before it and the active range of
+ * the axes after it, so edges and corners compose the faces' rules.
+ * PPM_EINVAL (nothing launched) for a bad patch index or kind, a periodic
+ * face whose opposite face is not periodic, a reflecting axis with fewer
+ * active cells than ghost layers, or inflow faces without values. */
+ppm_status ppm_fill_boundary(ppm_plan *plan, int32_t patch, const int32_t *kinds,
+                             const double *inflow, void *hip_stream);
+
 /* Hydro CFL timestep per level (Sec. "Timestepping"):
  *   dt_dev[l] = cfl / max over the active cells of the level's patches of
  *               sum_d (c_s + |v_d|) / dx_d,

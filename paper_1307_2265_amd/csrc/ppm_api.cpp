@@ -504,6 +504,36 @@ ppm_status ppm_fill_periodic(ppm_plan *plan, void *hip_stream) {
   return PPM_OK;
 }
 
+ppm_status ppm_fill_boundary(ppm_plan *plan, int32_t patch, const int32_t *kinds,
+                             const double *inflow, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (patch < 0 || patch >= plan->npatch)
+    return fail(PPM_EINVAL, "patch %d outside [0, %d)", patch, plan->npatch);
+  if (!kinds) return fail(PPM_EINVAL, "kinds is NULL");
+  const PatchDev &pd = plan->host[patch];
+  ppm::FaceRules fr{};
+  for (int f = 0; f < 6; ++f) {
+    const int32_t k = kinds[f];
+    if (k < PPM_FACE_PERIODIC || k > PPM_FACE_INFLOW)
+      return fail(PPM_EINVAL, "face %d: unknown boundary kind %d", f, k);
+    if (k == PPM_FACE_INFLOW && !inflow)
+      return fail(PPM_EINVAL, "face %d is PPM_FACE_INFLOW but inflow is NULL", f);
+    if (k == PPM_FACE_REFLECTING && pd.n[f / 2] < pd.ghost)
+      return fail(PPM_EINVAL, "face %d: reflecting needs at least %d active cells", f, pd.ghost);
+    fr.kind[f] = k;
+    if (k == PPM_FACE_INFLOW)
+      for (int q = 0; q < 6; ++q) fr.inflow[f][q] = inflow[f * 6 + q];
+  }
+  for (int a = 0; a < 3; ++a)
+    if ((kinds[2 * a] == PPM_FACE_PERIODIC) != (kinds[2 * a + 1] == PPM_FACE_PERIODIC))
+      return fail(PPM_EINVAL, "axis %d: periodic faces come in pairs", a);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = plan->prec == PPM_FP64 ? ppm::launch_fill_boundary<ppm::PrecF64>(pd, fr, s)
+                                        : ppm::launch_fill_boundary<ppm::PrecMixed>(pd, fr, s);
+  if (e != hipSuccess) return hip_fail(e, "fill_boundary launch");
+  return PPM_OK;
+}
+
 ppm_status ppm_cfl_dt(ppm_plan *plan, double *dt_dev, void *hip_stream) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");

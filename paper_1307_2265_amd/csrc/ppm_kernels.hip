@@ -21,7 +21,8 @@
 //     device-wide max by atomicMax on the bit pattern of the non-negative
 //     double; the finalise kernel turns the max into dt and clears it.
 //   * fill_periodic_kernel: periodic ghost fill of one patch over its ghost
-//     shell only.
+//     shell only; fill_boundary_kernel: the same shell by per-face domain
+//     boundary conditions.
 #include "ppm_kernels.hpp"
 #include "ppm_lanes.hpp"
 
@@ -330,6 +331,101 @@ __global__ void cfl_finalize_kernel(int32_t nlevels, double cfl,
 }
 
 // ---------------------------------------------------------------------------
+// Ghost shell of a patch, cell t of shell_cells(): the two z slabs (full x,
+// y), the two y slabs of the active z range (full x), then the two x slabs of
+// the active y, z range.  False past the end.
+__device__ __forceinline__ bool shell_cell(int g, const int64_t (&N)[3], const int64_t (&nf)[3],
+                                           int64_t t, int64_t (&c)[3]) {
+  const int64_t sz = 2 * g * nf[1] * nf[0];
+  const int64_t sy = N[2] * 2 * g * nf[0];
+  const int64_t sx = N[2] * N[1] * 2 * g;
+  if (t >= sz + sy + sx) return false;
+  if (t < sz) {
+    c[0] = t % nf[0];
+    c[1] = (t / nf[0]) % nf[1];
+    const int64_t k = t / (nf[0] * nf[1]);
+    c[2] = k < g ? k : N[2] + k;
+  } else if (t < sz + sy) {
+    const int64_t u = t - sz;
+    c[0] = u % nf[0];
+    const int64_t j = (u / nf[0]) % (2 * g);
+    c[1] = j < g ? j : N[1] + j;
+    c[2] = g + u / (nf[0] * 2 * g);
+  } else {
+    const int64_t u = t - sz - sy;
+    const int64_t i = u % (2 * g);
+    c[0] = i < g ? i : N[0] + i;
+    c[1] = g + (u / (2 * g)) % N[1];
+    c[2] = g + u / (2 * g * N[1]);
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Domain boundary fill of one patch (Sec. "Boundary conditions"): per face
+// periodic, reflecting (mirror image, normal velocity reversed), outflow
+// (copy of the edge cell) or inflow (fixed values).  The definition fills
+// the axes in order x, y, z, each over the whole extent of the axes before it
+// and the active range of the axes after it; a ghost cell is therefore
+// written by its highest ghost axis from the cell that axis's rule points to,
+// which is written the same way by its own highest ghost axis.  Each thread
+// unrolls that chain for one shell cell: axes from z down to x, each ghost
+// coordinate mapped by its face's rule (velocity flips collected on the
+// way), an inflow face ending the chain with its values.
+template <class Prec>
+__global__ void __launch_bounds__(256)
+fill_boundary_kernel(PatchDev pd, FaceRules fr) {
+  using S = typename Prec::S;
+  const int g = pd.ghost;
+  const int64_t N[3] = {pd.n[0], pd.n[1], pd.n[2]};
+  const int64_t nf[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
+  int64_t c[3];
+  if (!shell_cell(g, N, nf, int64_t(blockIdx.x) * blockDim.x + threadIdx.x, c)) return;
+  int64_t sc[3] = {c[0], c[1], c[2]};
+  bool flip[3] = {false, false, false};
+  int inflow = -1;
+  for (int a = 2; a >= 0; --a) {
+    if (sc[a] >= g && sc[a] < g + N[a]) continue;
+    const int side = sc[a] < g ? 0 : 1;
+    const int kind = fr.kind[2 * a + side];
+    if (kind == kFaceInflow) {
+      inflow = 2 * a + side;
+      break;
+    }
+    if (kind == kFacePeriodic) {
+      sc[a] = g + (((sc[a] - g) % N[a]) + N[a]) % N[a];
+    } else if (kind == kFaceReflecting) {
+      sc[a] = side == 0 ? 2 * g - 1 - sc[a] : 2 * (g + N[a]) - 1 - sc[a];
+      flip[a] = true;
+    } else {
+      sc[a] = side == 0 ? g : g + N[a] - 1;
+    }
+  }
+  S *rho = static_cast<S *>(pd.rho);
+  S *vel[3] = {static_cast<S *>(pd.vel[0]), static_cast<S *>(pd.vel[1]),
+               static_cast<S *>(pd.vel[2])};
+  const int64_t dst = (c[2] * nf[1] + c[1]) * nf[0] + c[0];
+  S r, v[3];
+  double E, e;
+  if (inflow >= 0) {
+    r = S(fr.inflow[inflow][0]);
+    for (int a = 0; a < 3; ++a) v[a] = S(fr.inflow[inflow][1 + a]);
+    E = fr.inflow[inflow][4];
+    e = fr.inflow[inflow][5];
+  } else {
+    const int64_t src = (sc[2] * nf[1] + sc[1]) * nf[0] + sc[0];
+    r = rho[src];
+    for (int a = 0; a < 3; ++a) v[a] = vel[a][src];
+    E = pd.etot[src];
+    e = pd.eint[src];
+  }
+  rho[dst] = r;
+  for (int a = 0; a < 3; ++a) vel[a][dst] = flip[a] ? -v[a] : v[a];
+  pd.etot[dst] = E;
+  pd.eint[dst] = e;
+}
+
+// ---------------------------------------------------------------------------
 // Periodic ghost fill of one patch: only ghost cells are visited.  The shell
 // is split into the two z slabs (full x, y), the two y slabs of the active z
 // range (full x), and the two x slabs of the active y, z range.
@@ -341,30 +437,9 @@ fill_periodic_kernel(PatchDev pd) {
   const int g = pd.ghost;
   const int64_t N[3] = {pd.n[0], pd.n[1], pd.n[2]};
   const int64_t nf[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
-  const int64_t sz = 2 * g * nf[1] * nf[0];
-  const int64_t sy = N[2] * 2 * g * nf[0];
-  const int64_t sx = N[2] * N[1] * 2 * g;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= sz + sy + sx) return;
-  int64_t x, y, z;
-  if (t < sz) {
-    x = t % nf[0];
-    y = (t / nf[0]) % nf[1];
-    const int64_t k = t / (nf[0] * nf[1]);
-    z = k < g ? k : N[2] + k;
-  } else if (t < sz + sy) {
-    const int64_t u = t - sz;
-    x = u % nf[0];
-    const int64_t j = (u / nf[0]) % (2 * g);
-    y = j < g ? j : N[1] + j;
-    z = g + u / (nf[0] * 2 * g);
-  } else {
-    const int64_t u = t - sz - sy;
-    const int64_t i = u % (2 * g);
-    x = i < g ? i : N[0] + i;
-    y = g + (u / (2 * g)) % N[1];
-    z = g + u / (2 * g * N[1]);
-  }
+  int64_t c[3];
+  if (!shell_cell(g, N, nf, int64_t(blockIdx.x) * blockDim.x + threadIdx.x, c)) return;
+  const int64_t x = c[0], y = c[1], z = c[2];
   auto wrap = [&](int64_t i, int d) { return g + (((i - g) % N[d]) + N[d]) % N[d]; };
   const int64_t dst = (z * nf[1] + y) * nf[0] + x;
   const int64_t src = (wrap(z, 2) * nf[1] + wrap(y, 1)) * nf[0] + wrap(x, 0);
@@ -483,6 +558,17 @@ hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32
 }
 
 template <class Prec>
+hipError_t launch_fill_boundary(const PatchDev &pd, const FaceRules &fr, hipStream_t s) {
+  const int64_t g = pd.ghost;
+  const int64_t N[3] = {pd.n[0], pd.n[1], pd.n[2]};
+  const int64_t nf[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
+  const int64_t total = 2 * g * nf[1] * nf[0] + N[2] * 2 * g * nf[0] + N[2] * N[1] * 2 * g;
+  const int64_t blocks = (total + 255) / 256;
+  hipLaunchKernelGGL(fill_boundary_kernel<Prec>, dim3(unsigned(blocks)), dim3(256), 0, s, pd, fr);
+  return hipGetLastError();
+}
+
+template <class Prec>
 hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
   const int64_t g = pd.ghost;
   const int64_t N[3] = {pd.n[0], pd.n[1], pd.n[2]};
@@ -524,5 +610,9 @@ template hipError_t launch_cfl<PrecMixed>(const PatchDev *, const int32_t *, int
                                           double *, hipStream_t);
 template hipError_t launch_fill<PrecF64>(const PatchDev &, hipStream_t);
 template hipError_t launch_fill<PrecMixed>(const PatchDev &, hipStream_t);
+template hipError_t launch_fill_boundary<PrecF64>(const PatchDev &, const FaceRules &,
+                                                  hipStream_t);
+template hipError_t launch_fill_boundary<PrecMixed>(const PatchDev &, const FaceRules &,
+                                                    hipStream_t);
 
 }  // namespace ppm

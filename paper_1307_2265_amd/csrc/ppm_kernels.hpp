@@ -60,4 +60,16 @@ hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32
 template <class Prec>
 hipError_t launch_fill(const PatchDev &pd, hipStream_t s);
 
+// Domain boundary conditions of the six faces (-x,+x,-y,+y,-z,+z) of a patch,
+// and the values of inflow faces (rho, vx, vy, vz, etot, eint).
+enum : int32_t { kFacePeriodic = 0, kFaceReflecting = 1, kFaceOutflow = 2, kFaceInflow = 3 };
+struct FaceRules {
+  int32_t kind[6];
+  double inflow[6][6];
+};
+
+// Ghost fill of one patch by per-face boundary conditions.
+template <class Prec>
+hipError_t launch_fill_boundary(const PatchDev &pd, const FaceRules &fr, hipStream_t s);
+
 }  // namespace ppm

@@ -22,6 +22,7 @@ PPM_HLLC = 16  # HLLC face fluxes instead of two-shock
 ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
 PPM_GRAPH_FILL, PPM_GRAPH_CFL, PPM_GRAPH_STEP, PPM_GRAPH_STEP_CFL = 1, 2, 4, 8
 PPM_BC_PERIODIC, PPM_BC_SUPPLIED = 0, 1
+PPM_FACE_PERIODIC, PPM_FACE_REFLECTING, PPM_FACE_OUTFLOW, PPM_FACE_INFLOW = 0, 1, 2, 3
 
 # Every function the header declares, with (restype, argtypes).
 _vp = C.c_void_p
@@ -48,6 +49,8 @@ SIGNATURES = {
                                   C.c_int, C.POINTER(ppm_params), C.c_char_p, _vp]),
     "ppm_plan_destroy": (C.c_int, [_vp]),
     "ppm_fill_periodic": (C.c_int, [_vp, _vp]),
+    "ppm_fill_boundary": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                    _vp]),
     "ppm_cfl_dt": (C.c_int, [_vp, _vp, _vp]),
     "ppm_step": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
     "ppm_step_cfl": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
@@ -176,6 +179,19 @@ class Plan:
 
     def ppm_fill_periodic(self, stream=None):
         _check(lib().ppm_fill_periodic(self._h, _stream_handle(stream)), "ppm_fill_periodic")
+
+    def ppm_fill_boundary(self, patch, kinds, inflow=None, stream=None):
+        """Ghost fill of one patch by per-face boundary conditions (PPM_FACE_*,
+        faces -x,+x,-y,+y,-z,+z); inflow: [6 faces][rho, vx, vy, vz, etot, eint]."""
+        k = (C.c_int32 * 6)(*[int(v) for v in kinds])
+        inf = None
+        if inflow is not None:
+            vals = [float(v) for row in inflow for v in row]
+            if len(vals) != 36:
+                raise ValueError("inflow must be 6 faces x 6 fields")
+            inf = (C.c_double * 36)(*vals)
+        _check(lib().ppm_fill_boundary(self._h, int(patch), k, inf, _stream_handle(stream)),
+               "ppm_fill_boundary")
 
     def ppm_cfl_dt(self, dt_dev, stream=None):
         _check(lib().ppm_cfl_dt(self._h, dt_dev.data_ptr(), _stream_handle(stream)), "ppm_cfl_dt")
