@@ -90,6 +90,11 @@ def lib():
         L.ppmo_cfl_dt.argtypes = [C.POINTER(_Grid), C.POINTER(Params)]
         L.ppmo_fill_periodic.argtypes = [C.POINTER(_Grid)]
         L.ppmo_fill_boundary.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32), dp]
+        L.ppmo_second_order_a.argtypes = [dp, C.c_int32, dp]
+        L.ppmo_fill_from_parent.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32),
+                                            C.POINTER(_Grid), C.POINTER(C.c_int32), C.c_int32]
+        L.ppmo_copy_from_sibling.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32),
+                                             C.POINTER(_Grid), C.POINTER(C.c_int32)]
         L.ppmo_two_shock.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.ppmo_hll_flux.argtypes = [C.POINTER(Params), dp, dp, dp]
         L.ppmo_hllc_flux.argtypes = [C.POINTER(Params), dp, dp, dp]
@@ -208,6 +213,30 @@ def fill_boundary(grid: Grid, kinds, inflow=None) -> None:
     g = grid._c()
     if lib().ppmo_fill_boundary(C.byref(g), k, None if inf is None else _ptr(inf)) != 0:
         raise ValueError("ppmo_fill_boundary: invalid argument")
+
+
+def second_order_a(nb, r: int) -> np.ndarray:
+    """SecondOrderA values [k][j][i] of the centre of a 3x3x3 neighbourhood [dz][dy][dx]."""
+    a = np.ascontiguousarray(nb, dtype=np.float64).reshape(27)
+    out = np.zeros(r ** 3)
+    lib().ppmo_second_order_a(_ptr(a), int(r), _ptr(out))
+    return out.reshape(r, r, r)
+
+
+def fill_from_parent(fine: Grid, fine_start, parent: Grid, parent_start, r: int) -> None:
+    fs = (C.c_int32 * 3)(*[int(v) for v in fine_start])
+    ps = (C.c_int32 * 3)(*[int(v) for v in parent_start])
+    gf, gp = fine._c(), parent._c()
+    if lib().ppmo_fill_from_parent(C.byref(gf), fs, C.byref(gp), ps, int(r)) != 0:
+        raise ValueError("ppmo_fill_from_parent: invalid argument")
+
+
+def copy_from_sibling(dst: Grid, dst_start, src: Grid, src_start) -> None:
+    ds = (C.c_int32 * 3)(*[int(v) for v in dst_start])
+    ss = (C.c_int32 * 3)(*[int(v) for v in src_start])
+    gd, gs = dst._c(), src._c()
+    if lib().ppmo_copy_from_sibling(C.byref(gd), ds, C.byref(gs), ss) != 0:
+        raise ValueError("ppmo_copy_from_sibling: invalid argument")
 
 
 def fill_periodic(grid: Grid) -> None:

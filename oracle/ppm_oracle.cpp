@@ -326,6 +326,71 @@ void hllc_flux(const ppmo_params &P, const R *sl, const R *sr, R *F) {
   F[FUB] = S;
 }
 
+template <class R> R minmod(R a, R b) {
+  if (a * b < 0.0) return R(0.0);
+  R m = fabs(a) < fabs(b) ? fabs(a) : fabs(b);
+  return a < 0.0 ? -m : m;
+}
+
+template <class R> R corner_avg(const R (&nb)[3][3][3], int sx, int sy, int sz) {
+  const int z0 = sz < 0 ? 0 : 1, y0 = sy < 0 ? 0 : 1, x0 = sx < 0 ? 0 : 1;
+  R sum = 0.0;
+  for (int z = z0; z <= z0 + 1; ++z)
+    for (int y = y0; y <= y0 + 1; ++y)
+      for (int x = x0; x <= x0 + 1; ++x) sum = sum + nb[z][y][x];
+  return sum * 0.125;
+}
+
+template <class R> void second_order_a(const R (&nb)[3][3][3], int r, R *out) {
+  const R q0 = nb[1][1][1];
+  // diagonal n runs from corner -c_n to corner +c_n
+  const int c[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+  R dq[4];
+  for (int n = 0; n < 4; ++n) {
+    R up = corner_avg<R>(nb, c[n][0], c[n][1], c[n][2]);
+    R dn = corner_avg<R>(nb, -c[n][0], -c[n][1], -c[n][2]);
+    dq[n] = minmod<R>(up - q0, q0 - dn);
+  }
+  const R sum = dq[1] + dq[2] + dq[3];
+  bool adjust = false, chi[4] = {false, false, false, false};
+  R target = 0.0;
+  if (dq[0] != 0.0) {
+    R s = sum / dq[0];
+    if (s < 0.0 || s > 1.0) {
+      adjust = true;
+      target = dq[0] * (s < 0.0 ? R(0.0) : R(1.0));
+      for (int n = 1; n < 4; ++n) {
+        R ratio = dq[n] / dq[0];
+        chi[n] = s < 0.0 ? ratio < 0.0 : ratio > 0.0;
+      }
+    }
+  } else if (sum != 0.0) {  // the (+,+,+) change must vanish: scale those along the sum
+    adjust = true;
+    for (int n = 1; n < 4; ++n) chi[n] = sum > 0.0 ? dq[n] > 0.0 : dq[n] < 0.0;
+  }
+  if (adjust) {
+    R sel = 0.0, rest = 0.0;
+    for (int n = 1; n < 4; ++n) {
+      if (chi[n]) sel = sel + dq[n];
+      else rest = rest + dq[n];
+    }
+    R f = (target - rest) / sel;
+    for (int n = 1; n < 4; ++n)
+      if (chi[n]) dq[n] = f * dq[n];
+  }
+  const R fx = dq[2] + dq[3], fy = dq[1] + dq[3], fz = dq[1] + dq[2];
+  for (int k = 0; k < r; ++k)
+    for (int j = 0; j < r; ++j)
+      for (int i = 0; i < r; ++i) {
+        const R wx = (R(i) + (1.0 - r) * 0.5) / R(r);
+        const R wy = (R(j) + (1.0 - r) * 0.5) / R(r);
+        const R wz = (R(k) + (1.0 - r) * 0.5) / R(r);
+        out[(k * r + j) * r + i] = q0 + wx * fx + wy * fy + wz * fz;
+      }
+}
+
+int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
 // ---------------------------------------------------------------------------
 // Step 8: conservative update of one active cell from its two face fluxes
 // (Eqs. mass_diff, momentum_diff, energy_diff, gasenergy_diff with a = 1,
@@ -860,6 +925,124 @@ int ppmo_fill_boundary(ppmo_grid *G, const int32_t kinds[6], const double *inflo
           if (kind == PPMO_FACE_REFLECTING) f[1 + a][dst] = -f[1 + a][src];
         }
   }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// SecondOrderA interpolation (Appendix "Interpolation", three-dimensional
+// form).  nb[dz][dy][dx] is the 3x3x3 neighbourhood of the coarse cell Q0 =
+// nb[1][1][1]; out[k][j][i] receives the r^3 fine values it covers.
+//  - The corner values Q_{sx,sy,sz} (s = -/+ 1/2) are the averages of the 8
+//    coarse cells sharing the corner (added in increasing z, y, x).
+//  - Limited slopes along the four diagonals (minmod of the two half-cell
+//    differences): dQ0 from corner (-,-,-) to (+,+,+), dQ1 from (+,-,-) to
+//    (-,+,+), dQ2 from (-,+,-) to (+,-,+), dQ3 from (-,-,+) to (+,+,-); these
+//    are the diagonals for which the paper's conversion f_x = dQ2 + dQ3,
+//    f_y = dQ1 + dQ3, f_z = dQ1 + dQ2 makes dQn the change from the centre
+//    to the corner.
+//  - A linear function's change to corner (+,+,+) is dQ1 + dQ2 + dQ3, so
+//    s = (dQ1 + dQ2 + dQ3) / dQ0 must lie in [0, 1]; otherwise the slopes
+//    that push it out (chi = 1: those opposite to dQ0 when s < 0, those along
+//    dQ0 when s > 1) are scaled by f so that the sum becomes dQ0 * s' with
+//    s' = min(max(s, 0), 1).  With dQ0 = 0 the sum must vanish: if it does
+//    not, the slopes along its sign are scaled to make it zero.
+//  - q(i,j,k) = Q0 + ((i + (1-r)/2)/r) f_x + ((j + (1-r)/2)/r) f_y
+//    + ((k + (1-r)/2)/r) f_z.
+void ppmo_second_order_a(const double *nb27, int32_t r, double *out) {
+  double nb[3][3][3];
+  for (int z = 0; z < 3; ++z)
+    for (int y = 0; y < 3; ++y)
+      for (int x = 0; x < 3; ++x) nb[z][y][x] = nb27[(z * 3 + y) * 3 + x];
+  second_order_a<double>(nb, r, out);
+}
+
+
+// Ghost cells of a fine grid from its parent (Sec. "Boundary conditions":
+// interpolation from the parent, conservative and monotonic): every cell of
+// the fine grid outside its active region takes the SecondOrderA value of
+// the conserved quantities rho, rho v, rho E, rho e of the parent cell that
+// covers it; the velocities and specific energies are those over the
+// interpolated density.
+int ppmo_fill_from_parent(ppmo_grid *F, const int32_t fine_start[3], const ppmo_grid *C,
+                          const int32_t parent_start[3], int32_t r) {
+  if (!F || !C || !fine_start || !parent_start || r < 2) return -1;
+  const int gf = F->ghost, gc = C->ghost;
+  const int Nf[3] = {F->nx, F->ny, F->nz}, Nc[3] = {C->nx, C->ny, C->nz};
+  const int64_t nf[3] = {Nf[0] + 2 * gf, Nf[1] + 2 * gf, Nf[2] + 2 * gf};
+  const int64_t nc[3] = {Nc[0] + 2 * gc, Nc[1] + 2 * gc, Nc[2] + 2 * gc};
+  // every coarse cell used, and its 27 neighbours, must lie in the parent array
+  for (int a = 0; a < 3; ++a) {
+    const int64_t lo = floor_div(fine_start[a] - gf, r) - parent_start[a] + gc;
+    const int64_t hi = floor_div(fine_start[a] + Nf[a] + gf - 1, r) - parent_start[a] + gc;
+    if (lo < 1 || hi > nc[a] - 2) return -1;
+  }
+  const double *cf[6] = {C->rho, C->vx, C->vy, C->vz, C->etot, C->eint};
+  double *ff[6] = {F->rho, F->vx, F->vy, F->vz, F->etot, F->eint};
+  std::vector<double> sub((size_t)r * r * r);
+  for (int64_t z = 0; z < nf[2]; ++z)
+    for (int64_t y = 0; y < nf[1]; ++y)
+      for (int64_t x = 0; x < nf[0]; ++x) {
+        const int64_t c[3] = {x, y, z};
+        bool active = true;
+        for (int a = 0; a < 3; ++a) active = active && c[a] >= gf && c[a] < gf + Nf[a];
+        if (active) continue;
+        int64_t lc[3];
+        int si[3];
+        for (int a = 0; a < 3; ++a) {
+          const int64_t gfine = fine_start[a] + (c[a] - gf);
+          const int64_t gcoarse = floor_div(gfine, r);
+          si[a] = int(gfine - gcoarse * r);
+          lc[a] = gcoarse - parent_start[a] + gc;
+        }
+        double q[6];
+        for (int comp = 0; comp < 6; ++comp) {
+          double nb[3][3][3];
+          for (int dz = 0; dz < 3; ++dz)
+            for (int dy = 0; dy < 3; ++dy)
+              for (int dx = 0; dx < 3; ++dx) {
+                const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] +
+                                  (lc[0] + dx - 1);
+                nb[dz][dy][dx] = comp == 0 ? cf[0][o] : cf[0][o] * cf[comp][o];
+              }
+          second_order_a<double>(nb, r, sub.data());
+          q[comp] = sub[((size_t)si[2] * r + si[1]) * r + si[0]];
+        }
+        const int64_t dst = (z * nf[1] + y) * nf[0] + x;
+        ff[0][dst] = q[0];
+        for (int comp = 1; comp < 6; ++comp) ff[comp][dst] = q[comp] / q[0];
+      }
+  return 0;
+}
+
+// Sibling copy: every cell of dst outside its active region that lies in the
+// active region of src (same level; starts are global indices of the first
+// active cells) takes src's values.
+int ppmo_copy_from_sibling(ppmo_grid *D, const int32_t dst_start[3], const ppmo_grid *S,
+                           const int32_t src_start[3]) {
+  if (!D || !S || !dst_start || !src_start) return -1;
+  const int gd = D->ghost, gs = S->ghost;
+  const int Nd[3] = {D->nx, D->ny, D->nz}, Ns[3] = {S->nx, S->ny, S->nz};
+  const int64_t nd[3] = {Nd[0] + 2 * gd, Nd[1] + 2 * gd, Nd[2] + 2 * gd};
+  const int64_t ns[3] = {Ns[0] + 2 * gs, Ns[1] + 2 * gs, Ns[2] + 2 * gs};
+  const double *sf[6] = {S->rho, S->vx, S->vy, S->vz, S->etot, S->eint};
+  double *df[6] = {D->rho, D->vx, D->vy, D->vz, D->etot, D->eint};
+  for (int64_t z = 0; z < nd[2]; ++z)
+    for (int64_t y = 0; y < nd[1]; ++y)
+      for (int64_t x = 0; x < nd[0]; ++x) {
+        const int64_t c[3] = {x, y, z};
+        bool active = true, inside = true;
+        int64_t sc[3];
+        for (int a = 0; a < 3; ++a) {
+          active = active && c[a] >= gd && c[a] < gd + Nd[a];
+          const int64_t g = dst_start[a] + (c[a] - gd) - src_start[a];  // src active index
+          inside = inside && g >= 0 && g < Ns[a];
+          sc[a] = g + gs;
+        }
+        if (active || !inside) continue;
+        const int64_t dst = (z * nd[1] + y) * nd[0] + x;
+        const int64_t src = (sc[2] * ns[1] + sc[1]) * ns[0] + sc[0];
+        for (int q = 0; q < 6; ++q) df[q][dst] = sf[q][src];
+      }
   return 0;
 }
 

@@ -32,7 +32,13 @@
  * boundary fill (ppmo_fill_boundary) is pinned by: periodic faces equal to
  * the periodic fill; reflecting walls evolving bit for bit as half of the
  * mirrored periodic box of twice the size; Sod between outflow faces against
- * the exact solution; uniform inflow-to-outflow flow staying uniform.
+ * the exact solution; uniform inflow-to-outflow flow staying uniform.  The
+ * SecondOrderA parent interpolation is pinned by the paper's own 1-D and 2-D
+ * formulas (data varying along one or two axes), exact linear fields,
+ * conservation of the coarse value, and every corner of the interpolant
+ * lying between the cell value and that corner's parent average; the patch
+ * fill from the parent on linear conserved fields, and the sibling copy on a
+ * tiling of one region by two patches.
  *
  * Parity unpinned (pinned only by these readings and by GPU == oracle):
  *   - the CW84 flattening slope omega_2 = 10 (f~ rises from 0 at a pressure
@@ -43,7 +49,11 @@
  *   - the Newton tolerance and iteration cap of the two-shock solver;
  *   - HLLC's outer wave speeds (the Davis estimates of the HLL fallback; the
  *     paper names none) and the internal energy carried with the density
- *     across its star states.
+ *     across its star states;
+ *   - SecondOrderA's readings: corner values as 8-cell averages, the printed
+ *     sign of the adjustment factor (read so the slopes sum to dQ0 s'), no
+ *     epsilon (the selected slopes never sum to zero), the dQ0 = 0 case, and
+ *     the interpolation of rho, rho v, rho E, rho e.
  *
  * Conventions (all host pointers, owned by the caller):
  *   - A grid has nx*ny*nz active cells and `ghost` ghost layers per side (3, as
@@ -146,6 +156,24 @@ enum {
  * Periodic faces come in pairs; a reflecting axis needs at least `ghost`
  * active cells.  Returns -1 on an invalid argument. */
 int ppmo_fill_boundary(ppmo_grid *g, const int32_t kinds[6], const double *inflow);
+
+/* SecondOrderA interpolation (Appendix "Interpolation") of the centre of a
+ * 3x3x3 coarse neighbourhood nb27[dz][dy][dx] to its r^3 fine cells
+ * out[k][j][i]. */
+void ppmo_second_order_a(const double *nb27, int32_t r, double *out);
+
+/* Ghost cells of fine grid `fine` (its first active cell at global index
+ * fine_start of its level) by SecondOrderA interpolation of the conserved
+ * quantities of its parent grid (first active cell at parent_start of the
+ * coarser level, refinement factor r >= 2).  -1 if a needed coarse cell or
+ * one of its neighbours lies outside the parent array. */
+int ppmo_fill_from_parent(ppmo_grid *fine, const int32_t fine_start[3], const ppmo_grid *parent,
+                          const int32_t parent_start[3], int32_t r);
+
+/* Ghost cells of dst that lie in the active region of src (same level) take
+ * src's values. */
+int ppmo_copy_from_sibling(ppmo_grid *dst, const int32_t dst_start[3], const ppmo_grid *src,
+                           const int32_t src_start[3]);
 
 /* Two-shock Riemann solver on (rho,u,p) left/right states.
  * out[0]=p*, out[1]=u*, out[2..4] = sampled (rho,u,p) at x/t=0,
