@@ -186,6 +186,32 @@ typedef enum {
 ppm_status ppm_fill_boundary(ppm_plan *plan, int32_t patch, const int32_t *kinds,
                              const double *inflow, void *hip_stream);
 
+/* Place of a patch in the AMR hierarchy. */
+typedef struct {
+  int32_t parent;   /* index of the parent patch in the plan (level - 1), or -1 */
+  int32_t refine;   /* refinement factor r >= 2 from the parent's cells to this patch's */
+  int32_t start[3]; /* global index, in this patch's level, of its first active cell */
+} ppm_patch_place;
+
+/* Record the hierarchy of the plan's patches (host array of npatch, copied)
+ * and build the device work lists of ppm_fill_ghosts: for every patch with a
+ * parent, its ghost cells; for every pair of patches of one level, the ghost
+ * cells of one that lie in the active region of the other.  PPM_EINVAL
+ * (nothing changed) if a parent index is out of range or not one level
+ * coarser, r < 2, or a ghost cell's parent cell or one of its 26 neighbours
+ * lies outside the parent's array (ghosts included).  Allocates device
+ * memory; call again to replace the hierarchy. */
+ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void *hip_stream);
+
+/* Ghost cells of every patch of `level` that has a parent (Sec. "Boundary
+ * conditions"): first SecondOrderA interpolation (Appendix "Interpolation")
+ * of the parent's rho, rho v, rho E, rho e, stored as rho, v, E, e; then the
+ * copy from every sibling of the level whose active region covers a ghost
+ * cell.  The parents' ghosts must be valid (filled before, level by level).
+ * Patches of the level without a parent are not touched.  PPM_EINVAL without
+ * a recorded hierarchy. */
+ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream);
+
 /* Hydro CFL timestep per level (Sec. "Timestepping"):
  *   dt_dev[l] = cfl / max over the active cells of the level's patches of
  *               sum_d (c_s + |v_d|) / dx_d,

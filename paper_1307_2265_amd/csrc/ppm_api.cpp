@@ -54,6 +54,13 @@ struct ppm_plan {
   unsigned long long *d_counters = nullptr;  // fallback faces, floored cells
   unsigned long long *d_smax = nullptr;      // per-level max signal speed bits
   int device = 0;
+  // AMR ghost fill work lists, grouped by level (ppm_set_hierarchy)
+  bool hier = false;
+  ppm::InterpItem *d_interp = nullptr;
+  ppm::SiblingBox *d_boxes = nullptr;
+  int64_t *d_iprefix = nullptr, *d_bprefix = nullptr;  // per level: items+1 / boxes+1 entries
+  std::vector<int32_t> ibeg, bbeg;        // per level: first item / box (nlevels+1 entries)
+  std::vector<int64_t> itotal, btotal;    // per level: ghost cells / box cells
 };
 
 namespace {
@@ -178,6 +185,10 @@ void free_plan(ppm_plan *p) {
   if (p->d_order) (void)hipFree(p->d_order);
   if (p->d_queue) (void)hipFree(p->d_queue);
   if (p->d_groups) (void)hipFree(p->d_groups);
+  if (p->d_interp) (void)hipFree(p->d_interp);
+  if (p->d_boxes) (void)hipFree(p->d_boxes);
+  if (p->d_iprefix) (void)hipFree(p->d_iprefix);
+  if (p->d_bprefix) (void)hipFree(p->d_bprefix);
   delete p;
 }
 
@@ -531,6 +542,152 @@ ppm_status ppm_fill_boundary(ppm_plan *plan, int32_t patch, const int32_t *kinds
   hipError_t e = plan->prec == PPM_FP64 ? ppm::launch_fill_boundary<ppm::PrecF64>(pd, fr, s)
                                         : ppm::launch_fill_boundary<ppm::PrecMixed>(pd, fr, s);
   if (e != hipSuccess) return hip_fail(e, "fill_boundary launch");
+  return PPM_OK;
+}
+
+namespace {
+int64_t floor_div64(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+int64_t shell_count(const PatchDev &d) {
+  const int64_t g = d.ghost;
+  const int64_t n0 = d.n[0] + 2 * g, n1 = d.n[1] + 2 * g, n2 = d.n[2] + 2 * g;
+  return n0 * n1 * n2 - int64_t(d.n[0]) * d.n[1] * d.n[2];
+}
+}  // namespace
+
+ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!place) return fail(PPM_EINVAL, "place is NULL");
+  const int np = plan->npatch, nl = plan->nlevels;
+  const auto &H = plan->host;
+  for (int i = 0; i < np; ++i) {
+    const ppm_patch_place &q = place[i];
+    if (q.parent < 0) continue;
+    if (q.parent >= np) return fail(PPM_EINVAL, "patch %d: parent %d out of range", i, q.parent);
+    if (H[q.parent].level != H[i].level - 1)
+      return fail(PPM_EINVAL, "patch %d: parent %d is not one level coarser", i, q.parent);
+    if (q.refine < 2) return fail(PPM_EINVAL, "patch %d: refine must be >= 2", i);
+    const PatchDev &f = H[i], &c = H[q.parent];
+    const ppm_patch_place &pp = place[q.parent];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t lo = floor_div64(int64_t(q.start[a]) - f.ghost, q.refine) - pp.start[a] + c.ghost;
+      const int64_t hi = floor_div64(int64_t(q.start[a]) + f.n[a] + f.ghost - 1, q.refine) -
+                         pp.start[a] + c.ghost;
+      if (lo < 1 || hi > int64_t(c.n[a]) + 2 * c.ghost - 2)
+        return fail(PPM_EINVAL, "patch %d: its ghost cells need parent cells outside parent %d "
+                                "(axis %d)", i, q.parent, a);
+    }
+  }
+  // interpolation items and sibling boxes, grouped by level
+  std::vector<ppm::InterpItem> items;
+  std::vector<ppm::SiblingBox> boxes;
+  std::vector<int64_t> ipre, bpre;
+  std::vector<int32_t> ibeg(nl + 1, 0), bbeg(nl + 1, 0);
+  std::vector<int64_t> itot(nl, 0), btot(nl, 0);
+  std::vector<std::vector<int>> bylevel(nl);
+  for (int i = 0; i < np; ++i) bylevel[H[i].level].push_back(i);
+  for (int L = 0; L < nl; ++L) {
+    ibeg[L] = int32_t(items.size());
+    int64_t acc = 0;
+    for (int i : bylevel[L]) {
+      if (place[i].parent < 0) continue;
+      ppm::InterpItem it{};
+      it.patch = i; it.parent = place[i].parent; it.r = place[i].refine;
+      for (int a = 0; a < 3; ++a) {
+        it.start[a] = place[i].start[a];
+        it.pstart[a] = place[place[i].parent].start[a];
+      }
+      items.push_back(it);
+      ipre.push_back(acc);
+      acc += shell_count(H[i]);
+    }
+    ipre.push_back(acc);
+    itot[L] = acc;
+    bbeg[L] = int32_t(boxes.size());
+    int64_t bacc = 0;
+    for (int d : bylevel[L]) {
+      if (place[d].parent < 0) continue;
+      for (int src : bylevel[L]) {
+        if (src == d) continue;
+        ppm::SiblingBox b{};
+        b.dst = d; b.src = src;
+        bool empty = false;
+        for (int a = 0; a < 3; ++a) {
+          const int64_t g = H[d].ghost;
+          const int64_t lo = std::max<int64_t>(int64_t(place[d].start[a]) - g, place[src].start[a]);
+          const int64_t hi = std::min<int64_t>(int64_t(place[d].start[a]) + H[d].n[a] + g,
+                                               int64_t(place[src].start[a]) + H[src].n[a]);
+          if (lo >= hi) { empty = true; break; }
+          b.lo[a] = int32_t(lo - place[d].start[a] + g);
+          b.hi[a] = int32_t(hi - place[d].start[a] + g);
+          b.shift[a] = int32_t(int64_t(place[d].start[a]) - g - place[src].start[a] + H[src].ghost);
+        }
+        if (empty) continue;
+        boxes.push_back(b);
+        bpre.push_back(bacc);
+        bacc += int64_t(b.hi[0] - b.lo[0]) * (b.hi[1] - b.lo[1]) * (b.hi[2] - b.lo[2]);
+      }
+    }
+    bpre.push_back(bacc);
+    btot[L] = bacc;
+  }
+  ibeg[nl] = int32_t(items.size());
+  bbeg[nl] = int32_t(boxes.size());
+  // replace the device lists
+  if (plan->d_interp) (void)hipFree(plan->d_interp);
+  if (plan->d_boxes) (void)hipFree(plan->d_boxes);
+  if (plan->d_iprefix) (void)hipFree(plan->d_iprefix);
+  if (plan->d_bprefix) (void)hipFree(plan->d_bprefix);
+  plan->d_interp = nullptr; plan->d_boxes = nullptr;
+  plan->d_iprefix = plan->d_bprefix = nullptr;
+  plan->hier = false;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipError_t e;
+  auto up = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(dst, bytes ? bytes : 8);
+    if (r != hipSuccess) return r;
+    return bytes ? hipMemcpyAsync(*dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  if ((e = up((void **)&plan->d_interp, items.data(), items.size() * sizeof(ppm::InterpItem))) !=
+          hipSuccess ||
+      (e = up((void **)&plan->d_boxes, boxes.data(), boxes.size() * sizeof(ppm::SiblingBox))) !=
+          hipSuccess ||
+      (e = up((void **)&plan->d_iprefix, ipre.data(), ipre.size() * sizeof(int64_t))) != hipSuccess ||
+      (e = up((void **)&plan->d_bprefix, bpre.data(), bpre.size() * sizeof(int64_t))) != hipSuccess)
+    return hip_fail(e, "hierarchy upload");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hierarchy upload");
+  plan->ibeg = ibeg; plan->bbeg = bbeg; plan->itotal = itot; plan->btotal = btot;
+  plan->hier = true;
+  return PPM_OK;
+}
+
+ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!plan->hier) return fail(PPM_EINVAL, "no hierarchy recorded (ppm_set_hierarchy)");
+  if (level < 0 || level >= plan->nlevels)
+    return fail(PPM_EINVAL, "level %d outside [0, %d)", level, plan->nlevels);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int32_t i0 = plan->ibeg[level], ni = plan->ibeg[level + 1] - i0;
+  const int32_t b0 = plan->bbeg[level], nb = plan->bbeg[level + 1] - b0;
+  // prefix arrays hold one extra entry per level before it
+  const int64_t *ip = plan->d_iprefix + i0 + level;
+  const int64_t *bp = plan->d_bprefix + b0 + level;
+  hipError_t e;
+  if (ni > 0) {
+    e = plan->prec == PPM_FP64
+        ? ppm::launch_fill_from_parent<ppm::PrecF64>(plan->d_patches, plan->d_interp + i0, ip, ni,
+                                                     plan->itotal[level], s)
+        : ppm::launch_fill_from_parent<ppm::PrecMixed>(plan->d_patches, plan->d_interp + i0, ip, ni,
+                                                       plan->itotal[level], s);
+    if (e != hipSuccess) return hip_fail(e, "fill_from_parent launch");
+  }
+  if (nb > 0) {
+    e = plan->prec == PPM_FP64
+        ? ppm::launch_copy_from_siblings<ppm::PrecF64>(plan->d_patches, plan->d_boxes + b0, bp, nb,
+                                                       plan->btotal[level], s)
+        : ppm::launch_copy_from_siblings<ppm::PrecMixed>(plan->d_patches, plan->d_boxes + b0, bp,
+                                                         nb, plan->btotal[level], s);
+    if (e != hipSuccess) return hip_fail(e, "copy_from_siblings launch");
+  }
   return PPM_OK;
 }
 

@@ -22,7 +22,8 @@
 //     double; the finalise kernel turns the max into dt and clears it.
 //   * fill_periodic_kernel: periodic ghost fill of one patch over its ghost
 //     shell only; fill_boundary_kernel: the same shell by per-face domain
-//     boundary conditions.
+//     boundary conditions; fill_from_parent_kernel / copy_from_siblings_kernel:
+//     AMR patch ghosts from the parent (SecondOrderA) and from siblings.
 #include "ppm_kernels.hpp"
 #include "ppm_lanes.hpp"
 
@@ -426,6 +427,194 @@ fill_boundary_kernel(PatchDev pd, FaceRules fr) {
 }
 
 // ---------------------------------------------------------------------------
+// Ghost cells of AMR patches from their parents and siblings (Sec. "Boundary
+// conditions": interpolate every boundary cell from the parent, then copy
+// from siblings wherever one covers it).
+//
+// SecondOrderA (Appendix "Interpolation", three-dimensional form) of one
+// conserved quantity at fine cell (i, j, k) of the r^3 that refine the centre
+// of nb[dz][dy][dx]: corner values are the averages of the 8 parent cells
+// sharing a corner; slopes along the four diagonals are minmod-limited; if
+// the change to corner (+,+,+) that dQ1..dQ3 imply leaves [0, dQ0] (s outside
+// [0, 1]), the slopes pushing it out are scaled so that it lands on the near
+// end (with dQ0 = 0: onto zero); the slopes are converted to the axes and
+// evaluated at the fine cell centre.  Off the hot path, so divisions are the
+// compiler's correctly rounded ones (exact also for subnormal operands).
+__device__ __forceinline__ double minmod(double a, double b) {
+  if (a * b < 0.0) return 0.0;
+  const double m = fabs(a) < fabs(b) ? fabs(a) : fabs(b);
+  return a < 0.0 ? -m : m;
+}
+
+__device__ __forceinline__ double corner_avg(const double (&nb)[3][3][3], int sx, int sy, int sz) {
+  const int z0 = sz < 0 ? 0 : 1, y0 = sy < 0 ? 0 : 1, x0 = sx < 0 ? 0 : 1;
+  double sum = 0.0;
+#pragma unroll
+  for (int z = 0; z < 2; ++z)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int x = 0; x < 2; ++x) sum = sum + nb[z0 + z][y0 + y][x0 + x];
+  return sum * 0.125;
+}
+
+__device__ double second_order_a_at(const double (&nb)[3][3][3], int r, int i, int j, int k) {
+  const double q0 = nb[1][1][1];
+  const int c[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
+  double dq[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const double up = corner_avg(nb, c[n][0], c[n][1], c[n][2]);
+    const double dn = corner_avg(nb, -c[n][0], -c[n][1], -c[n][2]);
+    dq[n] = minmod(up - q0, q0 - dn);
+  }
+  const double sum = dq[1] + dq[2] + dq[3];
+  bool adjust = false, chi[4] = {false, false, false, false};
+  double target = 0.0;
+  if (dq[0] != 0.0) {
+    const double s = sum / dq[0];
+    if (s < 0.0 || s > 1.0) {
+      adjust = true;
+      target = dq[0] * (s < 0.0 ? 0.0 : 1.0);
+#pragma unroll
+      for (int n = 1; n < 4; ++n) {
+        const double ratio = dq[n] / dq[0];
+        chi[n] = s < 0.0 ? ratio < 0.0 : ratio > 0.0;
+      }
+    }
+  } else if (sum != 0.0) {
+    adjust = true;
+#pragma unroll
+    for (int n = 1; n < 4; ++n) chi[n] = sum > 0.0 ? dq[n] > 0.0 : dq[n] < 0.0;
+  }
+  if (adjust) {
+    double sel = 0.0, rest = 0.0;
+#pragma unroll
+    for (int n = 1; n < 4; ++n) {
+      if (chi[n]) sel = sel + dq[n];
+      else rest = rest + dq[n];
+    }
+    const double f = (target - rest) / sel;
+#pragma unroll
+    for (int n = 1; n < 4; ++n)
+      if (chi[n]) dq[n] = f * dq[n];
+  }
+  const double fx = dq[2] + dq[3], fy = dq[1] + dq[3], fz = dq[1] + dq[2];
+  const double wx = (double(i) + (1.0 - r) * 0.5) / double(r);
+  const double wy = (double(j) + (1.0 - r) * 0.5) / double(r);
+  const double wz = (double(k) + (1.0 - r) * 0.5) / double(r);
+  return q0 + wx * fx + wy * fy + wz * fz;
+}
+
+__device__ __forceinline__ int64_t floor_div(int64_t a, int64_t b) {
+  return a >= 0 ? a / b : -((-a + b - 1) / b);
+}
+
+__device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64_t t) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= t) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One thread per ghost cell of the listed patches: the cell's parent cell,
+// its 27-cell neighbourhood of rho, rho v, rho E, rho e, the SecondOrderA
+// value of each at the cell, stored as rho, v = (rho v)/rho, E, e.
+template <class Prec>
+__global__ void __launch_bounds__(256)
+fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *__restrict__ items,
+                        const int64_t *__restrict__ prefix, int32_t nitems, int64_t total) {
+  using S = typename Prec::S;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int it = find_item(prefix, nitems, t);
+  const InterpItem item = items[it];
+  const PatchDev fd = patches[item.patch];
+  const PatchDev cd = patches[item.parent];
+  const int gf = fd.ghost, gc = cd.ghost, r = item.r;
+  const int64_t Nf[3] = {fd.n[0], fd.n[1], fd.n[2]};
+  const int64_t nf[3] = {Nf[0] + 2 * gf, Nf[1] + 2 * gf, Nf[2] + 2 * gf};
+  const int64_t nc[3] = {int64_t(cd.n[0]) + 2 * gc, int64_t(cd.n[1]) + 2 * gc,
+                         int64_t(cd.n[2]) + 2 * gc};
+  int64_t c[3];
+  if (!shell_cell(gf, Nf, nf, t - prefix[it], c)) return;
+  int64_t lc[3];
+  int si[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int64_t gfine = item.start[a] + (c[a] - gf);
+    const int64_t gcoarse = floor_div(gfine, r);
+    si[a] = int(gfine - gcoarse * r);
+    lc[a] = gcoarse - item.pstart[a] + gc;
+  }
+  const S *crho = static_cast<const S *>(cd.rho);
+  const S *cvel[3] = {static_cast<const S *>(cd.vel[0]), static_cast<const S *>(cd.vel[1]),
+                      static_cast<const S *>(cd.vel[2])};
+  double q[6];
+  for (int comp = 0; comp < 6; ++comp) {
+    double nb[3][3][3];
+    for (int dz = 0; dz < 3; ++dz)
+      for (int dy = 0; dy < 3; ++dy)
+        for (int dx = 0; dx < 3; ++dx) {
+          const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
+          const double rho = double(crho[o]);
+          double v;
+          if (comp == 0) v = rho;
+          else if (comp < 4) v = rho * double(cvel[comp - 1][o]);
+          else if (comp == 4) v = rho * cd.etot[o];
+          else v = rho * cd.eint[o];
+          nb[dz][dy][dx] = v;
+        }
+    q[comp] = second_order_a_at(nb, r, si[0], si[1], si[2]);
+  }
+  const int64_t dst = (c[2] * nf[1] + c[1]) * nf[0] + c[0];
+  static_cast<S *>(fd.rho)[dst] = S(q[0]);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) static_cast<S *>(fd.vel[a])[dst] = S(q[1 + a] / q[0]);
+  fd.etot[dst] = q[4] / q[0];
+  fd.eint[dst] = q[5] / q[0];
+}
+
+// One thread per cell of the listed boxes: the sibling's value, unless the
+// cell is active in its own patch.
+template <class Prec>
+__global__ void __launch_bounds__(256)
+copy_from_siblings_kernel(const PatchDev *__restrict__ patches, const SiblingBox *__restrict__ boxes,
+                          const int64_t *__restrict__ prefix, int32_t nboxes, int64_t total) {
+  using S = typename Prec::S;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int b = find_item(prefix, nboxes, t);
+  const SiblingBox box = boxes[b];
+  const int64_t u = t - prefix[b];
+  const int64_t ex = box.hi[0] - box.lo[0], ey = box.hi[1] - box.lo[1];
+  const int64_t c[3] = {box.lo[0] + u % ex, box.lo[1] + (u / ex) % ey, box.lo[2] + u / (ex * ey)};
+  const PatchDev dd = patches[box.dst];
+  const PatchDev sd = patches[box.src];
+  const int gd = dd.ghost, gs = sd.ghost;
+  bool active = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) active = active && c[a] >= gd && c[a] < gd + dd.n[a];
+  if (active) return;
+  const int64_t nd[3] = {int64_t(dd.n[0]) + 2 * gd, int64_t(dd.n[1]) + 2 * gd,
+                         int64_t(dd.n[2]) + 2 * gd};
+  const int64_t ns[3] = {int64_t(sd.n[0]) + 2 * gs, int64_t(sd.n[1]) + 2 * gs,
+                         int64_t(sd.n[2]) + 2 * gs};
+  const int64_t sc[3] = {c[0] + box.shift[0], c[1] + box.shift[1], c[2] + box.shift[2]};
+  const int64_t dst = (c[2] * nd[1] + c[1]) * nd[0] + c[0];
+  const int64_t src = (sc[2] * ns[1] + sc[1]) * ns[0] + sc[0];
+  static_cast<S *>(dd.rho)[dst] = static_cast<const S *>(sd.rho)[src];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    static_cast<S *>(dd.vel[a])[dst] = static_cast<const S *>(sd.vel[a])[src];
+  dd.etot[dst] = sd.etot[src];
+  dd.eint[dst] = sd.eint[src];
+}
+
+// ---------------------------------------------------------------------------
 // Periodic ghost fill of one patch: only ghost cells are visited.  The shell
 // is split into the two z slabs (full x, y), the two y slabs of the active z
 // range (full x), and the two x slabs of the active y, z range.
@@ -569,6 +758,26 @@ hipError_t launch_fill_boundary(const PatchDev &pd, const FaceRules &fr, hipStre
 }
 
 template <class Prec>
+hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *items,
+                                   const int64_t *prefix, int32_t nitems, int64_t total,
+                                   hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_from_parent_kernel<Prec>, dim3(unsigned((total + 255) / 256)), dim3(256),
+                     0, s, patches, items, prefix, nitems, total);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_copy_from_siblings(const PatchDev *patches, const SiblingBox *boxes,
+                                     const int64_t *prefix, int32_t nboxes, int64_t total,
+                                     hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_from_siblings_kernel<Prec>, dim3(unsigned((total + 255) / 256)),
+                     dim3(256), 0, s, patches, boxes, prefix, nboxes, total);
+  return hipGetLastError();
+}
+
+template <class Prec>
 hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
   const int64_t g = pd.ghost;
   const int64_t N[3] = {pd.n[0], pd.n[1], pd.n[2]};
@@ -612,6 +821,18 @@ template hipError_t launch_fill<PrecF64>(const PatchDev &, hipStream_t);
 template hipError_t launch_fill<PrecMixed>(const PatchDev &, hipStream_t);
 template hipError_t launch_fill_boundary<PrecF64>(const PatchDev &, const FaceRules &,
                                                   hipStream_t);
+template hipError_t launch_fill_from_parent<PrecF64>(const PatchDev *, const InterpItem *,
+                                                     const int64_t *, int32_t, int64_t,
+                                                     hipStream_t);
+template hipError_t launch_fill_from_parent<PrecMixed>(const PatchDev *, const InterpItem *,
+                                                       const int64_t *, int32_t, int64_t,
+                                                       hipStream_t);
+template hipError_t launch_copy_from_siblings<PrecF64>(const PatchDev *, const SiblingBox *,
+                                                       const int64_t *, int32_t, int64_t,
+                                                       hipStream_t);
+template hipError_t launch_copy_from_siblings<PrecMixed>(const PatchDev *, const SiblingBox *,
+                                                         const int64_t *, int32_t, int64_t,
+                                                         hipStream_t);
 template hipError_t launch_fill_boundary<PrecMixed>(const PatchDev &, const FaceRules &,
                                                     hipStream_t);
 

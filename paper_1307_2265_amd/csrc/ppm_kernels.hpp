@@ -72,4 +72,33 @@ struct FaceRules {
 template <class Prec>
 hipError_t launch_fill_boundary(const PatchDev &pd, const FaceRules &fr, hipStream_t s);
 
+// A patch whose ghost cells come from its parent: indices into the patch
+// table, refinement factor, global start of the first active cell of the
+// patch (in its level) and of its parent (in the parent's level).
+struct InterpItem {
+  int32_t patch, parent, r;
+  int32_t start[3], pstart[3];
+};
+// Cells of patch dst outside its active region that lie in the active
+// region of sibling src: the box [lo, hi) in dst's local (ghosted) indices,
+// and the offset from dst-local to src-local indices.
+struct SiblingBox {
+  int32_t dst, src;
+  int32_t lo[3], hi[3], shift[3];
+};
+
+// Ghost cells of items[0..nitems): SecondOrderA interpolation of the parent's
+// conserved quantities.  prefix[i] = first ghost cell of item i in the launch
+// (prefix[nitems] = total).
+template <class Prec>
+hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *items,
+                                   const int64_t *prefix, int32_t nitems, int64_t total,
+                                   hipStream_t s);
+
+// Sibling copies of boxes[0..nboxes); prefix as above, over box volumes.
+template <class Prec>
+hipError_t launch_copy_from_siblings(const PatchDev *patches, const SiblingBox *boxes,
+                                     const int64_t *prefix, int32_t nboxes, int64_t total,
+                                     hipStream_t s);
+
 }  // namespace ppm

@@ -43,12 +43,18 @@ class ppm_params(C.Structure):
                 ("riemann_max_iter", C.c_int32), ("flags", C.c_uint32)]
 
 
+class ppm_patch_place(C.Structure):
+    _fields_ = [("parent", C.c_int32), ("refine", C.c_int32), ("start", C.c_int32 * 3)]
+
+
 SIGNATURES = {
     "ppm_flux_reg_size": (C.c_int64, [C.c_int32, C.c_int32, C.c_int32]),
     "ppm_plan_create": (C.c_int, [C.POINTER(_vp), C.POINTER(ppm_patch), C.c_int32, C.c_int32,
                                   C.c_int, C.POINTER(ppm_params), C.c_char_p, _vp]),
     "ppm_plan_destroy": (C.c_int, [_vp]),
     "ppm_fill_periodic": (C.c_int, [_vp, _vp]),
+    "ppm_set_hierarchy": (C.c_int, [_vp, C.POINTER(ppm_patch_place), _vp]),
+    "ppm_fill_ghosts": (C.c_int, [_vp, C.c_int32, _vp]),
     "ppm_fill_boundary": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                     _vp]),
     "ppm_cfl_dt": (C.c_int, [_vp, _vp, _vp]),
@@ -192,6 +198,18 @@ class Plan:
             inf = (C.c_double * 36)(*vals)
         _check(lib().ppm_fill_boundary(self._h, int(patch), k, inf, _stream_handle(stream)),
                "ppm_fill_boundary")
+
+    def ppm_set_hierarchy(self, places, stream=None):
+        """places: per patch (parent index or -1, refinement factor, (start x, y, z))."""
+        arr = (ppm_patch_place * len(places))()
+        for i, (parent, refine, start) in enumerate(places):
+            arr[i].parent, arr[i].refine = int(parent), int(refine)
+            for a in range(3):
+                arr[i].start[a] = int(start[a])
+        _check(lib().ppm_set_hierarchy(self._h, arr, _stream_handle(stream)), "ppm_set_hierarchy")
+
+    def ppm_fill_ghosts(self, level, stream=None):
+        _check(lib().ppm_fill_ghosts(self._h, int(level), _stream_handle(stream)), "ppm_fill_ghosts")
 
     def ppm_cfl_dt(self, dt_dev, stream=None):
         _check(lib().ppm_cfl_dt(self._h, dt_dev.data_ptr(), _stream_handle(stream)), "ppm_cfl_dt")

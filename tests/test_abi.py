@@ -72,6 +72,8 @@ def test_calls_on_null_plan_are_rejected():
     assert L.ppm_sweep_cfl(None, None, 0, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_cfl_finalize(None, None, None) == ppm.PPM_EINVAL
     assert L.ppm_fill_boundary(None, 0, None, None, None) == ppm.PPM_EINVAL
+    assert L.ppm_set_hierarchy(None, None, None) == ppm.PPM_EINVAL
+    assert L.ppm_fill_ghosts(None, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_event_counts(None, None, None, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_plan_destroy(None) == ppm.PPM_OK
 
