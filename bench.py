@@ -11,7 +11,8 @@ synthetic and resident in HBM when the timed region starts; launch shapes
 come from the autotuner's table (data/tiles.json) when it exists.
 
 Also measured: the same grid and steps with the HLLC solver in place of
-two-shock (FP64 and mixed); the batched form -- 4096 uneven AMR patches (dims from
+two-shock (FP64 and mixed); the AMR patch ghost fill (parent interpolation and
+sibling copies) on a nested hierarchy; the batched form -- 4096 uneven AMR patches (dims from
 {8,12,16,24,32}, levels 0-6 with their own dt, seeded ghosts, flux registers
 on) advanced by replaying one captured HIP graph per step (the three sweeps
 and the next timestep) -- and its rate relative to the single grid.
@@ -63,6 +64,7 @@ def parse():
     ap.add_argument("--tiles", default=None, help="tile_config of the single-grid plans")
     ap.add_argument("--batch-tiles", default=None, help="tile_config of the batch plans")
     ap.add_argument("--no-hllc", action="store_true", help="skip the HLLC-solver runs")
+    ap.add_argument("--no-amr-fill", action="store_true", help="skip the AMR ghost-fill timing")
     return ap.parse_args()
 
 
@@ -87,6 +89,47 @@ def cpu_baseline(d, n, planes, steps):
     what = f"the full {n}^3 grid" if planes == n else f"a {n}x{n}x{planes} periodic slab of the grid"
     return dict(value=cells / el, unit="cell-updates/s", cores=O.num_threads(), kind="oracle",
                 sample=f"{steps} steps of {what} (same seeded input), FP64, sweeps {el:.1f}s wall")
+
+
+def amr_ghost_fill(reps: int = 5) -> dict:
+    """Time ppm_fill_ghosts (parent interpolation + sibling copies) level by
+    level on a nested FP64 hierarchy: a 128^3 root, 64 level-1 blocks of 32^3
+    tiling its centre, 512 level-2 blocks of 24^3 (8 in each level-1 block)."""
+    import numpy as np
+    import torch
+    from paper_1307_2265_amd import ppm, workloads as W
+    from paper_1307_2265_amd import harness as H
+    hier = W.nested_hierarchy(128, (32, 24), (4, 2))
+    fields = [W.random_grid(*h.dims, 4000 + i, W.SHOCKED) for i, h in enumerate(hier)]
+    run = H.Run(fields, [(*h.dims, h.level, 0.5 ** h.level / 128) for h in hier], ppm.PPM_FP64,
+                3, False)
+    run.plan.ppm_set_hierarchy([(h.parent, 2, h.start) for h in hier])
+    run.plan.ppm_fill_boundary(0, [ppm.PPM_FACE_PERIODIC] * 6)
+    g = W.GHOST
+    out = {"workload": "nested FP64 hierarchy: 128^3 root, 64 level-1 blocks of 32^3, 512 "
+                       "level-2 blocks of 24^3 (refinement 2, siblings abutting)",
+           "levels": {}}
+    for level in (1, 2):
+        run.plan.ppm_fill_ghosts(level)   # warm-up
+    torch.cuda.synchronize()
+    for level in (1, 2):
+        cells = sum((h.dims[0] + 2 * g) ** 3 - h.dims[0] ** 3 for h in hier if h.level == level)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            run.plan.ppm_fill_ghosts(level)
+        b.record()
+        torch.cuda.synchronize()
+        sec = a.elapsed_time(b) / 1e3 / reps
+        # algorithmic bytes: 48 B written per ghost cell, plus the parent cell
+        # that covers it read once per r^3 = 8 fine cells
+        byt = cells * (48.0 + 48.0 / 8)
+        out["levels"][str(level)] = {"ghost_cells": cells, "ms": sec * 1e3,
+                                     "ghost_cells_per_s": cells / sec,
+                                     "algorithmic_GBps": byt / sec / 1e9,
+                                     "hbm_frac": byt / sec / 1e9 / HBM_PEAK_GBS}
+    run.close()
+    return out
 
 
 def measured_traffic(kernel: str):
@@ -180,6 +223,14 @@ def main():
                           "events": {"fallback_faces": fb, "floored_cells": fl}}
             log(f"hllc {name}: {cells * K / total / 1e9:.3f} G cell-updates/s")
             r.close()
+        torch.cuda.empty_cache()
+
+    amr = None
+    if not args.no_amr_fill:
+        amr = amr_ghost_fill()
+        log("amr ghost fill: " + ", ".join(
+            f"level {k} {v['ms']:.3f} ms ({v['ghost_cells_per_s'] / 1e9:.2f} G cells/s)"
+            for k, v in amr["levels"].items()))
         torch.cuda.empty_cache()
 
     # ---- batch of uneven patches, one captured graph per step
@@ -316,6 +367,8 @@ def main():
                          "tiles": mx["tiles"]}
     if hllc is not None:
         line["hllc"] = hllc
+    if amr is not None:
+        line["amr_ghost_fill"] = amr
     if batch is not None:
         line["batch"] = batch
     if cpu is not None:

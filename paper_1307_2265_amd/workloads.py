@@ -240,3 +240,42 @@ def inject_patch(root: dict, spec: HierPatch, n_root: int, ghost: int = GHOST) -
     ix, iy, iz = idx(spec.nx, spec.origin[0]), idx(spec.ny, spec.origin[1]), idx(spec.nz, spec.origin[2])
     sel = (iz[:, None, None], iy[None, :, None], ix[None, None, :])
     return {k: v[sel] for k, v in root.items()}
+
+
+# ---------------------------------------------------------------------------
+# A nested hierarchy for the patch ghost fill: a root grid, and on each finer
+# level (refinement 2) blocks of dims[l]^3 cells laid on a lattice inside every
+# patch of the level above, abutting each other (so siblings cover each
+# other's ghost cells) and kept `margin` parent cells away from the parent's
+# active edge.  Only the geometry; fields come from random_grid.
+
+@dataclass
+class NestedPatch:
+    level: int
+    parent: int          # index in the list, -1 for the root
+    start: tuple         # global index of the first active cell in its level
+    dims: tuple
+
+
+def nested_hierarchy(n_root: int, dims: tuple, per_axis: tuple, margin: int = 2) -> list:
+    """dims[l], per_axis[l]: block size and lattice of level l + 1."""
+    out = [NestedPatch(0, -1, (0, 0, 0), (n_root,) * 3)]
+    frontier = [0]
+    for lev in range(1, len(dims) + 1):
+        dim, per = dims[lev - 1], per_axis[lev - 1]
+        nxt = []
+        for pi in frontier:
+            par = out[pi]
+            span = per * dim // 2                            # parent cells the block lattice covers
+            room = par.dims[0] - 2 * margin - span
+            if room < 0:
+                continue
+            o = [par.start[a] + margin + room // 2 for a in range(3)]
+            for k in range(per):
+                for j in range(per):
+                    for i in range(per):
+                        start = (2 * o[0] + i * dim, 2 * o[1] + j * dim, 2 * o[2] + k * dim)
+                        out.append(NestedPatch(lev, pi, start, (dim, dim, dim)))
+                        nxt.append(len(out) - 1)
+        frontier = nxt
+    return out
