@@ -293,16 +293,16 @@ def main():
     flops_launch = mean_pencils * n * ops["flops"]
     sw = kern[dom]
     # kernel names as the profiler reports them (template arguments: precision,
-    # takes the next dt, spans patches)
-    kname = ("sweep_kernel<PrecF64, false, false>" if dom == "march"
-             else "sweep_lanes_kernel<PrecF64, false>")
+    # takes the next dt, spans patches, HLLC solver)
+    kname = ("sweep_kernel<PrecF64, false, false, false>" if dom == "march"
+             else "sweep_lanes_kernel<PrecF64, false, false>")
     tr = measured_traffic(kname)
     traffic = None if tr is None else tr["bytes"]
     if dom == "march" and traffic is not None:
-        tt = measured_traffic("sweep_tail_kernel<PrecF64, false>")
+        tt = measured_traffic("sweep_tail_kernel<PrecF64, false, false>")
         if tt is not None:  # mean bytes of the tail launches of the same sweeps
             traffic += tt["bytes"]
-            kname += " + sweep_tail_kernel<PrecF64, false>"
+            kname += " + sweep_tail_kernel<PrecF64, false, false>"
 
     hbm = dict(bound="hbm", achieved=bytes_launch / sw / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                frac=0.0, traffic=traffic, kernel=kname, algorithmic_bytes=bytes_launch,
@@ -323,7 +323,8 @@ def main():
         fl_h = mean_pencils * n * hops
         hllc["fp64"]["roofline"] = dict(
             bound="alu", achieved=fl_h / sw_h / 1e12, peak=FP64_OP_PEAK_T, unit="TFLOP/s",
-            frac=fl_h / sw_h / 1e12 / FP64_OP_PEAK_T, kernel=kname.split(" + ")[0],
+            frac=fl_h / sw_h / 1e12 / FP64_OP_PEAK_T,
+            kernel="sweep_kernel<PrecF64, false, false, true> + sweep_tail_kernel<PrecF64, false, true>",
             algorithmic_flops=fl_h, launch_ms=sw_h * 1e3, ops_per_cell_sweep=hops)
 
     cpu = None

@@ -411,8 +411,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     for (int c = 0; c < 2; ++c) {
       int64_t cap = pl->tail_round;  // marching threads resident at once
       if (cap == 0) {
-        const int bpc = prec == PPM_FP64 ? ppm::march_blocks_per_cu<ppm::PrecF64>(pl->block, c)
-                                         : ppm::march_blocks_per_cu<ppm::PrecMixed>(pl->block, c);
+        const bool hllc = (pl->P.flags & PPM_HLLC) != 0;
+        const int bpc = prec == PPM_FP64
+                            ? ppm::march_blocks_per_cu<ppm::PrecF64>(pl->block, c, hllc)
+                            : ppm::march_blocks_per_cu<ppm::PrecMixed>(pl->block, c, hllc);
         cap = int64_t(cus) * bpc * pl->block;
       }
       if (cap <= 0) continue;

@@ -85,7 +85,7 @@ __device__ __forceinline__ void cfl_commit_levels(double smax, int level,
 // patches of a run are views into six shared arrays at one element offset
 // per patch, so the field pointers of the run's first patch serve the whole
 // wave and only the offset, strides and cell width vary per lane.
-template <class Prec, bool kCFL, bool kGrouped>
+template <class Prec, bool kCFL, bool kGrouped, bool kUseHLLC>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
              int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
@@ -132,7 +132,7 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
       pc.rho = ref.rho; pc.u = ref.u; pc.v1 = ref.v1; pc.v2 = ref.v2; pc.E = ref.E; pc.e = ref.e;
     }
     const double dt = dt_dev[pd.level];
-    march_pencil<Prec, kCFL>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
+    march_pencil<Prec, kCFL, kUseHLLC>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
   }
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
@@ -145,7 +145,7 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
 // One wavefront streams a run of `rows` consecutive pencils (rows_per_wave(n)
 // if rows is 0) with the cells across its lanes, from pencil `pencil0` of the
 // patch on.
-template <class Prec, bool kCFL>
+template <class Prec, bool kCFL, bool kUseHLLC>
 __device__ __forceinline__ void stream_pencils(const PatchDev *__restrict__ patches,
                                                const int32_t *__restrict__ chunk_start,
                                                int32_t npatch, int32_t axis, int32_t mask,
@@ -165,32 +165,35 @@ __device__ __forceinline__ void stream_pencils(const PatchDev *__restrict__ patc
   const double dt = dt_dev[pd.level];
   uint32_t nfb = 0, nfl = 0;
   CflAcc cfl = cfl_acc(pd, axis, nullptr);
-  sweep_rows_lanes<Prec, kCFL>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl, cfl);
+  sweep_rows_lanes<Prec, kCFL, kUseHLLC>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl,
+                                         cfl);
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
   if (kCFL) cfl_commit(cfl.smax, &smax_bits[pd.level]);
 }
 
 // Lane-parallel sweep: each wavefront streams rows_per_wave(n) pencils.
-template <class Prec, bool kCFL>
+template <class Prec, bool kCFL, bool kUseHLLC>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
                    int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
                    Params P, unsigned long long *__restrict__ counters,
                    unsigned long long *__restrict__ smax_bits) {
-  stream_pencils<Prec, kCFL>(patches, chunk_start, npatch, axis, mask, 0, 0, dt_dev, P, counters,
+  stream_pencils<Prec, kCFL, kUseHLLC>(patches, chunk_start, npatch, axis, mask, 0, 0, dt_dev, P,
+                                       counters,
                              smax_bits);
 }
 
 // The pencils of one patch from `pencil0` on, one per wavefront: what is
 // left of a marching sweep after whole rounds of resident marching threads.
-template <class Prec, bool kCFL>
+template <class Prec, bool kCFL, bool kUseHLLC>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_tail_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
                   int32_t axis, int32_t mask, int32_t pencil0, const double *__restrict__ dt_dev,
                   Params P, unsigned long long *__restrict__ counters,
                   unsigned long long *__restrict__ smax_bits) {
-  stream_pencils<Prec, kCFL>(patches, chunk_start, 1, axis, mask, pencil0, 1, dt_dev, P, counters,
+  stream_pencils<Prec, kCFL, kUseHLLC>(patches, chunk_start, 1, axis, mask, pencil0, 1, dt_dev, P,
+                                       counters,
                              smax_bits);
 }
 
@@ -207,7 +210,7 @@ sweep_tail_kernel(const PatchDev *__restrict__ patches, const int32_t *__restric
 __constant__ int kStepOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1},
                                       {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
 
-template <class Prec, bool kCFL>
+template <class Prec, bool kCFL, bool kUseHLLC>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ order,
                         int32_t npatch, int32_t sweep_order, int32_t lanes_mask,
@@ -245,20 +248,22 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
         const int K = rows_per_wave(n);
         for (int first = wave * K; first < np; first += waves * K) {
           if (kCFL && k == 2)
-            sweep_rows_lanes<Prec, true>(P, pd, axis, mask, first, min(K, np - first), dt, nfb,
-                                         nfl, cfl);
+            sweep_rows_lanes<Prec, true, kUseHLLC>(P, pd, axis, mask, first, min(K, np - first),
+                                                   dt, nfb, nfl, cfl);
           else
-            sweep_rows_lanes<Prec, false>(P, pd, axis, mask, first, min(K, np - first), dt, nfb,
-                                          nfl, cfl);
+            sweep_rows_lanes<Prec, false, kUseHLLC>(P, pd, axis, mask, first, min(K, np - first),
+                                                    dt, nfb, nfl, cfl);
         }
       } else {
         for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
           pencil_index(pd, axis, mask, idx, i1, i2);
           const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
           if (kCFL && k == 2)
-            march_pencil<Prec, true>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
+            march_pencil<Prec, true, kUseHLLC>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl,
+                                               cfl);
           else
-            march_pencil<Prec, false>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
+            march_pencil<Prec, false, kUseHLLC>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb,
+                                                nfl, cfl);
         }
       }
       if (kCFL && k == 2)
@@ -654,17 +659,22 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
                         unsigned long long *smax_bits, const int32_t *groups, int32_t ngroups,
                         hipStream_t s) {
   const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
-#define PPM_LAUNCH_MARCH(CFL, GRP)                                                           \
-  hipLaunchKernelGGL((sweep_kernel<Prec, CFL, GRP>), dim3(nblocks), dim3(block), lds, s,      \
+  const bool hllc = (P.flags & kHLLC) != 0;
+#define PPM_LAUNCH_MARCH(CFL, GRP, HLLC)                                                     \
+  hipLaunchKernelGGL((sweep_kernel<Prec, CFL, GRP, HLLC>), dim3(nblocks), dim3(block), lds, s, \
                      patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits, \
                      groups, ngroups)
+#define PPM_LAUNCH_MARCH_SOLVER(CFL, GRP)                \
+  if (hllc) PPM_LAUNCH_MARCH(CFL, GRP, true);            \
+  else PPM_LAUNCH_MARCH(CFL, GRP, false)
   if (groups) {
-    if (smax_bits) PPM_LAUNCH_MARCH(true, true);
-    else PPM_LAUNCH_MARCH(false, true);
+    if (smax_bits) { PPM_LAUNCH_MARCH_SOLVER(true, true); }
+    else { PPM_LAUNCH_MARCH_SOLVER(false, true); }
   } else {
-    if (smax_bits) PPM_LAUNCH_MARCH(true, false);
-    else PPM_LAUNCH_MARCH(false, false);
+    if (smax_bits) { PPM_LAUNCH_MARCH_SOLVER(true, false); }
+    else { PPM_LAUNCH_MARCH_SOLVER(false, false); }
   }
+#undef PPM_LAUNCH_MARCH_SOLVER
 #undef PPM_LAUNCH_MARCH
   return hipGetLastError();
 }
@@ -675,12 +685,18 @@ hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_star
                               const double *dt_dev, const Params &P,
                               unsigned long long *counters, unsigned long long *smax_bits,
                               hipStream_t s) {
-  if (smax_bits)
-    hipLaunchKernelGGL((sweep_lanes_kernel<Prec, true>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
-  else
-    hipLaunchKernelGGL((sweep_lanes_kernel<Prec, false>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits);
+#define PPM_LAUNCH_LANES(CFL, HLLC)                                                          \
+  hipLaunchKernelGGL((sweep_lanes_kernel<Prec, CFL, HLLC>), dim3(nblocks), dim3(block), 0, s, \
+                     patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits)
+  const bool hllc = (P.flags & kHLLC) != 0;
+  if (smax_bits) {
+    if (hllc) PPM_LAUNCH_LANES(true, true);
+    else PPM_LAUNCH_LANES(true, false);
+  } else {
+    if (hllc) PPM_LAUNCH_LANES(false, true);
+    else PPM_LAUNCH_LANES(false, false);
+  }
+#undef PPM_LAUNCH_LANES
   return hipGetLastError();
 }
 
@@ -689,26 +705,30 @@ hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start
                              int32_t block, int32_t axis, int32_t mask, int32_t pencil0,
                              const double *dt_dev, const Params &P, unsigned long long *counters,
                              unsigned long long *smax_bits, hipStream_t s) {
-  if (smax_bits)
-    hipLaunchKernelGGL((sweep_tail_kernel<Prec, true>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, axis, mask, pencil0, dt_dev, P, counters, smax_bits);
-  else
-    hipLaunchKernelGGL((sweep_tail_kernel<Prec, false>), dim3(nblocks), dim3(block), 0, s,
-                       patches, chunk_start, axis, mask, pencil0, dt_dev, P, counters, smax_bits);
+#define PPM_LAUNCH_TAIL(CFL, HLLC)                                                           \
+  hipLaunchKernelGGL((sweep_tail_kernel<Prec, CFL, HLLC>), dim3(nblocks), dim3(block), 0, s,  \
+                     patches, chunk_start, axis, mask, pencil0, dt_dev, P, counters, smax_bits)
+  const bool hllc = (P.flags & kHLLC) != 0;
+  if (smax_bits) {
+    if (hllc) PPM_LAUNCH_TAIL(true, true);
+    else PPM_LAUNCH_TAIL(true, false);
+  } else {
+    if (hllc) PPM_LAUNCH_TAIL(false, true);
+    else PPM_LAUNCH_TAIL(false, false);
+  }
+#undef PPM_LAUNCH_TAIL
   return hipGetLastError();
 }
 
 template <class Prec>
-int march_blocks_per_cu(int32_t block, bool cfl) {
+int march_blocks_per_cu(int32_t block, bool cfl, bool hllc) {
   const size_t lds = size_t(kLdsMarch + (cfl ? 1 : 0)) * block * sizeof(double);
+  const void *k = cfl ? (hllc ? reinterpret_cast<const void *>(sweep_kernel<Prec, true, false, true>)
+                              : reinterpret_cast<const void *>(sweep_kernel<Prec, true, false, false>))
+                      : (hllc ? reinterpret_cast<const void *>(sweep_kernel<Prec, false, false, true>)
+                              : reinterpret_cast<const void *>(sweep_kernel<Prec, false, false, false>));
   int nb = 0;
-  hipError_t e = cfl ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &nb, reinterpret_cast<const void *>(sweep_kernel<Prec, true, false>),
-                           block, lds)
-                     : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                           &nb, reinterpret_cast<const void *>(sweep_kernel<Prec, false, false>),
-                           block, lds);
-  return e == hipSuccess ? nb : 0;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, block, lds) == hipSuccess ? nb : 0;
 }
 
 template <class Prec>
@@ -717,14 +737,19 @@ hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t n
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned int *queue, unsigned long long *smax_bits, hipStream_t s) {
   const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
-  if (smax_bits)
-    hipLaunchKernelGGL((batch_persistent_kernel<Prec, true>), dim3(nblocks), dim3(block), lds, s,
-                       patches, order, npatch, sweep_order, lanes_mask, dt_dev, P, counters,
-                       queue, smax_bits);
-  else
-    hipLaunchKernelGGL((batch_persistent_kernel<Prec, false>), dim3(nblocks), dim3(block), lds,
-                       s, patches, order, npatch, sweep_order, lanes_mask, dt_dev, P, counters,
-                       queue, smax_bits);
+#define PPM_LAUNCH_BATCH(CFL, HLLC)                                                         \
+  hipLaunchKernelGGL((batch_persistent_kernel<Prec, CFL, HLLC>), dim3(nblocks), dim3(block), \
+                     lds, s, patches, order, npatch, sweep_order, lanes_mask, dt_dev, P,    \
+                     counters, queue, smax_bits)
+  const bool hllc = (P.flags & kHLLC) != 0;
+  if (smax_bits) {
+    if (hllc) PPM_LAUNCH_BATCH(true, true);
+    else PPM_LAUNCH_BATCH(true, false);
+  } else {
+    if (hllc) PPM_LAUNCH_BATCH(false, true);
+    else PPM_LAUNCH_BATCH(false, false);
+  }
+#undef PPM_LAUNCH_BATCH
   return hipGetLastError();
 }
 
@@ -803,7 +828,7 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                               int32_t, int32_t, int32_t, const double *,          \
                                               const Params &, unsigned long long *,               \
                                               unsigned long long *, hipStream_t);                  \
-  template int march_blocks_per_cu<Prec>(int32_t, bool);                                          \
+  template int march_blocks_per_cu<Prec>(int32_t, bool, bool);                                    \
   template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *, unsigned int *,    \

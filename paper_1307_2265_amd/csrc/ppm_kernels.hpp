@@ -37,9 +37,10 @@ hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start
                              unsigned long long *smax_bits, hipStream_t s);
 
 // Resident workgroups per compute unit of the (ungrouped) marching sweep
-// with `block` threads, with or without the CFL maximum; 0 if unknown.
+// with `block` threads, with or without the CFL maximum, for the two-shock
+// or the HLLC build; 0 if unknown.
 template <class Prec>
-int march_blocks_per_cu(int32_t block, bool cfl);
+int march_blocks_per_cu(int32_t block, bool cfl, bool hllc);
 
 // Persistent batch kernel: the whole step of every patch in one launch.
 template <class Prec>

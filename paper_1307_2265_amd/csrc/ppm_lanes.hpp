@@ -75,7 +75,7 @@ struct CellLoad {
 // lane beyond the stream, which no valid result uses).  `in` is this lane's
 // input cell; the lane writes its cell (and counts its events) if `mine`.
 // lam = dt / pc.dx (the same for every pencil of the patch).
-template <class Prec, bool kCFL>
+template <class Prec, bool kCFL, bool kUseHLLC>
 __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                               double lam, int j, bool mine, const CellLoad &in,
                               uint32_t &n_fallback, uint32_t &n_floor, CflAcc &cfl) {
@@ -170,7 +170,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
 #pragma unroll
   for (int k = 0; k < 7; ++k) F.f[k] = 0.0;
   if (face_ok) {
-    F = riemann_flux(P, double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p),
+    F = riemann_flux<kUseHLLC>(P, double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p),
                      double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p));
   }
 
@@ -235,7 +235,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
 
 // One wave streams pencils first .. first+nrows-1 of a sweep's pencil set,
 // concatenated, segment by segment.
-template <class Prec, bool kCFL>
+template <class Prec, bool kCFL, bool kUseHLLC>
 __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, int mask,
                                  int first, int nrows, double dt, uint32_t &n_fallback,
                                  uint32_t &n_floor, CflAcc &cfl) {
@@ -273,7 +273,7 @@ __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, 
       cur = CellLoad{1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
     }
     const bool mine = in && lane >= kLaneHalo && lane < kLaneHalo + kLaneOut;
-    sweep_segment<Prec, kCFL>(P, pc, dt, lam, j, mine, cur, n_fallback, n_floor, cfl);
+    sweep_segment<Prec, kCFL, kUseHLLC>(P, pc, dt, lam, j, mine, cur, n_fallback, n_floor, cfl);
   }
 }
 

@@ -203,7 +203,7 @@ __device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis, double *
 
 // One thread marches one pencil.  kCFL: also take the signal speed of every
 // cell written (the sweep must then be the last of its step).
-template <class Prec, bool kCFL>
+template <class Prec, bool kCFL, bool kUseHLLC>
 __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                              double *lds_slots, int slot_stride, uint32_t &n_fallback,
                              uint32_t &n_floor, CflAcc &cfl) {
@@ -366,7 +366,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     for (int j = 0; j < 7; ++j) ft_c.f[j] = 0.0;
     double *slot_c = lds_slots + (k & 1) * kSlotDoubles * slot_stride;
     if (r - 1 >= a0 - 1 && r - 1 <= a1) {
-      ft_c = riemann_flux(P, double(lcarry.r), double(lcarry.u), double(lcarry.v1),
+      ft_c = riemann_flux<kUseHLLC>(P, double(lcarry.r), double(lcarry.u), double(lcarry.v1),
                           double(lcarry.v2), double(lcarry.p), double(rstate.r),
                           double(rstate.u), double(rstate.v1), double(rstate.v2),
                           double(rstate.p));

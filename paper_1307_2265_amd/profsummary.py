@@ -3,6 +3,8 @@
 kernels  -- from a `rocprofv3 --kernel-trace --stats --output-format csv`
             run: per kernel (and per launch grid of the sweep kernels) the
             number of dispatches and their mean / total duration.
+sq       -- from one `rocprofv3 --pmc` run of SQ counters: issue and wait
+            fractions and VALU instructions per wave of the sweep kernels.
 traffic  -- from two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs:
             HBM bytes per dispatch of every kernel, each counter scaled by
             what it reads for a device-to-device copy of known size that the
@@ -84,8 +86,11 @@ def kernels(stats_csv: str, trace_csv: str, cmd: str, out: str):
     sweeps = []
     for prec in ("PrecF64", "PrecMixed"):
         for cfl in ("false", "true"):
-            m, t = f"sweep_kernel<{prec}, {cfl}, false>", f"sweep_tail_kernel<{prec}, {cfl}>"
-            if m in means and t in means:
+            for hllc in ("false", "true"):
+                m = f"sweep_kernel<{prec}, {cfl}, false, {hllc}>"
+                t = f"sweep_tail_kernel<{prec}, {cfl}, {hllc}>"
+                if m not in means or t not in means:
+                    continue
                 sweeps.append(f"| `{m}` + `{t}` | {means[m]:.3f} | {means[t]:.3f} | "
                               f"{means[m] + means[t]:.3f} |")
     if sweeps:
@@ -167,9 +172,48 @@ def traffic(fetch_csv: str, write_csv: str, n: int, ghost: int, cmd_fetch: str, 
                        "kernels": per_kernel}, fo, indent=1)
 
 
+def sq(counters_csv: str, cmd: str, out: str):
+    """Per dispatch group (kernel, grid): per-wave fractions of SQ_WAVE_CYCLES
+    issuing VALU / anything, waiting on memory counters, ready but not issued,
+    and VALU instructions per wave."""
+    agg = collections.defaultdict(lambda: collections.defaultdict(float))
+    n = collections.Counter()
+    for r in csv.DictReader(open(counters_csv)):
+        k = (short(r["Kernel_Name"]), int(r["Grid_Size"]), int(r["Workgroup_Size"]))
+        agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
+        if r["Counter_Name"] == "SQ_WAVES":
+            n[k] += 1
+    lines = [f"# SQ counters: {os.path.basename(out)[:-3]}", "",
+             "Command (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```", cmd, "```", "",
+             "Per dispatch group (kernel, grid threads): per-wave fractions of SQ_WAVE_CYCLES spent "
+             "issuing VALU (SQ_ACTIVE_INST_VALU), issuing anything (SQ_ACTIVE_INST_ANY), waiting on "
+             "a memory counter (SQ_WAIT_ANY) and ready but not issued (SQ_WAIT_INST_ANY); VALU "
+             "instructions per wave.  With w waves per SIMD sharing one VALU, w x the VALU fraction "
+             "is the SIMD's VALU occupancy (the marching kernels hold 2 waves per SIMD, the lane "
+             "kernels 4; values slightly above 1 come from the counters' cycle granularity).", "",
+             "| kernel | grid threads | block | dispatches | waves | VALU | any | wait mem | "
+             "wait issue | VALU instr / wave |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    for k, c in sorted(agg.items()):
+        if "sweep" not in k[0]:
+            continue
+        wc = c["SQ_WAVE_CYCLES"]
+        lines.append(f"| `{k[0]}` | {k[1]} | {k[2]} | {n[k]} | {c['SQ_WAVES'] / n[k]:.0f} | "
+                     f"{c['SQ_ACTIVE_INST_VALU'] / wc:.2f} | {c['SQ_ACTIVE_INST_ANY'] / wc:.2f} | "
+                     f"{c['SQ_WAIT_ANY'] / wc:.2f} | {c['SQ_WAIT_INST_ANY'] / wc:.2f} | "
+                     f"{c['SQ_INSTS_VALU'] / c['SQ_WAVES']:.0f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("counters")
+    q.add_argument("--cmd", required=True)
+    q.add_argument("--out", required=True)
     k = sub.add_parser("kernels")
     k.add_argument("stats")
     k.add_argument("trace")
@@ -185,7 +229,9 @@ def main():
     t.add_argument("--out", required=True)
     t.add_argument("--json", default=None)
     a = ap.parse_args()
-    if a.mode == "kernels":
+    if a.mode == "sq":
+        sq(a.counters, a.cmd, a.out)
+    elif a.mode == "kernels":
         kernels(a.stats, a.trace, a.cmd, a.out)
     else:
         traffic(a.fetch, a.write, a.n, a.ghost, a.cmd_fetch, a.cmd_write, a.out, a.json)
