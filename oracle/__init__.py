@@ -45,14 +45,15 @@ class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("cfl", C.c_double), ("eta1", C.c_double),
                 ("eta2", C.c_double), ("rho_floor", C.c_double), ("p_floor", C.c_double),
                 ("e_floor", C.c_double), ("riemann_rtol", C.c_double),
-                ("riemann_max_iter", C.c_int32), ("flags", C.c_uint32)]
+                ("riemann_max_iter", C.c_int32), ("flags", C.c_uint32),
+                ("a", C.c_double), ("adot", C.c_double)]
 
 
 class _Grid(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("ghost", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double)] + \
                [(f, C.POINTER(C.c_double)) for f in
-                ("rho", "vx", "vy", "vz", "etot", "eint", "flux_reg")]
+                ("rho", "vx", "vy", "vz", "etot", "eint", "flux_reg", "gx", "gy", "gz")]
 
 
 class Counts(C.Structure):
@@ -60,9 +61,10 @@ class Counts(C.Structure):
 
 
 def params(gamma=5.0 / 3.0, cfl=0.4, eta1=1e-3, eta2=0.1, rho_floor=1e-20, p_floor=1e-20,
-           e_floor=1e-30, riemann_rtol=1e-13, riemann_max_iter=20, flags=ALL_FLAGS) -> Params:
+           e_floor=1e-30, riemann_rtol=1e-13, riemann_max_iter=20, flags=ALL_FLAGS,
+           a=1.0, adot=0.0) -> Params:
     return Params(gamma, cfl, eta1, eta2, rho_floor, p_floor, e_floor, riemann_rtol,
-                  riemann_max_iter, flags)
+                  riemann_max_iter, flags, a, adot)
 
 
 _lib = None
@@ -89,6 +91,7 @@ def lib():
         L.ppmo_cfl_dt.restype = C.c_double
         L.ppmo_cfl_dt.argtypes = [C.POINTER(_Grid), C.POINTER(Params)]
         L.ppmo_fill_periodic.argtypes = [C.POINTER(_Grid)]
+        L.ppmo_expansion.argtypes = [C.POINTER(_Grid), C.POINTER(Params), C.c_double]
         L.ppmo_fill_boundary.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32), dp]
         L.ppmo_second_order_a.argtypes = [dp, C.c_int32, dp]
         L.ppmo_fill_from_parent.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32),
@@ -130,6 +133,7 @@ class Grid:
     dz: float
     ghost: int = 3
     flux_reg: np.ndarray | None = None
+    accel: tuple | None = None  # (gx, gy, gz) at the cell centres, same shape as the fields
 
     @property
     def active_shape(self):
@@ -142,14 +146,23 @@ class Grid:
 
     def copy(self) -> "Grid":
         return Grid(*[f.copy() for f in self.fields()], self.dx, self.dy, self.dz, self.ghost,
-                    None if self.flux_reg is None else self.flux_reg.copy())
+                    None if self.flux_reg is None else self.flux_reg.copy(),
+                    None if self.accel is None else tuple(a.copy() for a in self.accel))
 
     def _c(self) -> _Grid:
         nx, ny, nz = self.active_shape
-        for f in self.fields():
+        for f in self.fields() + list(self.accel or ()):
             assert f.dtype == np.float64 and f.flags.c_contiguous and f.shape == self.rho.shape
+        acc = [_ptr(a) for a in self.accel] if self.accel is not None else [None] * 3
         return _Grid(nx, ny, nz, self.ghost, self.dx, self.dy, self.dz,
-                     *[_ptr(f) for f in self.fields()], _ptr(self.flux_reg))
+                     *[_ptr(f) for f in self.fields()], _ptr(self.flux_reg), *acc)
+
+
+def expansion(grid: Grid, prm: Params, dt: float) -> None:
+    """The split expansion terms of the comoving equations over dt (active cells)."""
+    g = grid._c()
+    if lib().ppmo_expansion(C.byref(g), C.byref(prm), float(dt)) != 0:
+        raise ValueError("ppmo_expansion: invalid argument")
 
 
 def flux_reg_size(nx, ny, nz) -> int:

@@ -393,14 +393,19 @@ int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1)
 
 // ---------------------------------------------------------------------------
 // Step 8: conservative update of one active cell from its two face fluxes
-// (Eqs. mass_diff, momentum_diff, energy_diff, gasenergy_diff with a = 1,
-// g = 0), then the eta2 resync of e (Eq. dualselect).  Returns true when the
-// new density or the eta1-selected new internal energy is not positive.
+// (Eqs. mass_diff, momentum_diff, energy_diff, gasenergy_diff; dtdx = dt /
+// (a dx) in comoving coordinates), then the eta2 resync of e (Eq.
+// dualselect).  With a gravity field, the time-centred source terms of Eqs.
+// momentum_diff and energy_diff: momentum + (dt/2)(g/a)(rho^n + rho^{n+1}),
+// total energy + (dt/2)(g/a)(rho^n u^n + rho^{n+1} u^{n+1}), with g the
+// acceleration along the sweep at the cell centre (hg = 0.5 dt / a times it).
+// Returns true when the new density or the eta1-selected new internal
+// energy is not positive.
 template <class R> struct CellIn { R rho, u, v1, v2, E, e, p, rhoEmax; };
 
 template <class R>
 bool update_cell(const ppmo_params &P, R dtdx, const CellIn<R> &c, const R *Fm, const R *Fp,
-                 R *out) {
+                 R *out, bool grav = false, R hg = R(0.0)) {
   const bool dual = (P.flags & PPMO_DUAL_ENERGY) != 0;
   R rn = c.rho - dtdx * (Fp[FR] - Fm[FR]);
   R mu = c.rho * c.u - dtdx * (Fp[FU] - Fm[FU]);
@@ -408,6 +413,10 @@ bool update_cell(const ppmo_params &P, R dtdx, const CellIn<R> &c, const R *Fm, 
   R m2 = c.rho * c.v2 - dtdx * (Fp[FV2] - Fm[FV2]);
   R mE = c.rho * c.E - dtdx * (Fp[FE] - Fm[FE]);
   R me = c.rho * c.e - dtdx * (Fp[FEI] - Fm[FEI]) - dtdx * c.p * (Fp[FUB] - Fm[FUB]);
+  if (grav) {
+    mu = mu + hg * (c.rho + rn);
+    mE = mE + hg * (c.rho * c.u + mu);
+  }
   R ir = 1.0 / rn;
   R un = mu * ir, v1n = m1 * ir, v2n = m2 * ir, En = mE * ir, eraw = me * ir;
   R ke = 0.5 * (un * un + v1n * v1n + v2n * v2n);
@@ -442,10 +451,12 @@ void floor_cell(const ppmo_params &P, const CellIn<R> &c, R *out) {
 // covers every cell whose stencil fits in the pencil.
 template <class R>
 void pencil_sweep(const ppmo_params &P, int n, int gh, R dt, R dx, R *rho, R *u, R *v1, R *v2,
-                  R *Etot, R *eint, R *reg_lo, R *reg_hi, ppmo_counts *cnt, Work<R> &w) {
+                  R *Etot, R *eint, R *reg_lo, R *reg_hi, ppmo_counts *cnt, Work<R> &w,
+                  const R *acc = nullptr) {
   const double g = P.gamma;
   const int a0 = gh, a1 = n - gh - 1;
-  const R dtdx = dt / dx;
+  const R dtdx = dt / (P.a * dx);
+  const R hgdt = 0.5 * dt / P.a;
   w.resize(n);
   R *a[NQ];
   for (int k = 0; k < NQ; ++k) a[k] = w.q[k].data();
@@ -649,7 +660,8 @@ void pencil_sweep(const ppmo_params &P, int n, int gh, R dt, R dx, R *rho, R *u,
   auto do_update = [&](int j) {
     R Fm[NF], Fp[NF];
     for (int k = 0; k < NF; ++k) { Fm[k] = w.F[k][j - 1]; Fp[k] = w.F[k][j]; }
-    return update_cell<R>(P, dtdx, cell_in(j), Fm, Fp, &out[(size_t)j * 6]);
+    return update_cell<R>(P, dtdx, cell_in(j), Fm, Fp, &out[(size_t)j * 6], acc != nullptr,
+                          acc ? hgdt * acc[j] : R(0.0));
   };
   for (int j = 0; j < n; ++j) w.bad[j] = 0;
   for (int j = a0; j <= a1; ++j) w.bad[j] = do_update(j) ? 1 : 0;
@@ -697,11 +709,13 @@ void pencil_sweep(const ppmo_params &P, int n, int gh, R dt, R dx, R *rho, R *u,
 bool valid_grid(const ppmo_grid *g) {
   return g && g->nx >= 1 && g->ny >= 1 && g->nz >= 1 && g->ghost >= 3 && g->ghost <= 6 &&
          g->dx > 0 &&
-         g->dy > 0 && g->dz > 0 && g->rho && g->vx && g->vy && g->vz && g->etot && g->eint;
+         g->dy > 0 && g->dz > 0 && g->rho && g->vx && g->vy && g->vz && g->etot && g->eint &&
+         ((g->gx && g->gy && g->gz) || (!g->gx && !g->gy && !g->gz));
 }
 bool valid_params(const ppmo_params *p) {
   return p && p->gamma > 1.0 && p->cfl > 0.0 && p->cfl <= 1.0 && p->riemann_max_iter >= 1 &&
-         p->riemann_rtol > 0.0 && p->rho_floor > 0.0 && p->p_floor > 0.0 && p->e_floor > 0.0;
+         p->riemann_rtol > 0.0 && p->rho_floor > 0.0 && p->p_floor > 0.0 && p->e_floor > 0.0 &&
+         p->a > 0.0 && std::isfinite(p->a) && std::isfinite(p->adot);
 }
 
 // Offset of face f's block in a grid's flux register.
@@ -741,8 +755,9 @@ int sweep_impl(ppmo_grid *G, const ppmo_params *P, double dt, int axis, int acti
 #pragma omp parallel reduction(+ : fb, fl)
   {
     Work<R> w;
-    std::vector<R> r(len), uu(len), a1(len), a2(len), E(len), e(len);
+    std::vector<R> r(len), uu(len), a1(len), a2(len), E(len), e(len), ga(len);
     std::vector<R> rl(6), rh(6);
+    const double *gfield = axis == 0 ? G->gx : (axis == 1 ? G->gy : G->gz);
     ppmo_counts c = {0, 0};
 #pragma omp for schedule(static)
     for (int64_t ip = 0; ip < np; ++ip) {
@@ -753,11 +768,12 @@ int sweep_impl(ppmo_grid *G, const ppmo_params *P, double dt, int axis, int acti
         const int64_t o = base + k * stride[axis];
         r[k] = G->rho[o]; uu[k] = vel[axis][o]; a1[k] = vel[t1][o]; a2[k] = vel[t2][o];
         E[k] = G->etot[o]; e[k] = G->eint[o];
+        if (gfield) ga[k] = gfield[o];
       }
       const bool reg = G->flux_reg && i1 >= g && i1 < g + N[t1] && i2 >= g && i2 < g + N[t2];
       pencil_sweep<R>(*P, len, g, R(dt), R(dxs[axis]), r.data(), uu.data(), a1.data(), a2.data(),
                       E.data(), e.data(), reg ? rl.data() : nullptr, reg ? rh.data() : nullptr,
-                      &c, w);
+                      &c, w, gfield ? ga.data() : nullptr);
       for (int k = g; k < g + N[axis]; ++k) {
         const int64_t o = base + k * stride[axis];
         G->rho[o] = opc_val(r[k]); vel[axis][o] = opc_val(uu[k]);
@@ -855,7 +871,30 @@ double ppmo_cfl_signal_max(const ppmo_grid *G, const ppmo_params *P) {
 double ppmo_cfl_dt(const ppmo_grid *G, const ppmo_params *P) {
   double s = ppmo_cfl_signal_max(G, P);
   if (!(s > 0)) return -1.0;
-  return P->cfl / s;
+  return (P->cfl * P->a) / s;  // Eq. dthydro: kappa a dx / (c_s + |v|)
+}
+
+int ppmo_expansion(ppmo_grid *G, const ppmo_params *P, double dt) {
+  if (!valid_grid(G) || !valid_params(P) || !(dt >= 0)) return -1;
+  const int g = G->ghost;
+  const int N[3] = {G->nx, G->ny, G->nz};
+  const int64_t n[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
+  const double H = P->adot / P->a;
+  const double xv = 0.5 * H * dt, xE = H * dt, xe = 1.5 * (P->gamma - 1.0) * H * dt;
+  const double fv = (1.0 - xv) / (1.0 + xv);
+  const double fE = (1.0 - xE) / (1.0 + xE);
+  const double fe = (1.0 - xe) / (1.0 + xe);
+  for (int64_t z = g; z < g + N[2]; ++z)
+    for (int64_t y = g; y < g + N[1]; ++y)
+      for (int64_t x = g; x < g + N[0]; ++x) {
+        const int64_t o = (z * n[1] + y) * n[0] + x;
+        G->vx[o] = G->vx[o] * fv;
+        G->vy[o] = G->vy[o] * fv;
+        G->vz[o] = G->vz[o] * fv;
+        G->etot[o] = G->etot[o] * fE;
+        G->eint[o] = G->eint[o] * fe;
+      }
+  return 0;
 }
 
 int ppmo_fill_periodic(ppmo_grid *G) {

@@ -95,6 +95,7 @@ typedef struct {
   double riemann_rtol; /* relative convergence tolerance on p* */
   int32_t riemann_max_iter;
   uint32_t flags;
+  double a, adot;      /* expansion factor and its rate at the half step (1, 0: static) */
 } ppmo_params;
 
 typedef struct {
@@ -102,6 +103,8 @@ typedef struct {
   double dx, dy, dz;
   double *rho, *vx, *vy, *vz, *etot, *eint;
   double *flux_reg; /* nullable */
+  double *gx, *gy, *gz; /* nullable: gravitational acceleration at the cell centres at the
+                           half step (all three or none), same layout as the fields */
 } ppmo_grid;
 
 /* Counters of the rare numerical events of a sweep or step. */
@@ -133,7 +136,14 @@ int ppmo_pencil(const ppmo_params *p, int32_t n, int32_t ghost, double dt, doubl
                 double *rho, double *u, double *v1, double *v2, double *etot,
                 double *eint, double *reg_lo, double *reg_hi, ppmo_counts *counts);
 
-/* max over active cells of sum_d (c_s + |v_d|)/dx_d, and kappa / that max. */
+/* Expansion terms of the comoving equations (Sec. "Physical Equations", split
+ * from the sweeps and solved implicitly and time-centred over dt with H =
+ * adot / a of the parameters): peculiar velocity x (1 - H dt/2)/(1 + H dt/2),
+ * specific total energy x (1 - H dt)/(1 + H dt), specific internal energy
+ * x (1 - 3(gamma-1) H dt/2)/(1 + 3(gamma-1) H dt/2), over the active cells. */
+int ppmo_expansion(ppmo_grid *g, const ppmo_params *p, double dt);
+
+/* max over active cells of sum_d (c_s + |v_d|)/dx_d, and kappa a / that max. */
 double ppmo_cfl_signal_max(const ppmo_grid *g, const ppmo_params *p);
 double ppmo_cfl_dt(const ppmo_grid *g, const ppmo_params *p);
 
