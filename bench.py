@@ -11,7 +11,9 @@ synthetic and resident in HBM when the timed region starts; launch shapes
 come from the autotuner's table (data/tiles.json) when it exists.
 
 Also measured: the same grid and steps with the HLLC solver in place of
-two-shock (FP64 and mixed); the AMR patch ghost fill (parent interpolation and
+two-shock (FP64 and mixed); the same grid with a seeded acceleration field
+and comoving expansion factors (gravity sources in every sweep, a pass of the
+expansion terms per step, FP64 and mixed); the AMR patch ghost fill (parent interpolation and
 sibling copies) on a nested hierarchy; the batched form -- 4096 uneven AMR patches (dims from
 {8,12,16,24,32}, levels 0-6 with their own dt, seeded ghosts, flux registers
 on) advanced by replaying one captured HIP graph per step (the three sweeps
@@ -65,6 +67,8 @@ def parse():
     ap.add_argument("--batch-tiles", default=None, help="tile_config of the batch plans")
     ap.add_argument("--no-hllc", action="store_true", help="skip the HLLC-solver runs")
     ap.add_argument("--no-amr-fill", action="store_true", help="skip the AMR ghost-fill timing")
+    ap.add_argument("--no-sources", action="store_true",
+                    help="skip the runs with gravity and comoving expansion")
     return ap.parse_args()
 
 
@@ -225,6 +229,48 @@ def main():
             r.close()
         torch.cuda.empty_cache()
 
+    # ---- the same grid with an acceleration field and comoving expansion:
+    # every sweep adds the gravity sources and divides by a, and a pass of
+    # the expansion terms precedes the sweeps
+    sources = None
+    if not args.no_sources:
+        src = dict(seed=4242, amp=3.0, a=1.7, adot=0.6)
+        sources = {"recipe": "acceleration: 4 random plane waves per component over the "
+                             "ghosted box, amplitude 3; a = 1.7, adot = 0.6", "kernels": {}}
+        for name, prec in (("fp64", ppm.PPM_FP64), ("mixed", ppm.PPM_MIXED)):
+            if name == "mixed" and args.no_mixed:
+                continue
+            tiles = args.tiles or autotune.best_tiles(f"single/{name}")
+            r = H.Run.single(d, n, prec, tiles, sources=src)
+            for s in range(Wm):
+                r.step(s)
+            torch.cuda.synchronize()
+            r.reset()
+            r.plan.ppm_event_counts(reset=True)
+            total, sk = r.timed(K, per_sweep=True)
+            fb, fl = r.plan.ppm_event_counts()
+            ex_ms = sk["expansion"] * 1e3
+            # algorithmic bytes of the expansion pass: read and write the three
+            # velocities (storage type) and the two energies (double) per cell
+            ex_bytes = cells * 2 * (3 * (8 if name == "fp64" else 4) + 2 * 8)
+            sources[name] = {"value": cells * K / total, "unit": "cell-updates/s",
+                             "ms_per_step": total / K * 1e3, "tiles": tiles,
+                             "sweep_kernel_ms": {k: v * 1e3 for k, v in sk.items()},
+                             "slowdown_vs_static": total / results[name]["seconds"],
+                             "expansion": {"ms": ex_ms, "bytes": ex_bytes,
+                                           "GB_per_s": ex_bytes / (ex_ms / 1e3) / 1e9,
+                                           "frac_of_hbm_peak":
+                                               ex_bytes / (ex_ms / 1e3) / 1e9 / HBM_PEAK_GBS},
+                             "events": {"fallback_faces": fb, "floored_cells": fl}}
+            log(f"sources {name}: {cells * K / total / 1e9:.3f} G cell-updates/s, "
+                f"expansion {ex_ms:.3f} ms ({ex_bytes / (ex_ms / 1e3) / 1e9:.0f} GB/s)")
+            r.close()
+        sources["kernels"] = {
+            "march": "sweep_kernel<Prec, cfl, false, true, true>",
+            "lanes": "sweep_lanes_kernel<Prec, cfl, true, true>",
+            "expansion": "expansion_kernel<Prec>"}
+        torch.cuda.empty_cache()
+
     amr = None
     if not args.no_amr_fill:
         amr = amr_ghost_fill()
@@ -293,16 +339,16 @@ def main():
     flops_launch = mean_pencils * n * ops["flops"]
     sw = kern[dom]
     # kernel names as the profiler reports them (template arguments: precision,
-    # takes the next dt, spans patches, HLLC solver)
-    kname = ("sweep_kernel<PrecF64, false, false, false>" if dom == "march"
-             else "sweep_lanes_kernel<PrecF64, false, false>")
+    # takes the next dt, spans patches, HLLC solver, gravity sources)
+    kname = ("sweep_kernel<PrecF64, false, false, false, false>" if dom == "march"
+             else "sweep_lanes_kernel<PrecF64, false, false, false>")
     tr = measured_traffic(kname)
     traffic = None if tr is None else tr["bytes"]
     if dom == "march" and traffic is not None:
-        tt = measured_traffic("sweep_tail_kernel<PrecF64, false, false>")
+        tt = measured_traffic("sweep_tail_kernel<PrecF64, false, false, false>")
         if tt is not None:  # mean bytes of the tail launches of the same sweeps
             traffic += tt["bytes"]
-            kname += " + sweep_tail_kernel<PrecF64, false, false>"
+            kname += " + sweep_tail_kernel<PrecF64, false, false, false>"
 
     hbm = dict(bound="hbm", achieved=bytes_launch / sw / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                frac=0.0, traffic=traffic, kernel=kname, algorithmic_bytes=bytes_launch,
@@ -324,7 +370,8 @@ def main():
         hllc["fp64"]["roofline"] = dict(
             bound="alu", achieved=fl_h / sw_h / 1e12, peak=FP64_OP_PEAK_T, unit="TFLOP/s",
             frac=fl_h / sw_h / 1e12 / FP64_OP_PEAK_T,
-            kernel="sweep_kernel<PrecF64, false, false, true> + sweep_tail_kernel<PrecF64, false, true>",
+            kernel=("sweep_kernel<PrecF64, false, false, true, false> + "
+                    "sweep_tail_kernel<PrecF64, false, true, false>"),
             algorithmic_flops=fl_h, launch_ms=sw_h * 1e3, ops_per_cell_sweep=hops)
 
     cpu = None
@@ -368,6 +415,8 @@ def main():
                          "tiles": mx["tiles"]}
     if hllc is not None:
         line["hllc"] = hllc
+    if sources is not None:
+        line["gravity_comoving"] = sources
     if amr is not None:
         line["amr_ghost_fill"] = amr
     if batch is not None:

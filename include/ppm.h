@@ -97,6 +97,13 @@ typedef struct {
   void *rho, *vx, *vy, *vz; /* double (PPM_FP64) or float (PPM_MIXED) */
   double *etot, *eint;      /* double in both precisions */
   double *flux_reg;         /* nullable; ppm_flux_reg_size(nx,ny,nz) doubles */
+  const void *gx, *gy, *gz; /* nullable (all three or none): gravitational
+                               acceleration at the cell centres at the half
+                               step, in rho's type and layout, over the whole
+                               ghosted box (the sweeps also update ghost cells);
+                               read by every sweep, whose update then adds the
+                               source terms of Eqs. momentum_diff and
+                               energy_diff.  Zero-initialise for no gravity. */
 } ppm_patch;
 
 typedef struct {
@@ -212,8 +219,29 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
  * a recorded hierarchy. */
 ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream);
 
+/* Comoving coordinates (Sec. "Physical Equations").  a_dev: device array of
+ * 2 * nlevels doubles, owned by the caller, holding for each level l the
+ * expansion factor a_l = a_dev[2l] > 0 and its rate adot_l = a_dev[2l+1] at
+ * the level's half step.  From this call on every sweep divides its flux
+ * differences by a_l (time ratio dt / (a_l dx)) and its gravity source by
+ * a_l, and the CFL timestep becomes cfl a_l / max; the values are read by each
+ * launch, so the caller may change them between steps without a new plan.  A
+ * graph made by ppm_graph_create keeps the pointer the plan had when it was
+ * made.  NULL restores the static equations (a = 1).  Values that are not
+ * positive and finite give meaningless results (no error is detected on the
+ * device). */
+ppm_status ppm_set_expansion(ppm_plan *plan, const double *a_dev);
+
+/* The expansion terms of the comoving equations, split from the sweeps and
+ * integrated over each level's dt (dt_dev[level]) implicitly and
+ * time-centred with H = adot / a of the level: velocities times
+ * (1 - H dt/2)/(1 + H dt/2), specific total energy times (1 - H dt)/(1 + H dt),
+ * specific internal energy times (1 - x)/(1 + x), x = 3 (gamma - 1) H dt / 2;
+ * active cells only.  Needs ppm_set_expansion (PPM_EINVAL otherwise). */
+ppm_status ppm_expansion(ppm_plan *plan, const double *dt_dev, void *hip_stream);
+
 /* Hydro CFL timestep per level (Sec. "Timestepping"):
- *   dt_dev[l] = cfl / max over the active cells of the level's patches of
+ *   dt_dev[l] = cfl a_l / max over the active cells of the level's patches of
  *               sum_d (c_s + |v_d|) / dx_d,
  * with c_s from the same dual-energy pressure the sweeps use.  dt_dev is a
  * device array of nlevels doubles; levels without patches get +inf. */

@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <algorithm>
 #include <cstdint>
@@ -119,6 +120,8 @@ ppm_status check_patch(const ppm_patch &q, int i, int32_t nlevels) {
     return fail(PPM_EINVAL, "patch %d: cell widths must be finite and > 0", i);
   if (!q.rho || !q.vx || !q.vy || !q.vz || !q.etot || !q.eint)
     return fail(PPM_EINVAL, "patch %d: NULL field pointer", i);
+  if (!((q.gx && q.gy && q.gz) || (!q.gx && !q.gy && !q.gz)))
+    return fail(PPM_EINVAL, "patch %d: acceleration needs all of gx, gy, gz or none", i);
   const int64_t lim = int64_t(1) << 30;
   const int64_t nf[3] = {int64_t(q.nx) + 2 * q.ghost, int64_t(q.ny) + 2 * q.ghost,
                          int64_t(q.nz) + 2 * q.ghost};
@@ -257,8 +260,9 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   pl->npatch = npatch;
   pl->nlevels = nlevels;
   pl->prec = prec;
-  std::memcpy(&pl->P, params, sizeof(ppm::Params));
-  static_assert(sizeof(ppm::Params) == sizeof(ppm_params), "params layout");
+  std::memcpy(&pl->P, params, sizeof(ppm_params));
+  static_assert(offsetof(ppm::Params, expand) == sizeof(ppm_params), "params layout");
+  pl->P.expand = nullptr;
   int64_t max_cells = 0;
   for (int i = 0; i < npatch; ++i)
     max_cells = std::max(max_cells, int64_t(patches[i].nx) * patches[i].ny * patches[i].nz);
@@ -293,6 +297,8 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     d.dx[0] = q.dx; d.dx[1] = q.dy; d.dx[2] = q.dz;
     d.rho = q.rho; d.vel[0] = q.vx; d.vel[1] = q.vy; d.vel[2] = q.vz;
     d.etot = q.etot; d.eint = q.eint; d.flux_reg = q.flux_reg;
+    d.acc[0] = q.gx; d.acc[1] = q.gy; d.acc[2] = q.gz;
+    if (q.gx) pl->P.flags |= ppm::kAnyGravity;
   }
   // prefix arrays of work chunks
   const int stride = npatch + 1;
@@ -341,8 +347,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
       return int64_t(reinterpret_cast<uintptr_t>(x)) - int64_t(reinterpret_cast<uintptr_t>(y));
     };
     const int64_t dr = d(q.rho, b.rho);
+    const bool qg = q.gx != nullptr, bg = b.gx != nullptr;
     return dr % sS == 0 && d(q.vx, b.vx) == dr && d(q.vy, b.vy) == dr && d(q.vz, b.vz) == dr &&
-           d(q.etot, b.etot) == dr / sS * 8 && d(q.eint, b.eint) == dr / sS * 8;
+           d(q.etot, b.etot) == dr / sS * 8 && d(q.eint, b.eint) == dr / sS * 8 && qg == bg &&
+           (!qg || (d(q.gx, b.gx) == dr && d(q.gy, b.gy) == dr && d(q.gz, b.gz) == dr));
   };
   std::vector<int32_t> gmap;
   bool runs_aligned = true;
@@ -411,10 +419,9 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
     for (int c = 0; c < 2; ++c) {
       int64_t cap = pl->tail_round;  // marching threads resident at once
       if (cap == 0) {
-        const bool hllc = (pl->P.flags & PPM_HLLC) != 0;
         const int bpc = prec == PPM_FP64
-                            ? ppm::march_blocks_per_cu<ppm::PrecF64>(pl->block, c, hllc)
-                            : ppm::march_blocks_per_cu<ppm::PrecMixed>(pl->block, c, hllc);
+                            ? ppm::march_blocks_per_cu<ppm::PrecF64>(pl->block, c, pl->P.flags)
+                            : ppm::march_blocks_per_cu<ppm::PrecMixed>(pl->block, c, pl->P.flags);
         cap = int64_t(cus) * bpc * pl->block;
       }
       if (cap <= 0) continue;
@@ -693,6 +700,29 @@ ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream) {
   return PPM_OK;
 }
 
+ppm_status ppm_set_expansion(ppm_plan *plan, const double *a_dev) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  plan->P.expand = a_dev;
+  return PPM_OK;
+}
+
+ppm_status ppm_expansion(ppm_plan *plan, const double *dt_dev, void *hip_stream) {
+  if (!plan) return fail(PPM_EINVAL, "plan is NULL");
+  if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
+  if (!plan->P.expand) return fail(PPM_EINVAL, "no expansion factors set (ppm_set_expansion)");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int32_t *cs = plan->d_chunks + size_t(24) * (plan->npatch + 1);
+  hipError_t e = plan->prec == PPM_FP64
+      ? ppm::launch_expansion<ppm::PrecF64>(plan->d_patches, cs, plan->npatch, plan->cfl_blocks,
+                                            plan->cfl_cells, plan->P.gamma, plan->P.expand,
+                                            dt_dev, s)
+      : ppm::launch_expansion<ppm::PrecMixed>(plan->d_patches, cs, plan->npatch,
+                                              plan->cfl_blocks, plan->cfl_cells, plan->P.gamma,
+                                              plan->P.expand, dt_dev, s);
+  if (e != hipSuccess) return hip_fail(e, "expansion launch");
+  return PPM_OK;
+}
+
 ppm_status ppm_cfl_dt(ppm_plan *plan, double *dt_dev, void *hip_stream) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
@@ -760,7 +790,8 @@ ppm_status ppm_sweep_cfl(ppm_plan *plan, const double *dt_dev, int32_t axis,
 ppm_status ppm_cfl_finalize(ppm_plan *plan, double *dt_dev, void *hip_stream) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!dt_dev) return fail(PPM_EINVAL, "dt_dev is NULL");
-  hipError_t e = ppm::launch_cfl_finalize(plan->nlevels, plan->P.cfl, plan->d_smax, dt_dev,
+  hipError_t e = ppm::launch_cfl_finalize(plan->nlevels, plan->P.cfl, plan->P.expand,
+                                          plan->d_smax, dt_dev,
                                           static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "cfl finalize launch");
   return PPM_OK;

@@ -85,7 +85,7 @@ __device__ __forceinline__ void cfl_commit_levels(double smax, int level,
 // patches of a run are views into six shared arrays at one element offset
 // per patch, so the field pointers of the run's first patch serve the whole
 // wave and only the offset, strides and cell width vary per lane.
-template <class Prec, bool kCFL, bool kGrouped, bool kUseHLLC>
+template <class Prec, bool kCFL, bool kGrouped, bool kUseHLLC, bool kGrav>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
              int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
@@ -130,9 +130,11 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
                                               axis, 0, 0);
       pc.base += pc.rho - ref.rho;
       pc.rho = ref.rho; pc.u = ref.u; pc.v1 = ref.v1; pc.v2 = ref.v2; pc.E = ref.E; pc.e = ref.e;
+      pc.acc = ref.acc;
     }
     const double dt = dt_dev[pd.level];
-    march_pencil<Prec, kCFL, kUseHLLC>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
+    march_pencil<Prec, kCFL, kUseHLLC, kGrav>(P, pc, dt, expansion_a(P, pd.level),
+                                              lds + threadIdx.x, blockDim.x, nfb, nfl, cfl);
   }
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
@@ -145,7 +147,7 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
 // One wavefront streams a run of `rows` consecutive pencils (rows_per_wave(n)
 // if rows is 0) with the cells across its lanes, from pencil `pencil0` of the
 // patch on.
-template <class Prec, bool kCFL, bool kUseHLLC>
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __device__ __forceinline__ void stream_pencils(const PatchDev *__restrict__ patches,
                                                const int32_t *__restrict__ chunk_start,
                                                int32_t npatch, int32_t axis, int32_t mask,
@@ -165,36 +167,34 @@ __device__ __forceinline__ void stream_pencils(const PatchDev *__restrict__ patc
   const double dt = dt_dev[pd.level];
   uint32_t nfb = 0, nfl = 0;
   CflAcc cfl = cfl_acc(pd, axis, nullptr);
-  sweep_rows_lanes<Prec, kCFL, kUseHLLC>(P, pd, axis, mask, first, min(K, np - first), dt, nfb, nfl,
-                                         cfl);
+  sweep_rows_lanes<Prec, kCFL, kUseHLLC, kGrav>(P, pd, axis, mask, first, min(K, np - first),
+                                                dt, expansion_a(P, pd.level), nfb, nfl, cfl);
   if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
   if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
   if (kCFL) cfl_commit(cfl.smax, &smax_bits[pd.level]);
 }
 
 // Lane-parallel sweep: each wavefront streams rows_per_wave(n) pencils.
-template <class Prec, bool kCFL, bool kUseHLLC>
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
                    int32_t npatch, int32_t axis, int32_t mask, const double *__restrict__ dt_dev,
                    Params P, unsigned long long *__restrict__ counters,
                    unsigned long long *__restrict__ smax_bits) {
-  stream_pencils<Prec, kCFL, kUseHLLC>(patches, chunk_start, npatch, axis, mask, 0, 0, dt_dev, P,
-                                       counters,
-                             smax_bits);
+  stream_pencils<Prec, kCFL, kUseHLLC, kGrav>(patches, chunk_start, npatch, axis, mask, 0, 0,
+                                              dt_dev, P, counters, smax_bits);
 }
 
 // The pencils of one patch from `pencil0` on, one per wavefront: what is
 // left of a marching sweep after whole rounds of resident marching threads.
-template <class Prec, bool kCFL, bool kUseHLLC>
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_tail_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
                   int32_t axis, int32_t mask, int32_t pencil0, const double *__restrict__ dt_dev,
                   Params P, unsigned long long *__restrict__ counters,
                   unsigned long long *__restrict__ smax_bits) {
-  stream_pencils<Prec, kCFL, kUseHLLC>(patches, chunk_start, 1, axis, mask, pencil0, 1, dt_dev, P,
-                                       counters,
-                             smax_bits);
+  stream_pencils<Prec, kCFL, kUseHLLC, kGrav>(patches, chunk_start, 1, axis, mask, pencil0, 1,
+                                              dt_dev, P, counters, smax_bits);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,7 +210,7 @@ sweep_tail_kernel(const PatchDev *__restrict__ patches, const int32_t *__restric
 __constant__ int kStepOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1},
                                       {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
 
-template <class Prec, bool kCFL, bool kUseHLLC>
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ order,
                         int32_t npatch, int32_t sweep_order, int32_t lanes_mask,
@@ -248,22 +248,28 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
         const int K = rows_per_wave(n);
         for (int first = wave * K; first < np; first += waves * K) {
           if (kCFL && k == 2)
-            sweep_rows_lanes<Prec, true, kUseHLLC>(P, pd, axis, mask, first, min(K, np - first),
-                                                   dt, nfb, nfl, cfl);
+            sweep_rows_lanes<Prec, true, kUseHLLC, kGrav>(P, pd, axis, mask, first,
+                                                          min(K, np - first), dt,
+                                                          expansion_a(P, pd.level), nfb, nfl,
+                                                          cfl);
           else
-            sweep_rows_lanes<Prec, false, kUseHLLC>(P, pd, axis, mask, first, min(K, np - first),
-                                                    dt, nfb, nfl, cfl);
+            sweep_rows_lanes<Prec, false, kUseHLLC, kGrav>(P, pd, axis, mask, first,
+                                                           min(K, np - first), dt,
+                                                           expansion_a(P, pd.level), nfb, nfl,
+                                                           cfl);
         }
       } else {
         for (int idx = threadIdx.x; idx < np; idx += blockDim.x) {
           pencil_index(pd, axis, mask, idx, i1, i2);
           const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
           if (kCFL && k == 2)
-            march_pencil<Prec, true, kUseHLLC>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb, nfl,
-                                               cfl);
+            march_pencil<Prec, true, kUseHLLC, kGrav>(P, pc, dt, expansion_a(P, pd.level),
+                                                      lds + threadIdx.x, blockDim.x, nfb, nfl,
+                                                      cfl);
           else
-            march_pencil<Prec, false, kUseHLLC>(P, pc, dt, lds + threadIdx.x, blockDim.x, nfb,
-                                                nfl, cfl);
+            march_pencil<Prec, false, kUseHLLC, kGrav>(P, pc, dt, expansion_a(P, pd.level),
+                                                       lds + threadIdx.x, blockDim.x, nfb, nfl,
+                                                       cfl);
         }
       }
       if (kCFL && k == 2)
@@ -326,14 +332,60 @@ cfl_reduce_kernel(const PatchDev *__restrict__ patches, const int32_t *__restric
   }
 }
 
+// dt = kappa a / max signal (Eq. dthydro in comoving coordinates).
 __global__ void cfl_finalize_kernel(int32_t nlevels, double cfl,
+                                    const double *__restrict__ expand,
                                     unsigned long long *__restrict__ smax_bits,
                                     double *__restrict__ dt_dev) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nlevels) return;
   const double s = __longlong_as_double((long long)smax_bits[l]);
-  dt_dev[l] = s > 0.0 ? cfl / s : __longlong_as_double(0x7ff0000000000000LL);
+  const double ka = cfl * (expand ? expand[2 * l] : 1.0);
+  dt_dev[l] = s > 0.0 ? ka / s : __longlong_as_double(0x7ff0000000000000LL);
   smax_bits[l] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// Expansion terms of the comoving equations (Sec. "Physical Equations"),
+// split from the sweeps and integrated implicitly and time-centred over the
+// level's dt with H = adot / a of the level: peculiar velocity times
+// (1 - H dt/2)/(1 + H dt/2), specific total energy times (1 - H dt)/(1 + H dt),
+// specific internal energy times (1 - x)/(1 + x) with x = 3 (gamma - 1) H dt / 2.
+// Active cells only, chunked over the patches like the CFL reduction.
+template <class Prec>
+__global__ void __launch_bounds__(256)
+expansion_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
+                 int32_t npatch, int32_t cells_per_block, double gamma,
+                 const double *__restrict__ expand, const double *__restrict__ dt_dev) {
+  using S = typename Prec::S;
+  const int p = find_patch(chunk_start, npatch, blockIdx.x);
+  const PatchDev pd = patches[p];
+  const int g = pd.ghost;
+  const int64_t nx = pd.n[0], ny = pd.n[1];
+  const int64_t total = nx * ny * pd.n[2];
+  const int64_t nfx = nx + 2 * g, nfy = ny + 2 * g;
+  const int64_t c0 = int64_t(blockIdx.x - chunk_start[p]) * cells_per_block;
+  const int64_t c1 = c0 + cells_per_block < total ? c0 + cells_per_block : total;
+  const double a = expand[2 * pd.level], adot = expand[2 * pd.level + 1];
+  const double dt = dt_dev[pd.level];
+  const double H = adot / a;
+  const double xv = 0.5 * H * dt, xE = H * dt, xe = 1.5 * (gamma - 1.0) * H * dt;
+  const double fv = (1.0 - xv) / (1.0 + xv);
+  const double fE = (1.0 - xE) / (1.0 + xE);
+  const double fe = (1.0 - xe) / (1.0 + xe);
+  S *vx = static_cast<S *>(pd.vel[0]);
+  S *vy = static_cast<S *>(pd.vel[1]);
+  S *vz = static_cast<S *>(pd.vel[2]);
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += blockDim.x) {
+    const int64_t x = c % nx, yz = c / nx;
+    const int64_t y = yz % ny, z = yz / ny;
+    const int64_t o = ((z + g) * nfy + (y + g)) * nfx + (x + g);
+    vx[o] = S(double(vx[o]) * fv);
+    vy[o] = S(double(vy[o]) * fv);
+    vz[o] = S(double(vz[o]) * fv);
+    pd.etot[o] = pd.etot[o] * fE;
+    pd.eint[o] = pd.eint[o] * fe;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -652,6 +704,14 @@ fill_periodic_kernel(PatchDev pd) {
 // ---------------------------------------------------------------------------
 // Launchers
 
+// The three builds of each sweep kernel (template arguments kUseHLLC, kGrav):
+// two-shock only; HLLC or two-shock as the flag says; the latter with the
+// gravity source terms, for plans where some patch has an acceleration field.
+#define PPM_BUILD(P, LAUNCH, ...)                                 \
+  if ((P).flags & kAnyGravity) LAUNCH(__VA_ARGS__, true, true);   \
+  else if ((P).flags & kHLLC) LAUNCH(__VA_ARGS__, true, false);   \
+  else LAUNCH(__VA_ARGS__, false, false)
+
 template <class Prec>
 hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
@@ -659,22 +719,17 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
                         unsigned long long *smax_bits, const int32_t *groups, int32_t ngroups,
                         hipStream_t s) {
   const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
-  const bool hllc = (P.flags & kHLLC) != 0;
-#define PPM_LAUNCH_MARCH(CFL, GRP, HLLC)                                                     \
-  hipLaunchKernelGGL((sweep_kernel<Prec, CFL, GRP, HLLC>), dim3(nblocks), dim3(block), lds, s, \
-                     patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits, \
-                     groups, ngroups)
-#define PPM_LAUNCH_MARCH_SOLVER(CFL, GRP)                \
-  if (hllc) PPM_LAUNCH_MARCH(CFL, GRP, true);            \
-  else PPM_LAUNCH_MARCH(CFL, GRP, false)
+#define PPM_LAUNCH_MARCH(CFL, GRP, HLLC, GRAV)                                               \
+  hipLaunchKernelGGL((sweep_kernel<Prec, CFL, GRP, HLLC, GRAV>), dim3(nblocks), dim3(block), \
+                     lds, s, patches, chunk_start, npatch, axis, mask, dt_dev, P, counters,   \
+                     smax_bits, groups, ngroups)
   if (groups) {
-    if (smax_bits) { PPM_LAUNCH_MARCH_SOLVER(true, true); }
-    else { PPM_LAUNCH_MARCH_SOLVER(false, true); }
+    if (smax_bits) { PPM_BUILD(P, PPM_LAUNCH_MARCH, true, true); }
+    else { PPM_BUILD(P, PPM_LAUNCH_MARCH, false, true); }
   } else {
-    if (smax_bits) { PPM_LAUNCH_MARCH_SOLVER(true, false); }
-    else { PPM_LAUNCH_MARCH_SOLVER(false, false); }
+    if (smax_bits) { PPM_BUILD(P, PPM_LAUNCH_MARCH, true, false); }
+    else { PPM_BUILD(P, PPM_LAUNCH_MARCH, false, false); }
   }
-#undef PPM_LAUNCH_MARCH_SOLVER
 #undef PPM_LAUNCH_MARCH
   return hipGetLastError();
 }
@@ -685,17 +740,12 @@ hipError_t launch_sweep_lanes(const PatchDev *patches, const int32_t *chunk_star
                               const double *dt_dev, const Params &P,
                               unsigned long long *counters, unsigned long long *smax_bits,
                               hipStream_t s) {
-#define PPM_LAUNCH_LANES(CFL, HLLC)                                                          \
-  hipLaunchKernelGGL((sweep_lanes_kernel<Prec, CFL, HLLC>), dim3(nblocks), dim3(block), 0, s, \
-                     patches, chunk_start, npatch, axis, mask, dt_dev, P, counters, smax_bits)
-  const bool hllc = (P.flags & kHLLC) != 0;
-  if (smax_bits) {
-    if (hllc) PPM_LAUNCH_LANES(true, true);
-    else PPM_LAUNCH_LANES(true, false);
-  } else {
-    if (hllc) PPM_LAUNCH_LANES(false, true);
-    else PPM_LAUNCH_LANES(false, false);
-  }
+#define PPM_LAUNCH_LANES(CFL, HLLC, GRAV)                                                    \
+  hipLaunchKernelGGL((sweep_lanes_kernel<Prec, CFL, HLLC, GRAV>), dim3(nblocks), dim3(block), \
+                     0, s, patches, chunk_start, npatch, axis, mask, dt_dev, P, counters,      \
+                     smax_bits)
+  if (smax_bits) { PPM_BUILD(P, PPM_LAUNCH_LANES, true); }
+  else { PPM_BUILD(P, PPM_LAUNCH_LANES, false); }
 #undef PPM_LAUNCH_LANES
   return hipGetLastError();
 }
@@ -705,28 +755,29 @@ hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start
                              int32_t block, int32_t axis, int32_t mask, int32_t pencil0,
                              const double *dt_dev, const Params &P, unsigned long long *counters,
                              unsigned long long *smax_bits, hipStream_t s) {
-#define PPM_LAUNCH_TAIL(CFL, HLLC)                                                           \
-  hipLaunchKernelGGL((sweep_tail_kernel<Prec, CFL, HLLC>), dim3(nblocks), dim3(block), 0, s,  \
-                     patches, chunk_start, axis, mask, pencil0, dt_dev, P, counters, smax_bits)
-  const bool hllc = (P.flags & kHLLC) != 0;
-  if (smax_bits) {
-    if (hllc) PPM_LAUNCH_TAIL(true, true);
-    else PPM_LAUNCH_TAIL(true, false);
-  } else {
-    if (hllc) PPM_LAUNCH_TAIL(false, true);
-    else PPM_LAUNCH_TAIL(false, false);
-  }
+#define PPM_LAUNCH_TAIL(CFL, HLLC, GRAV)                                                     \
+  hipLaunchKernelGGL((sweep_tail_kernel<Prec, CFL, HLLC, GRAV>), dim3(nblocks), dim3(block),  \
+                     0, s, patches, chunk_start, axis, mask, pencil0, dt_dev, P, counters,     \
+                     smax_bits)
+  if (smax_bits) { PPM_BUILD(P, PPM_LAUNCH_TAIL, true); }
+  else { PPM_BUILD(P, PPM_LAUNCH_TAIL, false); }
 #undef PPM_LAUNCH_TAIL
   return hipGetLastError();
 }
 
+template <class Prec, bool kCFL>
+const void *march_kernel_ptr(uint32_t flags) {
+  if (flags & kAnyGravity)
+    return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, true, true>);
+  if (flags & kHLLC)
+    return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, true, false>);
+  return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, false, false>);
+}
+
 template <class Prec>
-int march_blocks_per_cu(int32_t block, bool cfl, bool hllc) {
+int march_blocks_per_cu(int32_t block, bool cfl, uint32_t flags) {
   const size_t lds = size_t(kLdsMarch + (cfl ? 1 : 0)) * block * sizeof(double);
-  const void *k = cfl ? (hllc ? reinterpret_cast<const void *>(sweep_kernel<Prec, true, false, true>)
-                              : reinterpret_cast<const void *>(sweep_kernel<Prec, true, false, false>))
-                      : (hllc ? reinterpret_cast<const void *>(sweep_kernel<Prec, false, false, true>)
-                              : reinterpret_cast<const void *>(sweep_kernel<Prec, false, false, false>));
+  const void *k = cfl ? march_kernel_ptr<Prec, true>(flags) : march_kernel_ptr<Prec, false>(flags);
   int nb = 0;
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, block, lds) == hipSuccess ? nb : 0;
 }
@@ -737,26 +788,31 @@ hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t n
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned int *queue, unsigned long long *smax_bits, hipStream_t s) {
   const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
-#define PPM_LAUNCH_BATCH(CFL, HLLC)                                                         \
-  hipLaunchKernelGGL((batch_persistent_kernel<Prec, CFL, HLLC>), dim3(nblocks), dim3(block), \
-                     lds, s, patches, order, npatch, sweep_order, lanes_mask, dt_dev, P,    \
-                     counters, queue, smax_bits)
-  const bool hllc = (P.flags & kHLLC) != 0;
-  if (smax_bits) {
-    if (hllc) PPM_LAUNCH_BATCH(true, true);
-    else PPM_LAUNCH_BATCH(true, false);
-  } else {
-    if (hllc) PPM_LAUNCH_BATCH(false, true);
-    else PPM_LAUNCH_BATCH(false, false);
-  }
+#define PPM_LAUNCH_BATCH(CFL, HLLC, GRAV)                                                    \
+  hipLaunchKernelGGL((batch_persistent_kernel<Prec, CFL, HLLC, GRAV>), dim3(nblocks),         \
+                     dim3(block), lds, s, patches, order, npatch, sweep_order, lanes_mask,     \
+                     dt_dev, P, counters, queue, smax_bits)
+  if (smax_bits) { PPM_BUILD(P, PPM_LAUNCH_BATCH, true); }
+  else { PPM_BUILD(P, PPM_LAUNCH_BATCH, false); }
 #undef PPM_LAUNCH_BATCH
   return hipGetLastError();
 }
+#undef PPM_BUILD
 
-hipError_t launch_cfl_finalize(int32_t nlevels, double cfl, unsigned long long *smax_bits,
-                               double *dt_dev, hipStream_t s) {
+template <class Prec>
+hipError_t launch_expansion(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                            int32_t nblocks, int32_t cells_per_block, double gamma,
+                            const double *expand, const double *dt_dev, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(expansion_kernel<Prec>, dim3(nblocks), dim3(256), 0, s, patches,
+                     chunk_start, npatch, cells_per_block, gamma, expand, dt_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl_finalize(int32_t nlevels, double cfl, const double *expand,
+                               unsigned long long *smax_bits, double *dt_dev, hipStream_t s) {
   hipLaunchKernelGGL(cfl_finalize_kernel, dim3((nlevels + 63) / 64), dim3(64), 0, s, nlevels,
-                     cfl, smax_bits, dt_dev);
+                     cfl, expand, smax_bits, dt_dev);
   return hipGetLastError();
 }
 
@@ -768,7 +824,7 @@ hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32
                      chunk_start, npatch, cells_per_block, P, smax_bits);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_cfl_finalize(nlevels, P.cfl, smax_bits, dt_dev, s);
+  return launch_cfl_finalize(nlevels, P.cfl, P.expand, smax_bits, dt_dev, s);
 }
 
 template <class Prec>
@@ -828,7 +884,7 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                               int32_t, int32_t, int32_t, const double *,          \
                                               const Params &, unsigned long long *,               \
                                               unsigned long long *, hipStream_t);                  \
-  template int march_blocks_per_cu<Prec>(int32_t, bool, bool);                                    \
+  template int march_blocks_per_cu<Prec>(int32_t, bool, uint32_t);                                \
   template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *, unsigned int *,    \
@@ -842,6 +898,12 @@ template hipError_t launch_cfl<PrecF64>(const PatchDev *, const int32_t *, int32
 template hipError_t launch_cfl<PrecMixed>(const PatchDev *, const int32_t *, int32_t, int32_t,
                                           int32_t, int32_t, const Params &, unsigned long long *,
                                           double *, hipStream_t);
+template hipError_t launch_expansion<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
+                                              int32_t, double, const double *, const double *,
+                                              hipStream_t);
+template hipError_t launch_expansion<PrecMixed>(const PatchDev *, const int32_t *, int32_t,
+                                                int32_t, int32_t, double, const double *,
+                                                const double *, hipStream_t);
 template hipError_t launch_fill<PrecF64>(const PatchDev &, hipStream_t);
 template hipError_t launch_fill<PrecMixed>(const PatchDev &, hipStream_t);
 template hipError_t launch_fill_boundary<PrecF64>(const PatchDev &, const FaceRules &,

@@ -37,10 +37,10 @@ hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start
                              unsigned long long *smax_bits, hipStream_t s);
 
 // Resident workgroups per compute unit of the (ungrouped) marching sweep
-// with `block` threads, with or without the CFL maximum, for the two-shock
-// or the HLLC build; 0 if unknown.
+// with `block` threads, with or without the CFL maximum, for the build that
+// the plan flags select; 0 if unknown.
 template <class Prec>
-int march_blocks_per_cu(int32_t block, bool cfl, bool hllc);
+int march_blocks_per_cu(int32_t block, bool cfl, uint32_t flags);
 
 // Persistent batch kernel: the whole step of every patch in one launch.
 template <class Prec>
@@ -49,14 +49,22 @@ hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t n
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned int *queue, unsigned long long *smax_bits, hipStream_t s);
 
-// dt_dev[l] = cfl / max signal speed of level l (+inf if none); clears the maxima.
-hipError_t launch_cfl_finalize(int32_t nlevels, double cfl, unsigned long long *smax_bits,
-                               double *dt_dev, hipStream_t s);
+// dt_dev[l] = cfl a_l / max signal speed of level l (+inf if none), a_l from
+// expand (nullable: a = 1); clears the maxima.
+hipError_t launch_cfl_finalize(int32_t nlevels, double cfl, const double *expand,
+                               unsigned long long *smax_bits, double *dt_dev, hipStream_t s);
 
 template <class Prec>
 hipError_t launch_cfl(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                       int32_t nblocks, int32_t cells_per_block, int32_t nlevels, const Params &P,
                       unsigned long long *smax_bits, double *dt_dev, hipStream_t s);
+
+// Expansion terms of the comoving equations over every patch's active cells
+// (chunked like launch_cfl); expand: per level (a, adot), not null.
+template <class Prec>
+hipError_t launch_expansion(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
+                            int32_t nblocks, int32_t cells_per_block, double gamma,
+                            const double *expand, const double *dt_dev, hipStream_t s);
 
 template <class Prec>
 hipError_t launch_fill(const PatchDev &pd, hipStream_t s);

@@ -74,10 +74,11 @@ struct CellLoad {
 // One segment: lane holds cell j of pencil pc (j = -1 for a placeholder
 // lane beyond the stream, which no valid result uses).  `in` is this lane's
 // input cell; the lane writes its cell (and counts its events) if `mine`.
-// lam = dt / pc.dx (the same for every pencil of the patch).
-template <class Prec, bool kCFL, bool kUseHLLC>
+// lam = dt / (a pc.dx) and hgdt = (dt / 2) / a, with a the level's expansion
+// factor (the same for every pencil of the patch).
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
-                              double lam, int j, bool mine, const CellLoad &in,
+                              double lam, double hgdt, int j, bool mine, const CellLoad &in,
                               uint32_t &n_fallback, uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
   using T = typename Prec::T;
@@ -182,7 +183,9 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
   double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   Flux Fm = flux_from_left(F);
   bool bad = false;
-  if (cell_ok) bad = update_cell(P, lam, cin, Fm, F, out);
+  const bool grav = kGrav && pc.acc != nullptr;
+  const double hg = grav && cell_ok ? hgdt * double(pc.acc[o]) : 0.0;
+  if (cell_ok) bad = update_cell(P, lam, cin, Fm, F, out, grav, hg);
   // the lane to the right holds cell j+1 of the same pencil whenever j+1 is
   // a cell this lane's results are needed for
   const bool mine_next = from_right(int(mine)) != 0;
@@ -201,7 +204,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
       }
       const bool hll_prev = from_left(int(hll)) != 0;
       Fm = flux_from_left(F);
-      if (cell_ok && (hll || hll_prev)) bad = update_cell(P, lam, cin, Fm, F, out);
+      if (cell_ok && (hll || hll_prev)) bad = update_cell(P, lam, cin, Fm, F, out, grav, hg);
     }
   }
   if (cell_ok && bad) {
@@ -235,16 +238,18 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
 
 // One wave streams pencils first .. first+nrows-1 of a sweep's pencil set,
 // concatenated, segment by segment.
-template <class Prec, bool kCFL, bool kUseHLLC>
+// a: the patch level's expansion factor.
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, int mask,
-                                 int first, int nrows, double dt, uint32_t &n_fallback,
+                                 int first, int nrows, double dt, double a, uint32_t &n_fallback,
                                  uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
   const int lane = threadIdx.x & 63;
   const int n = (axis == 0 ? pd.n[0] : (axis == 1 ? pd.n[1] : pd.n[2])) + 2 * pd.ghost;
   const int L = nrows * n;
   const int nseg = (L + kLaneOut - 1) / kLaneOut;
-  const double lam = dt / pick3(axis, pd.dx[0], pd.dx[1], pd.dx[2]);
+  const double lam = dt / (a * pick3(axis, pd.dx[0], pd.dx[1], pd.dx[2]));
+  const double hgdt = 0.5 * dt / a;
   CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
   for (int s = 0; s < nseg; ++s) {
     const int t = s * kLaneOut - kLaneHalo + lane;  // stream position of this lane
@@ -273,7 +278,8 @@ __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, 
       cur = CellLoad{1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
     }
     const bool mine = in && lane >= kLaneHalo && lane < kLaneHalo + kLaneOut;
-    sweep_segment<Prec, kCFL, kUseHLLC>(P, pc, dt, lam, j, mine, cur, n_fallback, n_floor, cfl);
+    sweep_segment<Prec, kCFL, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, mine, cur, n_fallback, n_floor,
+                                        cfl);
   }
 }
 

@@ -29,12 +29,23 @@ constexpr double kFlatOmega2 = 10.0;
 constexpr double kFlatEps = 0.33;
 
 enum : uint32_t { kSteepen = 1u, kFlatten = 2u, kDualEnergy = 4u, kFallbackHLL = 8u, kHLLC = 16u };
+// Set by the library, never by a caller: some patch carries an acceleration
+// field, so the sweeps launch their build with the gravity source terms.
+constexpr uint32_t kAnyGravity = 0x80000000u;
 
 struct Params {
   double gamma, cfl, eta1, eta2, rho_floor, p_floor, e_floor, riemann_rtol;
   int32_t riemann_max_iter;
   uint32_t flags;
+  // nullable: per level, the expansion factor a and its rate adot at the
+  // level's half step (device memory); null is the static case a = 1
+  const double *expand;
 };
+
+// Expansion factor of a level (1 without expansion factors).
+__device__ __forceinline__ double expansion_a(const Params &P, int level) {
+  return P.expand ? P.expand[2 * level] : 1.0;
+}
 
 template <class T> __device__ __forceinline__ T vmin(T a, T b) { return a < b ? a : b; }
 template <class T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
@@ -460,10 +471,16 @@ struct CellIn {
 
 // Conservative update of one cell from its two face fluxes (Eqs. mass_diff,
 // momentum_diff, energy_diff, gasenergy_diff with the flux difference taken
-// with a minus sign), then the eta2 resync (Eq. dualselect).  Returns true
-// when the new density or the eta1-selected internal energy is not positive.
+// with a minus sign; lam = dt / (a dx) in comoving coordinates), then the
+// eta2 resync (Eq. dualselect).  With a gravity field (grav), the
+// time-centred sources of Eqs. momentum_diff and energy_diff: momentum gains
+// hg (rho^n + rho^{n+1}) and total energy hg (rho^n u^n + rho^{n+1} u^{n+1}),
+// where hg = (dt / 2) g / a with g the acceleration along the sweep at the
+// cell centre.  Returns true when the new density or the eta1-selected
+// internal energy is not positive.
 __device__ __forceinline__ bool update_cell(const Params &P, double lam, const CellIn &c,
-                                            const Flux &Fm, const Flux &Fp, double (&out)[6]) {
+                                            const Flux &Fm, const Flux &Fp, double (&out)[6],
+                                            bool grav = false, double hg = 0.0) {
   const bool dual = (P.flags & kDualEnergy) != 0;
   double rn = c.rho - lam * (Fp.f[0] - Fm.f[0]);
   double mu = c.rho * c.u - lam * (Fp.f[1] - Fm.f[1]);
@@ -471,6 +488,10 @@ __device__ __forceinline__ bool update_cell(const Params &P, double lam, const C
   double m2 = c.rho * c.v2 - lam * (Fp.f[3] - Fm.f[3]);
   double mE = c.rho * c.E - lam * (Fp.f[4] - Fm.f[4]);
   double me = c.rho * c.e - lam * (Fp.f[5] - Fm.f[5]) - lam * c.p * (Fp.f[6] - Fm.f[6]);
+  if (grav) {
+    mu = mu + hg * (c.rho + rn);
+    mE = mE + hg * (c.rho * c.u + mu);
+  }
   double ir = ddiv(1.0, rn);
   double un = mu * ir, v1n = m1 * ir, v2n = m2 * ir, En = mE * ir, eraw = me * ir;
   double ke = 0.5 * (un * un + v1n * v1n + v2n * v2n);

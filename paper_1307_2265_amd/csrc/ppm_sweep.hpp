@@ -46,6 +46,7 @@ struct PatchDev {
   void *rho, *vel[3];
   double *etot, *eint;
   double *flux_reg;
+  const void *acc[3];  // nullable: gravitational acceleration per axis (storage type)
 };
 
 // One pencil as the marcher sees it: fields in pencil order (normal velocity
@@ -59,6 +60,7 @@ template <class S> struct PencilRef {
   double *reg_lo, *reg_hi;  // nullable: register slots of this pencil
   int64_t reg_stride;       // stride between the six register fields
   int lab[6];               // lab field index of each pencil-order flux slot
+  const S *acc;             // nullable: acceleration along the pencil
 };
 
 // LDS of a marching thread, in doubles (strided by the block size): two
@@ -121,6 +123,7 @@ __device__ __forceinline__ PencilRef<S> make_pencil(const PatchDev &pd, int axis
   pc.reg_stride = 0;
   pc.lab[0] = 0; pc.lab[1] = 1 + axis; pc.lab[2] = 1 + t1; pc.lab[3] = 1 + t2;
   pc.lab[4] = 4; pc.lab[5] = 5;
+  pc.acc = static_cast<const S *>(pick3(axis, pd.acc[0], pd.acc[1], pd.acc[2]));
   if (pd.flux_reg && i1 >= g && i1 < g + Nt1 && i2 >= g && i2 < g + Nt2) {
     const int64_t ro = int64_t(i2 - g) * Nt1 + (i1 - g);
     pc.reg_lo = pd.flux_reg + reg_face_offset(N0, N1, N2, axis, 0) + ro;
@@ -203,9 +206,12 @@ __device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis, double *
 
 // One thread marches one pencil.  kCFL: also take the signal speed of every
 // cell written (the sweep must then be the last of its step).
-template <class Prec, bool kCFL, bool kUseHLLC>
+// a: the level's expansion factor (1 for the static equations).  kGrav: the
+// build with the gravity source terms (applied where the pencil has an
+// acceleration field).
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
-                             double *lds_slots, int slot_stride, uint32_t &n_fallback,
+                             double a, double *lds_slots, int slot_stride, uint32_t &n_fallback,
                              uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
   using T = typename Prec::T;
@@ -213,8 +219,10 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   constexpr bool kExactP = sizeof(T) == sizeof(double);
   const int n = pc.n, g = pc.g;
   const int a0 = g, a1 = n - g - 1;
-  const double lam = dt / pc.dx;
+  const double lam = dt / (a * pc.dx);
   const T tlam = T(lam);
+  const bool grav = kGrav && pc.acc != nullptr;
+  const double hgdt = 0.5 * dt / a;
   const double gam = P.gamma;
   const bool steepen = (P.flags & kSteepen) != 0;
   const bool flatten = (P.flags & kFlatten) != 0;
@@ -283,11 +291,12 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   const int kend = n - g + 4;  // the iteration that finalises cell a1
   for (int k = 0; k <= kend; ++k) {
     // energies of cell B = k-4 (updated below), fetched early to hide latency
-    double EB = 0.0, eB = 0.0;
+    double EB = 0.0, eB = 0.0, gB = 0.0;
     if (k - 4 >= a0 && k - 4 <= a1) {
       const int64_t o = pc.base + int64_t(k - 4) * pc.stride;
       EB = pc.E[o];
       eB = pc.e[o];
+      if (grav) gB = double(pc.acc[o]);
     }
     // ---- 1. head cell: load and equation of state
     if (k < n) {
@@ -395,7 +404,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       cin.E = EB; cin.e = eB;
       cin.p = kExactP ? double(q[0][4]) : pd[0];
       cin.rhoEmax = m3[1];
-      bad_b = update_cell(P, lam, cin, ft_b, ft_c, prov_b);
+      bad_b = update_cell(P, lam, cin, ft_b, ft_c, prov_b, grav, hgdt * gB);
     }
 
     // ---- 8. face fb = (r-2)+1/2 becomes final: HLL if a neighbour went bad
@@ -446,7 +455,8 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
         Flux fa;
 #pragma unroll
         for (int j = 0; j < 7; ++j) fa.f[j] = ff_a[j * slot_stride];
-        bad = update_cell(P, lam, cin, fa, ff_b, out);
+        bad = update_cell(P, lam, cin, fa, ff_b, out, grav,
+                          grav ? hgdt * double(pc.acc[o]) : 0.0);
       }
       if (bad) {
         CellIn cin;

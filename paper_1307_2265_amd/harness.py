@@ -35,7 +35,12 @@ class Run:
 
     def __init__(self, host_fields: list, specs: list, prec: int, nlevels: int, periodic: bool,
                  tiles: str | None = None, with_reg: bool = False, ghost: int = W.GHOST,
-                 flags: int | None = None):
+                 flags: int | None = None, sources: dict | None = None):
+        """sources (optional): dict(seed=, amp=, a=, adot=): every patch gets a
+        seeded acceleration field (W.acceleration_field, in rho's type) and
+        every level the expansion factor a and rate adot; a step is then the
+        expansion terms followed by the sweeps with the gravity sources, both
+        over the step's dt."""
         torch = _torch()
         low = torch.float32 if prec == ppm.PPM_MIXED else torch.float64
         self.prec, self.periodic, self.tiles, self.nlevels = prec, periodic, tiles, nlevels
@@ -59,18 +64,33 @@ class Run:
             views = {k: v[offs[i]:offs[i + 1]].view(shape) for k, v in self.flat.items()}
             reg = None if self.reg is None else self.reg[roffs[i]:roffs[i + 1]]
             nx, ny, nz, level, dx = sp
+            acc = None
+            if sources is not None:
+                acc = W.acceleration_field(shape, sources["seed"] + i, sources["amp"],
+                                           device="cuda", dtype=low)
             self.patches.append(ppm.Patch(**views, dx=dx, dy=dx, dz=dx, ghost=ghost,
-                                          level=level, flux_reg=reg))
+                                          level=level, flux_reg=reg, accel=acc))
         self.cells = int(sum(s[0] * s[1] * s[2] for s in specs))
-        self.plan = ppm.Plan(self.patches, nlevels, prec, self.params, tile_config=tiles)
+        self.expand = None
+        if sources is not None:
+            self.expand = torch.tensor([sources["a"], sources["adot"]] * nlevels,
+                                       dtype=torch.float64, device="cuda")
+        self.plan = self._new_plan(tiles)
         self.dt = torch.zeros(nlevels, dtype=torch.float64, device="cuda")
         self.graphs = None
         self.dt_valid = False
 
+    def _new_plan(self, tiles):
+        plan = ppm.Plan(self.patches, self.nlevels, self.prec, self.params, tile_config=tiles)
+        if self.expand is not None:
+            plan.ppm_set_expansion(self.expand)
+        return plan
+
     # -- construction helpers -------------------------------------------------
     @classmethod
-    def single(cls, d: dict, n: int, prec: int, tiles=None, flags=None):
-        return cls([d], [(n, n, n, 0, 1.0 / n)], prec, 1, True, tiles, flags=flags)
+    def single(cls, d: dict, n: int, prec: int, tiles=None, flags=None, sources=None):
+        return cls([d], [(n, n, n, 0, 1.0 / n)], prec, 1, True, tiles, flags=flags,
+                   sources=sources)
 
     @classmethod
     def batch(cls, specs: list, fields: list, prec: int, tiles=None, nlevels=7):
@@ -85,8 +105,7 @@ class Run:
             self.graphs = None
         self.plan.close()
         self.tiles = tiles
-        self.plan = ppm.Plan(self.patches, self.nlevels, self.prec, self.params,
-                             tile_config=tiles)
+        self.plan = self._new_plan(tiles)
 
     # -- stepping -------------------------------------------------------------
     def reset(self):
@@ -105,6 +124,8 @@ class Run:
 
     def step(self, s: int):
         self.ensure_dt()
+        if self.expand is not None:  # split expansion terms first, over the same dt
+            self.plan.ppm_expansion(self.dt)
         if self.periodic:
             self.plan.ppm_fill_periodic()
         self.plan.ppm_step_cfl(self.dt, s % 2)
@@ -123,7 +144,8 @@ class Run:
         as ppm_sweep, ppm_sweep, ppm_sweep_cfl + ppm_cfl_finalize bracketed by
         HIP events (the same kernels and extents ppm_step_cfl launches when it
         is not persistent) and return the mean duration per kernel kind
-        ("march", "lanes", and "+cfl" for the last sweep's variant).
+        ("march", "lanes", and "+cfl" for the last sweep's variant, and
+        "expansion" for the expansion pass of a run with sources).
         Returns (seconds, {kind: s})."""
         torch = _torch()
         E = lambda: torch.cuda.Event(enable_timing=True)
@@ -137,11 +159,19 @@ class Run:
         t0.record()
         for s in range(steps):
             if graphs:
+                if self.expand is not None:
+                    self.plan.ppm_expansion(self.dt)
                 self.graphs[s % 2].ppm_graph_launch()
                 continue
             if not per_sweep:
                 self.step(s)
                 continue
+            if self.expand is not None:
+                a, b = E(), E()
+                a.record()
+                self.plan.ppm_expansion(self.dt)
+                b.record()
+                ev.append(("expansion", a, b))
             if self.periodic:
                 self.plan.ppm_fill_periodic()
             mask = 0

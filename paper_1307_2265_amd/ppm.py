@@ -33,7 +33,8 @@ class ppm_patch(C.Structure):
                 ("level", C.c_int32), ("bc", C.c_int32),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("rho", _vp), ("vx", _vp), ("vy", _vp), ("vz", _vp),
-                ("etot", _vp), ("eint", _vp), ("flux_reg", _vp)]
+                ("etot", _vp), ("eint", _vp), ("flux_reg", _vp),
+                ("gx", _vp), ("gy", _vp), ("gz", _vp)]
 
 
 class ppm_params(C.Structure):
@@ -57,6 +58,8 @@ SIGNATURES = {
     "ppm_fill_ghosts": (C.c_int, [_vp, C.c_int32, _vp]),
     "ppm_fill_boundary": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                     _vp]),
+    "ppm_set_expansion": (C.c_int, [_vp, _vp]),
+    "ppm_expansion": (C.c_int, [_vp, _vp, _vp]),
     "ppm_cfl_dt": (C.c_int, [_vp, _vp, _vp]),
     "ppm_step": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
     "ppm_step_cfl": (C.c_int, [_vp, _vp, C.c_int32, _vp]),
@@ -131,6 +134,8 @@ class Patch:
     eint are float64.  flux_reg is an optional float64 tensor of
     ppm_flux_reg_size(nx, ny, nz) elements.  bc: PPM_BC_PERIODIC (ghosts filled
     by ppm_fill_periodic) or PPM_BC_SUPPLIED (ghosts filled by the caller).
+    accel: optional (gx, gy, gz), tensors of rho's dtype and shape, the
+    gravitational acceleration at the cell centres (ghosts included).
     """
     rho: object
     vx: object
@@ -145,6 +150,7 @@ class Patch:
     level: int = 0
     flux_reg: object = None
     bc: int = PPM_BC_PERIODIC
+    accel: tuple | None = None
 
     @property
     def dims(self):
@@ -161,9 +167,15 @@ class Patch:
         for t in self.fields():
             if tuple(t.shape) != shp or not t.is_contiguous() or t.device.type != "cuda":
                 raise ValueError("patch fields must be contiguous CUDA tensors of one shape")
+        acc = list(self.accel) if self.accel is not None else [None] * 3
+        for t in acc:
+            if t is not None and (tuple(t.shape) != shp or not t.is_contiguous()
+                                  or t.dtype != self.rho.dtype or t.device.type != "cuda"):
+                raise ValueError("accel must be contiguous CUDA tensors of rho's dtype and shape")
         ptr = lambda t: None if t is None else t.data_ptr()
         return ppm_patch(nx, ny, nz, self.ghost, self.level, self.bc, self.dx, self.dy, self.dz,
-                         *[ptr(t) for t in self.fields()], ptr(self.flux_reg))
+                         *[ptr(t) for t in self.fields()], ptr(self.flux_reg),
+                         *[ptr(t) for t in acc])
 
 
 class Plan:
@@ -210,6 +222,17 @@ class Plan:
 
     def ppm_fill_ghosts(self, level, stream=None):
         _check(lib().ppm_fill_ghosts(self._h, int(level), _stream_handle(stream)), "ppm_fill_ghosts")
+
+    def ppm_set_expansion(self, a_dev):
+        """a_dev: float64 device tensor of 2 * nlevels values (a, adot per
+        level), kept alive by the plan; None restores the static equations."""
+        self._expand = a_dev
+        _check(lib().ppm_set_expansion(self._h, None if a_dev is None else a_dev.data_ptr()),
+               "ppm_set_expansion")
+
+    def ppm_expansion(self, dt_dev, stream=None):
+        _check(lib().ppm_expansion(self._h, dt_dev.data_ptr(), _stream_handle(stream)),
+               "ppm_expansion")
 
     def ppm_cfl_dt(self, dt_dev, stream=None):
         _check(lib().ppm_cfl_dt(self._h, dt_dev.data_ptr(), _stream_handle(stream)), "ppm_cfl_dt")

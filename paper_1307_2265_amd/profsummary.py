@@ -87,8 +87,8 @@ def kernels(stats_csv: str, trace_csv: str, cmd: str, out: str):
     for prec in ("PrecF64", "PrecMixed"):
         for cfl in ("false", "true"):
             for hllc in ("false", "true"):
-                m = f"sweep_kernel<{prec}, {cfl}, false, {hllc}>"
-                t = f"sweep_tail_kernel<{prec}, {cfl}, {hllc}>"
+                m = f"sweep_kernel<{prec}, {cfl}, false, {hllc}, false>"
+                t = f"sweep_tail_kernel<{prec}, {cfl}, {hllc}, false>"
                 if m not in means or t not in means:
                     continue
                 sweeps.append(f"| `{m}` + `{t}` | {means[m]:.3f} | {means[t]:.3f} | "

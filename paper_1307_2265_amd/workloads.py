@@ -121,6 +121,36 @@ def patch_fields(spec: PatchSpec, recipe: FieldRecipe = SHOCKED, gamma: float = 
     return random_grid(spec.nx, spec.ny, spec.nz, spec.seed, recipe, gamma, seeded_ghosts=True)
 
 
+def acceleration_field(shape, seed: int, amp: float = 1.0, modes: int = 4, device=None,
+                       dtype=None) -> tuple:
+    """Three arrays of `shape` (z, y, x), a smooth seeded acceleration field:
+    per component, a sum of `modes` plane waves over the array's cell indices
+    with wave numbers drawn from 1..3 per axis (in units of 2 pi over the
+    array extent), random phases and standard normal amplitudes, scaled by
+    amp / sqrt(modes).  numpy float64 arrays, or, with `device`, torch tensors
+    of `dtype` (default float64) evaluated there from the same draws."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    draws = [[(rng.integers(1, 4, size=3), rng.uniform(0.0, 2.0 * np.pi), rng.standard_normal())
+              for _ in range(modes)] for _ in range(3)]
+    if device is None:
+        axes = [np.arange(n, dtype=np.float64) / n for n in shape]
+        sin, zeros, cast = np.sin, (lambda: np.zeros(shape)), np.ascontiguousarray
+    else:
+        import torch
+        axes = [torch.arange(n, dtype=torch.float64, device=device) / n for n in shape]
+        sin = torch.sin
+        zeros = lambda: torch.zeros(shape, dtype=torch.float64, device=device)
+        cast = lambda t: t.to(dtype or torch.float64).contiguous()
+    z, y, x = axes[0][:, None, None], axes[1][None, :, None], axes[2][None, None, :]
+    out = []
+    for comp in draws:
+        g = zeros()
+        for k, ph, amp_k in comp:
+            g += amp_k * sin(2.0 * np.pi * (int(k[0]) * z + int(k[1]) * y + int(k[2]) * x) + ph)
+        out.append(cast(g * (amp / np.sqrt(modes))))
+    return tuple(out)
+
+
 # ---------------------------------------------------------------------------
 # Named workloads.
 

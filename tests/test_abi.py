@@ -50,6 +50,8 @@ def _patch(**kw):
     ({}, dict(cfl=1.5), "cfl"),
     ({}, dict(riemann_max_iter=0), "riemann_max_iter"),
     ({}, dict(flags=99), "flag"),
+    ({}, dict(flags=0x80000000), "flag"),     # library-internal bit
+    (dict(gx=1, gy=1), {}, "acceleration"),   # gz missing
 ])
 def test_plan_create_rejects_invalid_arguments(patch_kw, prm_kw, msg):
     L = ppm.lib()
@@ -75,6 +77,8 @@ def test_calls_on_null_plan_are_rejected():
     assert L.ppm_set_hierarchy(None, None, None) == ppm.PPM_EINVAL
     assert L.ppm_fill_ghosts(None, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_event_counts(None, None, None, 0, None) == ppm.PPM_EINVAL
+    assert L.ppm_set_expansion(None, None) == ppm.PPM_EINVAL
+    assert L.ppm_expansion(None, None, None) == ppm.PPM_EINVAL
     assert L.ppm_plan_destroy(None) == ppm.PPM_OK
 
 
