@@ -56,6 +56,19 @@ class _Grid(C.Structure):
                 ("rho", "vx", "vy", "vz", "etot", "eint", "flux_reg", "gx", "gy", "gz")]
 
 
+class Box(C.Structure):
+    """Active cells [lo, hi) of a grid (a finer patch's footprint)."""
+    _fields_ = [("lo", C.c_int32 * 3), ("hi", C.c_int32 * 3)]
+
+
+def box(lo, hi) -> Box:
+    return Box((C.c_int32 * 3)(*[int(v) for v in lo]), (C.c_int32 * 3)(*[int(v) for v in hi]))
+
+
+def box_reg_size(b: Box) -> int:
+    return flux_reg_size(*[b.hi[a] - b.lo[a] for a in range(3)])
+
+
 class Counts(C.Structure):
     _fields_ = [("fallback_faces", C.c_int64), ("floored_cells", C.c_int64)]
 
@@ -94,6 +107,13 @@ def lib():
         L.ppmo_expansion.argtypes = [C.POINTER(_Grid), C.POINTER(Params), C.c_double]
         L.ppmo_fill_boundary.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32), dp]
         L.ppmo_second_order_a.argtypes = [dp, C.c_int32, dp]
+        L.ppmo_step_capture.argtypes = [C.POINTER(_Grid), C.POINTER(Params), C.c_double,
+                                        C.c_int32, C.POINTER(Counts), C.POINTER(Box), C.c_int32,
+                                        dp]
+        L.ppmo_flux_correct.argtypes = [C.POINTER(_Grid), C.POINTER(Params), C.POINTER(Box),
+                                        C.c_int32, dp, dp, C.c_int32]
+        L.ppmo_project.argtypes = [C.POINTER(_Grid), C.POINTER(Box), C.POINTER(_Grid),
+                                   C.c_int32]
         L.ppmo_fill_from_parent.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32),
                                             C.POINTER(_Grid), C.POINTER(C.c_int32), C.c_int32]
         L.ppmo_copy_from_sibling.argtypes = [C.POINTER(_Grid), C.POINTER(C.c_int32),
@@ -234,6 +254,37 @@ def second_order_a(nb, r: int) -> np.ndarray:
     out = np.zeros(r ** 3)
     lib().ppmo_second_order_a(_ptr(a), int(r), _ptr(out))
     return out.reshape(r, r, r)
+
+
+def step_capture(grid: Grid, prm: Params, dt: float, order, boxes: list) -> tuple:
+    """ppmo_step that also returns the fluxes dt*F through the faces of each
+    box (list of Box), one register-shaped block per box, concatenated."""
+    order = ORDERS.get(order, order)
+    c = Counts(0, 0)
+    arr = (Box * max(len(boxes), 1))(*boxes)
+    out = np.zeros(max(sum(box_reg_size(b) for b in boxes), 1))
+    g = grid._c()
+    if lib().ppmo_step_capture(C.byref(g), C.byref(prm), dt, int(order), C.byref(c), arr,
+                               len(boxes), _ptr(out)) != 0:
+        raise ValueError("ppmo_step_capture: invalid argument")
+    return c, out[:sum(box_reg_size(b) for b in boxes)]
+
+
+def flux_correct(coarse: Grid, prm: Params, boxes: list, caps: np.ndarray,
+                 fine_sums: np.ndarray, r: int) -> None:
+    arr = (Box * max(len(boxes), 1))(*boxes)
+    caps = np.ascontiguousarray(caps, dtype=np.float64)
+    fine_sums = np.ascontiguousarray(fine_sums, dtype=np.float64)
+    g = coarse._c()
+    if lib().ppmo_flux_correct(C.byref(g), C.byref(prm), arr, len(boxes), _ptr(caps),
+                               _ptr(fine_sums), int(r)) != 0:
+        raise ValueError("ppmo_flux_correct: invalid argument")
+
+
+def project(coarse: Grid, b: Box, fine: Grid, r: int) -> None:
+    gc, gf = coarse._c(), fine._c()
+    if lib().ppmo_project(C.byref(gc), C.byref(b), C.byref(gf), int(r)) != 0:
+        raise ValueError("ppmo_project: invalid argument")
 
 
 def fill_from_parent(fine: Grid, fine_start, parent: Grid, parent_start, r: int) -> None:

@@ -726,9 +726,21 @@ int64_t reg_face_offset(int nx, int ny, int nz, int face) {
   return off;
 }
 
+// Boxes of active cells (a finer patch's footprint) whose boundary fluxes a
+// step records: the faces lo[a]-1/2 and hi[a]-1/2 of each axis a, for the
+// pencils along a whose transverse cells lie in the box, as dt * F in the
+// layout of a flux register of a grid with the box's dimensions.
+struct Capture {
+  const ppmo_box *boxes = nullptr;
+  int nboxes = 0;
+  double *out = nullptr;
+};
+
+int64_t box_dim(const ppmo_box &b, int a) { return (int64_t)b.hi[a] - b.lo[a]; }
+
 template <class R>
 int sweep_impl(ppmo_grid *G, const ppmo_params *P, double dt, int axis, int active_mask,
-               ppmo_counts *counts) {
+               ppmo_counts *counts, const Capture &cap = Capture()) {
   const int g = G->ghost;
   const int N[3] = {G->nx, G->ny, G->nz};
   const int64_t n[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
@@ -787,6 +799,25 @@ int sweep_impl(ppmo_grid *G, const ppmo_params *P, double dt, int axis, int acti
           reg_hi_base[lab_of[k] * reg_field_stride + ro] = opc_val(rh[k]);
         }
       }
+      // fluxes through the faces of capture boxes crossed by this pencil
+      // (w.F holds the final fluxes of faces a0-1 .. a1; face j is j+1/2)
+      int64_t boff = 0;
+      for (int b = 0; b < cap.nboxes; ++b) {
+        const ppmo_box &B = cap.boxes[b];
+        const int64_t bd[3] = {box_dim(B, 0), box_dim(B, 1), box_dim(B, 2)};
+        const int c1 = i1 - g - B.lo[t1], c2 = i2 - g - B.lo[t2];
+        if (c1 >= 0 && c1 < bd[t1] && c2 >= 0 && c2 < bd[t2]) {
+          const int64_t fs = bd[t1] * bd[t2], ro = (int64_t)c2 * bd[t1] + c1;
+          const int jf[2] = {g + B.lo[axis] - 1, g + B.hi[axis] - 1};
+          for (int side = 0; side < 2; ++side) {
+            double *dst = cap.out + boff + reg_face_offset((int)bd[0], (int)bd[1], (int)bd[2],
+                                                           2 * axis + side);
+            for (int k = 0; k < 6; ++k)
+              dst[lab_of[k] * fs + ro] = opc_val(R(dt) * w.F[k][jf[side]]);
+          }
+        }
+        boff += reg_face_offset((int)bd[0], (int)bd[1], (int)bd[2], 6);
+      }
     }
     fb += c.fallback_faces;
     fl += c.floored_cells;
@@ -801,14 +832,27 @@ int sweep_impl(ppmo_grid *G, const ppmo_params *P, double dt, int axis, int acti
 const int kOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
 
 template <class R>
-int step_impl(ppmo_grid *G, const ppmo_params *P, double dt, int order, ppmo_counts *counts) {
+int step_impl(ppmo_grid *G, const ppmo_params *P, double dt, int order, ppmo_counts *counts,
+              const Capture &cap = Capture()) {
   int mask = 0;
   for (int s = 0; s < 3; ++s) {
     const int axis = kOrders[order][s];
     mask |= 1 << axis;  // axes swept so far (including this one) are restricted
-    sweep_impl<R>(G, P, dt, axis, mask & ~(1 << axis), counts);
+    sweep_impl<R>(G, P, dt, axis, mask & ~(1 << axis), counts, cap);
   }
   return 0;
+}
+
+bool box_inside(const ppmo_grid *G, const ppmo_box &b, int margin) {
+  const int N[3] = {G->nx, G->ny, G->nz};
+  for (int a = 0; a < 3; ++a)
+    if (b.lo[a] < margin || b.hi[a] > N[a] - margin || b.hi[a] <= b.lo[a]) return false;
+  return true;
+}
+
+bool in_box(const ppmo_box &b, int x, int y, int z) {
+  return x >= b.lo[0] && x < b.hi[0] && y >= b.lo[1] && y < b.hi[1] && z >= b.lo[2] &&
+         z < b.hi[2];
 }
 
 }  // namespace
@@ -830,6 +874,138 @@ int ppmo_step(ppmo_grid *g, const ppmo_params *p, double dt, int32_t order,
               ppmo_counts *counts) {
   if (!valid_grid(g) || !valid_params(p) || order < 0 || order > 5 || !(dt > 0)) return -1;
   return step_impl<double>(g, p, dt, order, counts);
+}
+
+int ppmo_step_capture(ppmo_grid *g, const ppmo_params *p, double dt, int32_t order,
+                      ppmo_counts *counts, const ppmo_box *boxes, int32_t nboxes, double *out) {
+  if (!valid_grid(g) || !valid_params(p) || order < 0 || order > 5 || !(dt > 0) ||
+      nboxes < 0 || (nboxes > 0 && (!boxes || !out)))
+    return -1;
+  for (int b = 0; b < nboxes; ++b)
+    if (!box_inside(g, boxes[b], 0)) return -1;
+  Capture cap;
+  cap.boxes = boxes;
+  cap.nboxes = nboxes;
+  cap.out = out;
+  return step_impl<double>(g, p, dt, order, counts, cap);
+}
+
+int ppmo_flux_correct(ppmo_grid *C, const ppmo_params *P, const ppmo_box *boxes,
+                      int32_t nboxes, const double *caps, const double *fine_sums, int32_t r) {
+  if (!valid_grid(C) || !valid_params(P) || r < 2 || nboxes < 0 ||
+      (nboxes > 0 && (!boxes || !caps || !fine_sums)))
+    return -1;
+  for (int b = 0; b < nboxes; ++b)
+    if (!box_inside(C, boxes[b], 1)) return -1;
+  const int g = C->ghost;
+  const int N[3] = {C->nx, C->ny, C->nz};
+  const int64_t n[3] = {N[0] + 2 * g, N[1] + 2 * g, N[2] + 2 * g};
+  const double dxs[3] = {C->dx, C->dy, C->dz};
+  // accumulated change of the conserved quantities rho, rho v, rho E, rho e
+  // of each coarse cell, contributions added in box, face, cell order
+  std::vector<double> delta((size_t)n[0] * n[1] * n[2] * 6, 0.0);
+  std::vector<char> touched((size_t)n[0] * n[1] * n[2], 0);
+  int64_t coff = 0, foff = 0;
+  for (int b = 0; b < nboxes; ++b) {
+    const ppmo_box &B = boxes[b];
+    const int bd[3] = {B.hi[0] - B.lo[0], B.hi[1] - B.lo[1], B.hi[2] - B.lo[2]};
+    const int fd[3] = {bd[0] * r, bd[1] * r, bd[2] * r};  // the fine patch's active dims
+    for (int face = 0; face < 6; ++face) {
+      const int a = face / 2, side = face % 2;
+      const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+      const int64_t cfs = (int64_t)bd[t1] * bd[t2], ffs = (int64_t)fd[t1] * fd[t2];
+      const double *cface = caps + coff + reg_face_offset(bd[0], bd[1], bd[2], face);
+      const double *fface = fine_sums + foff + reg_face_offset(fd[0], fd[1], fd[2], face);
+      for (int c2 = 0; c2 < bd[t2]; ++c2)
+        for (int c1 = 0; c1 < bd[t1]; ++c1) {
+          // the coarse cell just outside this face
+          int c[3];
+          c[a] = side == 0 ? B.lo[a] - 1 : B.hi[a];
+          c[t1] = B.lo[t1] + c1;
+          c[t2] = B.lo[t2] + c2;
+          bool covered = false;
+          for (int o = 0; o < nboxes && !covered; ++o) covered = in_box(boxes[o], c[0], c[1], c[2]);
+          if (covered) continue;
+          const int64_t cell = ((int64_t)(c[2] + g) * n[1] + (c[1] + g)) * n[0] + (c[0] + g);
+          touched[cell] = 1;
+          for (int k = 0; k < 6; ++k) {
+            // area average of the r x r fine faces that make up the coarse face
+            double sum = 0.0;
+            for (int jj = 0; jj < r; ++jj)
+              for (int ii = 0; ii < r; ++ii)
+                sum += fface[k * ffs + (int64_t)(c2 * r + jj) * fd[t1] + (c1 * r + ii)];
+            const double fine = sum / (double)(r * r);
+            const double coarse = cface[k * cfs + (int64_t)c2 * bd[t1] + c1];
+            // the outside cell's update used the coarse flux through this face
+            // (its +a face on the low side, its -a face on the high side)
+            const double d = side == 0 ? coarse - fine : fine - coarse;
+            delta[(size_t)cell * 6 + k] += d / (P->a * dxs[a]);
+          }
+        }
+    }
+    coff += reg_face_offset(bd[0], bd[1], bd[2], 6);
+    foff += reg_face_offset(fd[0], fd[1], fd[2], 6);
+  }
+  for (size_t cell = 0; cell < touched.size(); ++cell) {
+    if (!touched[cell]) continue;
+    const double *dq = &delta[cell * 6];
+    const double rho = C->rho[cell];
+    const double rn = rho + dq[0];
+    const double mx = rho * C->vx[cell] + dq[1];
+    const double my = rho * C->vy[cell] + dq[2];
+    const double mz = rho * C->vz[cell] + dq[3];
+    const double mE = rho * C->etot[cell] + dq[4];
+    const double me = rho * C->eint[cell] + dq[5];
+    C->rho[cell] = rn;
+    C->vx[cell] = mx / rn;
+    C->vy[cell] = my / rn;
+    C->vz[cell] = mz / rn;
+    C->etot[cell] = mE / rn;
+    C->eint[cell] = me / rn;
+  }
+  return 0;
+}
+
+int ppmo_project(ppmo_grid *C, const ppmo_box *box, const ppmo_grid *F, int32_t r) {
+  if (!valid_grid(C) || !valid_grid(F) || !box || r < 2 || !box_inside(C, *box, 0)) return -1;
+  const ppmo_box &B = *box;
+  if (F->nx != r * (B.hi[0] - B.lo[0]) || F->ny != r * (B.hi[1] - B.lo[1]) ||
+      F->nz != r * (B.hi[2] - B.lo[2]))
+    return -1;
+  const int gc = C->ghost, gf = F->ghost;
+  const int64_t nc[3] = {C->nx + 2 * gc, C->ny + 2 * gc, C->nz + 2 * gc};
+  const int64_t nf[3] = {F->nx + 2 * gf, F->ny + 2 * gf, F->nz + 2 * gf};
+  const double vol = (double)(r * r * r);
+  for (int z = B.lo[2]; z < B.hi[2]; ++z)
+    for (int y = B.lo[1]; y < B.hi[1]; ++y)
+      for (int x = B.lo[0]; x < B.hi[0]; ++x) {
+        // volume average of the conserved quantities of the r^3 fine cells
+        double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int kk = 0; kk < r; ++kk)
+          for (int jj = 0; jj < r; ++jj)
+            for (int ii = 0; ii < r; ++ii) {
+              const int64_t fx = gf + (int64_t)(x - B.lo[0]) * r + ii;
+              const int64_t fy = gf + (int64_t)(y - B.lo[1]) * r + jj;
+              const int64_t fz = gf + (int64_t)(z - B.lo[2]) * r + kk;
+              const int64_t o = (fz * nf[1] + fy) * nf[0] + fx;
+              const double rho = F->rho[o];
+              s[0] += rho;
+              s[1] += rho * F->vx[o];
+              s[2] += rho * F->vy[o];
+              s[3] += rho * F->vz[o];
+              s[4] += rho * F->etot[o];
+              s[5] += rho * F->eint[o];
+            }
+        const int64_t o = ((int64_t)(z + gc) * nc[1] + (y + gc)) * nc[0] + (x + gc);
+        const double rho = s[0] / vol;
+        C->rho[o] = rho;
+        C->vx[o] = (s[1] / vol) / rho;
+        C->vy[o] = (s[2] / vol) / rho;
+        C->vz[o] = (s[3] / vol) / rho;
+        C->etot[o] = (s[4] / vol) / rho;
+        C->eint[o] = (s[5] / vol) / rho;
+      }
+  return 0;
 }
 
 int ppmo_pencil(const ppmo_params *p, int32_t n, int32_t ghost, double dt, double dx,

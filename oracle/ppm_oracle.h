@@ -185,6 +185,40 @@ int ppmo_fill_from_parent(ppmo_grid *fine, const int32_t fine_start[3], const pp
 int ppmo_copy_from_sibling(ppmo_grid *dst, const int32_t dst_start[3], const ppmo_grid *src,
                            const int32_t src_start[3]);
 
+/* A box of active cells [lo, hi) of a grid, in active-local indices (the
+ * footprint of a finer patch, in this grid's cells). */
+typedef struct {
+  int32_t lo[3], hi[3];
+} ppmo_box;
+
+/* ppmo_step that also records, for every box, dt * F through its six faces
+ * (faces lo[a]-1/2 and hi[a]-1/2 of each axis a, during the sweep along a)
+ * into out: per box, in order, a block laid out like the flux register of a
+ * grid with the box's dimensions.  Boxes lie inside the active region. */
+int ppmo_step_capture(ppmo_grid *g, const ppmo_params *p, double dt, int32_t order,
+                      ppmo_counts *counts, const ppmo_box *boxes, int32_t nboxes, double *out);
+
+/* Flux correction (Sec. "Flux correction") of coarse grid C after its
+ * children -- the finer patches whose footprints are boxes[0..nboxes), each
+ * at least one cell inside C's active region, refinement factor r -- have
+ * reached C's time.  caps: the coarse fluxes recorded by ppmo_step_capture
+ * for the same boxes; fine_sums: per box, the child's flux register summed
+ * over its substeps (its layout, dimensions r times the box's).  Every coarse
+ * cell that shares a face with a box and lies in no box has the conserved
+ * quantities rho, rho v, rho E and rho e corrected by the difference between
+ * the coarse flux and the area average of the r^2 fine fluxes through that
+ * face, divided by a dx; contributions are summed per cell in box, face
+ * order and applied once. */
+int ppmo_flux_correct(ppmo_grid *C, const ppmo_params *p, const ppmo_box *boxes,
+                      int32_t nboxes, const double *caps, const double *fine_sums, int32_t r);
+
+/* Projection (Sec. "Projection"): every coarse cell of `box` (inside C's
+ * active region) gets the volume average of the conserved quantities rho,
+ * rho v, rho E, rho e of the r^3 cells of fine grid F that cover it (F's
+ * active region is exactly the box refined by r); v, E and e are stored as
+ * the averages' ratios to the averaged density. */
+int ppmo_project(ppmo_grid *C, const ppmo_box *box, const ppmo_grid *F, int32_t r);
+
 /* Two-shock Riemann solver on (rho,u,p) left/right states.
  * out[0]=p*, out[1]=u*, out[2..4] = sampled (rho,u,p) at x/t=0,
  * out[5] = iterations taken, out[6] = 1 if the left side is upwind. */

@@ -1,0 +1,191 @@
+"""Pins of the oracle's AMR level step on a static hierarchy (CPU only).
+
+The W-cycle (Sec. "Adaptive Mesh Refinement"), flux correction (Sec. "Flux
+correction") and projection (Sec. "Projection") are pinned by what the paper
+fixes independently of their code: the composite solution of a periodic
+hierarchy conserves mass, momentum and total energy to round-off over a root
+step with subcycled levels (and does not without the correction -- the
+negative control shows the pin bites); a hierarchy of one level is plain
+stepping, bit for bit; the face fluxes a step records for a box equal the
+flux registers of a grid that is exactly that box; projection conserves the
+mass of what it averages; the parent state a child's ghosts see is linear in
+time between the parent's states; and a smooth contact advected through a
+refined region is more accurate on the fine patch than on the coarse grid
+alone, with the refined run's coarse cells no worse than the unrefined run's.
+"""
+import numpy as np
+import pytest
+
+from oracle import amr
+from paper_1307_2265_amd import workloads as W
+
+GH = 4
+
+
+def _grid(O, d, dx, ghost=GH, reg=False):
+    nz, ny, nx = (s - 2 * ghost for s in d["rho"].shape)
+    G = O.Grid(**{k: np.ascontiguousarray(v) for k, v in d.items()}, dx=dx[0], dy=dx[1],
+               dz=dx[2], ghost=ghost)
+    if reg:
+        G.flux_reg = np.zeros(O.flux_reg_size(nx, ny, nz))
+    return G
+
+
+def _nested(O, seed, recipe=W.GENTLE, siblings=False):
+    """Periodic 16^3 root, a level-1 child and a level-2 grandchild (r = 2),
+    each at least one parent cell inside its parent; siblings adds a second
+    level-1 child that does not touch the first."""
+    spec = [(0, -1, (0, 0, 0), (16, 16, 16)),
+            (1, 0, (8, 8, 8), (12, 12, 12)),
+            (2, 1, (20, 20, 20), (8, 8, 8))]
+    if siblings:
+        spec.append((1, 0, (2, 22, 4), (8, 6, 10)))
+    nodes = []
+    for i, (lev, par, start, dims) in enumerate(spec):
+        d = W.random_grid(*dims, seed + i, recipe, ghost=GH)
+        h = 1.0 / 16 * 0.5 ** lev
+        nodes.append(amr.Node(_grid(O, d, (h, h, h), reg=lev > 0), lev, par, start, 2))
+    return nodes
+
+
+def test_composite_conservation_over_a_root_step(O):
+    H = amr.Hierarchy(_nested(O, 500, siblings=True), [O.params()] * 3)
+    H.fill(0)
+    for l in (1, 2):
+        H.fill(l)
+    t0 = H.composite_totals()
+    for _ in range(2):
+        H.evolve()
+    t1 = H.composite_totals()
+    # several substeps of each finer level per root step
+    assert sum(1 for l, _ in H.dts if l == 2) > sum(1 for l, _ in H.dts if l == 0)
+    scale = np.array([t0[0], t0[0], t0[0], t0[0], t0[4]])
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * scale), (t1 - t0) / scale
+
+
+def test_without_flux_correction_conservation_fails(O):
+    H = amr.Hierarchy(_nested(O, 500, siblings=True), [O.params()] * 3, correct=False)
+    for l in (0, 1, 2):
+        H.fill(l)
+    t0 = H.composite_totals()
+    H.evolve()
+    t1 = H.composite_totals()
+    assert abs(t1[0] - t0[0]) > 1e-9 * t0[0]
+
+
+def test_one_level_is_plain_stepping(O):
+    d = W.random_grid(12, 10, 8, 510, W.SHOCKED, ghost=GH)
+    A = _grid(O, {k: v.copy() for k, v in d.items()}, (1 / 12, 1 / 10, 1 / 8))
+    B = _grid(O, {k: v.copy() for k, v in d.items()}, (1 / 12, 1 / 10, 1 / 8))
+    prm = O.params()
+    H = amr.Hierarchy([amr.Node(A, 0)], [prm])
+    for s in range(3):
+        H.evolve()
+        O.fill_periodic(B)
+        dt = O.cfl_dt(B, prm)
+        O.step(B, prm, dt, s % 2)
+        assert H.dts[-1] == (0, dt)
+    O.fill_periodic(B)
+    for f in O.FIELDS:
+        assert np.array_equal(getattr(A, f), getattr(B, f)), f
+
+
+def test_captured_fluxes_of_a_whole_grid_box_are_its_registers(O):
+    d = W.random_grid(10, 8, 6, 520, W.SHOCKED, ghost=GH)
+    A = _grid(O, {k: v.copy() for k, v in d.items()}, (0.1, 0.125, 1 / 6), reg=True)
+    B = _grid(O, {k: v.copy() for k, v in d.items()}, (0.1, 0.125, 1 / 6), reg=True)
+    O.fill_periodic(A)
+    O.fill_periodic(B)
+    prm = O.params()
+    dt = O.cfl_dt(A, prm)
+    sub = O.box((2, 1, 3), (7, 6, 5))
+    _, cap = O.step_capture(A, prm, dt, 1, [O.box((0, 0, 0), (10, 8, 6)), sub])
+    O.step(B, prm, dt, 1)
+    n0 = O.flux_reg_size(10, 8, 6)
+    assert np.array_equal(cap[:n0], B.flux_reg)
+    for f in O.FIELDS:
+        assert np.array_equal(getattr(A, f), getattr(B, f))
+    # an interior box: its -x face fluxes are the ones that cross x = 2 - 1/2
+    assert np.abs(cap[n0:]).max() > 0
+
+
+def test_projection_conserves_the_mass_it_averages(O):
+    d = W.random_grid(8, 8, 8, 530, W.SHOCKED, ghost=GH)
+    C = _grid(O, d, (0.125,) * 3)
+    f = W.random_grid(6, 4, 8, 531, W.SHOCKED, ghost=GH)
+    F = _grid(O, f, (0.0625,) * 3)
+    b = O.box((2, 3, 1), (5, 5, 5))
+    fact = (slice(GH, -GH),) * 3
+    fine = [F.rho[fact].sum() * F.dx ** 3, (F.rho * F.vx)[fact].sum() * F.dx ** 3,
+            (F.rho * F.etot)[fact].sum() * F.dx ** 3]
+    O.project(C, b, F, 2)
+    cs = (slice(GH + 1, GH + 5), slice(GH + 3, GH + 5), slice(GH + 2, GH + 5))
+    coarse = [C.rho[cs].sum() * C.dx ** 3, (C.rho * C.vx)[cs].sum() * C.dx ** 3,
+              (C.rho * C.etot)[cs].sum() * C.dx ** 3]
+    for a, c in zip(fine, coarse):
+        assert c == pytest.approx(a, rel=1e-13, abs=1e-15)
+    # cells outside the box are untouched
+    assert np.array_equal(C.rho[GH, GH, GH], d["rho"][GH, GH, GH])
+
+
+def test_child_ghosts_see_the_parent_linearly_in_time(O):
+    # a uniform parent at 1.0 before its step and 2.0 after it: a child at a
+    # quarter of the step sees 1.25 in every ghost cell
+    nodes = _nested(O, 540)[:2]
+    for n in nodes:
+        for f in O.FIELDS:
+            getattr(n.grid, f)[...] = 1.0
+    H = amr.Hierarchy(nodes, [O.params()] * 2)
+    H.old[0] = nodes[0].grid.copy()
+    nodes[0].grid.rho[...] = 2.0
+    H.t_old[0], H.t[0] = 0.0, 1.0
+    H.t[1] = 0.25
+    H.fill(1)
+    g = nodes[1].grid
+    assert np.all(g.rho[:GH] == 1.25) and np.all(g.rho[GH:-GH, GH:-GH, GH:-GH] == 1.0)
+    # momentum and energy densities are interpolated; v = (rho v) / rho = 1
+    assert np.allclose(g.vx[:GH], 1.0, rtol=1e-15)
+
+
+def _contact(nx, ny, nz, x0, dx, ghost=GH, amp=0.2):
+    """rho = 1 + amp sin(2 pi x) at the cell centres (x0: global x of the first
+    active cell's left face), v = (1, 0, 0), p = 1."""
+    x = x0 + (np.arange(nx + 2 * ghost) - ghost + 0.5) * dx
+    shape = (nz + 2 * ghost, ny + 2 * ghost, nx + 2 * ghost)
+    rho = np.broadcast_to(1.0 + amp * np.sin(2 * np.pi * x), shape).copy()
+    one, zero = np.ones(shape), np.zeros(shape)
+    st = W.stored_from_primitive(rho, one, zero, zero.copy(), one.copy(), 5.0 / 3.0)
+    return dict(zip(("rho", "vx", "vy", "vz", "etot", "eint"), st))
+
+
+def test_smooth_contact_is_more_accurate_on_the_refined_patch(O):
+    n = 32
+    h = 1.0 / n
+    prm = O.params()
+    root = _grid(O, _contact(n, 8, 8, 0.0, h), (h, h, h))
+    ref = _grid(O, _contact(n, 8, 8, 0.0, h), (h, h, h))
+    # child: coarse x 8..24, y 1..7, z 1..7 (r = 2)
+    child = _grid(O, _contact(32, 12, 12, 8 * h, h / 2), (h / 2,) * 3, reg=True)
+    H = amr.Hierarchy([amr.Node(root, 0), amr.Node(child, 1, 0, (16, 2, 2), 2)], [prm, prm])
+    T = 0.25
+    while H.t[0] < T - 1e-12:
+        H.evolve()
+    t = H.t[0]
+    # the unrefined run to the same time, with the same root steps
+    s = 0
+    for l, dt in H.dts:
+        if l == 0:
+            O.fill_periodic(ref)
+            O.step(ref, prm, dt, s % 2)
+            s += 1
+    exact = lambda x: 1.0 + 0.2 * np.sin(2 * np.pi * (x - t))
+    xc = (np.arange(n) + 0.5) * h
+    xf = 8 * h + (np.arange(32) + 0.5) * h / 2
+    a = (slice(GH, -GH),) * 3
+    err_f = np.abs(child.rho[a][3, 3] - exact(xf)).mean()
+    err_c = np.abs(ref.rho[a][3, 3, 8:24] - exact(xc[8:24])).mean()
+    out = np.r_[0:7, 25:32]
+    err_out_h = np.abs(root.rho[a][3, 3, out] - exact(xc[out])).mean()
+    err_out_c = np.abs(ref.rho[a][3, 3, out] - exact(xc[out])).mean()
+    assert err_f < 0.5 * err_c, (err_f, err_c)
+    assert err_out_h < 1.5 * err_out_c, (err_out_h, err_out_c)
