@@ -219,6 +219,57 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
  * a recorded hierarchy. */
 ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream);
 
+/* ---- AMR level step on a static hierarchy -------------------------------
+ * The W-cycle of Sec. "Adaptive Mesh Refinement" (EvolveLevel) over a fixed
+ * patch tree: the root takes one step with its CFL timestep; then every finer
+ * level takes as many steps of its own CFL timestep as it needs to reach its
+ * parent's time (the last one cut to land on it exactly), recursively; after
+ * a level's children have caught up, the level's cells that share a face
+ * with a child footprint are corrected with the difference between the
+ * coarse flux through that face and the area average of the child's fluxes
+ * summed over its substeps (Sec. "Flux correction"), and the cells a child
+ * covers get the volume average of its conserved quantities (Sec.
+ * "Projection").  Ghost zones are set at the start of a level's steps and
+ * after each step: the root's by its domain boundary conditions, the others
+ * by SecondOrderA interpolation from the parent's state at the patch's time
+ * -- linear in time between the parent's states before and after its step --
+ * and then from siblings (as ppm_fill_ghosts).
+ *
+ * patches / place: every patch and its placement as for ppm_set_hierarchy
+ * (level from ppm_patch.level); exactly one root patch (level 0, parent -1);
+ * every other patch needs a flux register, starts and ends on parent cell
+ * boundaries, lies at least one parent cell inside its parent's active
+ * region, does not overlap its siblings, and shares its refinement factor
+ * with them.  root_kinds (nullable): the root's six domain boundary kinds as
+ * for ppm_fill_boundary (with root_inflow); NULL means periodic, which needs
+ * a PPM_BC_PERIODIC root.  The hierarchy keeps pointers to the caller's
+ * fields and registers, allocates a copy of the fields of every patch that
+ * has children (its state before its last step), and a few small device
+ * work lists. */
+typedef struct ppm_amr ppm_amr;
+ppm_status ppm_amr_create(ppm_amr **out, const ppm_patch *patches, const ppm_patch_place *place,
+                          int32_t npatch, int32_t nlevels, ppm_precision prec,
+                          const ppm_params *params, const int32_t *root_kinds,
+                          const double *root_inflow, void *hip_stream);
+ppm_status ppm_amr_destroy(ppm_amr *amr); /* NULL is accepted */
+
+/* One root step of the W-cycle.  The host reads each level's timestep from
+ * the device before that level's step (one small copy and a stream
+ * synchronisation per level step) and returns after the stream has finished. */
+ppm_status ppm_amr_step(ppm_amr *amr, void *hip_stream);
+
+/* Current time and steps taken of every level (arrays of nlevels, nullable). */
+ppm_status ppm_amr_times(ppm_amr *amr, double *t, int64_t *steps);
+
+/* The (level, dt) of every level step of the last ppm_amr_step, in the order
+ * taken: *count gets their number, the first `capacity` are written. */
+ppm_status ppm_amr_step_log(ppm_amr *amr, int32_t *levels, double *dts, int32_t capacity,
+                            int32_t *count);
+
+/* Event counters (HLL faces, floored cells) summed over the levels. */
+ppm_status ppm_amr_event_counts(ppm_amr *amr, int64_t *fallback_faces, int64_t *floored_cells,
+                                void *hip_stream);
+
 /* Comoving coordinates (Sec. "Physical Equations").  a_dev: device array of
  * 2 * nlevels doubles, owned by the caller, holding for each level l the
  * expansion factor a_l = a_dev[2l] > 0 and its rate adot_l = a_dev[2l+1] at

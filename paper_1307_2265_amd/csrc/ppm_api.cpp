@@ -20,51 +20,10 @@
 
 #include "ppm.h"
 #include "ppm_kernels.hpp"
+#include "ppm_plan.hpp"
 
-using ppm::PatchDev;
 
-struct ppm_plan {
-  int32_t npatch = 0, nlevels = 0;
-  ppm_precision prec = PPM_FP64;
-  ppm::Params P{};
-  int32_t block = 256;            // threads (pencils) per marching-sweep block
-  int32_t lanes_block = 256;      // threads per lane-parallel block (64 per pencil)
-  int32_t lanes_mask = 1;         // bit a: sweeps along axis a use the lane-parallel kernel
-  int32_t cfl_cells = 4096;       // active cells per CFL block
-  int32_t persistent = 0;         // ppm_step as one persistent launch over all patches
-  int32_t batch_block = 256;      // threads per workgroup of the persistent kernel
-  int32_t batch_blocks = 0;       // workgroups of the persistent kernel
-  int32_t group = 0;              // marching sweeps number pencils across equal-length patches
-  bool group_set = false;         // group given in the tile config
-  int32_t tail = 1;               // one patch: lanes launch for a marching sweep's last round
-  int32_t tail_round = 0;         // pencils per marching round (0: from the occupancy)
-  int32_t tail_pencil0[2][12] = {};  // [cfl][slot]: first pencil of the lanes tail
-  int32_t tail_main[2][12] = {};     // marching blocks before it
-  int32_t tail_blocks[2][12] = {};   // lane-parallel blocks of the tail (0: no tail)
-  int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
-  unsigned int *d_queue = nullptr;  // persistent queue head and exit count
-  std::vector<PatchDev> host;
-  std::vector<int32_t> bc;        // boundary kind of each patch
-  PatchDev *d_patches = nullptr;
-  int32_t *d_chunks = nullptr;    // 12 marching, 12 lane-parallel prefix arrays, then CFL
-  int32_t nblocks[24] = {};
-  int32_t *d_groups = nullptr;    // grouped marching maps of the 12 (axis, extent) slots
-  int64_t gofs[12] = {};          // offset of each slot's map in d_groups
-  int32_t ngroups[12] = {};
-  int32_t cfl_blocks = 0;
-  unsigned long long *d_counters = nullptr;  // fallback faces, floored cells
-  unsigned long long *d_smax = nullptr;      // per-level max signal speed bits
-  int device = 0;
-  // AMR ghost fill work lists, grouped by level (ppm_set_hierarchy)
-  bool hier = false;
-  ppm::InterpItem *d_interp = nullptr;
-  ppm::SiblingBox *d_boxes = nullptr;
-  int64_t *d_iprefix = nullptr, *d_bprefix = nullptr;  // per level: items+1 / boxes+1 entries
-  std::vector<int32_t> ibeg, bbeg;        // per level: first item / box (nlevels+1 entries)
-  std::vector<int64_t> itotal, btotal;    // per level: ghost cells / box cells
-};
-
-namespace {
+namespace ppm_detail {
 
 thread_local std::string g_last_error;
 
@@ -81,6 +40,13 @@ ppm_status fail(ppm_status s, const char *fmt, ...) {
 ppm_status hip_fail(hipError_t e, const char *what) {
   return fail(PPM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace ppm_detail
+
+using ppm_detail::fail;
+using ppm_detail::hip_fail;
+
+namespace {
 
 const int kOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
 // Largest patch (active cells) that one workgroup of the persistent launch owns.
@@ -670,11 +636,17 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
 }
 
 ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream) {
+  return ppm_detail::fill_ghosts(plan, level, nullptr, 1.0, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"
+
+ppm_status ppm_detail::fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *old_patches,
+                                   double w, hipStream_t s) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!plan->hier) return fail(PPM_EINVAL, "no hierarchy recorded (ppm_set_hierarchy)");
   if (level < 0 || level >= plan->nlevels)
     return fail(PPM_EINVAL, "level %d outside [0, %d)", level, plan->nlevels);
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
   const int32_t i0 = plan->ibeg[level], ni = plan->ibeg[level + 1] - i0;
   const int32_t b0 = plan->bbeg[level], nb = plan->bbeg[level + 1] - b0;
   // prefix arrays hold one extra entry per level before it
@@ -684,9 +656,10 @@ ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream) {
   if (ni > 0) {
     e = plan->prec == PPM_FP64
         ? ppm::launch_fill_from_parent<ppm::PrecF64>(plan->d_patches, plan->d_interp + i0, ip, ni,
-                                                     plan->itotal[level], s)
-        : ppm::launch_fill_from_parent<ppm::PrecMixed>(plan->d_patches, plan->d_interp + i0, ip, ni,
-                                                       plan->itotal[level], s);
+                                                     plan->itotal[level], old_patches, w, s)
+        : ppm::launch_fill_from_parent<ppm::PrecMixed>(plan->d_patches, plan->d_interp + i0, ip,
+                                                       ni, plan->itotal[level], old_patches, w,
+                                                       s);
     if (e != hipSuccess) return hip_fail(e, "fill_from_parent launch");
   }
   if (nb > 0) {
@@ -699,6 +672,8 @@ ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream) {
   }
   return PPM_OK;
 }
+
+extern "C" {
 
 ppm_status ppm_set_expansion(ppm_plan *plan, const double *a_dev) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
@@ -914,6 +889,6 @@ const char *ppm_status_str(ppm_status st) {
   return "unknown ppm_status";
 }
 
-const char *ppm_last_error(void) { return g_last_error.c_str(); }
+const char *ppm_last_error(void) { return ppm_detail::g_last_error.c_str(); }
 
 }  // extern "C"

@@ -583,7 +583,8 @@ __device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64
 template <class Prec>
 __global__ void __launch_bounds__(256)
 fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *__restrict__ items,
-                        const int64_t *__restrict__ prefix, int32_t nitems, int64_t total) {
+                        const int64_t *__restrict__ prefix, int32_t nitems, int64_t total,
+                        const PatchDev *__restrict__ old_patches, double w) {
   using S = typename Prec::S;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= total) return;
@@ -610,6 +611,15 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
   const S *crho = static_cast<const S *>(cd.rho);
   const S *cvel[3] = {static_cast<const S *>(cd.vel[0]), static_cast<const S *>(cd.vel[1]),
                       static_cast<const S *>(cd.vel[2])};
+  // the parent's state before its last step, when the patch lies between
+  // the parent's two times
+  const bool blend = old_patches != nullptr;
+  PatchDev od = cd;
+  if (blend) od = old_patches[item.parent];
+  const S *orho = static_cast<const S *>(od.rho);
+  const S *ovel[3] = {static_cast<const S *>(od.vel[0]), static_cast<const S *>(od.vel[1]),
+                      static_cast<const S *>(od.vel[2])};
+  const double wo = 1.0 - w;
   double q[6];
   for (int comp = 0; comp < 6; ++comp) {
     double nb[3][3][3];
@@ -617,13 +627,18 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
       for (int dy = 0; dy < 3; ++dy)
         for (int dx = 0; dx < 3; ++dx) {
           const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
-          const double rho = double(crho[o]);
-          double v;
-          if (comp == 0) v = rho;
-          else if (comp < 4) v = rho * double(cvel[comp - 1][o]);
-          else if (comp == 4) v = rho * cd.etot[o];
-          else v = rho * cd.eint[o];
-          nb[dz][dy][dx] = v;
+          double rho = double(crho[o]);
+          double x = comp == 0 ? 0.0
+                   : comp < 4 ? double(cvel[comp - 1][o])
+                   : comp == 4 ? cd.etot[o] : cd.eint[o];
+          if (blend) {
+            rho = wo * double(orho[o]) + w * rho;
+            const double xo = comp == 0 ? 0.0
+                            : comp < 4 ? double(ovel[comp - 1][o])
+                            : comp == 4 ? od.etot[o] : od.eint[o];
+            x = wo * xo + w * x;
+          }
+          nb[dz][dy][dx] = comp == 0 ? rho : rho * x;
         }
     q[comp] = second_order_a_at(nb, r, si[0], si[1], si[2]);
   }
@@ -669,6 +684,163 @@ copy_from_siblings_kernel(const PatchDev *__restrict__ patches, const SiblingBox
     static_cast<S *>(dd.vel[a])[dst] = static_cast<const S *>(sd.vel[a])[src];
   dd.etot[dst] = sd.etot[src];
   dd.eint[dst] = sd.eint[src];
+}
+
+// ---------------------------------------------------------------------------
+// AMR level step: the coarse fluxes through the faces of child footprints,
+// the fine registers summed over substeps, flux correction and projection
+// (Secs. "Flux correction" and "Projection").
+
+// One wavefront per captured face: the lane-parallel segment code over the
+// 64 cells of the face's pencil centred on it (lane 31 holds the cell left of
+// the face), which yields the same final flux as the sweep that follows (a
+// face's flux, fallback included, depends on the five cells either side,
+// and lanes outside the pencil are placeholders no valid result uses).
+// Nothing is written but dt F of the face.
+template <class Prec, bool kUseHLLC, bool kGrav>
+__global__ void __launch_bounds__(256)
+capture_kernel(const PatchDev *__restrict__ patches, const CaptureRow *__restrict__ rows,
+               int32_t nrows, int32_t axis, const double *__restrict__ dt_dev, Params P) {
+  using S = typename Prec::S;
+  const int row = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
+  if (row >= nrows) return;  // the whole wave leaves
+  const int lane = threadIdx.x & 63;
+  const CaptureRow cr = rows[row];
+  const PatchDev pd = patches[cr.patch];
+  PencilRef<S> pc = make_pencil<S>(pd, axis, cr.i1, cr.i2);
+  pc.reg_lo = pc.reg_hi = nullptr;
+  const double dt = dt_dev[pd.level];
+  const double a = expansion_a(P, pd.level);
+  const double lam = dt / (a * pc.dx);
+  const double hgdt = 0.5 * dt / a;
+  const int jc = cr.j - 31 + lane;
+  const bool in = jc >= 0 && jc < pc.n;
+  const int j = in ? jc : -1;
+  CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
+  if (in) {
+    const int64_t o = pc.base + int64_t(j) * pc.stride;
+    cur.r = double(pc.rho[o]); cur.u = double(pc.u[o]);
+    cur.v1 = double(pc.v1[o]); cur.v2 = double(pc.v2[o]);
+    cur.E = pc.E[o]; cur.e = pc.e[o];
+  }
+  uint32_t nfb = 0, nfl = 0;
+  CflAcc cfl = cfl_acc(pd, axis, nullptr);
+  const Flux F = sweep_segment<Prec, false, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, false, cur,
+                                                             nfb, nfl, cfl);
+  if (j == cr.j) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) cr.dst[pc.lab[k] * cr.fstride] = dt * F.f[k];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+accumulate_kernel(const AccItem *__restrict__ items, const int64_t *__restrict__ prefix,
+                  int32_t nitems, int64_t total) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int it = find_item(prefix, nitems, t);
+  const AccItem item = items[it];
+  const int64_t u = t - prefix[it];
+  item.acc[u] = item.acc[u] + item.reg[u];
+}
+
+// One thread per corrected coarse cell: the changes of rho, rho v, rho E,
+// rho e from each face it shares with a child footprint (coarse flux minus
+// the area average of the fine fluxes, over a dx, signed by the side),
+// summed in list order, then applied to the conserved quantities and stored.
+template <class Prec>
+__global__ void __launch_bounds__(256)
+flux_correct_kernel(const PatchDev *__restrict__ patches, const CorrTarget *__restrict__ targets,
+                    int32_t ntargets, const CorrContrib *__restrict__ contribs, Params P) {
+  using S = typename Prec::S;
+  const int t = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= ntargets) return;
+  const CorrTarget tg = targets[t];
+  const PatchDev pd = patches[tg.patch];
+  const double a = expansion_a(P, pd.level);
+  double dq[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int c = tg.first; c < tg.first + tg.count; ++c) {
+    const CorrContrib cb = contribs[c];
+    const double rr = double(cb.r * cb.r);
+    for (int k = 0; k < 6; ++k) {
+      double sum = 0.0;
+      for (int jj = 0; jj < cb.r; ++jj)
+        for (int ii = 0; ii < cb.r; ++ii)
+          sum += cb.fine[k * cb.fine_fstride + int64_t(jj) * cb.fine_row + ii];
+      const double fine = sum / rr;
+      const double coarse = cb.cap[k * cb.cap_fstride];
+      const double d = cb.side == 0 ? coarse - fine : fine - coarse;
+      dq[k] += d / (a * pd.dx[cb.axis]);
+    }
+  }
+  const int64_t o = tg.cell;
+  S *rho_p = static_cast<S *>(pd.rho);
+  S *vx = static_cast<S *>(pd.vel[0]);
+  S *vy = static_cast<S *>(pd.vel[1]);
+  S *vz = static_cast<S *>(pd.vel[2]);
+  const double rho = double(rho_p[o]);
+  const double rn = rho + dq[0];
+  const double mx = rho * double(vx[o]) + dq[1];
+  const double my = rho * double(vy[o]) + dq[2];
+  const double mz = rho * double(vz[o]) + dq[3];
+  const double mE = rho * pd.etot[o] + dq[4];
+  const double me = rho * pd.eint[o] + dq[5];
+  rho_p[o] = S(rn);
+  vx[o] = S(mx / rn);
+  vy[o] = S(my / rn);
+  vz[o] = S(mz / rn);
+  pd.etot[o] = mE / rn;
+  pd.eint[o] = me / rn;
+}
+
+// One thread per coarse cell of a child footprint: the volume average of the
+// conserved quantities of the r^3 fine cells over it.
+template <class Prec>
+__global__ void __launch_bounds__(256)
+project_kernel(const PatchDev *__restrict__ patches, const ProjItem *__restrict__ items,
+               const int64_t *__restrict__ prefix, int32_t nitems, int64_t total) {
+  using S = typename Prec::S;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int it = find_item(prefix, nitems, t);
+  const ProjItem item = items[it];
+  const int64_t u = t - prefix[it];
+  const int64_t ex = item.hi[0] - item.lo[0], ey = item.hi[1] - item.lo[1];
+  const int64_t x = item.lo[0] + u % ex, y = item.lo[1] + (u / ex) % ey;
+  const int64_t z = item.lo[2] + u / (ex * ey);
+  const PatchDev cd = patches[item.coarse];
+  const PatchDev fd = patches[item.fine];
+  const int gc = cd.ghost, gf = fd.ghost, r = item.r;
+  const int64_t nc[2] = {int64_t(cd.n[0]) + 2 * gc, int64_t(cd.n[1]) + 2 * gc};
+  const int64_t nf[2] = {int64_t(fd.n[0]) + 2 * gf, int64_t(fd.n[1]) + 2 * gf};
+  const S *frho = static_cast<const S *>(fd.rho);
+  const S *fv[3] = {static_cast<const S *>(fd.vel[0]), static_cast<const S *>(fd.vel[1]),
+                    static_cast<const S *>(fd.vel[2])};
+  double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int kk = 0; kk < r; ++kk)
+    for (int jj = 0; jj < r; ++jj)
+      for (int ii = 0; ii < r; ++ii) {
+        const int64_t fx = gf + (x - item.lo[0]) * r + ii;
+        const int64_t fy = gf + (y - item.lo[1]) * r + jj;
+        const int64_t fz = gf + (z - item.lo[2]) * r + kk;
+        const int64_t o = (fz * nf[1] + fy) * nf[0] + fx;
+        const double rho = double(frho[o]);
+        s[0] += rho;
+        s[1] += rho * double(fv[0][o]);
+        s[2] += rho * double(fv[1][o]);
+        s[3] += rho * double(fv[2][o]);
+        s[4] += rho * fd.etot[o];
+        s[5] += rho * fd.eint[o];
+      }
+  const double vol = double(r * r * r);
+  const int64_t o = ((z + gc) * nc[1] + (y + gc)) * nc[0] + (x + gc);
+  const double rho = s[0] / vol;
+  static_cast<S *>(cd.rho)[o] = S(rho);
+  static_cast<S *>(cd.vel[0])[o] = S((s[1] / vol) / rho);
+  static_cast<S *>(cd.vel[1])[o] = S((s[2] / vol) / rho);
+  static_cast<S *>(cd.vel[2])[o] = S((s[3] / vol) / rho);
+  cd.etot[o] = (s[4] / vol) / rho;
+  cd.eint[o] = (s[5] / vol) / rho;
 }
 
 // ---------------------------------------------------------------------------
@@ -841,10 +1013,52 @@ hipError_t launch_fill_boundary(const PatchDev &pd, const FaceRules &fr, hipStre
 template <class Prec>
 hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *items,
                                    const int64_t *prefix, int32_t nitems, int64_t total,
-                                   hipStream_t s) {
+                                   const PatchDev *old_patches, double w, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_from_parent_kernel<Prec>, dim3(unsigned((total + 255) / 256)), dim3(256),
-                     0, s, patches, items, prefix, nitems, total);
+                     0, s, patches, items, prefix, nitems, total, old_patches, w);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32_t nrows,
+                          int32_t axis, const double *dt_dev, const Params &P, hipStream_t s) {
+  if (nrows <= 0) return hipSuccess;
+  const unsigned blocks = unsigned((int64_t(nrows) + 3) / 4);
+#define PPM_LAUNCH_CAPTURE(HLLC, GRAV)                                                       \
+  hipLaunchKernelGGL((capture_kernel<Prec, HLLC, GRAV>), dim3(blocks), dim3(256), 0, s,       \
+                     patches, rows, nrows, axis, dt_dev, P)
+  if (P.flags & kAnyGravity) PPM_LAUNCH_CAPTURE(true, true);
+  else if (P.flags & kHLLC) PPM_LAUNCH_CAPTURE(true, false);
+  else PPM_LAUNCH_CAPTURE(false, false);
+#undef PPM_LAUNCH_CAPTURE
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(const AccItem *items, const int64_t *prefix, int32_t nitems,
+                             int64_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(accumulate_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s,
+                     items, prefix, nitems, total);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_flux_correct(const PatchDev *patches, const CorrTarget *targets,
+                               int32_t ntargets, const CorrContrib *contribs, const Params &P,
+                               hipStream_t s) {
+  if (ntargets <= 0) return hipSuccess;
+  hipLaunchKernelGGL(flux_correct_kernel<Prec>, dim3(unsigned((ntargets + 255) / 256)), dim3(256),
+                     0, s, patches, targets, ntargets, contribs, P);
+  return hipGetLastError();
+}
+
+template <class Prec>
+hipError_t launch_project(const PatchDev *patches, const ProjItem *items, const int64_t *prefix,
+                          int32_t nitems, int64_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(project_kernel<Prec>, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s,
+                     patches, items, prefix, nitems, total);
   return hipGetLastError();
 }
 
@@ -904,16 +1118,27 @@ template hipError_t launch_expansion<PrecF64>(const PatchDev *, const int32_t *,
 template hipError_t launch_expansion<PrecMixed>(const PatchDev *, const int32_t *, int32_t,
                                                 int32_t, int32_t, double, const double *,
                                                 const double *, hipStream_t);
+#define PPM_INSTANTIATE_AMR(Prec)                                                              \
+  template hipError_t launch_capture<Prec>(const PatchDev *, const CaptureRow *, int32_t, int32_t, \
+                                           const double *, const Params &, hipStream_t);        \
+  template hipError_t launch_flux_correct<Prec>(const PatchDev *, const CorrTarget *, int32_t,   \
+                                                const CorrContrib *, const Params &,             \
+                                                hipStream_t);                                    \
+  template hipError_t launch_project<Prec>(const PatchDev *, const ProjItem *, const int64_t *,  \
+                                           int32_t, int64_t, hipStream_t);
+PPM_INSTANTIATE_AMR(PrecF64)
+PPM_INSTANTIATE_AMR(PrecMixed)
+#undef PPM_INSTANTIATE_AMR
 template hipError_t launch_fill<PrecF64>(const PatchDev &, hipStream_t);
 template hipError_t launch_fill<PrecMixed>(const PatchDev &, hipStream_t);
 template hipError_t launch_fill_boundary<PrecF64>(const PatchDev &, const FaceRules &,
                                                   hipStream_t);
 template hipError_t launch_fill_from_parent<PrecF64>(const PatchDev *, const InterpItem *,
                                                      const int64_t *, int32_t, int64_t,
-                                                     hipStream_t);
+                                                     const PatchDev *, double, hipStream_t);
 template hipError_t launch_fill_from_parent<PrecMixed>(const PatchDev *, const InterpItem *,
                                                        const int64_t *, int32_t, int64_t,
-                                                       hipStream_t);
+                                                       const PatchDev *, double, hipStream_t);
 template hipError_t launch_copy_from_siblings<PrecF64>(const PatchDev *, const SiblingBox *,
                                                        const int64_t *, int32_t, int64_t,
                                                        hipStream_t);

@@ -98,11 +98,66 @@ struct SiblingBox {
 
 // Ghost cells of items[0..nitems): SecondOrderA interpolation of the parent's
 // conserved quantities.  prefix[i] = first ghost cell of item i in the launch
-// (prefix[nitems] = total).
+// (prefix[nitems] = total).  old_patches (nullable): the parents' states
+// before their last step (same table layout); the parent's stored fields
+// are then (1 - w) old + w new.
 template <class Prec>
 hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *items,
                                    const int64_t *prefix, int32_t nitems, int64_t total,
-                                   hipStream_t s);
+                                   const PatchDev *old_patches, double w, hipStream_t s);
+
+// A face whose flux a coarse step records: the pencil (i1, i2) of `patch`
+// along the capture launch's axis, the face between its cells j and j+1
+// (ghosted indices), and where dt F goes: dst[lab * fstride] for the six lab
+// quantities.
+struct CaptureRow {
+  int32_t patch, i1, i2, j;
+  double *dst;
+  int64_t fstride;
+};
+
+// Final fluxes of rows[0..nrows) from the current state (the input of the
+// sweep along `axis` that follows), one wavefront per row.
+template <class Prec>
+hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32_t nrows,
+                          int32_t axis, const double *dt_dev, const Params &P, hipStream_t s);
+
+// acc[i] += reg[i] over the listed register blocks (prefix over their sizes).
+struct AccItem {
+  double *acc;
+  const double *reg;
+};
+hipError_t launch_accumulate(const AccItem *items, const int64_t *prefix, int32_t nitems,
+                             int64_t total, hipStream_t s);
+
+// Flux correction: one coarse cell per target, its contributions applied in
+// list order.  A contribution is one face of a child footprint: the coarse
+// dt F of the face (cap[k * cap_fstride]) and the r x r fine accumulated
+// fluxes (fine[k * fine_fstride + jj * fine_row + ii]).
+struct CorrTarget {
+  int32_t patch, first, count, pad;
+  int64_t cell;
+};
+struct CorrContrib {
+  const double *cap;
+  const double *fine;
+  int64_t cap_fstride, fine_fstride;
+  int32_t fine_row, r, side, axis;
+};
+template <class Prec>
+hipError_t launch_flux_correct(const PatchDev *patches, const CorrTarget *targets,
+                               int32_t ntargets, const CorrContrib *contribs, const Params &P,
+                               hipStream_t s);
+
+// Projection of children onto the coarse cells of their footprints (boxes in
+// the coarse patch's active-local cells); prefix over box volumes.
+struct ProjItem {
+  int32_t coarse, fine, r, pad;
+  int32_t lo[3], hi[3];
+};
+template <class Prec>
+hipError_t launch_project(const PatchDev *patches, const ProjItem *items, const int64_t *prefix,
+                          int32_t nitems, int64_t total, hipStream_t s);
 
 // Sibling copies of boxes[0..nboxes); prefix as above, over box volumes.
 template <class Prec>

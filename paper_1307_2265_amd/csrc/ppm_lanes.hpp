@@ -75,9 +75,10 @@ struct CellLoad {
 // lane beyond the stream, which no valid result uses).  `in` is this lane's
 // input cell; the lane writes its cell (and counts its events) if `mine`.
 // lam = dt / (a pc.dx) and hgdt = (dt / 2) / a, with a the level's expansion
-// factor (the same for every pencil of the patch).
+// factor (the same for every pencil of the patch).  Returns the final flux
+// (after the fallback) of face j+1/2.
 template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
-__device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
+__device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                               double lam, double hgdt, int j, bool mine, const CellLoad &in,
                               uint32_t &n_fallback, uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
@@ -234,6 +235,7 @@ __device__ void sweep_segment(const Params &P, const PencilRef<typename Prec::S>
                            out[4], out[5]);
   }
   if (kCFL) cfl.smax = sig > cfl.smax ? sig : cfl.smax;  // per lane; reduced at the end
+  return F;
 }
 
 // One wave streams pencils first .. first+nrows-1 of a sweep's pencil set,

@@ -1,0 +1,70 @@
+// ppm_plan.hpp -- the plan behind the C ABI's opaque ppm_plan, and the
+// library-internal helpers the ABI's source files share.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ppm.h"
+#include "ppm_kernels.hpp"
+
+using ppm::PatchDev;
+
+struct ppm_plan {
+  int32_t npatch = 0, nlevels = 0;
+  ppm_precision prec = PPM_FP64;
+  ppm::Params P{};
+  int32_t block = 256;            // threads (pencils) per marching-sweep block
+  int32_t lanes_block = 256;      // threads per lane-parallel block (64 per pencil)
+  int32_t lanes_mask = 1;         // bit a: sweeps along axis a use the lane-parallel kernel
+  int32_t cfl_cells = 4096;       // active cells per CFL block
+  int32_t persistent = 0;         // ppm_step as one persistent launch over all patches
+  int32_t batch_block = 256;      // threads per workgroup of the persistent kernel
+  int32_t batch_blocks = 0;       // workgroups of the persistent kernel
+  int32_t group = 0;              // marching sweeps number pencils across equal-length patches
+  bool group_set = false;         // group given in the tile config
+  int32_t tail = 1;               // one patch: lanes launch for a marching sweep's last round
+  int32_t tail_round = 0;         // pencils per marching round (0: from the occupancy)
+  int32_t tail_pencil0[2][12] = {};  // [cfl][slot]: first pencil of the lanes tail
+  int32_t tail_main[2][12] = {};     // marching blocks before it
+  int32_t tail_blocks[2][12] = {};   // lane-parallel blocks of the tail (0: no tail)
+  int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
+  unsigned int *d_queue = nullptr;  // persistent queue head and exit count
+  std::vector<PatchDev> host;
+  std::vector<int32_t> bc;        // boundary kind of each patch
+  PatchDev *d_patches = nullptr;
+  int32_t *d_chunks = nullptr;    // 12 marching, 12 lane-parallel prefix arrays, then CFL
+  int32_t nblocks[24] = {};
+  int32_t *d_groups = nullptr;    // grouped marching maps of the 12 (axis, extent) slots
+  int64_t gofs[12] = {};          // offset of each slot's map in d_groups
+  int32_t ngroups[12] = {};
+  int32_t cfl_blocks = 0;
+  unsigned long long *d_counters = nullptr;  // fallback faces, floored cells
+  unsigned long long *d_smax = nullptr;      // per-level max signal speed bits
+  int device = 0;
+  // AMR ghost fill work lists, grouped by level (ppm_set_hierarchy)
+  bool hier = false;
+  ppm::InterpItem *d_interp = nullptr;
+  ppm::SiblingBox *d_boxes = nullptr;
+  int64_t *d_iprefix = nullptr, *d_bprefix = nullptr;  // per level: items+1 / boxes+1 entries
+  std::vector<int32_t> ibeg, bbeg;        // per level: first item / box (nlevels+1 entries)
+  std::vector<int64_t> itotal, btotal;    // per level: ghost cells / box cells
+};
+
+namespace ppm_detail {
+
+// Record the error message of the last failing call (ppm_last_error) and
+// return s.
+ppm_status fail(ppm_status s, const char *fmt, ...);
+ppm_status hip_fail(hipError_t e, const char *what);
+
+// ppm_fill_ghosts of `level`, with the parents' stored fields taken as
+// (1 - w) old + w current when old_patches (a device copy of the plan's patch
+// table pointing at the parents' earlier states) is given.
+ppm_status fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *old_patches, double w,
+                       hipStream_t s);
+
+}  // namespace ppm_detail

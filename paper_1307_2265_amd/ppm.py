@@ -58,6 +58,16 @@ SIGNATURES = {
     "ppm_fill_ghosts": (C.c_int, [_vp, C.c_int32, _vp]),
     "ppm_fill_boundary": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                     _vp]),
+    "ppm_amr_create": (C.c_int, [C.POINTER(_vp), C.POINTER(ppm_patch),
+                                 C.POINTER(ppm_patch_place), C.c_int32, C.c_int32, C.c_int,
+                                 C.POINTER(ppm_params), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_double), _vp]),
+    "ppm_amr_destroy": (C.c_int, [_vp]),
+    "ppm_amr_step": (C.c_int, [_vp, _vp]),
+    "ppm_amr_times": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "ppm_amr_step_log": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
+                                   C.POINTER(C.c_int32)]),
+    "ppm_amr_event_counts": (C.c_int, [_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), _vp]),
     "ppm_set_expansion": (C.c_int, [_vp, _vp]),
     "ppm_expansion": (C.c_int, [_vp, _vp, _vp]),
     "ppm_cfl_dt": (C.c_int, [_vp, _vp, _vp]),
@@ -268,6 +278,70 @@ class Plan:
     def close(self):
         if getattr(self, "_h", None):
             lib().ppm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Amr:
+    """Owns a ppm_amr: the W-cycle over a static hierarchy of patches.
+
+    places: per patch (parent index or -1, refinement factor, (start x, y, z)),
+    as for Plan.ppm_set_hierarchy; root_kinds / root_inflow: the root's domain
+    boundary conditions (None: periodic)."""
+
+    def __init__(self, patches: list, places: list, nlevels: int, precision: int = PPM_FP64,
+                 prm: ppm_params | None = None, root_kinds=None, root_inflow=None, stream=None):
+        self._patches = list(patches)
+        self.nlevels = nlevels
+        arr = (ppm_patch * len(patches))(*[p.to_c() for p in patches])
+        pl = (ppm_patch_place * len(places))()
+        for i, (parent, refine, start) in enumerate(places):
+            pl[i].parent, pl[i].refine = int(parent), int(refine)
+            for a in range(3):
+                pl[i].start[a] = int(start[a])
+        self.params = prm if prm is not None else params()
+        kinds = None if root_kinds is None else (C.c_int32 * 6)(*[int(k) for k in root_kinds])
+        inflow = None
+        if root_inflow is not None:
+            inflow = (C.c_double * 36)(*[float(v) for row in root_inflow for v in row])
+        h = _vp()
+        _check(lib().ppm_amr_create(C.byref(h), arr, pl, len(patches), nlevels, precision,
+                                    C.byref(self.params), kinds, inflow, _stream_handle(stream)),
+               "ppm_amr_create")
+        self._h = h
+
+    def ppm_amr_step(self, stream=None):
+        _check(lib().ppm_amr_step(self._h, _stream_handle(stream)), "ppm_amr_step")
+
+    def ppm_amr_times(self):
+        t = (C.c_double * self.nlevels)()
+        n = (C.c_int64 * self.nlevels)()
+        _check(lib().ppm_amr_times(self._h, t, n), "ppm_amr_times")
+        return list(t), list(n)
+
+    def ppm_amr_step_log(self):
+        cnt = C.c_int32(0)
+        _check(lib().ppm_amr_step_log(self._h, None, None, 0, C.byref(cnt)), "ppm_amr_step_log")
+        lv = (C.c_int32 * max(cnt.value, 1))()
+        dt = (C.c_double * max(cnt.value, 1))()
+        _check(lib().ppm_amr_step_log(self._h, lv, dt, cnt.value, C.byref(cnt)),
+               "ppm_amr_step_log")
+        return [(lv[i], dt[i]) for i in range(cnt.value)]
+
+    def ppm_amr_event_counts(self, stream=None):
+        a, b = C.c_int64(0), C.c_int64(0)
+        _check(lib().ppm_amr_event_counts(self._h, C.byref(a), C.byref(b),
+                                          _stream_handle(stream)), "ppm_amr_event_counts")
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().ppm_amr_destroy(self._h)
             self._h = None
 
     def __del__(self):

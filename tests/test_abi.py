@@ -78,6 +78,11 @@ def test_calls_on_null_plan_are_rejected():
     assert L.ppm_fill_ghosts(None, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_event_counts(None, None, None, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_set_expansion(None, None) == ppm.PPM_EINVAL
+    assert L.ppm_amr_step(None, None) == ppm.PPM_EINVAL
+    assert L.ppm_amr_times(None, None, None) == ppm.PPM_EINVAL
+    assert L.ppm_amr_step_log(None, None, None, 0, None) == ppm.PPM_EINVAL
+    assert L.ppm_amr_event_counts(None, None, None, None) == ppm.PPM_EINVAL
+    assert L.ppm_amr_destroy(None) == ppm.PPM_OK
     assert L.ppm_expansion(None, None, None) == ppm.PPM_EINVAL
     assert L.ppm_plan_destroy(None) == ppm.PPM_OK
 
@@ -124,3 +129,42 @@ def test_grouping_needs_patches_in_shared_arrays():
                            b"group=1 persistent=0", None)
     assert st == ppm.PPM_EINVAL and "group=1" in L.ppm_last_error().decode()
     assert not h.value
+
+
+def _amr_patch(level, dims, reg=True, bc=0):
+    return _patch(nx=dims[0], ny=dims[1], nz=dims[2], level=level, bc=bc,
+                  flux_reg=1 if (reg and level > 0) else None)
+
+
+@pytest.mark.parametrize("spec,msg", [
+    ([(0, -1, (0, 0, 0), (16, 16, 16)), (0, -1, (0, 0, 0), (16, 16, 16))], "exactly one root"),
+    ([(0, -1, (0, 0, 0), (16, 16, 16)), (1, 0, (8, 8, 8), (12, 12, 12), False)], "flux registers"),
+    ([(0, -1, (0, 0, 0), (16, 16, 16)), (1, 0, (9, 8, 8), (12, 12, 12))], "cell boundaries"),
+    ([(0, -1, (0, 0, 0), (16, 16, 16)), (1, 0, (0, 8, 8), (12, 12, 12))], "inside the parent"),
+    ([(0, -1, (0, 0, 0), (16, 16, 16)), (1, 0, (8, 8, 8), (12, 12, 12)),
+      (1, 0, (12, 12, 12), (8, 8, 8))], "overlap"),
+    ([(0, -1, (0, 0, 0), (16, 16, 16), True, 1)], "PPM_BC_PERIODIC"),
+])
+def test_amr_create_rejects_invalid_hierarchies(spec, msg):
+    # validation happens before any device call
+    L = ppm.lib()
+    pts, pls = [], []
+    for s in spec:
+        lev, par, start, dims = s[:4]
+        reg = s[4] if len(s) > 4 else True
+        bc = s[5] if len(s) > 5 else 0
+        pts.append(_amr_patch(lev, dims, reg, bc))
+        pl = ppm.ppm_patch_place()
+        pl.parent, pl.refine = par, 2
+        for a in range(3):
+            pl.start[a] = start[a]
+        pls.append(pl)
+    arr = (ppm.ppm_patch * len(pts))(*pts)
+    parr = (ppm.ppm_patch_place * len(pls))(*pls)
+    prm = ppm.params()
+    h = C.c_void_p()
+    st = L.ppm_amr_create(C.byref(h), arr, parr, len(pts), 3, ppm.PPM_FP64, C.byref(prm), None,
+                          None, None)
+    assert st == ppm.PPM_EINVAL
+    assert not h.value
+    assert msg in L.ppm_last_error().decode()

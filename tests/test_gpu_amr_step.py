@@ -1,0 +1,117 @@
+"""AMR level step (W-cycle) on the GPU vs the oracle (GPU).
+
+ppm_amr_step runs EvolveLevel over a static hierarchy: per-level CFL
+timesteps with subcycling, ghost zones from the parent blended in time and
+from siblings, the coarse fluxes through child footprints recorded during the
+coarse sweeps, the fine registers summed over substeps, flux correction and
+projection (Secs. "Adaptive Mesh Refinement", "Flux correction",
+"Projection").  FP64 must reproduce the oracle's W-cycle (oracle/amr.py) bit
+for bit: the sequence of (level, dt) steps, every field of every patch,
+ghosts included, every flux register and the event counts, over two root
+steps; the composite totals of the nested hierarchy are conserved to
+round-off.  Mixed precision is checked by per-field relative L1.
+"""
+import numpy as np
+import pytest
+
+from oracle import amr
+from paper_1307_2265_amd import workloads as W
+from tests.helpers import FIELDS, from_device, oracle_grid, stored_inputs, to_device
+
+pytestmark = pytest.mark.gpu
+
+# (level, parent, start, dims): nested with a non-touching sibling (ghost 4),
+# and three levels with abutting siblings (ghost 3)
+NESTED = [(0, -1, (0, 0, 0), (16, 16, 16)),
+          (1, 0, (8, 8, 8), (12, 12, 12)),
+          (2, 1, (20, 20, 20), (8, 8, 8)),
+          (1, 0, (2, 22, 4), (8, 6, 10))]
+ABUTTING = [(0, -1, (0, 0, 0), (16, 16, 16)),
+            (1, 0, (6, 6, 6), (10, 8, 8)),
+            (1, 0, (16, 6, 6), (8, 8, 8)),
+            (1, 0, (6, 14, 6), (12, 6, 8)),
+            (2, 1, (16, 16, 16), (8, 8, 8)),
+            (2, 1, (24, 16, 16), (6, 6, 6))]
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    from paper_1307_2265_amd import ppm
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ppm.lib()
+    return ppm
+
+
+def _setup(P, O, spec, ghost, seed, recipe, prec, flags=None):
+    fields, dxs = [], []
+    for i, (lev, _, _, dims) in enumerate(spec):
+        fields.append(stored_inputs(W.random_grid(*dims, seed + i, recipe, ghost=ghost), prec))
+        dxs.append((1.0 / 16 * 0.5 ** lev,) * 3)
+    patches = [to_device(f, prec, ghost=ghost, dx=dx, level=lev, with_reg=lev > 0)
+               for f, dx, (lev, *_) in zip(fields, dxs, spec)]
+    prm = P.params() if flags is None else P.params(flags=flags)
+    h = P.Amr(patches, [(par, 2, start) for _, par, start, _ in spec], 1 + max(s[0] for s in spec),
+              prec, prm)
+    oprm = O.params() if flags is None else O.params(flags=flags)
+    nodes = [amr.Node(oracle_grid(O, f, ghost=ghost, dx=dx, with_reg=lev > 0), lev, par, start, 2)
+             for f, dx, (lev, par, start, _) in zip(fields, dxs, spec)]
+    H = amr.Hierarchy(nodes, [oprm] * (1 + max(s[0] for s in spec)))
+    return patches, h, H
+
+
+@pytest.mark.parametrize("case", ["nested", "nested-hllc", "abutting"])
+def test_w_cycle_equals_oracle_fp64(P, O, case):
+    spec, ghost, recipe = (ABUTTING, 3, W.SHOCKED) if case == "abutting" else (NESTED, 4, W.GENTLE)
+    flags = P.PPM_ALL_FLAGS | P.PPM_HLLC if case == "nested-hllc" else None
+    print(f"case {case}", flush=True)
+    patches, h, H = _setup(P, O, spec, ghost, 600, recipe, P.PPM_FP64, flags)
+    for step in range(2):
+        n0 = len(H.dts)
+        H.evolve()
+        h.ppm_amr_step()
+        assert h.ppm_amr_step_log() == H.dts[n0:], step
+    t, n = h.ppm_amr_times()
+    assert t == H.t and n == H.nsteps
+    for i, (p, node) in enumerate(zip(patches, H.nodes)):
+        g = from_device(p)
+        for f in FIELDS:
+            assert np.array_equal(g[f], getattr(node.grid, f)), (i, f)
+        if p.flux_reg is not None:
+            assert np.array_equal(p.flux_reg.cpu().numpy(), node.grid.flux_reg), i
+    print(f"{case}: steps per level {n}, events {h.ppm_amr_event_counts()}")
+    h.close()
+
+
+def test_w_cycle_conserves_composite_totals_on_the_gpu(P, O):
+    patches, h, H = _setup(P, O, NESTED, 4, 610, W.GENTLE, P.PPM_FP64)
+    # the composite totals of the device state, in the oracle's bookkeeping
+    def totals():
+        for p, node in zip(patches, H.nodes):
+            g = from_device(p)
+            for f in FIELDS:
+                getattr(node.grid, f)[...] = g[f]
+        return H.composite_totals()
+    t0 = totals()
+    h.ppm_amr_step()
+    h.ppm_amr_step()
+    t1 = totals()
+    scale = np.array([t0[0], t0[0], t0[0], t0[0], t0[4]])
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * scale), (t1 - t0) / scale
+    h.close()
+
+
+def test_w_cycle_mixed_precision_l1(P, O):
+    patches, h, H = _setup(P, O, NESTED, 4, 620, W.GENTLE, P.PPM_MIXED)
+    H.evolve()
+    h.ppm_amr_step()
+    assert [lv for lv, _ in h.ppm_amr_step_log()] == [lv for lv, _ in H.dts]
+    for i, (p, node) in enumerate(zip(patches, H.nodes)):
+        g = from_device(p)
+        gh = p.ghost
+        act = (slice(gh, -gh),) * 3
+        for f in FIELDS:
+            ref = getattr(node.grid, f)[act]
+            l1 = np.abs(g[f][act] - ref).sum() / np.abs(ref).sum()
+            assert l1 <= 1e-5, (i, f, l1)
+    h.close()
