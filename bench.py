@@ -13,7 +13,9 @@ come from the autotuner's table (data/tiles.json) when it exists.
 Also measured: the same grid and steps with the HLLC solver in place of
 two-shock (FP64 and mixed); the same grid with a seeded acceleration field
 and comoving expansion factors (gravity sources in every sweep, a pass of the
-expansion terms per step, FP64 and mixed); the AMR patch ghost fill (parent interpolation and
+expansion terms per step, FP64 and mixed); the AMR W-cycle (ppm_amr_step:
+subcycled levels, flux correction, projection) on a nested hierarchy; the AMR
+patch ghost fill (parent interpolation and
 sibling copies) on a nested hierarchy; the batched form -- 4096 uneven AMR patches (dims from
 {8,12,16,24,32}, levels 0-6 with their own dt, seeded ghosts, flux registers
 on) advanced by replaying one captured HIP graph per step (the three sweeps
@@ -67,6 +69,7 @@ def parse():
     ap.add_argument("--batch-tiles", default=None, help="tile_config of the batch plans")
     ap.add_argument("--no-hllc", action="store_true", help="skip the HLLC-solver runs")
     ap.add_argument("--no-amr-fill", action="store_true", help="skip the AMR ghost-fill timing")
+    ap.add_argument("--no-amr-step", action="store_true", help="skip the AMR W-cycle timing")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the runs with gravity and comoving expansion")
     return ap.parse_args()
@@ -133,6 +136,49 @@ def amr_ghost_fill(reps: int = 5) -> dict:
                                      "algorithmic_GBps": byt / sec / 1e9,
                                      "hbm_frac": byt / sec / 1e9 / HBM_PEAK_GBS}
     run.close()
+    return out
+
+
+def amr_w_cycle(steps: int = 3, warmup: int = 1) -> dict:
+    """Time ppm_amr_step (the W-cycle with subcycling, flux correction and
+    projection) on the nested hierarchy of amr_ghost_fill with gentle fields
+    (rms Mach 0.5) and a periodic root, in FP64 and mixed precision.  A
+    cell-update is one active cell through one level step."""
+    import time as _time
+    import torch
+    from paper_1307_2265_amd import ppm, workloads as W
+    from paper_1307_2265_amd import harness as H
+    hier = W.nested_hierarchy(128, (32, 24), (4, 2))
+    fields = [W.random_grid(*h.dims, 5000 + i, W.GENTLE) for i, h in enumerate(hier)]
+    cells = [h.dims[0] * h.dims[1] * h.dims[2] for h in hier]
+    per_level = [sum(c for c, h in zip(cells, hier) if h.level == l) for l in range(3)]
+    out = {"workload": "nested hierarchy: 128^3 periodic root, 64 level-1 blocks of 32^3, 512 "
+                       "level-2 blocks of 24^3 (refinement 2, abutting siblings), gentle fields",
+           "active_cells_per_level": per_level}
+    for name, prec in (("fp64", ppm.PPM_FP64), ("mixed", ppm.PPM_MIXED)):
+        run = H.Run(fields, [(*h.dims, h.level, 0.5 ** h.level / 128) for h in hier], prec, 3,
+                    True, with_reg=True)
+        run.plan.close()
+        amr = ppm.Amr(run.patches, [(h.parent, 2, h.start) for h in hier], 3, prec)
+        for _ in range(warmup):
+            amr.ppm_amr_step()
+        _, n0 = amr.ppm_amr_times()
+        torch.cuda.synchronize()
+        t0 = _time.perf_counter()
+        for _ in range(steps):
+            amr.ppm_amr_step()
+        torch.cuda.synchronize()
+        sec = _time.perf_counter() - t0
+        _, n1 = amr.ppm_amr_times()
+        nsteps = [b - a for a, b in zip(n0, n1)]
+        upd = sum(n * c for n, c in zip(nsteps, per_level))
+        fb, fl = amr.ppm_amr_event_counts()
+        out[name] = {"root_steps": steps, "level_steps": nsteps,
+                     "ms_per_root_step": sec / steps * 1e3, "cell_updates_per_s": upd / sec,
+                     "events": {"fallback_faces": fb, "floored_cells": fl}}
+        amr.close()
+        del run
+        torch.cuda.empty_cache()
     return out
 
 
@@ -278,6 +324,13 @@ def main():
             f"level {k} {v['ms']:.3f} ms ({v['ghost_cells_per_s'] / 1e9:.2f} G cells/s)"
             for k, v in amr["levels"].items()))
         torch.cuda.empty_cache()
+    wcyc = None
+    if not args.no_amr_step:
+        wcyc = amr_w_cycle()
+        for name in ("fp64", "mixed"):
+            v = wcyc[name]
+            log(f"amr W-cycle {name}: {v['ms_per_root_step']:.2f} ms per root step, level steps "
+                f"{v['level_steps']}, {v['cell_updates_per_s'] / 1e9:.3f} G cell-updates/s")
 
     # ---- batch of uneven patches, one captured graph per step
     batch = None
@@ -419,6 +472,8 @@ def main():
         line["gravity_comoving"] = sources
     if amr is not None:
         line["amr_ghost_fill"] = amr
+    if wcyc is not None:
+        line["amr_w_cycle"] = wcyc
     if batch is not None:
         line["batch"] = batch
     if cpu is not None:

@@ -258,6 +258,13 @@ ppm_status ppm_amr_destroy(ppm_amr *amr); /* NULL is accepted */
  * synchronisation per level step) and returns after the stream has finished. */
 ppm_status ppm_amr_step(ppm_amr *amr, void *hip_stream);
 
+/* Comoving coordinates for the whole hierarchy: a_dev as for
+ * ppm_set_expansion (2 * nlevels doubles, a and adot of each level at its
+ * half step, read by every launch; NULL: static).  Each level step then also
+ * applies the split expansion terms (ppm_expansion) to its patches after its
+ * sweeps, over the same dt. */
+ppm_status ppm_amr_set_expansion(ppm_amr *amr, const double *a_dev);
+
 /* Current time and steps taken of every level (arrays of nlevels, nullable). */
 ppm_status ppm_amr_times(ppm_amr *amr, double *t, int64_t *steps);
 

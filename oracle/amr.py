@@ -26,7 +26,10 @@ Readings (the paper shows the control flow, not these details):
     region, so every corrected cell belongs to the parent;
   * the sweep order alternates xyz / zyx with each step of a level;
   * a step whose CFL timestep reaches the parent's time takes exactly the
-    remaining interval and lands on the parent's time.
+    remaining interval and lands on the parent's time;
+  * in comoving coordinates each level uses its own a, adot (its params), and
+    a level step applies the split expansion terms to its active cells after
+    its sweeps, over the same dt (before the ghost zones are set again).
 """
 from __future__ import annotations
 
@@ -37,6 +40,7 @@ import numpy as np
 from . import (FIELDS, Grid, box, box_reg_size, cfl_signal_max, copy_from_sibling,
                fill_boundary, fill_from_parent, fill_periodic, flux_correct, flux_reg_size,
                project, step, step_capture)
+from . import expansion as expansion_step
 
 
 @dataclass
@@ -53,7 +57,9 @@ class Hierarchy:
     nodes: list
     params: list               # one oracle Params per level (a, adot of that level)
     root_kinds: list | None = None   # domain boundary kinds of the root (None: periodic)
+    root_inflow: object = None       # [face][rho, vx, vy, vz, etot, eint] of inflow faces
     correct: bool = True       # flux correction on (off only for negative controls)
+    expansion: bool = False    # apply the comoving expansion terms after each level step
     t: list = field(default_factory=list)
     t_old: list = field(default_factory=list)
     nsteps: list = field(default_factory=list)
@@ -119,7 +125,7 @@ class Hierarchy:
             if self.root_kinds is None:
                 fill_periodic(root)
             else:
-                fill_boundary(root, self.root_kinds)
+                fill_boundary(root, self.root_kinds, self.root_inflow)
             return
         for i in ids:
             n = self.nodes[i]
@@ -161,6 +167,9 @@ class Hierarchy:
                     step(g, prm, dt, order)
                 if l > 0:
                     self.acc[i] = self.acc[i] + g.flux_reg
+            if self.expansion:
+                for i in ids:
+                    expansion_step(self.nodes[i].grid, prm, dt)
             self.t_old[l] = self.t[l]
             self.t[l] = t_new
             self.nsteps[l] += 1

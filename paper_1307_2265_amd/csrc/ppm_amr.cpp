@@ -75,6 +75,10 @@ struct ppm_amr {
   // parents' states before their last step
   std::vector<void *> old_bufs;
   PatchDev *d_old = nullptr;
+  ppm::CopyItem *d_copyitems = nullptr;        // per level: the fields of its parents
+  int64_t *d_copyprefix = nullptr;
+  std::vector<int32_t> copy_beg;               // nlevels + 1
+  std::vector<int64_t> copy_total;
   // coarse fluxes through child footprints, per level and axis
   double *d_cap = nullptr;
   ppm::CaptureRow *d_rows = nullptr;
@@ -100,6 +104,7 @@ struct ppm_amr {
   std::vector<int64_t> nsteps;
   std::vector<char> stepped;
   std::vector<std::pair<int32_t, double>> log; // (level, dt) since the last ppm_amr_step
+  const double *expand = nullptr;              // per-level a, adot (ppm_amr_set_expansion)
 };
 
 namespace {
@@ -112,7 +117,7 @@ void destroy(ppm_amr *h) {
   for (void *b : h->old_bufs) (void)hipFree(b);
   void *bufs[] = {h->d_dt,      h->d_cfl,       h->d_old,     h->d_cap,      h->d_rows,
                   h->d_acc,     h->d_accitems,  h->d_accprefix, h->d_targets, h->d_contribs,
-                  h->d_proj,    h->d_projprefix};
+                  h->d_proj,    h->d_projprefix, h->d_copyitems, h->d_copyprefix};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete h;
@@ -176,19 +181,11 @@ ppm_status step_level(ppm_amr *h, int l, int order, hipStream_t s) {
 }
 
 ppm_status save_old(ppm_amr *h, int l, hipStream_t s) {
-  const size_t sb = storage_bytes(h->prec);
-  for (int32_t p : h->members[l]) {
-    if (h->children[p].empty()) continue;
-    const ppm_patch &q = h->patches[p];
-    const int64_t n = ghosted_cells(q);
-    const void *src[6] = {q.rho, q.vx, q.vy, q.vz, q.etot, q.eint};
-    for (int f = 0; f < 6; ++f) {
-      const size_t bytes = size_t(n) * (f < 4 ? sb : 8);
-      hipError_t e = hipMemcpyAsync(h->old_bufs[size_t(p) * 6 + f], src[f], bytes,
-                                    hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return hip_fail(e, "old-state copy");
-    }
-  }
+  const int32_t i0 = h->copy_beg[l], ni = h->copy_beg[l + 1] - i0;
+  if (ni == 0) return PPM_OK;
+  hipError_t e = ppm::launch_copy_words(h->d_copyitems + i0, h->d_copyprefix + i0 + l, ni,
+                                        h->copy_total[l], s);
+  if (e != hipSuccess) return hip_fail(e, "old-state copy launch");
   return PPM_OK;
 }
 
@@ -248,6 +245,7 @@ ppm_status evolve(ppm_amr *h, int l, double t_end, bool has_end, hipStream_t s) 
                                  h->acc_total[l], s);
       if (e != hipSuccess) return hip_fail(e, "register sum launch");
     }
+    if (h->expand && (st = ppm_expansion(h->lplan[l], h->d_dt, s)) != PPM_OK) return st;
     h->t_old[l] = h->t[l];
     h->t[l] = t_new;
     h->nsteps[l] += 1;
@@ -285,6 +283,34 @@ ppm_status build_lists(ppm_amr *h) {
     d.eint = static_cast<double *>(h->old_bufs[size_t(p) * 6 + 5]);
   }
   if ((e = upload(&h->d_old, old_tab)) != hipSuccess) return hip_fail(e, "old-state table");
+  // the copies that save them, per level, in 32-bit words (prefix arrays with
+  // one extra entry per level)
+  std::vector<ppm::CopyItem> copies;
+  std::vector<int64_t> cprefix;
+  h->copy_beg.assign(size_t(L) + 1, 0);
+  h->copy_total.assign(size_t(L) + 1, 0);
+  for (int l = 0; l < L; ++l) {
+    h->copy_beg[l] = int32_t(copies.size());
+    int64_t run = 0;
+    for (int32_t p : h->members[l]) {
+      if (h->children[p].empty()) continue;
+      const ppm_patch &q = h->patches[p];
+      const int64_t n = ghosted_cells(q);
+      const void *src[6] = {q.rho, q.vx, q.vy, q.vz, q.etot, q.eint};
+      for (int f = 0; f < 6; ++f) {
+        copies.push_back(ppm::CopyItem{static_cast<const uint32_t *>(src[f]),
+                                       static_cast<uint32_t *>(h->old_bufs[size_t(p) * 6 + f])});
+        cprefix.push_back(run);
+        run += n * int64_t(f < 4 ? sb : 8) / 4;
+      }
+    }
+    cprefix.push_back(run);
+    h->copy_total[l] = run;
+  }
+  h->copy_beg[L] = int32_t(copies.size());
+  if ((e = upload(&h->d_copyitems, copies)) != hipSuccess ||
+      (e = upload(&h->d_copyprefix, cprefix)) != hipSuccess)
+    return hip_fail(e, "old-state copy lists");
 
   // capture blocks: per parent, per child, a register-shaped block
   std::vector<int64_t> cap_off(size_t(np), -1);  // per child
@@ -586,6 +612,14 @@ ppm_status ppm_amr_step(ppm_amr *h, void *hip_stream) {
   if (st != PPM_OK) return st;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "W-cycle");
+  return PPM_OK;
+}
+
+ppm_status ppm_amr_set_expansion(ppm_amr *h, const double *a_dev) {
+  if (!h) return fail(PPM_EINVAL, "hierarchy is NULL");
+  for (ppm_plan *p : h->lplan)
+    if (p) ppm_set_expansion(p, a_dev);
+  h->expand = a_dev;
   return PPM_OK;
 }
 

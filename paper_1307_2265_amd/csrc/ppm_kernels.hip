@@ -580,7 +580,7 @@ __device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64
 // One thread per ghost cell of the listed patches: the cell's parent cell,
 // its 27-cell neighbourhood of rho, rho v, rho E, rho e, the SecondOrderA
 // value of each at the cell, stored as rho, v = (rho v)/rho, E, e.
-template <class Prec>
+template <class Prec, bool kBlend>
 __global__ void __launch_bounds__(256)
 fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *__restrict__ items,
                         const int64_t *__restrict__ prefix, int32_t nitems, int64_t total,
@@ -608,34 +608,28 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
     si[a] = int(gfine - gcoarse * r);
     lc[a] = gcoarse - item.pstart[a] + gc;
   }
-  const S *crho = static_cast<const S *>(cd.rho);
-  const S *cvel[3] = {static_cast<const S *>(cd.vel[0]), static_cast<const S *>(cd.vel[1]),
-                      static_cast<const S *>(cd.vel[2])};
-  // the parent's state before its last step, when the patch lies between
-  // the parent's two times
-  const bool blend = old_patches != nullptr;
-  PatchDev od = cd;
-  if (blend) od = old_patches[item.parent];
-  const S *orho = static_cast<const S *>(od.rho);
-  const S *ovel[3] = {static_cast<const S *>(od.vel[0]), static_cast<const S *>(od.vel[1]),
-                      static_cast<const S *>(od.vel[2])};
+  // the parent's state before its last step (kBlend: the patch lies between
+  // the parent's two times, and the parent's stored fields are blended)
+  const PatchDev od = kBlend ? old_patches[item.parent] : cd;
   const double wo = 1.0 - w;
   double q[6];
+#pragma unroll 1
   for (int comp = 0; comp < 6; ++comp) {
+    // the stored field whose product with rho is this component (none for rho)
+    const S *xs = comp >= 1 && comp <= 3 ? static_cast<const S *>(cd.vel[comp - 1]) : nullptr;
+    const double *xd = comp == 4 ? cd.etot : cd.eint;
+    const S *oxs = comp >= 1 && comp <= 3 ? static_cast<const S *>(od.vel[comp - 1]) : nullptr;
+    const double *oxd = comp == 4 ? od.etot : od.eint;
     double nb[3][3][3];
     for (int dz = 0; dz < 3; ++dz)
       for (int dy = 0; dy < 3; ++dy)
         for (int dx = 0; dx < 3; ++dx) {
           const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
-          double rho = double(crho[o]);
-          double x = comp == 0 ? 0.0
-                   : comp < 4 ? double(cvel[comp - 1][o])
-                   : comp == 4 ? cd.etot[o] : cd.eint[o];
-          if (blend) {
-            rho = wo * double(orho[o]) + w * rho;
-            const double xo = comp == 0 ? 0.0
-                            : comp < 4 ? double(ovel[comp - 1][o])
-                            : comp == 4 ? od.etot[o] : od.eint[o];
+          double rho = double(static_cast<const S *>(cd.rho)[o]);
+          double x = comp == 0 ? 0.0 : (xs ? double(xs[o]) : xd[o]);
+          if (kBlend) {
+            rho = wo * double(static_cast<const S *>(od.rho)[o]) + w * rho;
+            const double xo = comp == 0 ? 0.0 : (oxs ? double(oxs[o]) : oxd[o]);
             x = wo * xo + w * x;
           }
           nb[dz][dy][dx] = comp == 0 ? rho : rho * x;
@@ -691,21 +685,29 @@ copy_from_siblings_kernel(const PatchDev *__restrict__ patches, const SiblingBox
 // the fine registers summed over substeps, flux correction and projection
 // (Secs. "Flux correction" and "Projection").
 
-// One wavefront per captured face: the lane-parallel segment code over the
-// 64 cells of the face's pencil centred on it (lane 31 holds the cell left of
-// the face), which yields the same final flux as the sweep that follows (a
-// face's flux, fallback included, depends on the five cells either side,
-// and lanes outside the pencil are placeholders no valid result uses).
+// Captured faces, six per wavefront: lanes 10w .. 10w+9 hold cells j-4 ..
+// j+5 of row w's pencil (j the cell left of the face) and run the
+// lane-parallel segment code, which yields the same final flux for the face
+// as the sweep that follows.  The flux through face j+1/2, fallback
+// included, depends only on those ten cells: the Riemann states of faces
+// j-1/2 .. j+3/2 use cells j-4 .. j+5 (the flattening of a cell looks two
+// cells out, and the neighbour whose flattening it may take one more), and
+// the fallback tests the provisional updates of cells j and j+1.  So what a
+// window's edge lanes read from the adjacent window never reaches that face.
 // Nothing is written but dt F of the face.
+constexpr int kCapWindow = 10, kCapPerWave = 6;
+
 template <class Prec, bool kUseHLLC, bool kGrav>
 __global__ void __launch_bounds__(256)
 capture_kernel(const PatchDev *__restrict__ patches, const CaptureRow *__restrict__ rows,
                int32_t nrows, int32_t axis, const double *__restrict__ dt_dev, Params P) {
   using S = typename Prec::S;
-  const int row = int(blockIdx.x) * 4 + int(threadIdx.x >> 6);
-  if (row >= nrows) return;  // the whole wave leaves
+  const int row0 = (int(blockIdx.x) * 4 + int(threadIdx.x >> 6)) * kCapPerWave;
+  if (row0 >= nrows) return;  // the whole wave leaves
   const int lane = threadIdx.x & 63;
-  const CaptureRow cr = rows[row];
+  const int slot = lane / kCapWindow, pos = lane - slot * kCapWindow;
+  const bool used = slot < kCapPerWave && row0 + slot < nrows;
+  const CaptureRow cr = rows[used ? row0 + slot : row0];
   const PatchDev pd = patches[cr.patch];
   PencilRef<S> pc = make_pencil<S>(pd, axis, cr.i1, cr.i2);
   pc.reg_lo = pc.reg_hi = nullptr;
@@ -713,8 +715,8 @@ capture_kernel(const PatchDev *__restrict__ patches, const CaptureRow *__restric
   const double a = expansion_a(P, pd.level);
   const double lam = dt / (a * pc.dx);
   const double hgdt = 0.5 * dt / a;
-  const int jc = cr.j - 31 + lane;
-  const bool in = jc >= 0 && jc < pc.n;
+  const int jc = cr.j - 4 + pos;
+  const bool in = used && jc >= 0 && jc < pc.n;
   const int j = in ? jc : -1;
   CellLoad cur = {1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
   if (in) {
@@ -727,10 +729,21 @@ capture_kernel(const PatchDev *__restrict__ patches, const CaptureRow *__restric
   CflAcc cfl = cfl_acc(pd, axis, nullptr);
   const Flux F = sweep_segment<Prec, false, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, false, cur,
                                                              nfb, nfl, cfl);
-  if (j == cr.j) {
+  if (used && pos == 4) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) cr.dst[pc.lab[k] * cr.fstride] = dt * F.f[k];
   }
+}
+
+__global__ void __launch_bounds__(256)
+copy_words_kernel(const CopyItem *__restrict__ items, const int64_t *__restrict__ prefix,
+                  int32_t nitems, int64_t total) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int it = find_item(prefix, nitems, t);
+  const CopyItem item = items[it];
+  const int64_t u = t - prefix[it];
+  item.dst[u] = item.src[u];
 }
 
 __global__ void __launch_bounds__(256)
@@ -1015,8 +1028,13 @@ hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *it
                                    const int64_t *prefix, int32_t nitems, int64_t total,
                                    const PatchDev *old_patches, double w, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_from_parent_kernel<Prec>, dim3(unsigned((total + 255) / 256)), dim3(256),
-                     0, s, patches, items, prefix, nitems, total, old_patches, w);
+  const dim3 grid(unsigned((total + 255) / 256));
+  if (old_patches)
+    hipLaunchKernelGGL((fill_from_parent_kernel<Prec, true>), grid, dim3(256), 0, s, patches,
+                       items, prefix, nitems, total, old_patches, w);
+  else
+    hipLaunchKernelGGL((fill_from_parent_kernel<Prec, false>), grid, dim3(256), 0, s, patches,
+                       items, prefix, nitems, total, old_patches, w);
   return hipGetLastError();
 }
 
@@ -1024,7 +1042,8 @@ template <class Prec>
 hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32_t nrows,
                           int32_t axis, const double *dt_dev, const Params &P, hipStream_t s) {
   if (nrows <= 0) return hipSuccess;
-  const unsigned blocks = unsigned((int64_t(nrows) + 3) / 4);
+  const int64_t waves = (int64_t(nrows) + kCapPerWave - 1) / kCapPerWave;
+  const unsigned blocks = unsigned((waves + 3) / 4);
 #define PPM_LAUNCH_CAPTURE(HLLC, GRAV)                                                       \
   hipLaunchKernelGGL((capture_kernel<Prec, HLLC, GRAV>), dim3(blocks), dim3(256), 0, s,       \
                      patches, rows, nrows, axis, dt_dev, P)
@@ -1032,6 +1051,14 @@ hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32
   else if (P.flags & kHLLC) PPM_LAUNCH_CAPTURE(true, false);
   else PPM_LAUNCH_CAPTURE(false, false);
 #undef PPM_LAUNCH_CAPTURE
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_words(const CopyItem *items, const int64_t *prefix, int32_t nitems,
+                             int64_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_words_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s,
+                     items, prefix, nitems, total);
   return hipGetLastError();
 }
 

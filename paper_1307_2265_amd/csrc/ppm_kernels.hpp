@@ -117,10 +117,19 @@ struct CaptureRow {
 };
 
 // Final fluxes of rows[0..nrows) from the current state (the input of the
-// sweep along `axis` that follows), one wavefront per row.
+// sweep along `axis` that follows), six rows per wavefront.
 template <class Prec>
 hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32_t nrows,
                           int32_t axis, const double *dt_dev, const Params &P, hipStream_t s);
+
+// dst[i] = src[i] over the listed blocks of 32-bit words (prefix over their
+// lengths): the parents' states saved before their steps, in one launch.
+struct CopyItem {
+  const uint32_t *src;
+  uint32_t *dst;
+};
+hipError_t launch_copy_words(const CopyItem *items, const int64_t *prefix, int32_t nitems,
+                             int64_t total, hipStream_t s);
 
 // acc[i] += reg[i] over the listed register blocks (prefix over their sizes).
 struct AccItem {

@@ -64,6 +64,7 @@ SIGNATURES = {
                                  C.POINTER(C.c_double), _vp]),
     "ppm_amr_destroy": (C.c_int, [_vp]),
     "ppm_amr_step": (C.c_int, [_vp, _vp]),
+    "ppm_amr_set_expansion": (C.c_int, [_vp, _vp]),
     "ppm_amr_times": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "ppm_amr_step_log": (C.c_int, [_vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
                                    C.POINTER(C.c_int32)]),
@@ -314,6 +315,12 @@ class Amr:
                                     C.byref(self.params), kinds, inflow, _stream_handle(stream)),
                "ppm_amr_create")
         self._h = h
+
+    def ppm_amr_set_expansion(self, a_dev):
+        """a_dev: float64 device tensor of 2 * nlevels values, kept alive here."""
+        self._expand = a_dev
+        _check(lib().ppm_amr_set_expansion(self._h, None if a_dev is None else a_dev.data_ptr()),
+               "ppm_amr_set_expansion")
 
     def ppm_amr_step(self, stream=None):
         _check(lib().ppm_amr_step(self._h, _stream_handle(stream)), "ppm_amr_step")

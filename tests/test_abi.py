@@ -79,6 +79,7 @@ def test_calls_on_null_plan_are_rejected():
     assert L.ppm_event_counts(None, None, None, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_set_expansion(None, None) == ppm.PPM_EINVAL
     assert L.ppm_amr_step(None, None) == ppm.PPM_EINVAL
+    assert L.ppm_amr_set_expansion(None, None) == ppm.PPM_EINVAL
     assert L.ppm_amr_times(None, None, None) == ppm.PPM_EINVAL
     assert L.ppm_amr_step_log(None, None, None, 0, None) == ppm.PPM_EINVAL
     assert L.ppm_amr_event_counts(None, None, None, None) == ppm.PPM_EINVAL

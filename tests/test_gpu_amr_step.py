@@ -115,3 +115,58 @@ def test_w_cycle_mixed_precision_l1(P, O):
             l1 = np.abs(g[f][act] - ref).sum() / np.abs(ref).sum()
             assert l1 <= 1e-5, (i, f, l1)
     h.close()
+
+
+def test_shock_pool_w_cycle_equals_oracle(P, O):
+    # the paper's shock pool (inflow and outflow root faces, static refined
+    # region): 25 root steps, bit for bit
+    import torch
+    from tests.test_oracle_amr import _shock_pool
+    H, _ = _shock_pool(O, True)
+    patches = []
+    for lev, node in enumerate(H.nodes):
+        g = node.grid
+        d = {f: getattr(g, f).copy() for f in FIELDS}
+        patches.append(to_device(d, P.PPM_FP64, ghost=g.ghost, dx=(g.dx, g.dy, g.dz), level=lev,
+                                 with_reg=lev > 0))
+    h = P.Amr(patches, [(-1, 2, (0, 0, 0)), (0, 2, (50, 2, 2))], 2, P.PPM_FP64,
+              P.params(gamma=1.4), root_kinds=H.root_kinds, root_inflow=H.root_inflow)
+    for step in range(25):
+        n0 = len(H.dts)
+        H.evolve()
+        h.ppm_amr_step()
+        assert h.ppm_amr_step_log() == H.dts[n0:], step
+    torch.cuda.synchronize()
+    for i, (p, node) in enumerate(zip(patches, H.nodes)):
+        g = from_device(p)
+        for f in FIELDS:
+            assert np.array_equal(g[f], getattr(node.grid, f)), (i, f)
+    h.close()
+
+
+def test_w_cycle_with_gravity_and_expansion_equals_oracle(P, O):
+    # every patch with an acceleration field, each level its own a and adot
+    import torch
+    patches, h, H = _setup(P, O, NESTED, 4, 630, W.GENTLE, P.PPM_FP64)
+    h.close()
+    expand = [(1.3, 0.4), (1.31, 0.41), (1.32, 0.42)]
+    for i, (p, node) in enumerate(zip(patches, H.nodes)):
+        acc = W.acceleration_field(p.rho.shape, 640 + i, 2.0)
+        node.grid.accel = acc
+        p.accel = tuple(torch.from_numpy(a).to("cuda") for a in acc)
+    H.params = [O.params(a=a, adot=ad) for a, ad in expand]
+    H.expansion = True
+    h = P.Amr(patches, [(par, 2, start) for _, par, start, _ in NESTED], 3, P.PPM_FP64,
+              P.params())
+    h.ppm_amr_set_expansion(torch.tensor([v for av in expand for v in av], dtype=torch.float64,
+                                         device="cuda"))
+    for step in range(2):
+        n0 = len(H.dts)
+        H.evolve()
+        h.ppm_amr_step()
+        assert h.ppm_amr_step_log() == H.dts[n0:], step
+    for i, (p, node) in enumerate(zip(patches, H.nodes)):
+        g = from_device(p)
+        for f in FIELDS:
+            assert np.array_equal(g[f], getattr(node.grid, f)), (i, f)
+    h.close()

@@ -189,3 +189,63 @@ def test_smooth_contact_is_more_accurate_on_the_refined_patch(O):
     err_out_c = np.abs(ref.rho[a][3, 3, out] - exact(xc[out])).mean()
     assert err_f < 0.5 * err_c, (err_f, err_c)
     assert err_out_h < 1.5 * err_out_c, (err_out_h, err_out_c)
+
+
+def _shock_pool(O, refined: bool):
+    """Sec. "Shock pool": gas at rest (rho = p = 1, gamma = 1.4) on x in [0, 1]
+    (100 root cells; 4 cells across, periodic in y and z), a Mach-2 shock
+    driven in from the left boundary (inflow of the post-shock state, outflow
+    on the right), a static refined region from x = 0.25 to 0.75 (r = 2; one
+    root cell of margin across)."""
+    g, gam, M = 3, 1.4, 2.0
+    rho2 = (gam + 1) * M * M / ((gam - 1) * M * M + 2)
+    p2 = (2 * gam * M * M - (gam - 1)) / (gam + 1)
+    S = M * np.sqrt(gam)
+    u2 = S * (1 - 1 / rho2)
+    e2 = p2 / ((gam - 1) * rho2)
+    inflow = np.zeros((6, 6))
+    inflow[0] = [rho2, u2, 0.0, 0.0, e2 + 0.5 * u2 * u2, e2]
+    def uniform(nx, ny, nz):
+        shape = (nz + 2 * g, ny + 2 * g, nx + 2 * g)
+        one, zero = np.ones(shape), np.zeros(shape)
+        st = W.stored_from_primitive(one, zero, zero.copy(), zero.copy(), one.copy(), gam)
+        return dict(zip(O.FIELDS, [np.ascontiguousarray(a) for a in st]))
+    prm = O.params(gamma=gam)
+    h = 0.01
+    nodes = [amr.Node(_grid(O, uniform(100, 4, 4), (h, h, h), ghost=g), 0)]
+    if refined:
+        nodes.append(amr.Node(_grid(O, uniform(100, 4, 4), (h / 2,) * 3, ghost=g, reg=True), 1, 0,
+                              (50, 2, 2), 2))
+    kinds = [3, 2, 0, 0, 0, 0]
+    H = amr.Hierarchy(nodes, [prm] * len(nodes), root_kinds=kinds, root_inflow=inflow)
+    return H, (rho2, S)
+
+
+def test_shock_pool_keeps_the_shock_on_both_levels(O):
+    # the shock enters and leaves the refined region at the exact speed, on
+    # the fine and the coarse cells, with the unrefined run's plateau
+    H, (rho2, S) = _shock_pool(O, True)
+    U, _ = _shock_pool(O, False)
+    g = 3
+    def front(grid, x0, dx):
+        r = grid.rho[g + 1, g + 1, g:-g]       # a row inside the refined region in y, z
+        i = int(np.argmax(r < 0.5 * (1 + rho2)))
+        return x0 + i * dx
+    for t_check in (0.2, 0.35):
+        while H.t[0] < t_check - 1e-12:
+            H.evolve()
+        while U.t[0] < t_check - 1e-12:
+            U.evolve()
+        xs = S * H.t[0]
+        root, fine = H.nodes[0].grid, H.nodes[1].grid
+        assert abs(front(root, 0.0, 0.01) - xs) <= 0.02, (t_check, front(root, 0.0, 0.01), xs)
+        assert abs(front(U.nodes[0].grid, 0.0, 0.01) - S * U.t[0]) <= 0.02
+        if t_check == 0.2:                     # inside the refined region
+            assert abs(front(fine, 0.25, 0.005) - xs) <= 0.01, (front(fine, 0.25, 0.005), xs)
+        # post-shock plateau behind the front, on the root
+        plat = root.rho[g + 1, g + 1, g + 5:g + int(100 * xs) - 5]
+        assert np.all(np.abs(plat - rho2) < 0.05 * rho2), plat
+    # the region the shock has crossed and left agrees with the unrefined run
+    a = H.nodes[0].grid.rho[g + 1, g + 1, g + 5:g + 70]
+    b = U.nodes[0].grid.rho[g + 1, g + 1, g + 5:g + 70]
+    assert np.abs(a - b).max() < 0.05 * rho2
