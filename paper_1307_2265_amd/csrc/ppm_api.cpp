@@ -522,10 +522,17 @@ ppm_status ppm_fill_boundary(ppm_plan *plan, int32_t patch, const int32_t *kinds
 
 namespace {
 int64_t floor_div64(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-int64_t shell_count(const PatchDev &d) {
-  const int64_t g = d.ghost;
-  const int64_t n0 = d.n[0] + 2 * g, n1 = d.n[1] + 2 * g, n2 = d.n[2] + 2 * g;
-  return n0 * n1 * n2 - int64_t(d.n[0]) * d.n[1] * d.n[2];
+// Parent cells (in the parent's level) whose r^3 fine cells meet the
+// ghosted box of a patch that starts at `start` of its level: one thread each
+// in the parent-interpolation launch.
+int64_t parent_box_count(const PatchDev &d, const int32_t start[3], int32_t r) {
+  int64_t v = 1;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t lo = floor_div64(int64_t(start[a]) - d.ghost, r);
+    const int64_t hi = floor_div64(int64_t(start[a]) + d.n[a] + d.ghost - 1, r);
+    v *= hi - lo + 1;
+  }
+  return v;
 }
 }  // namespace
 
@@ -573,7 +580,7 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
       }
       items.push_back(it);
       ipre.push_back(acc);
-      acc += shell_count(H[i]);
+      acc += parent_box_count(H[i], place[i].start, place[i].refine);
     }
     ipre.push_back(acc);
     itot[L] = acc;

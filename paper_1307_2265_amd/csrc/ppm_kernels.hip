@@ -489,8 +489,8 @@ fill_boundary_kernel(PatchDev pd, FaceRules fr) {
 // from siblings wherever one covers it).
 //
 // SecondOrderA (Appendix "Interpolation", three-dimensional form) of one
-// conserved quantity at fine cell (i, j, k) of the r^3 that refine the centre
-// of nb[dz][dy][dx]: corner values are the averages of the 8 parent cells
+// conserved quantity of the r^3 fine cells that refine the centre of
+// nb[dz][dy][dx]: corner values are the averages of the 8 parent cells
 // sharing a corner; slopes along the four diagonals are minmod-limited; if
 // the change to corner (+,+,+) that dQ1..dQ3 imply leaves [0, dQ0] (s outside
 // [0, 1]), the slopes pushing it out are scaled so that it lands on the near
@@ -515,7 +515,8 @@ __device__ __forceinline__ double corner_avg(const double (&nb)[3][3][3], int sx
   return sum * 0.125;
 }
 
-__device__ double second_order_a_at(const double (&nb)[3][3][3], int r, int i, int j, int k) {
+__device__ void second_order_a_slopes(const double (&nb)[3][3][3], double &fx, double &fy,
+                                      double &fz) {
   const double q0 = nb[1][1][1];
   const int c[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
   double dq[4];
@@ -556,7 +557,14 @@ __device__ double second_order_a_at(const double (&nb)[3][3][3], int r, int i, i
     for (int n = 1; n < 4; ++n)
       if (chi[n]) dq[n] = f * dq[n];
   }
-  const double fx = dq[2] + dq[3], fy = dq[1] + dq[3], fz = dq[1] + dq[2];
+  fx = dq[2] + dq[3];
+  fy = dq[1] + dq[3];
+  fz = dq[1] + dq[2];
+}
+
+// The interpolant at fine cell (i, j, k) of the r^3 that refine the centre.
+__device__ __forceinline__ double second_order_a_eval(double q0, double fx, double fy, double fz,
+                                                      int r, int i, int j, int k) {
   const double wx = (double(i) + (1.0 - r) * 0.5) / double(r);
   const double wy = (double(j) + (1.0 - r) * 0.5) / double(r);
   const double wz = (double(k) + (1.0 - r) * 0.5) / double(r);
@@ -577,9 +585,12 @@ __device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64
   return lo;
 }
 
-// One thread per ghost cell of the listed patches: the cell's parent cell,
-// its 27-cell neighbourhood of rho, rho v, rho E, rho e, the SecondOrderA
-// value of each at the cell, stored as rho, v = (rho v)/rho, E, e.
+// One thread per parent cell whose fine cells meet a listed patch's ghosted
+// box (the box of such cells in the parent's level, in x-fastest order): if
+// any of its r^3 fine cells is a ghost cell of the patch, the 27-cell
+// neighbourhood of rho, rho v, rho E, rho e around it, the SecondOrderA slopes
+// of each, and for every such fine cell the interpolant's values, stored as
+// rho, v = (rho v)/rho, E, e.
 template <class Prec, bool kBlend>
 __global__ void __launch_bounds__(256)
 fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *__restrict__ items,
@@ -597,22 +608,42 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
   const int64_t nf[3] = {Nf[0] + 2 * gf, Nf[1] + 2 * gf, Nf[2] + 2 * gf};
   const int64_t nc[3] = {int64_t(cd.n[0]) + 2 * gc, int64_t(cd.n[1]) + 2 * gc,
                          int64_t(cd.n[2]) + 2 * gc};
-  int64_t c[3];
-  if (!shell_cell(gf, Nf, nf, t - prefix[it], c)) return;
-  int64_t lc[3];
-  int si[3];
+  int64_t clo[3], cext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const int64_t gfine = item.start[a] + (c[a] - gf);
-    const int64_t gcoarse = floor_div(gfine, r);
-    si[a] = int(gfine - gcoarse * r);
-    lc[a] = gcoarse - item.pstart[a] + gc;
+    clo[a] = floor_div(int64_t(item.start[a]) - gf, r);
+    cext[a] = floor_div(int64_t(item.start[a]) + Nf[a] + gf - 1, r) - clo[a] + 1;
   }
+  const int64_t u = t - prefix[it];
+  const int64_t cc[3] = {clo[0] + u % cext[0], clo[1] + (u / cext[0]) % cext[1],
+                         clo[2] + u / (cext[0] * cext[1])};
+  // local index of the first of its fine cells in the patch; which are ghosts
+  int64_t f0[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) f0[a] = cc[a] * r - item.start[a] + gf;
+  auto ghost_at = [&](int i, int j, int k) {
+    const int64_t f[3] = {f0[0] + i, f0[1] + j, f0[2] + k};
+    bool inside = true, active = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      inside = inside && f[a] >= 0 && f[a] < nf[a];
+      active = active && f[a] >= gf && f[a] < gf + Nf[a];
+    }
+    return inside && !active;
+  };
+  bool any = false;
+  for (int k = 0; k < r; ++k)
+    for (int j = 0; j < r; ++j)
+      for (int i = 0; i < r; ++i) any = any || ghost_at(i, j, k);
+  if (!any) return;
+  int64_t lc[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) lc[a] = cc[a] - item.pstart[a] + gc;
   // the parent's state before its last step (kBlend: the patch lies between
   // the parent's two times, and the parent's stored fields are blended)
   const PatchDev od = kBlend ? old_patches[item.parent] : cd;
   const double wo = 1.0 - w;
-  double q[6];
+  double q0[6], fx[6], fy[6], fz[6];
 #pragma unroll 1
   for (int comp = 0; comp < 6; ++comp) {
     // the stored field whose product with rho is this component (none for rho)
@@ -634,14 +665,27 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
           }
           nb[dz][dy][dx] = comp == 0 ? rho : rho * x;
         }
-    q[comp] = second_order_a_at(nb, r, si[0], si[1], si[2]);
+    q0[comp] = nb[1][1][1];
+    second_order_a_slopes(nb, fx[comp], fy[comp], fz[comp]);
   }
-  const int64_t dst = (c[2] * nf[1] + c[1]) * nf[0] + c[0];
-  static_cast<S *>(fd.rho)[dst] = S(q[0]);
+  S *rho_p = static_cast<S *>(fd.rho);
+  S *vel[3] = {static_cast<S *>(fd.vel[0]), static_cast<S *>(fd.vel[1]),
+               static_cast<S *>(fd.vel[2])};
+  for (int k = 0; k < r; ++k)
+    for (int j = 0; j < r; ++j)
+      for (int i = 0; i < r; ++i) {
+        if (!ghost_at(i, j, k)) continue;
+        double q[6];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) static_cast<S *>(fd.vel[a])[dst] = S(q[1 + a] / q[0]);
-  fd.etot[dst] = q[4] / q[0];
-  fd.eint[dst] = q[5] / q[0];
+        for (int comp = 0; comp < 6; ++comp)
+          q[comp] = second_order_a_eval(q0[comp], fx[comp], fy[comp], fz[comp], r, i, j, k);
+        const int64_t dst = ((f0[2] + k) * nf[1] + (f0[1] + j)) * nf[0] + (f0[0] + i);
+        rho_p[dst] = S(q[0]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) vel[a][dst] = S(q[1 + a] / q[0]);
+        fd.etot[dst] = q[4] / q[0];
+        fd.eint[dst] = q[5] / q[0];
+      }
 }
 
 // One thread per cell of the listed boxes: the sibling's value, unless the
