@@ -72,9 +72,13 @@ struct ppm_amr {
   bool has_inflow = false;
   double *d_dt = nullptr, *d_cfl = nullptr;    // nlevels doubles each
   double h_dt[64] = {}, h_cfl = 0.0;
-  // parents' states before their last step
-  std::vector<void *> old_bufs;
-  PatchDev *d_old = nullptr;
+  // parents' states before their last step, and blended to a child's time
+  std::vector<void *> old_bufs, blend_bufs;
+  PatchDev *d_blend = nullptr;                 // patch table with the parents' blends
+  ppm::BlendItem *d_blend_s = nullptr, *d_blend_d = nullptr;  // per level: float/double fields
+  int64_t *d_blend_sp = nullptr, *d_blend_dp = nullptr;
+  std::vector<int32_t> blend_sbeg, blend_dbeg;  // nlevels + 1
+  std::vector<int64_t> blend_stot, blend_dtot;
   ppm::CopyItem *d_copyitems = nullptr;        // per level: the fields of its parents
   int64_t *d_copyprefix = nullptr;
   std::vector<int32_t> copy_beg;               // nlevels + 1
@@ -115,9 +119,11 @@ void destroy(ppm_amr *h) {
   for (ppm_plan *p : h->lplan)
     if (p) ppm_plan_destroy(p);
   for (void *b : h->old_bufs) (void)hipFree(b);
-  void *bufs[] = {h->d_dt,      h->d_cfl,       h->d_old,     h->d_cap,      h->d_rows,
+  for (void *b : h->blend_bufs) (void)hipFree(b);
+  void *bufs[] = {h->d_dt,      h->d_cfl,       h->d_blend,   h->d_cap,      h->d_rows,
                   h->d_acc,     h->d_accitems,  h->d_accprefix, h->d_targets, h->d_contribs,
-                  h->d_proj,    h->d_projprefix, h->d_copyitems, h->d_copyprefix};
+                  h->d_proj,    h->d_projprefix, h->d_copyitems, h->d_copyprefix,
+                  h->d_blend_s, h->d_blend_d,   h->d_blend_sp, h->d_blend_dp};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete h;
@@ -139,13 +145,19 @@ ppm_status fill(ppm_amr *h, int l, hipStream_t s) {
                              h->has_inflow ? h->root_inflow : nullptr, s);
   }
   const int pl = l - 1;
-  const PatchDev *old = nullptr;
-  double w = 1.0;
-  if (h->t[pl] != h->t_old[pl] && h->stepped[pl]) {
-    old = h->d_old;
-    w = (h->t[l] - h->t_old[pl]) / (h->t[pl] - h->t_old[pl]);
-  }
-  return ppm_detail::fill_ghosts(h->all, l, old, w, s);
+  if (!(h->t[pl] != h->t_old[pl] && h->stepped[pl]))
+    return ppm_detail::fill_ghosts(h->all, l, nullptr, s);
+  // the parents' stored fields at this level's time, blended in double
+  const double w = (h->t[l] - h->t_old[pl]) / (h->t[pl] - h->t_old[pl]);
+  const int32_t s0 = h->blend_sbeg[pl], ns = h->blend_sbeg[pl + 1] - s0;
+  const int32_t d0 = h->blend_dbeg[pl], nd = h->blend_dbeg[pl + 1] - d0;
+  hipError_t e = ppm::launch_blend(h->d_blend_s + s0, h->d_blend_sp + s0 + pl, ns,
+                                   h->blend_stot[pl], h->prec == PPM_MIXED, w, s);
+  if (e == hipSuccess)
+    e = ppm::launch_blend(h->d_blend_d + d0, h->d_blend_dp + d0 + pl, nd, h->blend_dtot[pl],
+                          false, w, s);
+  if (e != hipSuccess) return hip_fail(e, "time blend launch");
+  return ppm_detail::fill_ghosts(h->all, l, h->d_blend, s);
 }
 
 ppm_status level_dt(ppm_amr *h, int l, hipStream_t s, double *dt) {
@@ -266,23 +278,72 @@ ppm_status build_lists(ppm_amr *h) {
   const int L = h->nlevels, np = h->npatch;
   const size_t sb = storage_bytes(h->prec);
   hipError_t e;
-  // old-state buffers and their patch table
+  // old-state and blend buffers of every patch with children, and the patch
+  // table through which the parent interpolation reads the blends
   h->old_bufs.assign(size_t(np) * 6, nullptr);
-  std::vector<PatchDev> old_tab(h->all->host);
+  h->blend_bufs.assign(size_t(np) * 6, nullptr);
+  std::vector<PatchDev> blend_tab(h->all->host);
   for (int p = 0; p < np; ++p) {
     if (h->children[p].empty()) continue;
     const int64_t n = ghosted_cells(h->patches[p]);
     for (int f = 0; f < 6; ++f) {
-      e = hipMalloc(&h->old_bufs[size_t(p) * 6 + f], size_t(n) * (f < 4 ? sb : 8));
-      if (e != hipSuccess) return hip_fail(e, "old-state allocation");
+      const size_t bytes = size_t(n) * (f < 4 ? sb : 8);
+      if ((e = hipMalloc(&h->old_bufs[size_t(p) * 6 + f], bytes)) != hipSuccess ||
+          (e = hipMalloc(&h->blend_bufs[size_t(p) * 6 + f], bytes)) != hipSuccess)
+        return hip_fail(e, "old-state allocation");
     }
-    PatchDev &d = old_tab[p];
-    d.rho = h->old_bufs[size_t(p) * 6];
-    for (int a = 0; a < 3; ++a) d.vel[a] = h->old_bufs[size_t(p) * 6 + 1 + a];
-    d.etot = static_cast<double *>(h->old_bufs[size_t(p) * 6 + 4]);
-    d.eint = static_cast<double *>(h->old_bufs[size_t(p) * 6 + 5]);
+    PatchDev &d = blend_tab[p];
+    d.rho = h->blend_bufs[size_t(p) * 6];
+    for (int a = 0; a < 3; ++a) d.vel[a] = h->blend_bufs[size_t(p) * 6 + 1 + a];
+    d.etot = static_cast<double *>(h->blend_bufs[size_t(p) * 6 + 4]);
+    d.eint = static_cast<double *>(h->blend_bufs[size_t(p) * 6 + 5]);
   }
-  if ((e = upload(&h->d_old, old_tab)) != hipSuccess) return hip_fail(e, "old-state table");
+  if ((e = upload(&h->d_blend, blend_tab)) != hipSuccess) return hip_fail(e, "blend table");
+  // per level, the blends of its parents: storage-type fields and double
+  // fields (prefix arrays with one extra entry per level)
+  {
+    std::vector<ppm::BlendItem> bs, bd;
+    std::vector<int64_t> ps, pd;
+    h->blend_sbeg.assign(size_t(L) + 1, 0);
+    h->blend_dbeg.assign(size_t(L) + 1, 0);
+    h->blend_stot.assign(size_t(L) + 1, 0);
+    h->blend_dtot.assign(size_t(L) + 1, 0);
+    for (int l = 0; l < L; ++l) {
+      h->blend_sbeg[l] = int32_t(bs.size());
+      h->blend_dbeg[l] = int32_t(bd.size());
+      int64_t rs = 0, rd = 0;
+      for (int32_t p : h->members[l]) {
+        if (h->children[p].empty()) continue;
+        const ppm_patch &q = h->patches[p];
+        const int64_t n = ghosted_cells(q);
+        const void *cur[6] = {q.rho, q.vx, q.vy, q.vz, q.etot, q.eint};
+        for (int f = 0; f < 6; ++f) {
+          const ppm::BlendItem it{h->old_bufs[size_t(p) * 6 + f], cur[f],
+                                  h->blend_bufs[size_t(p) * 6 + f]};
+          if (f < 4) {
+            bs.push_back(it);
+            ps.push_back(rs);
+            rs += n;
+          } else {
+            bd.push_back(it);
+            pd.push_back(rd);
+            rd += n;
+          }
+        }
+      }
+      ps.push_back(rs);
+      pd.push_back(rd);
+      h->blend_stot[l] = rs;
+      h->blend_dtot[l] = rd;
+    }
+    h->blend_sbeg[L] = int32_t(bs.size());
+    h->blend_dbeg[L] = int32_t(bd.size());
+    if ((e = upload(&h->d_blend_s, bs)) != hipSuccess ||
+        (e = upload(&h->d_blend_d, bd)) != hipSuccess ||
+        (e = upload(&h->d_blend_sp, ps)) != hipSuccess ||
+        (e = upload(&h->d_blend_dp, pd)) != hipSuccess)
+      return hip_fail(e, "blend lists");
+  }
   // the copies that save them, per level, in 32-bit words (prefix arrays with
   // one extra entry per level)
   std::vector<ppm::CopyItem> copies;

@@ -643,13 +643,13 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
 }
 
 ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream) {
-  return ppm_detail::fill_ghosts(plan, level, nullptr, 1.0, static_cast<hipStream_t>(hip_stream));
+  return ppm_detail::fill_ghosts(plan, level, nullptr, static_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"
 
-ppm_status ppm_detail::fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *old_patches,
-                                   double w, hipStream_t s) {
+ppm_status ppm_detail::fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *parent_tab,
+                                   hipStream_t s) {
   if (!plan) return fail(PPM_EINVAL, "plan is NULL");
   if (!plan->hier) return fail(PPM_EINVAL, "no hierarchy recorded (ppm_set_hierarchy)");
   if (level < 0 || level >= plan->nlevels)
@@ -663,10 +663,9 @@ ppm_status ppm_detail::fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev
   if (ni > 0) {
     e = plan->prec == PPM_FP64
         ? ppm::launch_fill_from_parent<ppm::PrecF64>(plan->d_patches, plan->d_interp + i0, ip, ni,
-                                                     plan->itotal[level], old_patches, w, s)
+                                                     plan->itotal[level], parent_tab, s)
         : ppm::launch_fill_from_parent<ppm::PrecMixed>(plan->d_patches, plan->d_interp + i0, ip,
-                                                       ni, plan->itotal[level], old_patches, w,
-                                                       s);
+                                                       ni, plan->itotal[level], parent_tab, s);
     if (e != hipSuccess) return hip_fail(e, "fill_from_parent launch");
   }
   if (nb > 0) {

@@ -590,19 +590,21 @@ __device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64
 // any of its r^3 fine cells is a ghost cell of the patch, the 27-cell
 // neighbourhood of rho, rho v, rho E, rho e around it, the SecondOrderA slopes
 // of each, and for every such fine cell the interpolant's values, stored as
-// rho, v = (rho v)/rho, E, e.
-template <class Prec, bool kBlend>
+// rho, v = (rho v)/rho, E, e.  The parent's state is read through
+// parent_tab[parent] when given (the parent blended in time), else from the
+// patch table.
+template <class Prec>
 __global__ void __launch_bounds__(256)
 fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *__restrict__ items,
                         const int64_t *__restrict__ prefix, int32_t nitems, int64_t total,
-                        const PatchDev *__restrict__ old_patches, double w) {
+                        const PatchDev *__restrict__ parent_tab) {
   using S = typename Prec::S;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= total) return;
   const int it = find_item(prefix, nitems, t);
   const InterpItem item = items[it];
   const PatchDev fd = patches[item.patch];
-  const PatchDev cd = patches[item.parent];
+  const PatchDev cd = parent_tab ? parent_tab[item.parent] : patches[item.parent];
   const int gf = fd.ghost, gc = cd.ghost, r = item.r;
   const int64_t Nf[3] = {fd.n[0], fd.n[1], fd.n[2]};
   const int64_t nf[3] = {Nf[0] + 2 * gf, Nf[1] + 2 * gf, Nf[2] + 2 * gf};
@@ -639,30 +641,19 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
   int64_t lc[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) lc[a] = cc[a] - item.pstart[a] + gc;
-  // the parent's state before its last step (kBlend: the patch lies between
-  // the parent's two times, and the parent's stored fields are blended)
-  const PatchDev od = kBlend ? old_patches[item.parent] : cd;
-  const double wo = 1.0 - w;
   double q0[6], fx[6], fy[6], fz[6];
 #pragma unroll 1
   for (int comp = 0; comp < 6; ++comp) {
     // the stored field whose product with rho is this component (none for rho)
     const S *xs = comp >= 1 && comp <= 3 ? static_cast<const S *>(cd.vel[comp - 1]) : nullptr;
     const double *xd = comp == 4 ? cd.etot : cd.eint;
-    const S *oxs = comp >= 1 && comp <= 3 ? static_cast<const S *>(od.vel[comp - 1]) : nullptr;
-    const double *oxd = comp == 4 ? od.etot : od.eint;
     double nb[3][3][3];
     for (int dz = 0; dz < 3; ++dz)
       for (int dy = 0; dy < 3; ++dy)
         for (int dx = 0; dx < 3; ++dx) {
           const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
-          double rho = double(static_cast<const S *>(cd.rho)[o]);
-          double x = comp == 0 ? 0.0 : (xs ? double(xs[o]) : xd[o]);
-          if (kBlend) {
-            rho = wo * double(static_cast<const S *>(od.rho)[o]) + w * rho;
-            const double xo = comp == 0 ? 0.0 : (oxs ? double(oxs[o]) : oxd[o]);
-            x = wo * xo + w * x;
-          }
+          const double rho = double(static_cast<const S *>(cd.rho)[o]);
+          const double x = comp == 0 ? 0.0 : (xs ? double(xs[o]) : xd[o]);
           nb[dz][dy][dx] = comp == 0 ? rho : rho * x;
         }
     q0[comp] = nb[1][1][1];
@@ -1070,15 +1061,36 @@ hipError_t launch_fill_boundary(const PatchDev &pd, const FaceRules &fr, hipStre
 template <class Prec>
 hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *items,
                                    const int64_t *prefix, int32_t nitems, int64_t total,
-                                   const PatchDev *old_patches, double w, hipStream_t s) {
+                                   const PatchDev *parent_tab, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_from_parent_kernel<Prec>, dim3(unsigned((total + 255) / 256)),
+                     dim3(256), 0, s, patches, items, prefix, nitems, total, parent_tab);
+  return hipGetLastError();
+}
+
+template <class T>
+__global__ void __launch_bounds__(256)
+blend_kernel(const BlendItem *__restrict__ items, const int64_t *__restrict__ prefix,
+             int32_t nitems, int64_t total, double w) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= total) return;
+  const int it = find_item(prefix, nitems, t);
+  const BlendItem item = items[it];
+  const int64_t u = t - prefix[it];
+  const double wo = 1.0 - w;
+  static_cast<T *>(item.dst)[u] =
+      T(wo * double(static_cast<const T *>(item.old)[u]) + w * double(static_cast<const T *>(item.cur)[u]));
+}
+
+hipError_t launch_blend(const BlendItem *items, const int64_t *prefix, int32_t nitems,
+                        int64_t total, bool single, double w, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   const dim3 grid(unsigned((total + 255) / 256));
-  if (old_patches)
-    hipLaunchKernelGGL((fill_from_parent_kernel<Prec, true>), grid, dim3(256), 0, s, patches,
-                       items, prefix, nitems, total, old_patches, w);
+  if (single)
+    hipLaunchKernelGGL(blend_kernel<float>, grid, dim3(256), 0, s, items, prefix, nitems, total, w);
   else
-    hipLaunchKernelGGL((fill_from_parent_kernel<Prec, false>), grid, dim3(256), 0, s, patches,
-                       items, prefix, nitems, total, old_patches, w);
+    hipLaunchKernelGGL(blend_kernel<double>, grid, dim3(256), 0, s, items, prefix, nitems, total,
+                       w);
   return hipGetLastError();
 }
 
@@ -1206,10 +1218,10 @@ template hipError_t launch_fill_boundary<PrecF64>(const PatchDev &, const FaceRu
                                                   hipStream_t);
 template hipError_t launch_fill_from_parent<PrecF64>(const PatchDev *, const InterpItem *,
                                                      const int64_t *, int32_t, int64_t,
-                                                     const PatchDev *, double, hipStream_t);
+                                                     const PatchDev *, hipStream_t);
 template hipError_t launch_fill_from_parent<PrecMixed>(const PatchDev *, const InterpItem *,
                                                        const int64_t *, int32_t, int64_t,
-                                                       const PatchDev *, double, hipStream_t);
+                                                       const PatchDev *, hipStream_t);
 template hipError_t launch_copy_from_siblings<PrecF64>(const PatchDev *, const SiblingBox *,
                                                        const int64_t *, int32_t, int64_t,
                                                        hipStream_t);

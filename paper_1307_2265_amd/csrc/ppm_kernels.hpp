@@ -98,13 +98,23 @@ struct SiblingBox {
 
 // Ghost cells of items[0..nitems): SecondOrderA interpolation of the parent's
 // conserved quantities.  prefix[i] = first ghost cell of item i in the launch
-// (prefix[nitems] = total).  old_patches (nullable): the parents' states
-// before their last step (same table layout); the parent's stored fields
-// are then (1 - w) old + w new.
+// (prefix[nitems] = total).  parent_tab (nullable): a patch table to read
+// the parents' states from instead of `patches` (the parents blended in
+// time).
 template <class Prec>
 hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *items,
                                    const int64_t *prefix, int32_t nitems, int64_t total,
-                                   const PatchDev *old_patches, double w, hipStream_t s);
+                                   const PatchDev *parent_tab, hipStream_t s);
+
+// dst[i] = (1 - w) old[i] + w cur[i], evaluated in double, over the listed
+// arrays of float (single) or double elements (prefix over their lengths):
+// a parent's stored fields at a time between its last two states.
+struct BlendItem {
+  const void *old, *cur;
+  void *dst;
+};
+hipError_t launch_blend(const BlendItem *items, const int64_t *prefix, int32_t nitems,
+                        int64_t total, bool single, double w, hipStream_t s);
 
 // A face whose flux a coarse step records: the pencil (i1, i2) of `patch`
 // along the capture launch's axis, the face between its cells j and j+1

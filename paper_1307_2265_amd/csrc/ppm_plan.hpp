@@ -61,10 +61,8 @@ namespace ppm_detail {
 ppm_status fail(ppm_status s, const char *fmt, ...);
 ppm_status hip_fail(hipError_t e, const char *what);
 
-// ppm_fill_ghosts of `level`, with the parents' stored fields taken as
-// (1 - w) old + w current when old_patches (a device copy of the plan's patch
-// table pointing at the parents' earlier states) is given.
-ppm_status fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *old_patches, double w,
-                       hipStream_t s);
+// ppm_fill_ghosts of `level`, with the parents' states read through
+// parent_tab (a device patch table in the plan's order) when it is given.
+ppm_status fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *parent_tab, hipStream_t s);
 
 }  // namespace ppm_detail
