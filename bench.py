@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--no-hllc", action="store_true", help="skip the HLLC-solver runs")
     ap.add_argument("--no-amr-fill", action="store_true", help="skip the AMR ghost-fill timing")
     ap.add_argument("--no-amr-step", action="store_true", help="skip the AMR W-cycle timing")
+    ap.add_argument("--amr-step-only", action="store_true",
+                    help="time only the AMR W-cycle and print its JSON (for profiling it)")
     ap.add_argument("--no-sources", action="store_true",
                     help="skip the runs with gravity and comoving expansion")
     return ap.parse_args()
@@ -208,6 +210,9 @@ def main():
     from paper_1307_2265_amd import harness as H
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     ppm.lib()
+    if args.amr_step_only:
+        print(json.dumps({"amr_w_cycle": amr_w_cycle()}))
+        return
     n, K, Wm = args.n, args.steps, args.warmup
     cells = n ** 3
     t0 = time.time()

@@ -79,10 +79,17 @@ def kernels(stats_csv: str, trace_csv: str, cmd: str, out: str):
     for k, d in sorted(byblock.items()):
         lines.append(f"| `{k[0]}` | {k[1]} | {len(d)} | {sum(d) / len(d):.3f} |")
     # a marching sweep of the big grid is its marching launch plus, when
-    # pencils are left over after whole rounds, a tail launch
-    means = {k: sum(d) / len(d) for k, d in
-             ((name, [x for kk, dd in agg.items() if kk[0] == name for x in dd])
-              for name in {kk[0] for kk in agg})}
+    # pencils are left over after whole rounds, a tail launch; the big grid's
+    # marching launches are the largest of their kernel (other workloads, such
+    # as the AMR root grid, launch the same kernel on fewer pencils), and only
+    # the big grid needs tail launches
+    def big_grid_mean(name):
+        grids = [kk[1] for kk in agg if kk[0] == name]
+        if "tail" not in name:
+            grids = [max(grids)]
+        d = [x for kk, dd in agg.items() if kk[0] == name and kk[1] in grids for x in dd]
+        return sum(d) / len(d)
+    means = {name: big_grid_mean(name) for name in {kk[0] for kk in agg}}
     sweeps = []
     for prec in ("PrecF64", "PrecMixed"):
         for cfl in ("false", "true"):
