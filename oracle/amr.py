@@ -84,6 +84,9 @@ class Hierarchy:
                     raise ValueError("patches below the root need flux registers")
                 self.children[n.parent].append(i)
         self.boxes = {i: [self.footprint(c) for c in ch] for i, ch in self.children.items()}
+        # the siblings each patch copies ghost cells from, in patch order
+        self.neighbours = {i: [j for j in self.level(n.level) if j != i and self._may_touch(i, j)]
+                           for i, n in enumerate(self.nodes)}
         self.acc = {i: np.zeros(flux_reg_size(*n.grid.active_shape))
                     for i, n in enumerate(self.nodes) if n.level > 0}
         self.old = {}
@@ -105,18 +108,21 @@ class Hierarchy:
         return box(lo, hi)
 
     # -- boundary values -----------------------------------------------------
-    def _parent_at(self, p, t):
+    def _parent_at(self, p, t, cache):
         """The parent's stored fields at time t, linear in time between its
-        states before and after its last step."""
+        states before and after its last step (cache: blends already made
+        for this fill, by parent)."""
         P = self.nodes[p]
         l = P.level
         if self.t[l] == self.t_old[l] or p not in self.old:
             return P.grid
-        w = (t - self.t_old[l]) / (self.t[l] - self.t_old[l])
-        old = self.old[p]
-        blend = {f: (1.0 - w) * getattr(old, f) + w * getattr(P.grid, f) for f in FIELDS}
-        g = P.grid
-        return Grid(**blend, dx=g.dx, dy=g.dy, dz=g.dz, ghost=g.ghost)
+        if p not in cache:
+            w = (t - self.t_old[l]) / (self.t[l] - self.t_old[l])
+            old = self.old[p]
+            blend = {f: (1.0 - w) * getattr(old, f) + w * getattr(P.grid, f) for f in FIELDS}
+            g = P.grid
+            cache[p] = Grid(**blend, dx=g.dx, dy=g.dy, dz=g.dz, ghost=g.ghost)
+        return cache[p]
 
     def fill(self, l):
         ids = self.level(l)
@@ -127,15 +133,24 @@ class Hierarchy:
             else:
                 fill_boundary(root, self.root_kinds, self.root_inflow)
             return
+        cache = {}
         for i in ids:
             n = self.nodes[i]
-            src = self._parent_at(n.parent, self.t[l])
+            src = self._parent_at(n.parent, self.t[l], cache)
             fill_from_parent(n.grid, n.start, src, self.nodes[n.parent].start, n.r)
         for i in ids:
-            for j in ids:
-                if j != i:
-                    copy_from_sibling(self.nodes[i].grid, self.nodes[i].start,
-                                      self.nodes[j].grid, self.nodes[j].start)
+            for j in self.neighbours[i]:
+                copy_from_sibling(self.nodes[i].grid, self.nodes[i].start,
+                                  self.nodes[j].grid, self.nodes[j].start)
+
+    def _may_touch(self, i, j):
+        """Whether patch j's active box meets patch i's ghosted box (else the
+        sibling copy from j to i copies nothing)."""
+        a, b = self.nodes[i], self.nodes[j]
+        da, db = a.grid.active_shape, b.grid.active_shape
+        g = a.grid.ghost
+        return all(a.start[k] - g < b.start[k] + db[k] and b.start[k] < a.start[k] + da[k] + g
+                   for k in range(3))
 
     # -- the W-cycle ---------------------------------------------------------
     def cfl_dt(self, l):

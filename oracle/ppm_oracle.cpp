@@ -28,6 +28,7 @@
 
 #include "ppm_oracle.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -1193,7 +1194,11 @@ int ppmo_fill_from_parent(ppmo_grid *F, const int32_t fine_start[3], const ppmo_
   }
   const double *cf[6] = {C->rho, C->vx, C->vy, C->vz, C->etot, C->eint};
   double *ff[6] = {F->rho, F->vx, F->vy, F->vz, F->etot, F->eint};
+  // ghost cells are independent: threads over z planes, same result
+#pragma omp parallel
+  {
   std::vector<double> sub((size_t)r * r * r);
+#pragma omp for schedule(static)
   for (int64_t z = 0; z < nf[2]; ++z)
     for (int64_t y = 0; y < nf[1]; ++y)
       for (int64_t x = 0; x < nf[0]; ++x) {
@@ -1226,6 +1231,7 @@ int ppmo_fill_from_parent(ppmo_grid *F, const int32_t fine_start[3], const ppmo_
         ff[0][dst] = q[0];
         for (int comp = 1; comp < 6; ++comp) ff[comp][dst] = q[comp] / q[0];
       }
+  }
   return 0;
 }
 
@@ -1241,9 +1247,16 @@ int ppmo_copy_from_sibling(ppmo_grid *D, const int32_t dst_start[3], const ppmo_
   const int64_t ns[3] = {Ns[0] + 2 * gs, Ns[1] + 2 * gs, Ns[2] + 2 * gs};
   const double *sf[6] = {S->rho, S->vx, S->vy, S->vz, S->etot, S->eint};
   double *df[6] = {D->rho, D->vx, D->vy, D->vz, D->etot, D->eint};
-  for (int64_t z = 0; z < nd[2]; ++z)
-    for (int64_t y = 0; y < nd[1]; ++y)
-      for (int64_t x = 0; x < nd[0]; ++x) {
+  // only dst cells whose image lies in src's active region can be copied:
+  // local c with 0 <= dst_start + c - gd - src_start < Ns, within dst's array
+  int64_t lo[3], hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = std::max<int64_t>(0, (int64_t)src_start[a] - dst_start[a] + gd);
+    hi[a] = std::min<int64_t>(nd[a], (int64_t)src_start[a] + Ns[a] - dst_start[a] + gd);
+  }
+  for (int64_t z = lo[2]; z < hi[2]; ++z)
+    for (int64_t y = lo[1]; y < hi[1]; ++y)
+      for (int64_t x = lo[0]; x < hi[0]; ++x) {
         const int64_t c[3] = {x, y, z};
         bool active = true, inside = true;
         int64_t sc[3];

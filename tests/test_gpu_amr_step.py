@@ -170,3 +170,31 @@ def test_w_cycle_with_gravity_and_expansion_equals_oracle(P, O):
         for f in FIELDS:
             assert np.array_equal(g[f], getattr(node.grid, f)), (i, f)
     h.close()
+
+
+def test_w_cycle_bench_hierarchy_one_root_step(P, O):
+    # The benchmark's W-cycle workload (128^3 periodic root, 64 level-1 blocks
+    # of 32^3, 512 level-2 blocks of 24^3, gentle fields) in its launch
+    # configuration: one root step (1 + 2 + 5 level steps) against the
+    # oracle's, bit for bit on every patch.
+    print("generating the nested hierarchy", flush=True)
+    hier = W.nested_hierarchy(128, (32, 24), (4, 2))
+    fields = [stored_inputs(W.random_grid(*h.dims, 5000 + i, W.GENTLE), P.PPM_FP64)
+              for i, h in enumerate(hier)]
+    dxs = [(0.5 ** h.level / 128,) * 3 for h in hier]
+    patches = [to_device(f, P.PPM_FP64, dx=dx, level=h.level, with_reg=h.level > 0)
+               for f, dx, h in zip(fields, dxs, hier)]
+    h = P.Amr(patches, [(x.parent, 2, x.start) for x in hier], 3, P.PPM_FP64)
+    H = amr.Hierarchy([amr.Node(oracle_grid(O, f, dx=dx, with_reg=x.level > 0), x.level,
+                                x.parent, x.start, 2)
+                       for f, dx, x in zip(fields, dxs, hier)], [O.params()] * 3)
+    print("oracle root step", flush=True)
+    H.evolve()
+    print("gpu root step", flush=True)
+    h.ppm_amr_step()
+    assert h.ppm_amr_step_log() == H.dts
+    bad = [i for i, (p, node) in enumerate(zip(patches, H.nodes))
+           if any(not np.array_equal(from_device(p)[f], getattr(node.grid, f)) for f in FIELDS)]
+    print(f"patches: {len(patches)}, not bitwise equal: {len(bad)}")
+    assert not bad
+    h.close()

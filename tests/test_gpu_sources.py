@@ -305,3 +305,47 @@ def test_expansion_step_alone_equals_oracle(P, O, prec):
                 ref = ref.astype(np.float32).astype(np.float64)
             assert np.array_equal(g[k], ref), (i, k)
     plan.close()
+
+
+def test_full_size_512_step_with_sources_in_bench_configuration(P, O):
+    # The benchmark's gravity + comoving workload: the shocked 512^3 grid with
+    # a seeded acceleration field and a = 1.7, adot = 0.6, in its launch
+    # configuration (autotuned tiles, the gravity builds); one step (CFL, the
+    # three sweeps, the expansion terms) against the oracle cell by cell.
+    import torch
+    from paper_1307_2265_amd import autotune
+    n = 512
+    cfg = W.CONFIGS[2]
+    print("generating 512^3 input", flush=True)
+    d = stored_inputs(W.random_grid(n, n, n, cfg["seed"], cfg["recipe"]), P.PPM_FP64)
+    acc = W.acceleration_field(d["rho"].shape, 4242, 3.0)
+    a, adot = 1.7, 0.6
+    print("oracle step", flush=True)
+    G = oracle_grid(O, d)
+    G.accel = acc
+    prm = O.params(a=a, adot=adot)
+    O.fill_periodic(G)
+    dto = O.cfl_dt(G, prm)
+    c = O.step(G, prm, dto, 0)
+    O.expansion(G, prm, dto)
+    print("gpu step", flush=True)
+    patch = to_device(d, P.PPM_FP64)
+    patch.accel = _dev(acc, torch.float64)
+    del acc
+    plan = P.Plan([patch], 1, P.PPM_FP64, P.params(),
+                  tile_config=autotune.best_tiles("single/fp64"))
+    plan.ppm_set_expansion(torch.tensor([a, adot], dtype=torch.float64, device="cuda"))
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    plan.ppm_fill_periodic()
+    plan.ppm_cfl_dt(dt)
+    plan.ppm_step(dt, 0)
+    plan.ppm_expansion(dt)
+    torch.cuda.synchronize()
+    assert float(dt.item()) == dto
+    assert plan.ppm_event_counts() == (c.fallback_faces, c.floored_cells)
+    for f in FIELDS:
+        g = getattr(patch, f)[3:-3, 3:-3, 3:-3].cpu().numpy()
+        differ = int(np.count_nonzero(g != getattr(G, f)[3:-3, 3:-3, 3:-3]))
+        print(f"{f}: cells not bitwise equal {differ}")
+        assert differ == 0, f
+    plan.close()
