@@ -25,6 +25,7 @@ _SOURCES = ["ppm_oracle.cpp", "exact_riemann.cpp"]
 
 STEEPEN, FLATTEN, DUAL_ENERGY, FALLBACK_HLL = 1, 2, 4, 8
 HLLC = 16  # HLLC face fluxes instead of the two-shock solver
+DIFFUSION = 32  # CW84's diffusive flux where the flow converges
 ALL_FLAGS = STEEPEN | FLATTEN | DUAL_ENERGY | FALLBACK_HLL
 ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
 

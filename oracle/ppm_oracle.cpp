@@ -46,6 +46,9 @@ namespace {
 const double C16 = 1.0 / 6.0;
 const double C23 = 2.0 / 3.0;
 // Contact steepening constants (CW84 Eqs. 1.16-1.17 and 3.2).
+// CW84's dissipation coefficient (the optional diffusive flux; CW84 is not
+// available here, K = 0.1 is its published value as read).
+const double DIFF_K = 0.1;
 const double STEEP_EPS = 0.01;
 const double STEEP_K0 = 0.1;
 const double STEEP_ETA1 = 20.0;
@@ -393,6 +396,28 @@ template <class R> void second_order_a(const R (&nb)[3][3][3], int r, R *out) {
 int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 // ---------------------------------------------------------------------------
+// Optional diffusive flux (Sec. "Hydrodynamics: The PPM method" refers to
+// CW84's appendix for it), in its form along the sweep: where the flow
+// converges across face j+1/2 (u_j > u_{j+1}, cell-centred normal
+// velocities of the sweep input), every conserved quantity's face flux gains
+// nu (Q_j - Q_{j+1}) with nu = K (u_j - u_{j+1}); nothing changes elsewhere.
+// Q: rho, rho u, rho v1, rho v2, rho E, rho e; the face velocity of the
+// p div v term is left alone.
+template <class R>
+void add_diffusion(const ppmo_params &P, const R *rho, const R *u, const R *v1, const R *v2,
+                   const R *E, const R *e, int j, R *F) {
+  if (!(P.flags & PPMO_DIFFUSION)) return;
+  const R du = u[j] - u[j + 1];
+  if (!(du > R(0.0))) return;
+  const R nu = R(DIFF_K) * du;
+  const R ql[6] = {rho[j], rho[j] * u[j], rho[j] * v1[j], rho[j] * v2[j], rho[j] * E[j],
+                   rho[j] * e[j]};
+  const R qr[6] = {rho[j + 1], rho[j + 1] * u[j + 1], rho[j + 1] * v1[j + 1],
+                   rho[j + 1] * v2[j + 1], rho[j + 1] * E[j + 1], rho[j + 1] * e[j + 1]};
+  for (int k = 0; k < 6; ++k) F[k] = F[k] + nu * (ql[k] - qr[k]);
+}
+
+// ---------------------------------------------------------------------------
 // Step 8: conservative update of one active cell from its two face fluxes
 // (Eqs. mass_diff, momentum_diff, energy_diff, gasenergy_diff; dtdx = dt /
 // (a dx) in comoving coordinates), then the eta2 resync of e (Eq.
@@ -641,11 +666,13 @@ void pencil_sweep(const ppmo_params &P, int n, int gh, R dt, R dx, R *rho, R *u,
     }
   }
 
-  // 7. Riemann problems and fluxes at faces j+1/2, j = a0-1..a1
+  // 7. Riemann problems and fluxes at faces j+1/2, j = a0-1..a1 (with the
+  //    optional diffusive flux)
   for (int j = a0 - 1; j <= a1; ++j) {
     R sl[NQ], sr[NQ], F[NF];
     for (int k = 0; k < NQ; ++k) { sl[k] = w.stl[k][j]; sr[k] = w.str[k][j]; }
     godunov_flux<R>(P, sl, sr, F);
+    add_diffusion<R>(P, rho, u, v1, v2, Etot, eint, j, F);
     for (int k = 0; k < NF; ++k) w.F[k][j] = F[k];
   }
 
@@ -678,6 +705,7 @@ void pencil_sweep(const ppmo_params &P, int n, int gh, R dt, R dx, R *rho, R *u,
         R sl[NQ], sr[NQ], F[NF];
         for (int k = 0; k < NQ; ++k) { sl[k] = w.stl[k][j]; sr[k] = w.str[k][j]; }
         hll_flux<R>(P, sl, sr, F);
+        add_diffusion<R>(P, rho, u, v1, v2, Etot, eint, j, F);
         for (int k = 0; k < NF; ++k) w.F[k][j] = F[k];
         if (cnt) cnt->fallback_faces++;
       }

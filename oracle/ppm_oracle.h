@@ -50,6 +50,10 @@
  *   - HLLC's outer wave speeds (the Davis estimates of the HLL fallback; the
  *     paper names none) and the internal energy carried with the density
  *     across its star states;
+ *   - the diffusive flux (flag PPMO_DIFFUSION): its coefficient K = 0.1
+ *     and its form along the sweep (CW84's multidimensional divergence is
+ *     not used); pinned only by properties: nothing changes where the flow
+ *     does not converge, conservation, fewer post-shock oscillations;
  *   - SecondOrderA's readings: corner values as 8-cell averages, the printed
  *     sign of the adjustment factor (read so the slopes sum to dQ0 s'), no
  *     epsilon (the selected slopes never sum to zero), the dQ0 = 0 case, and
@@ -84,7 +88,8 @@ enum {
   PPMO_FLATTEN = 2u,      /* CW84 appendix shock flattening */
   PPMO_DUAL_ENERGY = 4u,  /* eta1 pressure selection and eta2 resync */
   PPMO_FALLBACK_HLL = 8u, /* re-solve faces of non-positive cells with HLL */
-  PPMO_HLLC = 16u         /* HLLC face fluxes instead of the two-shock solver */
+  PPMO_HLLC = 16u,        /* HLLC face fluxes instead of the two-shock solver */
+  PPMO_DIFFUSION = 32u    /* CW84's diffusive flux where the flow converges */
 };
 
 typedef struct {
