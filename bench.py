@@ -11,7 +11,7 @@ synthetic and resident in HBM when the timed region starts; launch shapes
 come from the autotuner's table (data/tiles.json) when it exists.
 
 Also measured: the same grid and steps with the HLLC solver in place of
-two-shock (FP64 and mixed); the same grid with a seeded acceleration field
+two-shock (FP64 and mixed), and with the optional diffusive flux; the same grid with a seeded acceleration field
 and comoving expansion factors (gravity sources in every sweep, a pass of the
 expansion terms per step, FP64 and mixed); the AMR W-cycle (ppm_amr_step:
 subcycled levels, flux correction, projection) on a nested hierarchy; the AMR
@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--no-hllc", action="store_true", help="skip the HLLC-solver runs")
     ap.add_argument("--no-amr-fill", action="store_true", help="skip the AMR ghost-fill timing")
     ap.add_argument("--no-amr-step", action="store_true", help="skip the AMR W-cycle timing")
+    ap.add_argument("--no-diffusion", action="store_true",
+                    help="skip the runs with the diffusive flux")
     ap.add_argument("--amr-step-only", action="store_true",
                     help="time only the AMR W-cycle and print its JSON (for profiling it)")
     ap.add_argument("--no-sources", action="store_true",
@@ -280,6 +282,31 @@ def main():
             r.close()
         torch.cuda.empty_cache()
 
+    # ---- the same grid and steps with the optional diffusive flux
+    diffusion = None
+    if not args.no_diffusion:
+        diffusion = {"flags": "PPM_ALL_FLAGS | PPM_DIFFUSION"}
+        for name, prec in (("fp64", ppm.PPM_FP64), ("mixed", ppm.PPM_MIXED)):
+            if name == "mixed" and args.no_mixed:
+                continue
+            tiles = args.tiles or autotune.best_tiles(f"single/{name}")
+            r = H.Run.single(d, n, prec, tiles, flags=ppm.PPM_ALL_FLAGS | ppm.PPM_DIFFUSION)
+            for s in range(Wm):
+                r.step(s)
+            torch.cuda.synchronize()
+            r.reset()
+            r.plan.ppm_event_counts(reset=True)
+            total, dk = r.timed(K, per_sweep=True)
+            fb, fl = r.plan.ppm_event_counts()
+            diffusion[name] = {"value": cells * K / total, "unit": "cell-updates/s",
+                               "ms_per_step": total / K * 1e3, "tiles": tiles,
+                               "sweep_kernel_ms": {k: v * 1e3 for k, v in dk.items()},
+                               "slowdown_vs_plain": total / results[name]["seconds"],
+                               "events": {"fallback_faces": fb, "floored_cells": fl}}
+            log(f"diffusion {name}: {cells * K / total / 1e9:.3f} G cell-updates/s")
+            r.close()
+        torch.cuda.empty_cache()
+
     # ---- the same grid with an acceleration field and comoving expansion:
     # every sweep adds the gravity sources and divides by a, and a pass of
     # the expansion terms precedes the sweeps
@@ -473,6 +500,8 @@ def main():
                          "tiles": mx["tiles"]}
     if hllc is not None:
         line["hllc"] = hllc
+    if diffusion is not None:
+        line["diffusion"] = diffusion
     if sources is not None:
         line["gravity_comoving"] = sources
     if amr is not None:

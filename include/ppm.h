@@ -81,10 +81,15 @@ enum {
   PPM_DUAL_ENERGY = 4u,  /* eta1 pressure selection and eta2 resync of e */
   PPM_FALLBACK_HLL = 8u, /* re-solve the faces of non-positive cells with HLL */
   PPM_ALL_FLAGS = 15u,   /* the four above: the paper's PPM with two-shock */
-  PPM_HLLC = 16u         /* face fluxes by the HLLC solver (Sec. "Riemann Solvers
+  PPM_HLLC = 16u,        /* face fluxes by the HLLC solver (Sec. "Riemann Solvers
                             and Fallback"; Davis outer wave speeds, contact speed
                             from the outer waves' jump conditions) instead of
                             two-shock; the HLL fallback still applies */
+  PPM_DIFFUSION = 32u    /* the optional diffusive flux (Sec. "Hydrodynamics: The
+                            PPM method", after CW84): where the flow converges
+                            across a face (u_l > u_r of the sweep input), every
+                            conserved quantity's flux gains 0.1 (u_l - u_r)(Q_l -
+                            Q_r); on the Riemann and on the HLL fallback flux */
 };
 
 /* One grid patch.  All pointers are device pointers owned by the caller. */
@@ -110,7 +115,9 @@ typedef struct {
   double gamma;            /* ratio of specific heats, > 1 */
   double cfl;              /* kappa_hydro, 0 < cfl <= 1 */
   double eta1, eta2;       /* dual-energy thresholds (paper: 1e-3, 0.1) */
-  double rho_floor, p_floor, e_floor; /* positive floors */
+  double rho_floor, p_floor, e_floor; /* floors: rho_floor, p_floor >= 1e-100 (they bound
+                                          the operands of the fast FP64 division and square
+                                          root), e_floor > 0; PPM_EINVAL otherwise */
   double riemann_rtol;     /* relative tolerance on the two-shock p*, > 0 */
   int32_t riemann_max_iter;/* Newton iteration cap, >= 1 */
   uint32_t flags;          /* PPM_STEEPEN | PPM_FLATTEN | ... */

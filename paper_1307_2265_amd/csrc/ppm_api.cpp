@@ -63,12 +63,12 @@ ppm_status check_params(const ppm_params *p) {
   if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(PPM_EINVAL, "gamma must be > 1");
   if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(PPM_EINVAL, "cfl must be in (0, 1]");
   if (!(p->eta1 >= 0.0) || !(p->eta2 >= 0.0)) return fail(PPM_EINVAL, "eta1/eta2 must be >= 0");
-  if (!(p->rho_floor > 0.0) || !(p->p_floor > 0.0) || !(p->e_floor > 0.0))
-    return fail(PPM_EINVAL, "floors must be > 0");
+  if (!(p->rho_floor >= 1e-100) || !(p->p_floor >= 1e-100) || !(p->e_floor > 0.0))
+    return fail(PPM_EINVAL, "rho_floor and p_floor must be >= 1e-100, e_floor > 0");
   if (!(p->riemann_rtol > 0.0)) return fail(PPM_EINVAL, "riemann_rtol must be > 0");
   if (p->riemann_max_iter < 1 || p->riemann_max_iter > 1000)
     return fail(PPM_EINVAL, "riemann_max_iter must be in [1, 1000]");
-  if (p->flags & ~uint32_t(PPM_ALL_FLAGS | PPM_HLLC))
+  if (p->flags & ~uint32_t(PPM_ALL_FLAGS | PPM_HLLC | PPM_DIFFUSION))
     return fail(PPM_EINVAL, "unknown flag bits 0x%x", p->flags);
   return PPM_OK;
 }

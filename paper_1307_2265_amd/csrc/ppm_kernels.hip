@@ -925,11 +925,12 @@ fill_periodic_kernel(PatchDev pd) {
 // Launchers
 
 // The three builds of each sweep kernel (template arguments kUseHLLC, kGrav):
-// two-shock only; HLLC or two-shock as the flag says; the latter with the
-// gravity source terms, for plans where some patch has an acceleration field.
-#define PPM_BUILD(P, LAUNCH, ...)                                 \
-  if ((P).flags & kAnyGravity) LAUNCH(__VA_ARGS__, true, true);   \
-  else if ((P).flags & kHLLC) LAUNCH(__VA_ARGS__, true, false);   \
+// two-shock only; HLLC or two-shock as the flag says; the general build,
+// which adds the gravity source terms and the diffusive flux, for plans where
+// some patch has an acceleration field or the diffusive flux is on.
+#define PPM_BUILD(P, LAUNCH, ...)                                              \
+  if ((P).flags & (kAnyGravity | kDiffusion)) LAUNCH(__VA_ARGS__, true, true); \
+  else if ((P).flags & kHLLC) LAUNCH(__VA_ARGS__, true, false);                \
   else LAUNCH(__VA_ARGS__, false, false)
 
 template <class Prec>
@@ -987,7 +988,7 @@ hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start
 
 template <class Prec, bool kCFL>
 const void *march_kernel_ptr(uint32_t flags) {
-  if (flags & kAnyGravity)
+  if (flags & (kAnyGravity | kDiffusion))
     return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, true, true>);
   if (flags & kHLLC)
     return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, true, false>);
@@ -1103,7 +1104,7 @@ hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32
 #define PPM_LAUNCH_CAPTURE(HLLC, GRAV)                                                       \
   hipLaunchKernelGGL((capture_kernel<Prec, HLLC, GRAV>), dim3(blocks), dim3(256), 0, s,       \
                      patches, rows, nrows, axis, dt_dev, P)
-  if (P.flags & kAnyGravity) PPM_LAUNCH_CAPTURE(true, true);
+  if (P.flags & (kAnyGravity | kDiffusion)) PPM_LAUNCH_CAPTURE(true, true);
   else if (P.flags & kHLLC) PPM_LAUNCH_CAPTURE(true, false);
   else PPM_LAUNCH_CAPTURE(false, false);
 #undef PPM_LAUNCH_CAPTURE

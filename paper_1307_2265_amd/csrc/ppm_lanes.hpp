@@ -166,8 +166,17 @@ __device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S>
   const State<T> srown = trace_edge<T, false>(gam, l, rr, dq, q6, q[1], cc, tlam, rho_floor, p_floor);
   const State<T> sr = state_from_right(srown);
 
-  // ---- Riemann problem at face j+1/2 (faces a0-1..a1)
+  // ---- Riemann problem at face j+1/2 (faces a0-1..a1), with the optional
+  // diffusive flux from this cell's and the right neighbour's input values
   const bool face_ok = j >= a0 - 1 && j <= a1;
+  const bool diffuse = kGrav && (P.flags & kDiffusion) != 0;
+  // the diffusive flux, from this cell's and the right neighbour's input
+  // values (the shifts run on every lane, outside divergent branches)
+  auto diffuse_into = [&](Flux &G) {
+    const double nr = from_right(in.r), nu = from_right(in.u), nv1 = from_right(in.v1);
+    const double nv2 = from_right(in.v2), nE = from_right(in.E), ne = from_right(in.e);
+    if (face_ok) add_diffusion(G, in.r, in.u, in.v1, in.v2, in.E, in.e, nr, nu, nv1, nv2, nE, ne);
+  };
   Flux F;
 #pragma unroll
   for (int k = 0; k < 7; ++k) F.f[k] = 0.0;
@@ -175,6 +184,7 @@ __device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S>
     F = riemann_flux<kUseHLLC>(P, double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p),
                      double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p));
   }
+  if (diffuse) diffuse_into(F);
 
   // ---- provisional update of cell j (a0..a1)
   const bool cell_ok = j >= a0 && j <= a1;
@@ -196,10 +206,15 @@ __device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S>
     const bool bad_next = from_right(int(bad)) != 0;
     const bool hll = face_ok && (bad || bad_next);
     if (__any(hll)) {
+      Flux H = F;
       if (hll) {
         const double L5[5] = {double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p)};
         const double R5[5] = {double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p)};
-        F = hll_flux(P, L5, R5);
+        H = hll_flux(P, L5, R5);
+      }
+      if (diffuse) diffuse_into(H);
+      if (hll) {
+        F = H;
         // face j+1/2 is counted by the wave that writes cell j (or cell a0 for the first face)
         if (mine || (j == a0 - 1 && mine_next)) ++n_fallback;
       }

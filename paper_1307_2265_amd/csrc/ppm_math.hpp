@@ -28,7 +28,12 @@ constexpr double kFlatOmega1 = 0.75;
 constexpr double kFlatOmega2 = 10.0;
 constexpr double kFlatEps = 0.33;
 
-enum : uint32_t { kSteepen = 1u, kFlatten = 2u, kDualEnergy = 4u, kFallbackHLL = 8u, kHLLC = 16u };
+enum : uint32_t {
+  kSteepen = 1u, kFlatten = 2u, kDualEnergy = 4u, kFallbackHLL = 8u, kHLLC = 16u,
+  kDiffusion = 32u
+};
+// CW84's dissipation coefficient K of the optional diffusive flux.
+constexpr double kDiffK = 0.1;
 // Set by the library, never by a caller: some patch carries an acceleration
 // field, so the sweeps launch their build with the gravity source terms.
 constexpr uint32_t kAnyGravity = 0x80000000u;
@@ -60,11 +65,15 @@ template <class T> __device__ __forceinline__ T clamp01(T x) {
 // theorem; the square root likewise).  They omit the operand scaling and
 // special-value fix-ups that a general IEEE division or square root needs for
 // operands within 2^768 of the overflow or underflow threshold, zeros,
-// infinities and NaNs: every divisor and radicand on the hot path is a
-// density, pressure, sound or shock speed, or a sum of them, bounded well
-// inside that range by the floors, and a value computed for a discarded
-// branch may be a NaN where IEEE gives an infinity.  Results are bit for bit
-// those of a / b and sqrt(x).
+// infinities and NaNs.  They serve only where the operands are bounded: the
+// equation of state and the Riemann solvers take floored states (floors of
+// at least 1e-100 are enforced at the interface), the Lagrangian wave speeds
+// and the two-shock star density are positive and finite for such states, and
+// the steepening and flattening ratios divide differences of floored cell
+// values; with state magnitudes below 1e100 every operand there is far inside
+// the range, and the results are bit for bit those of a / b and sqrt(x).  The
+// characteristic tracing, whose reconstructed edge values no floor bounds
+// (an edge density or pressure can be zero), uses xdiv / xsqrt instead.
 __device__ __forceinline__ double ddiv(double a, double b) {
   double y = __builtin_amdgcn_rcp(b);
   double e = fma(-b, y, 1.0);
@@ -96,12 +105,15 @@ template <class T> __device__ __forceinline__ T rdiv(T a, T b) { return ddiv(a, 
 template <> __device__ __forceinline__ float rdiv<float>(float a, float b) {
   return a * __builtin_amdgcn_rcpf(b);
 }
-template <class T> __device__ __forceinline__ T rrcp(T a) { return ddiv(1.0, a); }
-template <> __device__ __forceinline__ float rrcp<float>(float a) {
-  return __builtin_amdgcn_rcpf(a);
+// IEEE quotient and square root for every operand (zeros, infinities and the
+// extreme exponents included), for the characteristic tracing; in the float
+// stages of the mixed precision the hardware reciprocal and square root.
+template <class T> __device__ __forceinline__ T xdiv(T a, T b) { return a / b; }
+template <> __device__ __forceinline__ float xdiv<float>(float a, float b) {
+  return a * __builtin_amdgcn_rcpf(b);
 }
-template <class T> __device__ __forceinline__ T rsqrt_exact(T a) { return dsqrt(a); }
-template <> __device__ __forceinline__ float rsqrt_exact<float>(float a) {
+template <class T> __device__ __forceinline__ T xsqrt(T a) { return __builtin_sqrt(a); }
+template <> __device__ __forceinline__ float xsqrt<float>(float a) {
   return __builtin_amdgcn_sqrtf(a);
 }
 
@@ -219,8 +231,11 @@ template <class T> struct State {
 // CW84 characteristic tracing (Eqs. 3.5-3.7) of one cell edge.
 // RightEdge: the left state of the face to the right of the cell, built from
 // the waves moving right (u-c, u, u+c > 0); the reference state is the
-// average over the u+c domain, so the u+c correction vanishes identically.
-// Left edge: the mirror image, with the u-c domain as reference.
+// average over the u+c domain, so the u+c correction vanishes whenever the
+// sound speed of the edge state is positive and finite; it is still formed as
+// the general formula writes it, which gives a NaN, not zero, when the edge
+// density or pressure is zero.  Left edge: the mirror image, with the u-c
+// domain as reference.
 // q: cell-centre u; c: sound speed; lam = dt/dx.
 template <class T, bool RightEdge>
 __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const T (&qrr)[5],
@@ -242,13 +257,18 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
     return RightEdge ? avg_right<T>(qrr[k], dq[k], q6[k], y) : avg_left<T>(ql[k], dq[k], q6[k], y);
   };
   T rt = avg(0, yref), ut = avg(1, yref), pt = avg(4, yref);
-  T C = rsqrt_exact<T>(T(g) * pt * rt);
-  T iC = rrcp<T>(C);
-  // b_fast: correction of the other acoustic wave; b0: entropy wave.  The
-  // reference wave's own correction is exactly zero.
-  T bslow = T(0), b0 = T(0);
+  T C = xsqrt<T>(T(g) * pt * rt);
+  T iC = xdiv<T>(T(1), C);
+  // bref: the reference wave's own correction (its averages are ut, pt);
+  // bslow: the other acoustic wave; b0: the entropy wave
+  T bref = T(0), bslow = T(0), b0 = T(0);
+  const bool ref_on = RightEdge ? (u + c > T(0)) : (u - c < T(0));
   const bool slow_on = RightEdge ? (u - c > T(0)) : (u + c < T(0));
   const bool zero_on = RightEdge ? (u > T(0)) : (u < T(0));
+  if (ref_on) {
+    if (RightEdge) bref = T(-0.5) * iC * ((ut - ut) + (pt - pt) * iC);        // beta-plus
+    else bref = T(0.5) * iC * ((ut - ut) - (pt - pt) * iC);                   // beta-minus
+  }
   if (slow_on) {
     T us = avg(1, yslow), ps = avg(4, yslow);
     if (RightEdge) bslow = T(0.5) * iC * ((ut - us) - (pt - ps) * iC);          // beta-minus
@@ -256,15 +276,14 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
   }
   if (zero_on) {
     T r0 = avg(0, y0), p0 = avg(4, y0);
-    b0 = (pt - p0) * iC * iC + rrcp<T>(rt) - rrcp<T>(r0);
+    b0 = (pt - p0) * iC * iC + xdiv<T>(T(1), rt) - xdiv<T>(T(1), r0);
   }
-  // With the reference wave's beta at zero: bp + bm = bslow, bp - bm = -+bslow.
-  T bp = RightEdge ? T(0) : bslow;
-  T bm = RightEdge ? bslow : T(0);
+  T bp = RightEdge ? bref : bslow;
+  T bm = RightEdge ? bslow : bref;
   T ps = pt + C * C * (bp + bm);
   T us = ut + C * (bp - bm);
-  T tau = rrcp<T>(rt) - (bp + bm + b0);
-  T rs = tau > T(0) ? rrcp<T>(tau) : rt;
+  T tau = xdiv<T>(T(1), rt) - (bp + bm + b0);
+  T rs = tau > T(0) ? xdiv<T>(T(1), tau) : rt;
   s.r = vmax<T>(rs, rho_floor);
   s.u = us;
   s.p = vmax<T>(ps, p_floor);
@@ -462,6 +481,24 @@ __device__ __forceinline__ Flux hll_flux(const Params &P, const double (&sl)[5],
     F.f[6] = um_m / um_r;
   }
   return F;
+}
+
+// Optional diffusive flux of CW84 along the sweep: where the flow converges
+// across the face (u_l > u_r, the two cells' normal velocities at the sweep
+// input), each conserved quantity's flux gains nu (Q_l - Q_r), nu = K (u_l -
+// u_r), Q = rho, rho u, rho v1, rho v2, rho E, rho e; the face velocity of the
+// p div v term is left alone.
+__device__ __forceinline__ void add_diffusion(Flux &F, double rl, double ul, double v1l,
+                                              double v2l, double El, double el, double rr,
+                                              double ur, double v1r, double v2r, double Er,
+                                              double er) {
+  const double du = ul - ur;
+  if (!(du > 0.0)) return;
+  const double nu = kDiffK * du;
+  const double ql[6] = {rl, rl * ul, rl * v1l, rl * v2l, rl * El, rl * el};
+  const double qr[6] = {rr, rr * ur, rr * v1r, rr * v2r, rr * Er, rr * er};
+#pragma unroll
+  for (int k = 0; k < 6; ++k) F.f[k] = F.f[k] + nu * (ql[k] - qr[k]);
 }
 
 // Sweep-input state of a cell as the update needs it.

@@ -207,8 +207,8 @@ __device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis, double *
 // One thread marches one pencil.  kCFL: also take the signal speed of every
 // cell written (the sweep must then be the last of its step).
 // a: the level's expansion factor (1 for the static equations).  kGrav: the
-// build with the gravity source terms (applied where the pencil has an
-// acceleration field).
+// general build, with the gravity source terms (applied where the pencil has
+// an acceleration field) and the optional diffusive flux.
 template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                              double a, double *lds_slots, int slot_stride, uint32_t &n_fallback,
@@ -223,6 +223,16 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   const T tlam = T(lam);
   const bool grav = kGrav && pc.acc != nullptr;
   const double hgdt = 0.5 * dt / a;
+  const bool diffuse = kGrav && (P.flags & kDiffusion) != 0;
+  // the diffusive flux of the face between cells jl and jl+1 (their stored
+  // sweep-input values, still in memory: a cell is written two iterations
+  // after its right face is final)
+  auto diffuse_face = [&](Flux &F, int jl) {
+    const int64_t ol = pc.base + int64_t(jl) * pc.stride, orr = ol + pc.stride;
+    add_diffusion(F, double(pc.rho[ol]), double(pc.u[ol]), double(pc.v1[ol]), double(pc.v2[ol]),
+                  pc.E[ol], pc.e[ol], double(pc.rho[orr]), double(pc.u[orr]),
+                  double(pc.v1[orr]), double(pc.v2[orr]), pc.E[orr], pc.e[orr]);
+  };
   const double gam = P.gamma;
   const bool steepen = (P.flags & kSteepen) != 0;
   const bool flatten = (P.flags & kFlatten) != 0;
@@ -379,6 +389,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
                           double(lcarry.v2), double(lcarry.p), double(rstate.r),
                           double(rstate.u), double(rstate.v1), double(rstate.v2),
                           double(rstate.p));
+      if (diffuse) diffuse_face(ft_c, r - 1);
       if (fallback) {
         slot_c[0 * slot_stride] = double(lcarry.r);
         slot_c[1 * slot_stride] = double(lcarry.u);
@@ -423,6 +434,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
           sr[j] = slot_b[(5 + j) * slot_stride];
         }
         ff_b = hll_flux(P, sl, sr);
+        if (diffuse) diffuse_face(ff_b, fb);
         ++n_fallback;
       }
       if (fb == a0 - 1 && pc.reg_lo) {

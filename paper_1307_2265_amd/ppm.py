@@ -19,6 +19,7 @@ PPM_FP64, PPM_MIXED = 0, 1
 PPM_STEEPEN, PPM_FLATTEN, PPM_DUAL_ENERGY, PPM_FALLBACK_HLL = 1, 2, 4, 8
 PPM_ALL_FLAGS = 15
 PPM_HLLC = 16  # HLLC face fluxes instead of two-shock
+PPM_DIFFUSION = 32  # CW84's diffusive flux where the flow converges
 ORDERS = {"xyz": 0, "zyx": 1, "xzy": 2, "yxz": 3, "yzx": 4, "zxy": 5}
 PPM_GRAPH_FILL, PPM_GRAPH_CFL, PPM_GRAPH_STEP, PPM_GRAPH_STEP_CFL = 1, 2, 4, 8
 PPM_BC_PERIODIC, PPM_BC_SUPPLIED = 0, 1

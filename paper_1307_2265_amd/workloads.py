@@ -82,6 +82,31 @@ def random_grid(nx: int, ny: int, nz: int, seed: int, recipe: FieldRecipe = GENT
     return out
 
 
+def vacuum_pockets(d: dict, seed: int, frac: float = 0.05, speed: float = 100.0,
+                   rho_vac: float = 1e-20, p_vac: float = 1e-20, gamma: float = GAMMA,
+                   ghost: int = GHOST) -> dict:
+    """Turn a seeded fraction of the active cells of d (in place) into
+    near-vacuum cells: density rho_vac, pressure p_vac (the default floors) and
+    normally distributed velocities of standard deviation speed.  Such cells
+    next to dense moving gas drive the reconstructed edge density or pressure
+    to zero."""
+    g = ghost
+    act = (slice(g, -g),) * 3
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shape = d["rho"][act].shape
+    vac = rng.random(shape) < frac
+    prim = {k: np.array(d[k][act]) for k in ("rho", "vx", "vy", "vz", "eint")}
+    p = (gamma - 1.0) * prim["rho"] * prim["eint"]
+    prim["rho"][vac] = rho_vac
+    p[vac] = p_vac
+    for k in ("vx", "vy", "vz"):
+        prim[k][vac] = rng.normal(0.0, speed, int(vac.sum()))
+    st = stored_from_primitive(prim["rho"], prim["vx"], prim["vy"], prim["vz"], p, gamma)
+    for k, a in zip(("rho", "vx", "vy", "vz", "etot", "eint"), st):
+        d[k][act] = a
+    return d
+
+
 def uniform_grid(nx, ny, nz, rho, v, p, gamma=GAMMA, ghost=GHOST) -> dict:
     g = ghost
     full = (nz + 2 * g, ny + 2 * g, nx + 2 * g)

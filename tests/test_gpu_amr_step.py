@@ -60,12 +60,16 @@ def _setup(P, O, spec, ghost, seed, recipe, prec, flags=None):
     return patches, h, H
 
 
-@pytest.mark.parametrize("case", ["nested", "nested-hllc", "abutting"])
+@pytest.mark.parametrize("case", ["nested", "nested-hllc", "nested-shocked", "abutting"])
 def test_w_cycle_equals_oracle_fp64(P, O, case):
-    spec, ghost, recipe = (ABUTTING, 3, W.SHOCKED) if case == "abutting" else (NESTED, 4, W.GENTLE)
+    # nested-shocked: level 1 steps four times per root step, its child once per
+    # level-1 step, and the child's sweeps meet near-vacuum edge states
+    spec, ghost, recipe, seed = {"abutting": (ABUTTING, 3, W.SHOCKED, 600),
+                                 "nested-shocked": (NESTED, 4, W.SHOCKED, 3170)}.get(
+                                     case, (NESTED, 4, W.GENTLE, 600))
     flags = P.PPM_ALL_FLAGS | P.PPM_HLLC if case == "nested-hllc" else None
     print(f"case {case}", flush=True)
-    patches, h, H = _setup(P, O, spec, ghost, 600, recipe, P.PPM_FP64, flags)
+    patches, h, H = _setup(P, O, spec, ghost, seed, recipe, P.PPM_FP64, flags)
     for step in range(2):
         n0 = len(H.dts)
         H.evolve()
