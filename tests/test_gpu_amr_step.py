@@ -148,6 +148,34 @@ def test_shock_pool_w_cycle_equals_oracle(P, O):
     h.close()
 
 
+def test_wave_pool_w_cycle_equals_oracle(P, O):
+    # the paper's wave pool (a short linear sound wave through a static refined
+    # region, outflow root faces): 40 root steps, bit for bit
+    import torch
+    from tests.test_oracle_amr import _wave_pool
+    H, _ = _wave_pool(O, True)
+    patches = []
+    for lev, node in enumerate(H.nodes):
+        g = node.grid
+        d = {f: getattr(g, f).copy() for f in FIELDS}
+        patches.append(to_device(d, P.PPM_FP64, ghost=g.ghost, dx=(g.dx, g.dy, g.dz), level=lev,
+                                 with_reg=lev > 0))
+    h = P.Amr(patches, [(-1, 2, (0, 0, 0)), (0, 2, (50, 2, 2))], 2, P.PPM_FP64,
+              P.params(gamma=1.4), root_kinds=H.root_kinds)
+    for step in range(40):
+        n0 = len(H.dts)
+        H.evolve()
+        h.ppm_amr_step()
+        assert h.ppm_amr_step_log() == H.dts[n0:], step
+    torch.cuda.synchronize()
+    for i, (p, node) in enumerate(zip(patches, H.nodes)):
+        g = from_device(p)
+        for f in FIELDS:
+            assert np.array_equal(g[f], getattr(node.grid, f)), (i, f)
+        assert i == 0 or np.array_equal(p.flux_reg.cpu().numpy(), node.grid.flux_reg), i
+    h.close()
+
+
 def test_w_cycle_with_gravity_and_expansion_equals_oracle(P, O):
     # every patch with an acceleration field, each level its own a and adot
     import torch

@@ -12,6 +12,10 @@ mass of what it averages; the parent state a child's ghosts see is linear in
 time between the parent's states; and a smooth contact advected through a
 refined region is more accurate on the fine patch than on the coarse grid
 alone, with the refined run's coarse cells no worse than the unrefined run's.
+The paper's shock pool and wave pool (Sec. "Shock pool", "Wave pool") pin
+the hierarchy on its own test problems: the shock crosses the refined region
+at the exact speed, and a short linear sound wave enters and leaves it
+without a reflection, at the speed of sound.
 """
 import numpy as np
 import pytest
@@ -249,3 +253,63 @@ def test_shock_pool_keeps_the_shock_on_both_levels(O):
     a = H.nodes[0].grid.rho[g + 1, g + 1, g + 5:g + 70]
     b = U.nodes[0].grid.rho[g + 1, g + 1, g + 5:g + 70]
     assert np.abs(a - b).max() < 0.05 * rho2
+
+
+def _wave_pool(O, refined: bool):
+    """Sec. "Wave pool": gas at rest (rho = p = 1, gamma = 1.4) on x in [0, 1]
+    (100 root cells; 4 cells across, periodic in y and z), a static refined
+    region from x = 0.25 to 0.75 (r = 2; one root cell of margin across),
+    outflow at both x faces.  The paper drives the wave in through the left
+    boundary; here the same right-moving linear sound wave (amplitude
+    A = 0.01, wavelength 0.1, i.e. 10 root cells) starts as a train of two
+    wavelengths on 0.02 <= x < 0.22: rho = 1 + A s, u = c0 A s,
+    p = 1 + gamma A s with s = sin(2 pi (x - 0.02) / 0.1), c0 = sqrt(gamma)."""
+    g, gam, A = 3, 1.4, 0.01
+    c0 = np.sqrt(gam)
+    def wave(nx, dx, x_lo):
+        shape = (4 + 2 * g, 4 + 2 * g, nx + 2 * g)
+        x = x_lo + (np.arange(nx + 2 * g) - g + 0.5) * dx
+        s = np.where((x >= 0.02) & (x < 0.22), np.sin(2 * np.pi * (x - 0.02) / 0.1), 0.0)
+        z = np.zeros(shape)
+        st = W.stored_from_primitive(np.broadcast_to(1 + A * s, shape).copy(),
+                                     np.broadcast_to(c0 * A * s, shape).copy(), z, z.copy(),
+                                     np.broadcast_to(1 + gam * A * s, shape).copy(), gam)
+        return dict(zip(O.FIELDS, [np.ascontiguousarray(a) for a in st]))
+    h = 0.01
+    nodes = [amr.Node(_grid(O, wave(100, h, 0.0), (h, h, h), ghost=g), 0)]
+    if refined:
+        nodes.append(amr.Node(_grid(O, wave(100, h / 2, 0.25), (h / 2,) * 3, ghost=g, reg=True),
+                              1, 0, (50, 2, 2), 2))
+    H = amr.Hierarchy(nodes, [O.params(gamma=gam)] * len(nodes), root_kinds=[2, 2, 0, 0, 0, 0])
+    return H, (A, c0)
+
+
+def test_wave_pool_passes_the_refined_region_cleanly(O):
+    # checked on the root as the paper plots it, before the wave enters
+    # (t = 0.2), once it is wholly inside (0.3) and wholly past the exit (0.64):
+    # the left-moving characteristic field the refined region adds to the
+    # unrefined run's stays below 1 % of the wave (no reflection), the wave is
+    # no more damped than without refinement, and it travels at c0
+    H, (A, c0) = _wave_pool(O, True)
+    U, _ = _wave_pool(O, False)
+    g = 3
+    xs = (np.arange(100) + 0.5) * 0.01
+    def invariants(grid):
+        r = grid.rho[g + 1, g + 1, g:-g]
+        u = grid.vx[g + 1, g + 1, g:-g]
+        p = 0.4 * r * grid.eint[g + 1, g + 1, g:-g]
+        return u + (p - 1) / c0, u - (p - 1) / c0      # right- and left-moving, linearised
+    amp = 2 * c0 * A
+    for t_check in (0.2, 0.3, 0.64):
+        while H.t[0] < t_check - 1e-12:
+            H.evolve()
+        while U.t[0] < t_check - 1e-12:
+            U.evolve()
+        jp, jm = invariants(H.nodes[0].grid)
+        jpu, jmu = invariants(U.nodes[0].grid)
+        behind = ((xs < 0.25) | (xs >= 0.75)) & (xs < 0.02 + c0 * H.t[0] - 0.03)
+        if behind.any():
+            assert np.abs(jm - jmu)[behind].max() < 0.01 * amp, t_check
+        assert np.abs(jp).max() >= np.abs(jpu).max(), t_check
+        centroid = (xs * np.abs(jp)).sum() / np.abs(jp).sum()
+        assert abs(centroid - (0.12 + c0 * H.t[0])) < 0.015, (t_check, centroid)
