@@ -259,6 +259,7 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
   T rt = avg(0, yref), ut = avg(1, yref), pt = avg(4, yref);
   T C = xsqrt<T>(T(g) * pt * rt);
   T iC = xdiv<T>(T(1), C);
+  const T irt = xdiv<T>(T(1), rt);
   // bref: the reference wave's own correction (its averages are ut, pt);
   // bslow: the other acoustic wave; b0: the entropy wave
   T bref = T(0), bslow = T(0), b0 = T(0);
@@ -276,13 +277,13 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
   }
   if (zero_on) {
     T r0 = avg(0, y0), p0 = avg(4, y0);
-    b0 = (pt - p0) * iC * iC + xdiv<T>(T(1), rt) - xdiv<T>(T(1), r0);
+    b0 = (pt - p0) * iC * iC + irt - xdiv<T>(T(1), r0);
   }
   T bp = RightEdge ? bref : bslow;
   T bm = RightEdge ? bslow : bref;
   T ps = pt + C * C * (bp + bm);
   T us = ut + C * (bp - bm);
-  T tau = xdiv<T>(T(1), rt) - (bp + bm + b0);
+  T tau = irt - (bp + bm + b0);
   T rs = tau > T(0) ? xdiv<T>(T(1), tau) : rt;
   s.r = vmax<T>(rs, rho_floor);
   s.u = us;
