@@ -100,7 +100,11 @@ typedef struct {
   int32_t bc;         /* PPM_BC_PERIODIC or PPM_BC_SUPPLIED */
   double dx, dy, dz;  /* cell widths, > 0 */
   void *rho, *vx, *vy, *vz; /* double (PPM_FP64) or float (PPM_MIXED) */
-  double *etot, *eint;      /* double in both precisions */
+  double *etot, *eint;      /* double in both precisions.  Every cell a sweep
+                               reads, ghosts included, must hold a physical
+                               state: finite values, rho >= rho_floor, and
+                               magnitudes below 1e100 (results for other
+                               input are unspecified; none is detected) */
   double *flux_reg;         /* nullable; ppm_flux_reg_size(nx,ny,nz) doubles */
   const void *gx, *gy, *gz; /* nullable (all three or none): gravitational
                                acceleration at the cell centres at the half
