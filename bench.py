@@ -186,6 +186,29 @@ def amr_w_cycle(steps: int = 3, warmup: int = 1) -> dict:
     return out
 
 
+def copy_bandwidth(nbytes: int = 1 << 31, reps: int = 10) -> dict:
+    """Achievable HBM bandwidth beside the published peak: a device-to-device
+    copy of nbytes (read and write counted), timed with events on the current
+    stream."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del src, dst
+    gbs = 2 * nbytes / sec / 1e9
+    return {"bytes_moved": 2 * nbytes, "ms": sec * 1e3, "GB_per_s": gbs,
+            "frac_of_published_peak": gbs / HBM_PEAK_GBS}
+
+
 def measured_traffic(kernel: str):
     """Calibrated HBM bytes per dispatch of `kernel` from the committed
     FETCH_SIZE / WRITE_SIZE summary, or None if the kernel sources changed
@@ -439,6 +462,9 @@ def main():
                frac=0.0, traffic=traffic, kernel=kname, algorithmic_bytes=bytes_launch,
                launch_ms=sw * 1e3)
     hbm["frac"] = hbm["achieved"] / hbm["peak"]
+    copy_bw = copy_bandwidth()
+    log(f"device-to-device copy: {copy_bw['GB_per_s']:.0f} GB/s")
+    hbm["frac_of_copy"] = hbm["achieved"] / copy_bw["GB_per_s"]
     alu = dict(bound="alu", achieved=flops_launch / sw / 1e12, peak=FP64_OP_PEAK_T,
                unit="TFLOP/s", frac=0.0, traffic=traffic, kernel=kname,
                algorithmic_flops=flops_launch, launch_ms=sw * 1e3,
@@ -490,6 +516,7 @@ def main():
         "roofline_other": other,
         "sweep_kernel_ms": {k: v * 1e3 for k, v in kern.items()},
         "events": {"fallback_faces": fp["fallback_faces"], "floored_cells": fp["floored_cells"]},
+        "hbm_copy": copy_bw,
     }
     if "mixed" in results:
         mx = results["mixed"]
