@@ -5,6 +5,9 @@ kernels  -- from a `rocprofv3 --kernel-trace --stats --output-format csv`
             number of dispatches and their mean / total duration.
 sq       -- from one `rocprofv3 --pmc` run of SQ counters: issue and wait
             fractions and VALU instructions per wave of the sweep kernels.
+valu     -- from two `rocprofv3 --pmc` runs: the VALU instruction mix by type
+            (FP64 / FP32 add, mul, fma, transcendental) with the FLOP rate it
+            gives, and LDS instructions with their bank-conflict cycles.
 traffic  -- from two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs:
             HBM bytes per dispatch of every kernel, each counter scaled by
             what it reads for a device-to-device copy of known size that the
@@ -214,6 +217,68 @@ def sq(counters_csv: str, cmd: str, out: str):
         f.write("\n".join(lines) + "\n")
 
 
+def valu(flops_csv: str, lds_csv: str, cmd_flops: str, cmd_lds: str, out: str):
+    """Per dispatch group of the sweep kernels: FP64 and FP32 VALU
+    instructions by type (SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F{64,32}) and the
+    FLOP rate they give, 64 lanes x (ADD + MUL + 2 FMA + TRANS) per
+    instruction over the dispatch's own duration (an upper bound on the
+    lane-level rate: the counters do not see the execution mask), against the
+    published vector peaks; LDS instructions and bank-conflict cycles."""
+    def load(path):
+        agg = collections.defaultdict(lambda: collections.defaultdict(float))
+        disp = collections.defaultdict(dict)
+        for r in csv.DictReader(open(path)):
+            k = (short(r["Kernel_Name"]), int(r["Grid_Size"]), int(r["Workgroup_Size"]))
+            agg[k][r["Counter_Name"]] += float(r["Counter_Value"])
+            disp[k][r["Dispatch_Id"]] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        return agg, disp
+    fa, fd = load(flops_csv)
+    la, ld = load(lds_csv)
+    lines = [f"# VALU mix, FLOP rate and LDS conflicts: {os.path.basename(out)[:-3]}", "",
+             "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
+             "```", cmd_flops, cmd_lds, "```", "",
+             "FP64 (FP32) FLOP per dispatch = 64 x (ADD + MUL + 2 FMA + TRANS) over the "
+             "SQ_INSTS_VALU_*_F64 (_F32) counters, an upper bound on the lane-level count (the "
+             "counters count wave instructions whatever the execution mask); rate over the mean "
+             "duration of the same dispatches in the counter run; peaks: FP64 vector 78.6 TFLOP/s, "
+             "FP32 vector 157.3 TFLOP/s (an FMA counted as two).  The hot path compiles with "
+             "-ffp-contract=off, so it issues separate adds and multiplies, and its FMAs are the "
+             "Newton and remainder steps of divisions and square roots.", "",
+             "| kernel | grid threads | dispatches | mean ms | F64 add / mul / fma / trans (M instr) "
+             "| FP64 TFLOP/s (frac) | F32 add / mul / fma / trans (M instr) | FP32 TFLOP/s (frac) |",
+             "|---|---:|---:|---:|---|---:|---|---:|"]
+    for k, c in sorted(fa.items()):
+        if "sweep" not in k[0] and "persistent" not in k[0]:
+            continue
+        nd = len(fd[k])
+        ms = sum(fd[k].values()) / nd / 1e6
+        def mix(t):
+            v = [c[f"SQ_INSTS_VALU_{op}_{t}"] / nd / 1e6 for op in ("ADD", "MUL", "FMA", "TRANS")]
+            flop = 64e6 * (v[0] + v[1] + 2 * v[2] + v[3])
+            return v, flop / (ms / 1e3) / 1e12
+        v64, r64 = mix("F64")
+        v32, r32 = mix("F32")
+        lines.append(f"| `{k[0]}` | {k[1]} | {nd} | {ms:.3f} | "
+                     + " / ".join(f"{x:.1f}" for x in v64) + f" | {r64:.2f} ({r64 / 78.6:.3f}) | "
+                     + " / ".join(f"{x:.1f}" for x in v32) + f" | {r32:.2f} ({r32 / 157.3:.3f}) |")
+    lines += ["", "LDS: instructions per dispatch, cycles issuing LDS and bank-conflict cycles "
+              "(SQ_INSTS_LDS, SQ_ACTIVE_INST_LDS, SQ_LDS_BANK_CONFLICT), and the conflict cycles "
+              "as a fraction of the LDS issue cycles.", "",
+              "| kernel | grid threads | dispatches | LDS instr (M) | LDS issue cycles (M) | "
+              "bank-conflict cycles (M) | conflict / issue |",
+              "|---|---:|---:|---:|---:|---:|---:|"]
+    for k, c in sorted(la.items()):
+        if "sweep" not in k[0] and "persistent" not in k[0]:
+            continue
+        nd = len(ld[k])
+        act = c["SQ_ACTIVE_INST_LDS"] / nd / 1e6
+        bc = c["SQ_LDS_BANK_CONFLICT"] / nd / 1e6
+        lines.append(f"| `{k[0]}` | {k[1]} | {nd} | {c['SQ_INSTS_LDS'] / nd / 1e6:.2f} | "
+                     f"{act:.2f} | {bc:.3f} | {bc / act if act else 0.0:.3f} |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -235,11 +300,19 @@ def main():
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out", required=True)
     t.add_argument("--json", default=None)
+    v = sub.add_parser("valu")
+    v.add_argument("flops")
+    v.add_argument("lds")
+    v.add_argument("--cmd-flops", required=True)
+    v.add_argument("--cmd-lds", required=True)
+    v.add_argument("--out", required=True)
     a = ap.parse_args()
     if a.mode == "sq":
         sq(a.counters, a.cmd, a.out)
     elif a.mode == "kernels":
         kernels(a.stats, a.trace, a.cmd, a.out)
+    elif a.mode == "valu":
+        valu(a.flops, a.lds, a.cmd_flops, a.cmd_lds, a.out)
     else:
         traffic(a.fetch, a.write, a.n, a.ghost, a.cmd_fetch, a.cmd_write, a.out, a.json)
 
