@@ -98,8 +98,23 @@ def cpu_baseline(d, n, planes, steps):
         el += time.perf_counter() - t0
     cells = n * n * planes * steps
     what = f"the full {n}^3 grid" if planes == n else f"a {n}x{n}x{planes} periodic slab of the grid"
-    return dict(value=cells / el, unit="cell-updates/s", cores=O.num_threads(), kind="oracle",
-                sample=f"{steps} steps of {what} (same seeded input), FP64, sweeps {el:.1f}s wall")
+    cores = O.num_threads()
+    # one host thread, on a 16-plane periodic slab of the same grid, one step
+    # (its ghost planes add 3/8 to the z-extent of the x and y sweeps)
+    O.set_num_threads(1)
+    sub1 = {f: np.array(a[:16 + 2 * g], dtype=np.float64, copy=True) for f, a in d.items()}
+    G1 = O.Grid(**sub1, dx=1.0 / n, dy=1.0 / n, dz=1.0 / n)
+    O.fill_periodic(G1)
+    dt1 = O.cfl_dt(G1, prm)
+    t0 = time.perf_counter()
+    O.step(G1, prm, dt1, 0)
+    el1 = time.perf_counter() - t0
+    O.set_num_threads(cores)
+    single = dict(value=n * n * 16 / el1, unit="cell-updates/s", cores=1,
+                  sample=f"1 step of a {n}x{n}x16 periodic slab of the grid, FP64, {el1:.1f}s wall")
+    return dict(value=cells / el, unit="cell-updates/s", cores=cores, kind="oracle",
+                sample=f"{steps} steps of {what} (same seeded input), FP64, sweeps {el:.1f}s wall",
+                single_thread=single)
 
 
 def amr_ghost_fill(reps: int = 5) -> dict:

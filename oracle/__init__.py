@@ -126,6 +126,7 @@ def lib():
         L.ppmo_count_ops.argtypes = [C.POINTER(_Grid), C.POINTER(Params), C.c_double, C.c_int32,
                                      C.POINTER(C.c_int64)]
         L.ppmo_num_threads.restype = C.c_int
+        L.ppmo_set_num_threads.argtypes = [C.c_int32]
         _lib = L
     return _lib
 
@@ -361,3 +362,8 @@ def count_ops(grid: Grid, prm: Params, dt: float, order: int | str = 0) -> dict:
 
 def num_threads() -> int:
     return int(lib().ppmo_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Host threads of later calls (results do not depend on it)."""
+    lib().ppmo_set_num_threads(int(n))

@@ -1354,4 +1354,12 @@ int ppmo_num_threads(void) {
 #endif
 }
 
+void ppmo_set_num_threads(int32_t n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 }  // extern "C"

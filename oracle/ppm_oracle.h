@@ -258,6 +258,9 @@ int ppmo_count_ops(ppmo_grid *g, const ppmo_params *p, double dt, int32_t sweep_
 
 /* Threads the OpenMP runtime will use (1 without OpenMP). */
 int ppmo_num_threads(void);
+/* Host threads of the following calls (OpenMP over independent pencils;
+   the results do not depend on it).  n < 1 is ignored. */
+void ppmo_set_num_threads(int32_t n);
 
 #ifdef __cplusplus
 }
