@@ -49,6 +49,9 @@ def _patch(**kw):
     ({}, dict(gamma=1.0), "gamma"),
     ({}, dict(cfl=1.5), "cfl"),
     ({}, dict(riemann_max_iter=0), "riemann_max_iter"),
+    ({}, dict(rho_floor=1e-120), "floor"),    # below the fast division's range bound
+    ({}, dict(p_floor=0.0), "floor"),
+    ({}, dict(e_floor=0.0), "floor"),
     ({}, dict(flags=99), "flag"),
     ({}, dict(flags=0x80000000), "flag"),     # library-internal bit
     (dict(gx=1, gy=1), {}, "acceleration"),   # gz missing
