@@ -499,6 +499,18 @@ def main():
             kernel=("sweep_kernel<PrecF64, false, false, true, false> + "
                     "sweep_tail_kernel<PrecF64, false, true, false>"),
             algorithmic_flops=fl_h, launch_ms=sw_h * 1e3, ops_per_cell_sweep=hops)
+    if (diffusion is not None and "fp64" in diffusion
+            and "march" in diffusion["fp64"]["sweep_kernel_ms"]):
+        # the same marching sweeps in the general build with the diffusive flux
+        dops = all_ops["shocked_diffusion"]["per_cell_sweep"]["flops"]
+        sw_d = diffusion["fp64"]["sweep_kernel_ms"]["march"] / 1e3
+        fl_d = mean_pencils * n * dops
+        diffusion["fp64"]["roofline"] = dict(
+            bound="alu", achieved=fl_d / sw_d / 1e12, peak=FP64_OP_PEAK_T, unit="TFLOP/s",
+            frac=fl_d / sw_d / 1e12 / FP64_OP_PEAK_T,
+            kernel=("sweep_kernel<PrecF64, false, false, true, true> + "
+                    "sweep_tail_kernel<PrecF64, false, true, true>"),
+            algorithmic_flops=fl_d, launch_ms=sw_d * 1e3, ops_per_cell_sweep=dops)
 
     cpu = None
     if not args.no_cpu_baseline:

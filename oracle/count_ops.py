@@ -40,10 +40,11 @@ def main():
     res = {
         "note": "FP64 operations per cell-sweep of one step, from the oracle's counting "
                 "scalar; flops = add + mul + div + sqrt; shocked_hllc: the HLLC solver in "
-                "place of two-shock",
+                "place of two-shock; shocked_diffusion: with the diffusive flux",
         "gentle": count(W.GENTLE, 48, 1000),
         "shocked": count(W.SHOCKED, 48, 1002),
         "shocked_hllc": count(W.SHOCKED, 48, 1002, O.ALL_FLAGS | O.HLLC),
+        "shocked_diffusion": count(W.SHOCKED, 48, 1002, O.ALL_FLAGS | O.DIFFUSION),
     }
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     with open(OUT, "w") as f:
