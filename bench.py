@@ -511,6 +511,19 @@ def main():
             kernel=("sweep_kernel<PrecF64, false, false, true, true> + "
                     "sweep_tail_kernel<PrecF64, false, true, true>"),
             algorithmic_flops=fl_d, launch_ms=sw_d * 1e3, ops_per_cell_sweep=dops)
+    if (sources is not None and "fp64" in sources
+            and "march" in sources["fp64"]["sweep_kernel_ms"]):
+        # the same marching sweeps in the general build with the gravity source
+        # terms and the expansion factor (the expansion pass is priced on HBM)
+        gops = all_ops["shocked_gravity_comoving"]["per_cell_sweep"]["flops"]
+        sw_g = sources["fp64"]["sweep_kernel_ms"]["march"] / 1e3
+        fl_g = mean_pencils * n * gops
+        sources["fp64"]["roofline"] = dict(
+            bound="alu", achieved=fl_g / sw_g / 1e12, peak=FP64_OP_PEAK_T, unit="TFLOP/s",
+            frac=fl_g / sw_g / 1e12 / FP64_OP_PEAK_T,
+            kernel=("sweep_kernel<PrecF64, false, false, true, true> + "
+                    "sweep_tail_kernel<PrecF64, false, true, true>"),
+            algorithmic_flops=fl_g, launch_ms=sw_g * 1e3, ops_per_cell_sweep=gops)
 
     cpu = None
     if not args.no_cpu_baseline:
