@@ -63,7 +63,7 @@ typedef enum {
   PPM_EINVAL = -1,      /* invalid argument; nothing was launched */
   PPM_ENOMEM = -2,      /* device or host allocation failed (plan creation only) */
   PPM_EHIP = -3,        /* a HIP runtime call failed */
-  PPM_EUNSUPPORTED = -4 /* valid request this build does not support */
+  PPM_EUNSUPPORTED = -4 /* a valid request the library does not support */
 } ppm_status;
 
 typedef enum { PPM_FP64 = 0, PPM_MIXED = 1 } ppm_precision;

@@ -225,10 +225,11 @@ def l1_per_field(a: Run, b: Run) -> dict:
     return out
 
 
-def single_grid_input(n: int, config: int = 2) -> dict:
-    """The seeded single-grid input of a named config, with rho and v rounded
-    to float32 so that both precisions start from the same stored values."""
-    cfg = W.CONFIGS[config]
+def single_grid_input(n: int, workload: str = "shocked512") -> dict:
+    """The seeded single-grid input of a named workload (its recipe and seed
+    at n^3 cells), with rho and v rounded to float32 so that both precisions
+    start from the same stored values."""
+    cfg = W.WORKLOADS[workload]
     d = W.random_grid(n, n, n, cfg["seed"], cfg["recipe"])
     for f in ("rho", "vx", "vy", "vz"):
         d[f] = d[f].astype(np.float32).astype(np.float64)

@@ -179,10 +179,10 @@ def acceleration_field(shape, seed: int, amp: float = 1.0, modes: int = 4, devic
 # ---------------------------------------------------------------------------
 # Named workloads.
 
-CONFIGS = {
-    0: dict(n=32, recipe=GENTLE, seed=1000, steps=1),
-    1: dict(n=256, recipe=GENTLE, seed=1001, steps=10),
-    2: dict(n=512, recipe=SHOCKED, seed=1002, steps=20),
+WORKLOADS = {
+    "gentle32": dict(n=32, recipe=GENTLE, seed=1000, steps=1),
+    "gentle256": dict(n=256, recipe=GENTLE, seed=1001, steps=10),
+    "shocked512": dict(n=512, recipe=SHOCKED, seed=1002, steps=20),
 }
 
 

@@ -26,8 +26,8 @@ def _announce(request):
     line = f"[start] {request.node.nodeid}\n"
     sys.stderr.write(line)
     sys.stderr.flush()
-    out = os.path.join(ROOT, "gpurun_out")
-    if os.path.isdir(out):
-        with open(os.path.join(out, "test_progress.log"), "a") as f:
+    out = os.environ.get("PPM_TEST_PROGRESS")   # optional file that mirrors these lines
+    if out:
+        with open(out, "a") as f:
             f.write(line)
     yield

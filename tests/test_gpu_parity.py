@@ -256,7 +256,7 @@ def test_full_size_512_step_in_bench_configuration(P, O):
     import torch
     from paper_1307_2265_amd import autotune
     n = 512
-    cfg = W.CONFIGS[2]
+    cfg = W.WORKLOADS["shocked512"]
     print("generating 512^3 input", flush=True)
     d = stored_inputs(W.random_grid(n, n, n, cfg["seed"], cfg["recipe"]), P.PPM_MIXED)
     print("oracle step", flush=True)
@@ -304,7 +304,7 @@ def test_config1_256_ten_steps_fp64(P, O):
     # device CFL dt each step, in the single-grid launch configuration of the
     # benchmark, against ten oracle steps with the oracle's own dt.
     from paper_1307_2265_amd import autotune
-    cfg = W.CONFIGS[1]
+    cfg = W.WORKLOADS["gentle256"]
     n = cfg["n"]
     print("generating 256^3 input", flush=True)
     d = W.random_grid(n, n, n, cfg["seed"], cfg["recipe"])

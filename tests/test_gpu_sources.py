@@ -315,7 +315,7 @@ def test_full_size_512_step_with_sources_in_bench_configuration(P, O):
     import torch
     from paper_1307_2265_amd import autotune
     n = 512
-    cfg = W.CONFIGS[2]
+    cfg = W.WORKLOADS["shocked512"]
     print("generating 512^3 input", flush=True)
     d = stored_inputs(W.random_grid(n, n, n, cfg["seed"], cfg["recipe"]), P.PPM_FP64)
     acc = W.acceleration_field(d["rho"].shape, 4242, 3.0)
