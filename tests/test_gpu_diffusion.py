@@ -5,7 +5,9 @@ flux of the sweep input (Sec. "Hydrodynamics: The PPM method", after CW84),
 on the Riemann flux and on the HLL fallback flux, in every sweep kernel, in
 the capture of coarse fluxes for flux correction, and in both solvers.  FP64
 must agree with the oracle bit for bit (fields, timesteps, registers, event
-counts); mixed precision by relative L1.
+counts); mixed precision by relative L1.  Captured graphs of the HLLC and
+diffusion builds replay exactly what the same steps give when launched
+eagerly.
 """
 import numpy as np
 import pytest
@@ -144,3 +146,44 @@ def test_mixed_precision_l1(P, O):
         l1 = np.abs(g[f][act] - ref).sum() / np.abs(ref).sum()
         print(f"mixed with diffusion {f}: relative L1 {l1:.2e}")
         assert l1 <= 1e-5, f
+
+
+@pytest.mark.parametrize("extra", ["diffusion", "hllc", "hllc+diffusion"])
+def test_graph_replays_equal_eager_steps(P, extra):
+    # one captured graph per sweep order (fill + step with the next dt),
+    # replayed with eager work between the replays, against the same steps
+    # launched eagerly: fields and timesteps identical after every step
+    import torch
+    flags = P.PPM_ALL_FLAGS
+    if "diffusion" in extra:
+        flags |= P.PPM_DIFFUSION
+    if "hllc" in extra:
+        flags |= P.PPM_HLLC
+    print(f"graph {extra}", flush=True)
+    d = W.random_grid(40, 24, 16, 3210, W.SHOCKED)
+    A, B = to_device(d, P.PPM_FP64), to_device(d, P.PPM_FP64)
+    pa = P.Plan([A], 1, P.PPM_FP64, P.params(flags=flags))
+    pb = P.Plan([B], 1, P.PPM_FP64, P.params(flags=flags))
+    dta = torch.zeros(1, dtype=torch.float64, device="cuda")
+    dtb = torch.zeros(1, dtype=torch.float64, device="cuda")
+    graphs = [P.Graph(pb, dtb, order, P.PPM_GRAPH_FILL | P.PPM_GRAPH_STEP_CFL)
+              for order in (0, 1)]
+    pa.ppm_fill_periodic()
+    pa.ppm_cfl_dt(dta)
+    pb.ppm_fill_periodic()
+    pb.ppm_cfl_dt(dtb)
+    for s in range(4):
+        pa.ppm_fill_periodic()
+        pa.ppm_step_cfl(dta, s % 2)
+        graphs[s % 2].ppm_graph_launch()
+        torch.cuda.synchronize()
+        junk = torch.ones(1000, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(dta, dtb), s
+        for f in FIELDS:
+            assert torch.equal(getattr(A, f), getattr(B, f)), (s, f)
+    del junk
+    for g in graphs:
+        g.close()
+    pa.close()
+    pb.close()
