@@ -299,8 +299,9 @@ ppm_status build_lists(ppm_amr *h) {
     d.eint = static_cast<double *>(h->blend_bufs[size_t(p) * 6 + 5]);
   }
   if ((e = upload(&h->d_blend, blend_tab)) != hipSuccess) return hip_fail(e, "blend table");
-  // per level, the blends of its parents: storage-type fields and double
-  // fields (prefix arrays with one extra entry per level)
+  // per level, the blends of its parents: the float fields of the mixed
+  // precision, and the double fields (all six in FP64, so one launch blends
+  // them) (prefix arrays with one extra entry per level)
   {
     std::vector<ppm::BlendItem> bs, bd;
     std::vector<int64_t> ps, pd;
@@ -320,7 +321,7 @@ ppm_status build_lists(ppm_amr *h) {
         for (int f = 0; f < 6; ++f) {
           const ppm::BlendItem it{h->old_bufs[size_t(p) * 6 + f], cur[f],
                                   h->blend_bufs[size_t(p) * 6 + f]};
-          if (f < 4) {
+          if (f < 4 && h->prec == PPM_MIXED) {
             bs.push_back(it);
             ps.push_back(rs);
             rs += n;
