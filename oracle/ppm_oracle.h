@@ -22,7 +22,12 @@
  * symmetry, 1-D embedded in 3-D, flux-register identity, the CFL definition,
  * the steepening and flattening thresholds, the dual-energy selection rules
  * (eta1 cold flow, eta2 neighbourhood maximum), the flux of a flattened shock
- * face, and the HLL fallback on a vacuum-forming rarefaction.  The HLLC
+ * face, and the HLL fallback on a vacuum-forming rarefaction.  The HLL flux
+ * inside the wave fan equals the flux the exact solution's average over the
+ * fan implies (integral conservation over the space-time box of the outer
+ * wave speeds), face velocity included; a cell still non-positive after the
+ * fallback is floored with its old velocity (density floor) or keeps the
+ * momentum of its update (pressure floor), at the floor pressure.  The HLLC
  * solver (flag PPMO_HLLC, in place of two-shock) is pinned by the
  * Rankine-Hugoniot conditions across its outer waves and contact, exact
  * isolated contacts (stationary and moving), consistency, supersonic
@@ -43,9 +48,8 @@
  * Parity unpinned (pinned only by these readings and by GPU == oracle):
  *   - the CW84 flattening slope omega_2 = 10 (f~ rises from 0 at a pressure
  *     ratio of omega_1 = 0.75 to 1 at 0.85; only the end points are pinned);
- *   - the HLL fallback's details: Davis wave-speed estimates, the face
- *     velocity of the HLL intermediate state in the p div v term, and the
- *     state given to a cell still non-positive after the fallback;
+ *   - the HLL fallback's choice of the Davis wave-speed estimates (the pin
+ *     of its flux takes them as given);
  *   - the Newton tolerance and iteration cap of the two-shock solver;
  *   - HLLC's outer wave speeds (the Davis estimates of the HLL fallback; the
  *     paper names none) and the internal energy carried with the density
