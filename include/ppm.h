@@ -13,18 +13,25 @@
  * update (Eq. gasenergy_diff) and the eta2 resync (Eq. dualselect), the
  * boundary fluxes that flux correction needs (Sec. "Flux correction"), and
  * the hydro CFL timestep (Sec. "Timestepping", harmonic multi-D form).
- * Cosmological expansion and gravity source terms are not included (a = 1,
- * g = 0).
+ * Optionally, the gravity source terms of Eqs. momentum_diff and energy_diff
+ * from a caller-supplied acceleration field (ppm_patch gx, gy, gz) and the
+ * comoving-coordinate terms of Sec. "Physical Equations" from per-level
+ * expansion factors (ppm_set_expansion, ppm_expansion); without them the
+ * static equations (a = 1, g = 0) are solved.
  *
  * Data layout.  Every patch holds nx*ny*nz active cells surrounded by `ghost`
  * ghost layers (Sec. "Adaptive mesh refinement": 3 for PPM).  Each field is a
  * separate device array of (nz+2g)*(ny+2g)*(nx+2g) elements, x fastest.
  * Fields: rho (density), vx, vy, vz (velocity), etot (specific total energy
  * E = e + |v|^2/2), eint (specific internal energy e, the dual-energy field).
- * PPM_FP64 stores all six as double.  PPM_MIXED stores rho, vx, vy, vz as
- * float and etot, eint as double; it reconstructs and traces in float and
- * keeps the Riemann iteration, the energy updates and the dual-energy
- * selection in double.
+ * PPM_FP64 stores all six as double and computes in double.  PPM_MIXED
+ * stores rho, vx, vy, vz as float and etot, eint as double.  It reconstructs,
+ * traces, samples the Riemann solution and forms the mass, momentum and
+ * internal-energy fluxes and the rho and v updates in float; it keeps the
+ * two-shock Newton iteration for p*, the total-energy flux, the total and
+ * internal energy accumulation (and their division by the new density), the
+ * dual-energy selection (eta1, eta2), the HLL fallback, the flux registers
+ * and the CFL timestep in double.
  *
  * Flux registers (optional, per patch, device, double): dt * F at the six
  * faces of the active region, laid out
@@ -119,9 +126,17 @@ typedef struct {
   double gamma;            /* ratio of specific heats, > 1 */
   double cfl;              /* kappa_hydro, 0 < cfl <= 1 */
   double eta1, eta2;       /* dual-energy thresholds (paper: 1e-3, 0.1) */
-  double rho_floor, p_floor, e_floor; /* floors: rho_floor, p_floor >= 1e-100 (they bound
-                                          the operands of the fast FP64 division and square
-                                          root), e_floor > 0; PPM_EINVAL otherwise */
+  double rho_floor, p_floor, e_floor; /* floors (Sec. "Riemann Solvers and Fallback": a
+                                          cell still non-positive after the HLL re-solve is
+                                          raised to them): rho_floor, p_floor >= 1e-100
+                                          (they bound the operands of the fast FP64
+                                          division and square root), e_floor > 0.
+                                          PPM_MIXED stores the density in float, so its
+                                          rho_floor and p_floor must also be normal floats
+                                          (>= FLT_MIN = 1.1754944e-38, <= FLT_MAX), and the
+                                          plan raises each to the nearest float at or above
+                                          it, the floor that a stored density can hold
+                                          exactly.  PPM_EINVAL otherwise */
   double riemann_rtol;     /* relative tolerance on the two-shock p*, > 0 */
   int32_t riemann_max_iter;/* Newton iteration cap, >= 1 */
   uint32_t flags;          /* PPM_STEEPEN | PPM_FLATTEN | ... */
@@ -132,7 +147,10 @@ typedef struct ppm_plan ppm_plan;
 /* Number of doubles in one patch's flux register. */
 int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
 
-/* Create a plan over `npatch` patches (host array, copied).  nlevels is the
+/* Create a plan over `npatch` patches (host array, copied): each patch is an
+ * independent problem with Dirichlet ghost data and every patch of a level
+ * shares that level's timestep (Secs. "Adaptive Mesh Refinement" and
+ * "Timestepping").  nlevels is the
  * length of every dt array later passed in.  tile_config (nullable) is a
  * text of "key=value" pairs separated by spaces that overrides the launch
  * shapes; unknown keys are an error.  Keys:
@@ -177,7 +195,8 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
  * enqueued work still uses it).  NULL is accepted. */
 ppm_status ppm_plan_destroy(ppm_plan *plan);
 
-/* Periodic ghost fill of every PPM_BC_PERIODIC patch of the plan (each is
+/* Periodic ghost fill (Sec. "Boundary conditions", the periodic kind) of
+ * every PPM_BC_PERIODIC patch of the plan (each is
  * treated as a periodic box of its own): ghost cell i takes the value of the
  * active cell g + ((i - g) mod N) along every axis.  PPM_BC_SUPPLIED patches
  * are not touched. */
@@ -317,7 +336,9 @@ ppm_status ppm_expansion(ppm_plan *plan, const double *dt_dev, void *hip_stream)
 ppm_status ppm_cfl_dt(ppm_plan *plan, double *dt_dev, void *hip_stream);
 
 /* One full step of every patch with its level's dt (device array of nlevels
- * doubles): three 1-D sweeps in the order sweep_order (0:xyz 1:zyx 2:xzy
+ * doubles): three 1-D PPM sweeps (Sec. "Hydrodynamics: The PPM method",
+ * dimensionally split; Sec. "Solving the hydrodynamic equations on a grid"
+ * for the one ghost fill per step) in the order sweep_order (0:xyz 1:zyx 2:xzy
  * 3:yxz 4:yzx 5:zxy).  The k-th sweep updates the cells that are active along
  * the axes swept so far and along its own axis, and every index (ghosts
  * included) along the axes still to come, so one ghost fill per step
@@ -349,8 +370,9 @@ ppm_status ppm_sweep_cfl(ppm_plan *plan, const double *dt_dev, int32_t axis,
                          int32_t active_mask, void *hip_stream);
 ppm_status ppm_cfl_finalize(ppm_plan *plan, double *dt_dev, void *hip_stream);
 
-/* Read (synchronising `hip_stream`) and optionally reset the plan's event
- * counters: faces re-solved with HLL, cells floored after the fallback. */
+/* Read (synchronising `hip_stream`) and optionally reset (reset != 0) the
+ * plan's event counters of the positivity fallback (Sec. "Riemann Solvers and
+ * Fallback"): faces re-solved with HLL, cells floored after the fallback. */
 ppm_status ppm_event_counts(ppm_plan *plan, int64_t *fallback_faces, int64_t *floored_cells,
                             int32_t reset, void *hip_stream);
 
@@ -368,6 +390,20 @@ ppm_status ppm_graph_create(ppm_graph **out, ppm_plan *plan, double *dt_dev,
                             int32_t sweep_order, uint32_t parts, void *hip_stream);
 ppm_status ppm_graph_launch(ppm_graph *graph, void *hip_stream);
 ppm_status ppm_graph_destroy(ppm_graph *graph); /* NULL is accepted */
+
+/* The correctly rounded FP64 division and square root that the sweeps use
+ * wherever their operands are bounded (the equation of state, the Riemann
+ * solvers, the update), exposed so that a caller can check them against host
+ * IEEE arithmetic: quot_dev[i] = a_dev[i] / b_dev[i] and root_dev[i] =
+ * sqrt(a_dev[i]) for i < n, device arrays of n doubles (caller-owned), on
+ * `hip_stream`.  Valid, i.e. equal to IEEE round-to-nearest, for finite
+ * a, b with |a|, |b| and |a / b| in [1e-250, 1e250] and a > 0 for the root:
+ * the range the floors (>= 1e-100) and state magnitudes (< 1e100) of
+ * ppm_patch keep every operand in.  Outside it the results are unspecified
+ * (no operand scaling, no special values).  PPM_EINVAL for n < 0 or NULL
+ * arrays. */
+ppm_status ppm_fp64_ops(const double *a_dev, const double *b_dev, double *quot_dev,
+                        double *root_dev, int64_t n, void *hip_stream);
 
 const char *ppm_status_str(ppm_status s);
 const char *ppm_last_error(void);

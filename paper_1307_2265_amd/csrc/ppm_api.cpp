@@ -6,6 +6,7 @@
 // flat grid.  Argument validation happens here, before anything is enqueued.
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -56,6 +57,13 @@ inline int t1_of(int axis) { return axis == 0 ? 1 : 0; }
 inline int t2_of(int axis) { return axis == 2 ? 1 : 2; }
 inline int tmask_of(int axis, int mask) {
   return ((mask >> t1_of(axis)) & 1) | (((mask >> t2_of(axis)) & 1) << 1);
+}
+
+// The smallest float not below x (x a positive double in the float range).
+double float_at_or_above(double x) {
+  float f = float(x);
+  if (double(f) < x) f = std::nextafter(f, FLT_MAX);
+  return double(f);
 }
 
 ppm_status check_params(const ppm_params *p) {
@@ -203,6 +211,16 @@ hipError_t sweep_any(ppm_plan *pl, const double *dt, int axis, int mask, unsigne
 
 extern "C" {
 
+ppm_status ppm_fp64_ops(const double *a_dev, const double *b_dev, double *quot_dev,
+                        double *root_dev, int64_t n, void *hip_stream) {
+  if (n < 0 || n > (int64_t(1) << 36)) return fail(PPM_EINVAL, "n must be in [0, 2^36]");
+  if (n > 0 && (!a_dev || !b_dev || !quot_dev || !root_dev))
+    return fail(PPM_EINVAL, "NULL array");
+  const hipError_t e = ppm::launch_fp64_ops(a_dev, b_dev, quot_dev, root_dev, n,
+                                            static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? PPM_OK : hip_fail(e, "ppm_fp64_ops");
+}
+
 int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz) {
   return 12 * (int64_t(ny) * nz + int64_t(nx) * nz + int64_t(nx) * ny);
 }
@@ -218,6 +236,13 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   if (prec != PPM_FP64 && prec != PPM_MIXED) return fail(PPM_EINVAL, "unknown precision %d", int(prec));
   ppm_status st = check_params(params);
   if (st != PPM_OK) return st;
+  // PPM_MIXED stores the density in float: a floor must be a normal float
+  if (prec == PPM_MIXED &&
+      (!(params->rho_floor >= double(FLT_MIN)) || !(params->rho_floor <= double(FLT_MAX)) ||
+       !(params->p_floor >= double(FLT_MIN)) || !(params->p_floor <= double(FLT_MAX))))
+    return fail(PPM_EINVAL,
+                "PPM_MIXED: rho_floor and p_floor must lie in the normal float range [%g, %g]",
+                double(FLT_MIN), double(FLT_MAX));
   for (int i = 0; i < npatch; ++i)
     if ((st = check_patch(patches[i], i, nlevels)) != PPM_OK) return st;
 
@@ -229,6 +254,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   std::memcpy(&pl->P, params, sizeof(ppm_params));
   static_assert(offsetof(ppm::Params, expand) == sizeof(ppm_params), "params layout");
   pl->P.expand = nullptr;
+  if (prec == PPM_MIXED) {  // floors a float density and pressure can hold exactly
+    pl->P.rho_floor = float_at_or_above(params->rho_floor);
+    pl->P.p_floor = float_at_or_above(params->p_floor);
+  }
   int64_t max_cells = 0;
   for (int i = 0; i < npatch; ++i)
     max_cells = std::max(max_cells, int64_t(patches[i].nx) * patches[i].ny * patches[i].nz);

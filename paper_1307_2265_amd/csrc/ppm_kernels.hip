@@ -762,11 +762,11 @@ capture_kernel(const PatchDev *__restrict__ patches, const CaptureRow *__restric
   }
   uint32_t nfb = 0, nfl = 0;
   CflAcc cfl = cfl_acc(pd, axis, nullptr);
-  const Flux F = sweep_segment<Prec, false, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, false, cur,
+  const auto F = sweep_segment<Prec, false, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, false, cur,
                                                              nfb, nfl, cfl);
   if (used && pos == 4) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) cr.dst[pc.lab[k] * cr.fstride] = dt * F.f[k];
+    for (int k = 0; k < 6; ++k) cr.dst[pc.lab[k] * cr.fstride] = dt * F.get(k);
   }
 }
 
@@ -1190,6 +1190,23 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
 PPM_INSTANTIATE(PrecF64)
 PPM_INSTANTIATE(PrecMixed)
 #undef PPM_INSTANTIATE
+__global__ void __launch_bounds__(256)
+fp64_ops_kernel(const double *a, const double *b, double *quot, double *root, int64_t n) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  quot[i] = ddiv(a[i], b[i]);
+  root[i] = dsqrt(a[i]);
+}
+
+hipError_t launch_fp64_ops(const double *a, const double *b, double *quot, double *root,
+                           int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(fp64_ops_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, a, b, quot, root,
+                     n);
+  return hipGetLastError();
+}
+
 template hipError_t launch_cfl<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
                                         int32_t, int32_t, const Params &, unsigned long long *,
                                         double *, hipStream_t);

@@ -184,4 +184,10 @@ hipError_t launch_copy_from_siblings(const PatchDev *patches, const SiblingBox *
                                      const int64_t *prefix, int32_t nboxes, int64_t total,
                                      hipStream_t s);
 
+// quot[i] = ddiv(a[i], b[i]) and root[i] = dsqrt(a[i]) over n elements: the
+// correctly rounded FP64 division and square root of the sweeps, exposed so
+// that they can be checked against host IEEE arithmetic.
+hipError_t launch_fp64_ops(const double *a, const double *b, double *quot, double *root,
+                           int64_t n, hipStream_t s);
+
 }  // namespace ppm

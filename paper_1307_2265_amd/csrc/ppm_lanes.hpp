@@ -54,10 +54,13 @@ template <class V> __device__ __forceinline__ V from_right(V v) { return dpp_shi
 template <class V> __device__ __forceinline__ V from_left2(V v) { return from_left(from_left(v)); }
 template <class V> __device__ __forceinline__ V from_right2(V v) { return from_right(from_right(v)); }
 
-__device__ __forceinline__ Flux flux_from_left(const Flux &F) {
-  Flux o;
+template <class T> __device__ __forceinline__ FluxT<T> flux_from_left(const FluxT<T> &F) {
+  FluxT<T> o;
 #pragma unroll
-  for (int k = 0; k < 7; ++k) o.f[k] = from_left(F.f[k]);
+  for (int k = 0; k < 4; ++k) o.m[k] = from_left(F.m[k]);
+  o.E = from_left(F.E);
+  o.e = from_left(F.e);
+  o.ub = from_left(F.ub);
   return o;
 }
 
@@ -78,7 +81,7 @@ struct CellLoad {
 // factor (the same for every pencil of the patch).  Returns the final flux
 // (after the fallback) of face j+1/2.
 template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
-__device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
+__device__ FluxT<typename Prec::T> sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                               double lam, double hgdt, int j, bool mine, const CellLoad &in,
                               uint32_t &n_fallback, uint32_t &n_floor, CflAcc &cfl) {
   using S = typename Prec::S;
@@ -172,27 +175,23 @@ __device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S>
   const bool diffuse = kGrav && (P.flags & kDiffusion) != 0;
   // the diffusive flux, from this cell's and the right neighbour's input
   // values (the shifts run on every lane, outside divergent branches)
-  auto diffuse_into = [&](Flux &G) {
+  auto diffuse_into = [&](FluxT<T> &G) {
     const double nr = from_right(in.r), nu = from_right(in.u), nv1 = from_right(in.v1);
     const double nv2 = from_right(in.v2), nE = from_right(in.E), ne = from_right(in.e);
     if (face_ok) add_diffusion(G, in.r, in.u, in.v1, in.v2, in.E, in.e, nr, nu, nv1, nv2, nE, ne);
   };
-  Flux F;
-#pragma unroll
-  for (int k = 0; k < 7; ++k) F.f[k] = 0.0;
-  if (face_ok) {
-    F = riemann_flux<kUseHLLC>(P, double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p),
-                     double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p));
-  }
+  FluxT<T> F = zero_flux<T>();
+  if (face_ok) F = face_flux<kUseHLLC, T>(P, sl, sr);
   if (diffuse) diffuse_into(F);
 
   // ---- provisional update of cell j (a0..a1)
   const bool cell_ok = j >= a0 && j <= a1;
-  CellIn cin;
-  cin.rho = r; cin.u = u; cin.v1 = v1; cin.v2 = v2; cin.E = E; cin.e = e; cin.p = pd;
+  CellInT<T> cin;
+  cin.rho = T(r); cin.u = T(u); cin.v1 = T(v1); cin.v2 = T(v2);
+  cin.E = E; cin.e = e; cin.p = pd;
   cin.rhoEmax = m3;
   double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  Flux Fm = flux_from_left(F);
+  FluxT<T> Fm = flux_from_left(F);
   bool bad = false;
   const bool grav = kGrav && pc.acc != nullptr;
   const double hg = grav && cell_ok ? hgdt * double(pc.acc[o]) : 0.0;
@@ -206,11 +205,11 @@ __device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S>
     const bool bad_next = from_right(int(bad)) != 0;
     const bool hll = face_ok && (bad || bad_next);
     if (__any(hll)) {
-      Flux H = F;
+      FluxT<T> H = F;
       if (hll) {
         const double L5[5] = {double(sl.r), double(sl.u), double(sl.v1), double(sl.v2), double(sl.p)};
         const double R5[5] = {double(sr.r), double(sr.u), double(sr.v1), double(sr.v2), double(sr.p)};
-        H = hll_flux(P, L5, R5);
+        H = narrow_flux<T>(hll_flux(P, L5, R5));
       }
       if (diffuse) diffuse_into(H);
       if (hll) {
@@ -231,11 +230,11 @@ __device__ Flux sweep_segment(const Params &P, const PencilRef<typename Prec::S>
   // ---- boundary flux registers and write-back
   if (pc.reg_lo && j == a0 - 1 && mine_next) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) pc.reg_lo[pc.lab[k] * pc.reg_stride] = dt * F.f[k];
+    for (int k = 0; k < 6; ++k) pc.reg_lo[pc.lab[k] * pc.reg_stride] = dt * F.get(k);
   }
   if (pc.reg_hi && j == a1 && mine) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) pc.reg_hi[pc.lab[k] * pc.reg_stride] = dt * F.f[k];
+    for (int k = 0; k < 6; ++k) pc.reg_hi[pc.lab[k] * pc.reg_stride] = dt * F.get(k);
   }
   double sig = 0.0;
   if (cell_ok && mine) {

@@ -257,9 +257,21 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
     return RightEdge ? avg_right<T>(qrr[k], dq[k], q6[k], y) : avg_left<T>(ql[k], dq[k], q6[k], y);
   };
   T rt = avg(0, yref), ut = avg(1, yref), pt = avg(4, yref);
-  T C = xsqrt<T>(T(g) * pt * rt);
-  T iC = xdiv<T>(T(1), C);
-  const T irt = xdiv<T>(T(1), rt);
+  T C, iC, irt;
+  if constexpr (sizeof(T) == sizeof(double)) {
+    C = xsqrt<T>(T(g) * pt * rt);
+    iC = xdiv<T>(T(1), C);
+    irt = xdiv<T>(T(1), rt);
+  } else {
+    // float: C = rho sqrt(g p / rho) and 1/C = (1/rho) / sqrt(g p / rho), so
+    // that no product of two edge values (each as small as the floors, whose
+    // product lies below the float range) is formed
+    irt = xdiv<T>(T(1), rt);
+    const T c2 = T(g) * pt * irt;
+    const T ic = __builtin_amdgcn_rsqf(c2);
+    C = rt * (c2 * ic);
+    iC = irt * ic;
+  }
   // bref: the reference wave's own correction (its averages are ut, pt);
   // bslow: the other acoustic wave; b0: the entropy wave
   T bref = T(0), bslow = T(0), b0 = T(0);
@@ -281,7 +293,9 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
   }
   T bp = RightEdge ? bref : bslow;
   T bm = RightEdge ? bslow : bref;
-  T ps = pt + C * C * (bp + bm);
+  T ps;
+  if constexpr (sizeof(T) == sizeof(double)) ps = pt + C * C * (bp + bm);
+  else ps = pt + C * (C * (bp + bm));  // C^2 alone can lie below the float range
   T us = ut + C * (bp - bm);
   T tau = irt - (bp + bm + b0);
   T rs = tau > T(0) ? xdiv<T>(T(1), tau) : rt;
@@ -293,17 +307,59 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
   return s;
 }
 
-// Face flux: F_rho, F_u, F_v1, F_v2, F_E, F_e and the face velocity.
-struct Flux {
-  double f[7];
+// Face flux in the flux type T of a precision: the mass and momentum fluxes
+// F_rho, F_u, F_v1, F_v2 (pencil order), the internal-energy flux F_e and the
+// face velocity of the p div v term in T, the total-energy flux F_E always in
+// double.  get/set address the six fluxes and the face velocity by slot
+// (0..3 mass and momenta, 4 F_E, 5 F_e, 6 the face velocity), in double.
+template <class T> struct FluxT {
+  T m[4];
+  double E;
+  T e;
+  T ub;
+  __device__ __forceinline__ double get(int k) const {
+    return k < 4 ? double(m[k]) : (k == 4 ? E : (k == 5 ? double(e) : double(ub)));
+  }
+  __device__ __forceinline__ void set(int k, double v) {
+    if (k < 4) m[k] = T(v);
+    else if (k == 4) E = v;
+    else if (k == 5) e = T(v);
+    else ub = T(v);
+  }
 };
+using Flux = FluxT<double>;
+
+template <class T> __device__ __forceinline__ FluxT<T> zero_flux() {
+  FluxT<T> F;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) F.set(k, 0.0);
+  return F;
+}
+
+// A double flux in the flux type T (the fallback's and HLLC's fluxes in the
+// mixed precision).
+template <class T> __device__ __forceinline__ FluxT<T> narrow_flux(const Flux &D) {
+  FluxT<T> F;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) F.set(k, D.get(k));
+  return F;
+}
 
 // Two-shock Riemann solver (Sec. "Riemann Solvers and Fallback"), sampled at
 // x/t = 0, and the fluxes of the sampled state.  Newton iteration on
 // u*_R(p) - u*_L(p) = 0 with the Lagrangian shock speeds W_s.
-__device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, double ul, double v1l,
-                                               double v2l, double pl, double rr, double ur,
-                                               double v1r, double v2r, double pr, int &iters) {
+// Star pressure of the two-shock problem: Newton iteration on
+// u*_R(p) - u*_L(p) = 0 with the Lagrangian shock speeds W_s, from the
+// acoustic guess, until the correction falls below rtol*p; the star state is
+// that last iterate, whose shock speeds are already at hand.  Returns p* and
+// the shock speeds, their reciprocals and the two sides' u* at p*.
+struct StarState {
+  double ps, wl, wr, iwl, iwr, usl, usr;
+  int iters;
+};
+__device__ __forceinline__ StarState two_shock_star(const Params &P, double rl, double ul,
+                                                    double pl, double rr, double ur,
+                                                    double pr) {
   const double g = P.gamma;
   const double G1 = (g + 1.0) / (2.0 * g);
   double cl = dsqrt(g * pl * rl);
@@ -311,8 +367,6 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   double ipl = ddiv(1.0, pl), ipr = ddiv(1.0, pr);
   double ps = ddiv(cr * pl + cl * pr - cl * cr * (ur - ul), cl + cr);
   if (ps < P.p_floor) ps = P.p_floor;
-  // Newton until the correction falls below rtol*p; the star state is that
-  // last iterate, whose shock speeds are already at hand.
   int it = 0;
   bool capped = false;
   double wl, wr, iwl, iwr, usl, usr;
@@ -333,6 +387,17 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
     ps = pn;
     if (it == P.riemann_max_iter) capped = true;
   }
+  return StarState{ps, wl, wr, iwl, iwr, usl, usr, it};
+}
+
+__device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, double ul, double v1l,
+                                               double v2l, double pl, double rr, double ur,
+                                               double v1r, double v2r, double pr, int &iters) {
+  const double g = P.gamma;
+  const StarState st = two_shock_star(P, rl, ul, pl, rr, ur, pr);
+  const double ps = st.ps, wl = st.wl, wr = st.wr, iwl = st.iwl, iwr = st.iwr;
+  const double usl = st.usl, usr = st.usr;
+  const int it = st.iters;
   iters = it;
   double us = 0.5 * (usl + usr);
   // sample the upwind side of the contact at x/t = 0
@@ -367,15 +432,75 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   double v2 = left ? v2l : v2r;
   Flux F;
   double fr = rb * ub;
-  F.f[0] = fr;
-  F.f[1] = fr * ub + pb;
-  F.f[2] = fr * v1;
-  F.f[3] = fr * v2;
+  F.m[0] = fr;
+  F.m[1] = fr * ub + pb;
+  F.m[2] = fr * v1;
+  F.m[3] = fr * v2;
   double eb = ddiv(pb, (g - 1.0) * rb);
   double Eb = eb + 0.5 * (ub * ub + v1 * v1 + v2 * v2);
-  F.f[4] = fr * Eb + ub * pb;
-  F.f[5] = fr * eb;
-  F.f[6] = ub;
+  F.E = fr * Eb + ub * pb;
+  F.e = fr * eb;
+  F.ub = ub;
+  return F;
+}
+
+// Two-shock flux of the mixed precision: the traced states come in float; the
+// star pressure is iterated in double exactly as above; the sampling of the
+// solution at x/t = 0 and the mass, momentum and internal-energy fluxes are
+// formed in float (hardware reciprocal and square root), the total-energy
+// flux in double from the sampled float state.
+__device__ __forceinline__ FluxT<float> two_shock_flux_mixed(const Params &P, float rl, float ul,
+                                                             float v1l, float v2l, float pl,
+                                                             float rr, float ur, float v1r,
+                                                             float v2r, float pr) {
+  const StarState st = two_shock_star(P, double(rl), double(ul), double(pl), double(rr),
+                                      double(ur), double(pr));
+  const float g = float(P.gamma);
+  const float ps = float(st.ps);
+  const float us = float(0.5 * (st.usl + st.usr));
+  const bool left = us >= 0.0f;
+  const float rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
+  const float wK = float(left ? st.wl : st.wr), iwK = float(left ? st.iwl : st.iwr);
+  const float irK = __builtin_amdgcn_rcpf(rK);
+  float rs = __builtin_amdgcn_rcpf(irK - (ps - pK) * iwK * iwK);
+  if (rs < float(P.rho_floor)) rs = float(P.rho_floor);
+  float rb, ub, pb;
+  if (ps > pK) {  // shock on the upwind side: its speed u_K -+ W_K / rho_K
+    const float S = left ? uK - wK * irK : uK + wK * irK;
+    const bool keep = left ? S >= 0.0f : S <= 0.0f;
+    if (keep) { rb = rK; ub = uK; pb = pK; }
+    else { rb = rs; ub = us; pb = ps; }
+  } else {        // rarefaction: linear through the fan
+    const float cK = __builtin_amdgcn_sqrtf(g * pK * irK);
+    const float cs = __builtin_amdgcn_sqrtf(g * ps * __builtin_amdgcn_rcpf(rs));
+    const float head = left ? uK - cK : uK + cK;
+    const float tail = left ? us - cs : us + cs;
+    const bool outside = left ? head >= 0.0f : head <= 0.0f;
+    const bool star = left ? tail <= 0.0f : tail >= 0.0f;
+    if (outside) { rb = rK; ub = uK; pb = pK; }
+    else if (star) { rb = rs; ub = us; pb = ps; }
+    else {
+      const float w = head * __builtin_amdgcn_rcpf(head - tail);
+      rb = (1.0f - w) * rK + w * rs;
+      ub = (1.0f - w) * uK + w * us;
+      pb = (1.0f - w) * pK + w * ps;
+    }
+  }
+  const float v1 = left ? v1l : v1r;
+  const float v2 = left ? v2l : v2r;
+  FluxT<float> F;
+  const float fr = rb * ub;
+  F.m[0] = fr;
+  F.m[1] = fr * ub + pb;
+  F.m[2] = fr * v1;
+  F.m[3] = fr * v2;
+  F.e = fr * (pb * __builtin_amdgcn_rcpf((g - 1.0f) * rb));
+  F.ub = ub;
+  // total energy flux in double: rho u is exact in double for float factors
+  const double rbd = rb, ubd = ub, pbd = pb, v1d = v1, v2d = v2;
+  const double frd = rbd * ubd;
+  const double eb = ddiv(pbd, (P.gamma - 1.0) * rbd);
+  F.E = frd * (eb + 0.5 * (ubd * ubd + v1d * v1d + v2d * v2d)) + ubd * pbd;
   return F;
 }
 
@@ -412,23 +537,23 @@ __device__ __forceinline__ Flux hllc_flux(const Params &P, double rl, double ul,
   const double EK = left ? El : Er, eK = left ? el : er, sK = left ? sL : sR;
   const double fr = rK * uK;
   Flux F;
-  F.f[0] = fr;
-  F.f[1] = fr * uK + pK;
-  F.f[2] = fr * v1K;
-  F.f[3] = fr * v2K;
-  F.f[4] = uK * (rK * EK + pK);
-  F.f[5] = fr * eK;
-  F.f[6] = uK;
+  F.m[0] = fr;
+  F.m[1] = fr * uK + pK;
+  F.m[2] = fr * v1K;
+  F.m[3] = fr * v2K;
+  F.E = uK * (rK * EK + pK);
+  F.e = fr * eK;
+  F.ub = uK;
   if (!fan) return F;
   const double mK = rK * (sK - uK);
   const double rs = ddiv(mK, sK - S);
-  F.f[0] = F.f[0] + sK * (rs - rK);
-  F.f[1] = F.f[1] + sK * (rs * S - rK * uK);
-  F.f[2] = F.f[2] + sK * (rs * v1K - rK * v1K);
-  F.f[3] = F.f[3] + sK * (rs * v2K - rK * v2K);
-  F.f[4] = F.f[4] + sK * (rs * (EK + (S - uK) * (S + ddiv(pK, mK))) - rK * EK);
-  F.f[5] = F.f[5] + sK * (rs * eK - rK * eK);
-  F.f[6] = S;
+  F.m[0] = F.m[0] + sK * (rs - rK);
+  F.m[1] = F.m[1] + sK * (rs * S - rK * uK);
+  F.m[2] = F.m[2] + sK * (rs * v1K - rK * v1K);
+  F.m[3] = F.m[3] + sK * (rs * v2K - rK * v2K);
+  F.E = F.E + sK * (rs * (EK + (S - uK) * (S + ddiv(pK, mK))) - rK * EK);
+  F.e = F.e + sK * (rs * eK - rK * eK);
+  F.ub = S;
   return F;
 }
 
@@ -446,6 +571,23 @@ __device__ __forceinline__ Flux riemann_flux(const Params &P, double rl, double 
   } else {
     int iters;
     return two_shock_flux(P, rl, ul, v1l, v2l, pl, rr, ur, v1r, v2r, pr, iters);
+  }
+}
+
+// The face flux of the solver a kernel is built for, in the flux type of
+// its precision: the double solvers above for FP64; in the mixed precision
+// the two-shock flux of the mixed form, and HLLC (kept in double) narrowed.
+template <bool kUseHLLC, class T>
+__device__ __forceinline__ FluxT<T> face_flux(const Params &P, const State<T> &l,
+                                              const State<T> &r) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    return riemann_flux<kUseHLLC>(P, l.r, l.u, l.v1, l.v2, l.p, r.r, r.u, r.v1, r.v2, r.p);
+  } else {
+    if (kUseHLLC && (P.flags & kHLLC))
+      return narrow_flux<T>(hllc_flux(P, double(l.r), double(l.u), double(l.v1), double(l.v2),
+                                      double(l.p), double(r.r), double(r.u), double(r.v1),
+                                      double(r.v2), double(r.p)));
+    return two_shock_flux_mixed(P, l.r, l.u, l.v1, l.v2, l.p, r.r, r.u, r.v1, r.v2, r.p);
   }
 }
 
@@ -469,17 +611,21 @@ __device__ __forceinline__ Flux hll_flux(const Params &P, const double (&sl)[5],
   double sR = vmax<double>(ul + cl, ur + cr);
   Flux F;
   if (sL >= 0.0) {
-    for (int k = 0; k < 6; ++k) F.f[k] = Fl[k];
-    F.f[6] = ul;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) F.set(k, Fl[k]);
+    F.ub = ul;
   } else if (sR <= 0.0) {
-    for (int k = 0; k < 6; ++k) F.f[k] = Fr[k];
-    F.f[6] = ur;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) F.set(k, Fr[k]);
+    F.ub = ur;
   } else {
     double id = 1.0 / (sR - sL);
-    for (int k = 0; k < 6; ++k) F.f[k] = (sR * Fl[k] - sL * Fr[k] + sL * sR * (Ur[k] - Ul[k])) * id;
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      F.set(k, (sR * Fl[k] - sL * Fr[k] + sL * sR * (Ur[k] - Ul[k])) * id);
     double um_r = (sR * Ur[0] - sL * Ul[0] - (Fr[0] - Fl[0])) * id;
     double um_m = (sR * Ur[1] - sL * Ul[1] - (Fr[1] - Fl[1])) * id;
-    F.f[6] = um_m / um_r;
+    F.ub = um_m / um_r;
   }
   return F;
 }
@@ -489,7 +635,8 @@ __device__ __forceinline__ Flux hll_flux(const Params &P, const double (&sl)[5],
 // input), each conserved quantity's flux gains nu (Q_l - Q_r), nu = K (u_l -
 // u_r), Q = rho, rho u, rho v1, rho v2, rho E, rho e; the face velocity of the
 // p div v term is left alone.
-__device__ __forceinline__ void add_diffusion(Flux &F, double rl, double ul, double v1l,
+template <class T>
+__device__ __forceinline__ void add_diffusion(FluxT<T> &F, double rl, double ul, double v1l,
                                               double v2l, double El, double el, double rr,
                                               double ur, double v1r, double v2r, double Er,
                                               double er) {
@@ -499,13 +646,17 @@ __device__ __forceinline__ void add_diffusion(Flux &F, double rl, double ul, dou
   const double ql[6] = {rl, rl * ul, rl * v1l, rl * v2l, rl * El, rl * el};
   const double qr[6] = {rr, rr * ur, rr * v1r, rr * v2r, rr * Er, rr * er};
 #pragma unroll
-  for (int k = 0; k < 6; ++k) F.f[k] = F.f[k] + nu * (ql[k] - qr[k]);
+  for (int k = 0; k < 6; ++k) F.set(k, F.get(k) + nu * (ql[k] - qr[k]));
 }
 
-// Sweep-input state of a cell as the update needs it.
-struct CellIn {
-  double rho, u, v1, v2, E, e, p, rhoEmax;
+// Sweep-input state of a cell as the update needs it: density and velocity
+// in the flux type T (as stored), energies, pressure and the eta2
+// neighbourhood maximum in double.
+template <class T> struct CellInT {
+  T rho, u, v1, v2;
+  double E, e, p, rhoEmax;
 };
+using CellIn = CellInT<double>;
 
 // Conservative update of one cell from its two face fluxes (Eqs. mass_diff,
 // momentum_diff, energy_diff, gasenergy_diff with the flux difference taken
@@ -520,12 +671,12 @@ __device__ __forceinline__ bool update_cell(const Params &P, double lam, const C
                                             const Flux &Fm, const Flux &Fp, double (&out)[6],
                                             bool grav = false, double hg = 0.0) {
   const bool dual = (P.flags & kDualEnergy) != 0;
-  double rn = c.rho - lam * (Fp.f[0] - Fm.f[0]);
-  double mu = c.rho * c.u - lam * (Fp.f[1] - Fm.f[1]);
-  double m1 = c.rho * c.v1 - lam * (Fp.f[2] - Fm.f[2]);
-  double m2 = c.rho * c.v2 - lam * (Fp.f[3] - Fm.f[3]);
-  double mE = c.rho * c.E - lam * (Fp.f[4] - Fm.f[4]);
-  double me = c.rho * c.e - lam * (Fp.f[5] - Fm.f[5]) - lam * c.p * (Fp.f[6] - Fm.f[6]);
+  double rn = c.rho - lam * (Fp.m[0] - Fm.m[0]);
+  double mu = c.rho * c.u - lam * (Fp.m[1] - Fm.m[1]);
+  double m1 = c.rho * c.v1 - lam * (Fp.m[2] - Fm.m[2]);
+  double m2 = c.rho * c.v2 - lam * (Fp.m[3] - Fm.m[3]);
+  double mE = c.rho * c.E - lam * (Fp.E - Fm.E);
+  double me = c.rho * c.e - lam * (Fp.e - Fm.e) - lam * c.p * (Fp.ub - Fm.ub);
   if (grav) {
     mu = mu + hg * (c.rho + rn);
     mE = mE + hg * (c.rho * c.u + mu);
@@ -544,13 +695,57 @@ __device__ __forceinline__ bool update_cell(const Params &P, double lam, const C
   return bad;
 }
 
+// The update of the mixed precision: density and momenta from the float
+// fluxes in float, the velocities by the float reciprocal of the new density;
+// total and internal energy accumulated in double (the energy fluxes, the
+// p div v term and the division by the new density in double), the
+// dual-energy selection (eta1) and resync (eta2) in double.
+__device__ __forceinline__ bool update_cell(const Params &P, double lam,
+                                            const CellInT<float> &c, const FluxT<float> &Fm,
+                                            const FluxT<float> &Fp, double (&out)[6],
+                                            bool grav = false, double hg = 0.0) {
+  const bool dual = (P.flags & kDualEnergy) != 0;
+  const float lf = float(lam);
+  const float rn = c.rho - lf * (Fp.m[0] - Fm.m[0]);
+  float mu = c.rho * c.u - lf * (Fp.m[1] - Fm.m[1]);
+  const float m1 = c.rho * c.v1 - lf * (Fp.m[2] - Fm.m[2]);
+  const float m2 = c.rho * c.v2 - lf * (Fp.m[3] - Fm.m[3]);
+  const double rd = c.rho;
+  double mE = rd * c.E - lam * (Fp.E - Fm.E);
+  const double me = rd * c.e - lam * (double(Fp.e) - double(Fm.e)) -
+                    lam * c.p * (double(Fp.ub) - double(Fm.ub));
+  if (grav) {
+    const float hf = float(hg);
+    mu = mu + hf * (c.rho + rn);
+    mE = mE + hg * (rd * double(c.u) + double(mu));
+  }
+  const float irf = __builtin_amdgcn_rcpf(rn);
+  const float unf = mu * irf, v1f = m1 * irf, v2f = m2 * irf;
+  const double rnd = rn;
+  const double ir = ddiv(1.0, rnd);
+  const double un = unf, v1n = v1f, v2n = v2f;
+  const double En = mE * ir, eraw = me * ir;
+  const double ke = 0.5 * (un * un + v1n * v1n + v2n * v2n);
+  const double epsE = En - ke;
+  bool bad = !(rnd > P.rho_floor);
+  double sel = epsE;
+  if (dual && !ratio_above(epsE, En, P.eta1)) sel = eraw;
+  if (!(sel > 0.0)) bad = true;
+  double en = eraw < P.e_floor ? P.e_floor : eraw;
+  if (dual && ratio_above(rnd * epsE, c.rhoEmax, P.eta2)) en = epsE;
+  out[0] = rnd; out[1] = un; out[2] = v1n; out[3] = v2n; out[4] = En; out[5] = en;
+  return bad;
+}
+
 // A cell still non-positive after the fallback: density raised to the floor
 // (keeping the old velocity if so), pressure set to the floor.
-__device__ __forceinline__ void floor_cell(const Params &P, const CellIn &c, double (&out)[6]) {
+template <class T>
+__device__ __forceinline__ void floor_cell(const Params &P, const CellInT<T> &c,
+                                           double (&out)[6]) {
   const double g = P.gamma;
   if (!(out[0] > P.rho_floor)) {
     out[0] = P.rho_floor;
-    out[1] = c.u; out[2] = c.v1; out[3] = c.v2;
+    out[1] = double(c.u); out[2] = double(c.v1); out[3] = double(c.v2);
   }
   double eps = P.p_floor / ((g - 1.0) * out[0]);
   out[5] = eps;

@@ -227,7 +227,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   // the diffusive flux of the face between cells jl and jl+1 (their stored
   // sweep-input values, still in memory: a cell is written two iterations
   // after its right face is final)
-  auto diffuse_face = [&](Flux &F, int jl) {
+  auto diffuse_face = [&](FluxT<T> &F, int jl) {
     const int64_t ol = pc.base + int64_t(jl) * pc.stride, orr = ol + pc.stride;
     add_diffusion(F, double(pc.rho[ol]), double(pc.u[ol]), double(pc.v1[ol]), double(pc.v2[ol]),
                   pc.E[ol], pc.e[ol], double(pc.rho[orr]), double(pc.u[orr]),
@@ -252,7 +252,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   T ft[3];         // cells k-4..k-2: flattening indicators
   T fc[3][5];      // faces (k-4)+1/2 .. (k-2)+1/2: interface values
   State<T> lcarry; // left state of face r+1/2 from the previous iteration
-  Flux ft_b;       // two-shock flux at face (r-2)+1/2
+  FluxT<T> ft_b;   // two-shock flux at face (r-2)+1/2
   // final flux at face (r-3)+1/2 and provisional update of cell A = r-2 live
   // in LDS (written every step; the flux is read only by the fallback)
   double *ff_a = lds_slots + kLdsFluxA * slot_stride;
@@ -282,11 +282,9 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   cw[0] = cw[1] = T(0);
   c_head = c_km1 = 0.0;
   lcarry = State<T>{T(0), T(0), T(0), T(0), T(0)};
+  ft_b = zero_flux<T>();
 #pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    ft_b.f[j] = 0.0;
-    ff_a[j * slot_stride] = 0.0;
-  }
+  for (int j = 0; j < 7; ++j) ff_a[j * slot_stride] = 0.0;
 #pragma unroll
   for (int j = 0; j < 6; ++j) prov_a[j * slot_stride] = 0.0;
 
@@ -380,15 +378,10 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     }
 
     // ---- 6. Riemann problem at face fc = (r-1)+1/2
-    Flux ft_c;
-#pragma unroll
-    for (int j = 0; j < 7; ++j) ft_c.f[j] = 0.0;
+    FluxT<T> ft_c = zero_flux<T>();
     double *slot_c = lds_slots + (k & 1) * kSlotDoubles * slot_stride;
     if (r - 1 >= a0 - 1 && r - 1 <= a1) {
-      ft_c = riemann_flux<kUseHLLC>(P, double(lcarry.r), double(lcarry.u), double(lcarry.v1),
-                          double(lcarry.v2), double(lcarry.p), double(rstate.r),
-                          double(rstate.u), double(rstate.v1), double(rstate.v2),
-                          double(rstate.p));
+      ft_c = face_flux<kUseHLLC, T>(P, lcarry, rstate);
       if (diffuse) diffuse_face(ft_c, r - 1);
       if (fallback) {
         slot_c[0 * slot_stride] = double(lcarry.r);
@@ -409,9 +402,9 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     bool bad_b = false;
     double prov_b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (B >= a0 && B <= a1) {
-      CellIn cin;
-      cin.rho = double(q[0][0]); cin.u = double(q[0][1]);
-      cin.v1 = double(q[0][2]); cin.v2 = double(q[0][3]);
+      CellInT<T> cin;
+      cin.rho = q[0][0]; cin.u = q[0][1];
+      cin.v1 = q[0][2]; cin.v2 = q[0][3];
       cin.E = EB; cin.e = eB;
       cin.p = kExactP ? double(q[0][4]) : pd[0];
       cin.rhoEmax = m3[1];
@@ -421,7 +414,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     // ---- 8. face fb = (r-2)+1/2 becomes final: HLL if a neighbour went bad
     const int A = r - 2;
     const int fb = r - 2;  // face index: fb+1/2 lies between cells A and B
-    Flux ff_b = ft_b;
+    FluxT<T> ff_b = ft_b;
     bool hll_b = false;
     if (fb >= a0 - 1 && fb <= a1) {
       hll_b = fallback && (bad_a || bad_b);
@@ -433,17 +426,17 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
           sl[j] = slot_b[j * slot_stride];
           sr[j] = slot_b[(5 + j) * slot_stride];
         }
-        ff_b = hll_flux(P, sl, sr);
+        ff_b = narrow_flux<T>(hll_flux(P, sl, sr));
         if (diffuse) diffuse_face(ff_b, fb);
         ++n_fallback;
       }
       if (fb == a0 - 1 && pc.reg_lo) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) pc.reg_lo[pc.lab[j] * pc.reg_stride] = dt * ff_b.f[j];
+        for (int j = 0; j < 6; ++j) pc.reg_lo[pc.lab[j] * pc.reg_stride] = dt * ff_b.get(j);
       }
       if (fb == a1 && pc.reg_hi) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) pc.reg_hi[pc.lab[j] * pc.reg_stride] = dt * ff_b.f[j];
+        for (int j = 0; j < 6; ++j) pc.reg_hi[pc.lab[j] * pc.reg_stride] = dt * ff_b.get(j);
       }
     }
 
@@ -456,24 +449,25 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       bool bad = bad_a;
       if (hll_a || hll_b) {
         // redo the update with the final fluxes (input of A is still in memory)
-        CellIn cin;
-        cin.rho = double(pc.rho[o]); cin.u = double(pc.u[o]);
-        cin.v1 = double(pc.v1[o]); cin.v2 = double(pc.v2[o]);
+        CellInT<T> cin;
+        cin.rho = T(pc.rho[o]); cin.u = T(pc.u[o]);
+        cin.v1 = T(pc.v1[o]); cin.v2 = T(pc.v2[o]);
         cin.E = pc.E[o]; cin.e = pc.e[o];
         double pp, cc;
-        eos(P, cin.rho, cin.u, cin.v1, cin.v2, cin.E, cin.e, pp, cc);
+        eos(P, double(cin.rho), double(cin.u), double(cin.v1), double(cin.v2), cin.E, cin.e, pp,
+            cc);
         cin.p = pp;
         cin.rhoEmax = m3[0];
-        Flux fa;
+        FluxT<T> fa;
 #pragma unroll
-        for (int j = 0; j < 7; ++j) fa.f[j] = ff_a[j * slot_stride];
+        for (int j = 0; j < 7; ++j) fa.set(j, ff_a[j * slot_stride]);
         bad = update_cell(P, lam, cin, fa, ff_b, out, grav,
                           grav ? hgdt * double(pc.acc[o]) : 0.0);
       }
       if (bad) {
-        CellIn cin;
-        cin.rho = double(pc.rho[o]); cin.u = double(pc.u[o]);
-        cin.v1 = double(pc.v1[o]); cin.v2 = double(pc.v2[o]);
+        CellInT<T> cin;
+        cin.rho = T(pc.rho[o]); cin.u = T(pc.u[o]);
+        cin.v1 = T(pc.v1[o]); cin.v2 = T(pc.v2[o]);
         cin.E = pc.E[o]; cin.e = pc.e[o]; cin.p = 0.0; cin.rhoEmax = 0.0;
         floor_cell(P, cin, out);
         ++n_floor;
@@ -494,7 +488,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
 
     // ---- 10. carry the face and cell state one step
 #pragma unroll
-    for (int j = 0; j < 7; ++j) ff_a[j * slot_stride] = ff_b.f[j];
+    for (int j = 0; j < 7; ++j) ff_a[j * slot_stride] = ff_b.get(j);
     hll_a = hll_b;
     ft_b = ft_c;
 #pragma unroll

@@ -83,6 +83,7 @@ SIGNATURES = {
     "ppm_graph_create": (C.c_int, [C.POINTER(_vp), _vp, _vp, C.c_int32, C.c_uint32, _vp]),
     "ppm_graph_launch": (C.c_int, [_vp, _vp]),
     "ppm_graph_destroy": (C.c_int, [_vp]),
+    "ppm_fp64_ops": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp]),
     "ppm_status_str": (C.c_char_p, [C.c_int]),
     "ppm_last_error": (C.c_char_p, []),
 }
@@ -127,6 +128,16 @@ def params(gamma=5.0 / 3.0, cfl=0.4, eta1=1e-3, eta2=0.1, rho_floor=1e-20, p_flo
 
 def ppm_flux_reg_size(nx: int, ny: int, nz: int) -> int:
     return int(lib().ppm_flux_reg_size(nx, ny, nz))
+
+
+def ppm_fp64_ops(a, b, quot, root, stream=None) -> None:
+    """quot = a / b and root = sqrt(a) by the library's FP64 division and
+    square root (device float64 tensors of one length)."""
+    n = a.numel()
+    for t in (b, quot, root):
+        assert t.numel() == n and t.is_contiguous()
+    _check(lib().ppm_fp64_ops(a.data_ptr(), b.data_ptr(), quot.data_ptr(), root.data_ptr(), n,
+                              _stream_handle(stream)), "ppm_fp64_ops")
 
 
 def _stream_handle(stream) -> int | None:

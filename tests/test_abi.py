@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_functions():
     src = open(os.path.join(ROOT, "include", "ppm.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ppm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(ppm_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_function():
@@ -67,6 +67,23 @@ def test_plan_create_rejects_invalid_arguments(patch_kw, prm_kw, msg):
     assert msg in L.ppm_last_error().decode()
 
 
+@pytest.mark.parametrize("prm_kw", [dict(rho_floor=1e-40), dict(p_floor=1e-45),
+                                    dict(rho_floor=1e-60, p_floor=1e-60), dict(p_floor=1e39)])
+def test_mixed_precision_rejects_floors_outside_the_normal_float_range(prm_kw):
+    # PPM_MIXED stores the density in float: a floor below FLT_MIN would be
+    # stored as a subnormal or zero, and the next sweep would divide by it
+    L = ppm.lib()
+    arr = (ppm.ppm_patch * 1)(_patch())
+    prm = ppm.params(**prm_kw)
+    h = C.c_void_p()
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_MIXED, C.byref(prm), None, None)
+    assert st == ppm.PPM_EINVAL and not h.value
+    assert "normal float range" in L.ppm_last_error().decode()
+    # the same floors are valid in FP64 (checked up to the first device call)
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"warp=1", None)
+    assert st == ppm.PPM_EINVAL and "unknown key" in L.ppm_last_error().decode()
+
+
 def test_calls_on_null_plan_are_rejected():
     L = ppm.lib()
     assert L.ppm_step(None, None, 0, None) == ppm.PPM_EINVAL
@@ -89,6 +106,7 @@ def test_calls_on_null_plan_are_rejected():
     assert L.ppm_amr_destroy(None) == ppm.PPM_OK
     assert L.ppm_expansion(None, None, None) == ppm.PPM_EINVAL
     assert L.ppm_plan_destroy(None) == ppm.PPM_OK
+    assert L.ppm_fp64_ops(None, None, None, None, 1, None) == ppm.PPM_EINVAL
 
 
 def test_bad_tile_config_is_rejected():

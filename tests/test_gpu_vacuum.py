@@ -100,23 +100,65 @@ def test_batch_equals_oracle(P, O, tiles):
     plan.close()
 
 
-def test_mixed_precision_stays_physical(P):
+def _mixed_floor(x):
+    """The floor a PPM_MIXED plan uses: the nearest float at or above x."""
+    f = np.float32(x)
+    if float(f) < x:
+        f = np.nextafter(f, np.float32(np.inf))
+    return float(f)
+
+
+def test_mixed_precision_stays_physical_and_tracks_the_oracle(P, O):
+    """Near-vacuum cells are beyond what float reconstruction resolves: the
+    interface value between a cell of density 1 and one at the floor (1e-20)
+    carries an absolute rounding error near 1e-8, so the vacuum side of such a
+    stencil, and the states traced from it, are wrong by many orders of
+    magnitude relative to their own size, more faces need the HLL fallback
+    and more cells the floors than in double.  What holds is that the mixed
+    path stays finite and above the floors, and that the mass, momentum and
+    energy it carries track the oracle's; the L1 it reaches on this input is
+    stated below as a regression bound (a few times the measured values),
+    not the bound of the benchmark workloads (no cells at the floors there),
+    which the other mixed-precision tests hold to 1e-5 per step."""
     import torch
     pr = P.PPM_MIXED
-    d = stored_inputs(_field(3192), pr)
-    patch = to_device(d, pr, ghost=GH)
     prm = P.params()
+    floor = _mixed_floor(prm.rho_floor)
+    d = W.vacuum_pockets(W.random_grid(14, 12, 10, 3192, W.SHOCKED, ghost=GH), 3193,
+                         rho_vac=floor, p_vac=floor, ghost=GH)
+    d = stored_inputs(d, pr)
+    patch = to_device(d, pr, ghost=GH)
     plan = P.Plan([patch], 1, pr, prm)
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
-    for s in range(4):
-        plan.ppm_fill_periodic()
-        plan.ppm_cfl_dt(dt)
-        plan.ppm_step(dt, s % 2)
-    torch.cuda.synchronize()
-    g = from_device(patch)
-    plan.close()
+    G = oracle_grid(O, d, ghost=GH)
+    po = O.params()
     act = (slice(GH, -GH),) * 3
+    l1 = []
+    for s in range(4):
+        # both take the oracle's timestep, so the comparison sees only precision
+        O.fill_periodic(G)
+        dto = O.cfl_dt(G, po)
+        O.step(G, po, dto, s % 2)
+        plan.ppm_fill_periodic()
+        dt.fill_(dto)
+        plan.ppm_step(dt, s % 2)
+        torch.cuda.synchronize()
+        g = from_device(patch)
+        o = {f: getattr(G, f)[act] for f in FIELDS}
+        m = {f: g[f][act] for f in FIELDS}
+        # density, and the conserved rho v, rho E, rho e
+        err = {"rho": float(np.abs(m["rho"] - o["rho"]).sum() / np.abs(o["rho"]).sum())}
+        for f in FIELDS[1:]:
+            cm, co = m["rho"] * m[f], o["rho"] * o[f]
+            err[f] = float(np.abs(cm - co).sum() / np.abs(co).sum())
+        l1.append(err)
+    plan.close()
+    print("mixed near-vacuum L1 of rho, rho v, rho E, rho e per step:", l1, flush=True)
     for f in FIELDS:
         assert np.isfinite(g[f][act]).all(), f
-    assert g["rho"][act].min() >= np.float32(prm.rho_floor)
+    assert g["rho"][act].min() >= floor
     assert g["eint"][act].min() > 0.0
+    bound = {"rho": 2e-4, "vx": 1e-2, "vy": 1e-2, "vz": 1e-2, "etot": 1e-2, "eint": 5e-2}
+    for s in range(4):
+        for f in FIELDS:
+            assert l1[s][f] <= bound[f], (s, f, l1[s][f])
