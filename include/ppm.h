@@ -405,6 +405,41 @@ ppm_status ppm_graph_destroy(ppm_graph *graph); /* NULL is accepted */
 ppm_status ppm_fp64_ops(const double *a_dev, const double *b_dev, double *quot_dev,
                         double *root_dev, int64_t n, void *hip_stream);
 
+/* ---- A step that allocates nothing ---------------------------------------
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ppm_step_cfl for up to PPM_NOALLOC_MAX_PATCHES patches without a plan.
+ * The patch table, launch maps, event counters and per-level CFL maxima
+ * live in a static device buffer of PPM_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds on every device it runs on until the process ends (its
+ * address is taken at the first call on that device); the call neither
+ * allocates nor frees anything.  Every call on a device rewrites and reuses
+ * that device's buffer: calls that overlap on one device (other host threads,
+ * or other streams whose work is still running) race on it and must be
+ * serialised by the caller.
+ *
+ * patches (host, npatch of them, 1..PPM_NOALLOC_MAX_PATCHES), nlevels
+ * (1..PPM_NOALLOC_MAX_PATCHES), prec, params: as for ppm_plan_create
+ * (default launch shapes).  dt_dev: device array of nlevels doubles.  parts:
+ * PPM_NOALLOC_FILL first fills the ghosts of every patch periodically (all
+ * patches must then be PPM_BC_PERIODIC), as ppm_fill_periodic;
+ * PPM_NOALLOC_CFL then reduces dt_dev from the current state, as ppm_cfl_dt
+ * (without it dt_dev holds the step's timesteps on entry).  Then one step in
+ * sweep_order with dt_dev, after which dt_dev holds the CFL timestep of the
+ * new state -- bit for bit what a plan over the same patches gives through
+ * ppm_fill_periodic, ppm_cfl_dt and ppm_step_cfl.  events (host, nullable):
+ * if given, the call waits for the stream and stores the step's HLL faces
+ * and floored cells in events[0] and events[1].  PPM_EINVAL (nothing
+ * launched) for more than PPM_NOALLOC_MAX_PATCHES patches or levels and for
+ * every argument ppm_plan_create rejects. */
+#define PPM_NOALLOC_MAX_PATCHES 16
+#define PPM_NOALLOC_SCRATCH_BYTES 4096
+enum { PPM_NOALLOC_FILL = 1u, PPM_NOALLOC_CFL = 2u };
+ppm_status ppm_step_cfl_noalloc(const ppm_patch *patches, int32_t npatch, int32_t nlevels,
+                                ppm_precision prec, const ppm_params *params, double *dt_dev,
+                                int32_t sweep_order, uint32_t parts, int64_t *events,
+                                void *hip_stream);
+
 const char *ppm_status_str(ppm_status s);
 const char *ppm_last_error(void);
 

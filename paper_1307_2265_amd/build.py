@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libppm.so")
-SOURCES = ["ppm_kernels.hip", "ppm_api.cpp", "ppm_amr.cpp"]
+SOURCES = ["ppm_kernels.hip", "ppm_api.cpp", "ppm_amr.cpp", "ppm_noalloc.cpp"]
 ARCH = os.environ.get("PPM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

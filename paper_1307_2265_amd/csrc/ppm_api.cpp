@@ -42,23 +42,6 @@ ppm_status hip_fail(hipError_t e, const char *what) {
   return fail(PPM_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-}  // namespace ppm_detail
-
-using ppm_detail::fail;
-using ppm_detail::hip_fail;
-
-namespace {
-
-const int kOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
-// Largest patch (active cells) that one workgroup of the persistent launch owns.
-const int64_t kPersistentMaxCells = int64_t(1) << 21;
-
-inline int t1_of(int axis) { return axis == 0 ? 1 : 0; }
-inline int t2_of(int axis) { return axis == 2 ? 1 : 2; }
-inline int tmask_of(int axis, int mask) {
-  return ((mask >> t1_of(axis)) & 1) | (((mask >> t2_of(axis)) & 1) << 1);
-}
-
 // The smallest float not below x (x a positive double in the float range).
 double float_at_or_above(double x) {
   float f = float(x);
@@ -102,6 +85,49 @@ ppm_status check_patch(const ppm_patch &q, int i, int32_t nlevels) {
   if (nf[0] > lim || nf[1] > lim || nf[2] > lim || nf[0] * nf[1] > lim)
     return fail(PPM_EINVAL, "patch %d: too large (a face of the ghosted box exceeds 2^30 cells)", i);
   return PPM_OK;
+}
+
+ppm_status check_mixed_floors(ppm_precision prec, const ppm_params *p) {
+  // PPM_MIXED stores the density in float: a floor must be a normal float
+  if (prec == PPM_MIXED &&
+      (!(p->rho_floor >= double(FLT_MIN)) || !(p->rho_floor <= double(FLT_MAX)) ||
+       !(p->p_floor >= double(FLT_MIN)) || !(p->p_floor <= double(FLT_MAX))))
+    return fail(PPM_EINVAL,
+                "PPM_MIXED: rho_floor and p_floor must lie in the normal float range [%g, %g]",
+                double(FLT_MIN), double(FLT_MAX));
+  return PPM_OK;
+}
+
+ppm::Params device_params(ppm_precision prec, const ppm_params *p) {
+  ppm::Params P;
+  std::memcpy(&P, p, sizeof(ppm_params));
+  static_assert(offsetof(ppm::Params, expand) == sizeof(ppm_params), "params layout");
+  P.expand = nullptr;
+  if (prec == PPM_MIXED) {  // floors a float density and pressure can hold exactly
+    P.rho_floor = float_at_or_above(p->rho_floor);
+    P.p_floor = float_at_or_above(p->p_floor);
+  }
+  return P;
+}
+
+}  // namespace ppm_detail
+
+using ppm_detail::fail;
+using ppm_detail::hip_fail;
+
+namespace {
+
+const int kOrders[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
+using ppm_detail::check_params;
+using ppm_detail::check_patch;
+using ppm_detail::float_at_or_above;
+// Largest patch (active cells) that one workgroup of the persistent launch owns.
+const int64_t kPersistentMaxCells = int64_t(1) << 21;
+
+inline int t1_of(int axis) { return axis == 0 ? 1 : 0; }
+inline int t2_of(int axis) { return axis == 2 ? 1 : 2; }
+inline int tmask_of(int axis, int mask) {
+  return ((mask >> t1_of(axis)) & 1) | (((mask >> t2_of(axis)) & 1) << 1);
 }
 
 ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
@@ -236,13 +262,7 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   if (prec != PPM_FP64 && prec != PPM_MIXED) return fail(PPM_EINVAL, "unknown precision %d", int(prec));
   ppm_status st = check_params(params);
   if (st != PPM_OK) return st;
-  // PPM_MIXED stores the density in float: a floor must be a normal float
-  if (prec == PPM_MIXED &&
-      (!(params->rho_floor >= double(FLT_MIN)) || !(params->rho_floor <= double(FLT_MAX)) ||
-       !(params->p_floor >= double(FLT_MIN)) || !(params->p_floor <= double(FLT_MAX))))
-    return fail(PPM_EINVAL,
-                "PPM_MIXED: rho_floor and p_floor must lie in the normal float range [%g, %g]",
-                double(FLT_MIN), double(FLT_MAX));
+  if ((st = ppm_detail::check_mixed_floors(prec, params)) != PPM_OK) return st;
   for (int i = 0; i < npatch; ++i)
     if ((st = check_patch(patches[i], i, nlevels)) != PPM_OK) return st;
 
@@ -251,13 +271,7 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   pl->npatch = npatch;
   pl->nlevels = nlevels;
   pl->prec = prec;
-  std::memcpy(&pl->P, params, sizeof(ppm_params));
-  static_assert(offsetof(ppm::Params, expand) == sizeof(ppm_params), "params layout");
-  pl->P.expand = nullptr;
-  if (prec == PPM_MIXED) {  // floors a float density and pressure can hold exactly
-    pl->P.rho_floor = float_at_or_above(params->rho_floor);
-    pl->P.p_floor = float_at_or_above(params->p_floor);
-  }
+  pl->P = ppm_detail::device_params(prec, params);
   int64_t max_cells = 0;
   for (int i = 0; i < npatch; ++i)
     max_cells = std::max(max_cells, int64_t(patches[i].nx) * patches[i].ny * patches[i].nz);

@@ -1207,6 +1207,30 @@ hipError_t launch_fp64_ops(const double *a, const double *b, double *quot, doubl
   return hipGetLastError();
 }
 
+// Up to kWordBlock 32-bit words by value.
+constexpr int kWordBlock = 240;
+struct WordBlock {
+  uint32_t w[kWordBlock];
+};
+
+__global__ void __launch_bounds__(256)
+write_words_kernel(uint32_t *__restrict__ dst, WordBlock blk, int32_t n) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = blk.w[i];
+}
+
+hipError_t launch_write_words(uint32_t *dst, const uint32_t *words, int64_t n, hipStream_t s) {
+  for (int64_t o = 0; o < n; o += kWordBlock) {
+    WordBlock blk;
+    const int m = int(n - o < kWordBlock ? n - o : kWordBlock);
+    for (int i = 0; i < m; ++i) blk.w[i] = words[o + i];
+    hipLaunchKernelGGL(write_words_kernel, dim3(1), dim3(256), 0, s, dst + o, blk, m);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template hipError_t launch_cfl<PrecF64>(const PatchDev *, const int32_t *, int32_t, int32_t,
                                         int32_t, int32_t, const Params &, unsigned long long *,
                                         double *, hipStream_t);

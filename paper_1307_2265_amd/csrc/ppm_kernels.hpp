@@ -190,4 +190,8 @@ hipError_t launch_copy_from_siblings(const PatchDev *patches, const SiblingBox *
 hipError_t launch_fp64_ops(const double *a, const double *b, double *quot, double *root,
                            int64_t n, hipStream_t s);
 
+// dst[i] = words[i] for i < n (32-bit words from host memory, carried to the
+// device as kernel arguments, so no staging copy and no memset is involved).
+hipError_t launch_write_words(uint32_t *dst, const uint32_t *words, int64_t n, hipStream_t s);
+
 }  // namespace ppm

@@ -61,6 +61,17 @@ namespace ppm_detail {
 ppm_status fail(ppm_status s, const char *fmt, ...);
 ppm_status hip_fail(hipError_t e, const char *what);
 
+// Argument checks shared by the entry points (PPM_EINVAL with a message).
+ppm_status check_params(const ppm_params *p);
+ppm_status check_patch(const ppm_patch &q, int i, int32_t nlevels);
+// PPM_MIXED: rho_floor and p_floor must be normal floats.
+ppm_status check_mixed_floors(ppm_precision prec, const ppm_params *p);
+// The smallest float not below x (x a positive double in the float range).
+double float_at_or_above(double x);
+// The device parameters of a precision (PPM_MIXED floors raised to floats;
+// no expansion factors).
+ppm::Params device_params(ppm_precision prec, const ppm_params *p);
+
 // ppm_fill_ghosts of `level`, with the parents' states read through
 // parent_tab (a device patch table in the plan's order) when it is given.
 ppm_status fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *parent_tab, hipStream_t s);

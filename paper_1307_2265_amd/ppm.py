@@ -84,6 +84,9 @@ SIGNATURES = {
     "ppm_graph_launch": (C.c_int, [_vp, _vp]),
     "ppm_graph_destroy": (C.c_int, [_vp]),
     "ppm_fp64_ops": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int64, _vp]),
+    "ppm_step_cfl_noalloc": (C.c_int, [C.POINTER(ppm_patch), C.c_int32, C.c_int32, C.c_int,
+                                       C.POINTER(ppm_params), _vp, C.c_int32, C.c_uint32,
+                                       C.POINTER(C.c_int64), _vp]),
     "ppm_status_str": (C.c_char_p, [C.c_int]),
     "ppm_last_error": (C.c_char_p, []),
 }
@@ -138,6 +141,23 @@ def ppm_fp64_ops(a, b, quot, root, stream=None) -> None:
         assert t.numel() == n and t.is_contiguous()
     _check(lib().ppm_fp64_ops(a.data_ptr(), b.data_ptr(), quot.data_ptr(), root.data_ptr(), n,
                               _stream_handle(stream)), "ppm_fp64_ops")
+
+
+PPM_NOALLOC_MAX_PATCHES = 16
+PPM_NOALLOC_FILL, PPM_NOALLOC_CFL = 1, 2
+
+
+def ppm_step_cfl_noalloc(patches: list, nlevels: int, precision: int, prm: ppm_params, dt,
+                         sweep_order: int, parts: int = 0, events: bool = False, stream=None):
+    """The C function of the same name: one step of up to 16 patches (and the
+    next timestep in dt) without a plan and without allocating; with
+    events=True returns (HLL faces, floored cells) of the step."""
+    arr = (ppm_patch * len(patches))(*[p.to_c() for p in patches])
+    ev = (C.c_int64 * 2)(0, 0)
+    _check(lib().ppm_step_cfl_noalloc(arr, len(patches), nlevels, precision, C.byref(prm),
+                                      dt.data_ptr(), sweep_order, parts, ev if events else None,
+                                      _stream_handle(stream)), "ppm_step_cfl_noalloc")
+    return (ev[0], ev[1]) if events else None
 
 
 def _stream_handle(stream) -> int | None:
