@@ -98,8 +98,9 @@ __device__ FluxT<typename Prec::T> sweep_segment(const Params &P, const PencilRe
   const bool has = j >= 0 && j < n;
   const int64_t o = pc.base + int64_t(has ? j : 0) * pc.stride;
   const double r = in.r, u = in.u, v1 = in.v1, v2 = in.v2, E = in.E, e = in.e;
-  double pd, cd;
-  eos(P, r, u, v1, v2, E, e, pd, cd);
+  double pd;
+  T cc;
+  eos_cell<T>(P, r, u, v1, v2, E, e, pd, cc);
   T q[5] = {T(r), T(u), T(v1), T(v2), T(pd)};
   const double rE = r * E;
 
@@ -143,8 +144,8 @@ __device__ FluxT<typename Prec::T> sweep_segment(const Params &P, const PencilRe
     const T dmm = from_left(dm[0]), dmp = from_right(dm[0]);
     T eta = steepen_eta<T>(gam, qm[0], qp[0], qm[4], qp[4], d2m, d2p);
     if (eta != T(0)) {
-      l[0] = l[0] * (T(1) - eta) + (qm[0] + T(0.5) * dmm) * eta;
-      rr[0] = rr[0] * (T(1) - eta) + (qp[0] - T(0.5) * dmp) * eta;
+      l[0] = mad<T>(l[0], T(1) - eta, mad<T>(T(0.5), dmm, qm[0]) * eta);
+      rr[0] = mad<T>(rr[0], T(1) - eta, mad<T>(T(-0.5), dmp, qp[0]) * eta);
     }
   }
   if (flatten) {
@@ -154,15 +155,14 @@ __device__ FluxT<typename Prec::T> sweep_segment(const Params &P, const PencilRe
     if (f != T(0)) {
 #pragma unroll
       for (int k = 0; k < 5; ++k) {
-        l[k] = f * q[k] + (T(1) - f) * l[k];
-        rr[k] = f * q[k] + (T(1) - f) * rr[k];
+        l[k] = mad<T>(f, q[k], (T(1) - f) * l[k]);
+        rr[k] = mad<T>(f, q[k], (T(1) - f) * rr[k]);
       }
     }
   }
 #pragma unroll
   for (int k = 0; k < 5; ++k) monotonize<T>(q[k], l[k], rr[k], dq[k], q6[k]);
   const T rho_floor = T(P.rho_floor), p_floor = T(P.p_floor);
-  const T cc = T(cd);
   // left state of face j+1/2 (from this cell) and right state of face
   // (j-1)+1/2 (from this cell); face j+1/2 takes its right state from lane j+1
   const State<T> sl = trace_edge<T, true>(gam, l, rr, dq, q6, q[1], cc, tlam, rho_floor, p_floor);

@@ -117,6 +117,14 @@ template <> __device__ __forceinline__ float xsqrt<float>(float a) {
   return __builtin_amdgcn_sqrtf(a);
 }
 
+// a * b + c: in double two rounded operations, exactly the expression as
+// written (the FP64 path reproduces the oracle bit for bit); in the float
+// stages of the mixed precision one fused multiply-add.
+template <class T> __device__ __forceinline__ T mad(T a, T b, T c) { return a * b + c; }
+template <> __device__ __forceinline__ float mad<float>(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
 // The ratio test a/b > t of the selection rules, as a > t*b when b > 0 (every
 // physical state) and as written otherwise; the quotient is formed only when
 // some lane of the wave has b <= 0.
@@ -128,16 +136,36 @@ __device__ __forceinline__ bool ratio_above(double a, double b, double t) {
 // ---------------------------------------------------------------------------
 // Pressure from the dual-energy selection rule (eta1) and the sound speed.
 // Velocities in pencil order: normal u, then the two transverse components.
-__device__ __forceinline__ void eos(const Params &P, double rho, double u, double v1, double v2,
-                                    double E, double e, double &p, double &c) {
+__device__ __forceinline__ double eos_pressure(const Params &P, double rho, double u, double v1,
+                                               double v2, double E, double e) {
   const double g = P.gamma;
   double ke = 0.5 * (u * u + v1 * v1 + v2 * v2);
   double eps = E - ke;
   if ((P.flags & kDualEnergy) && !ratio_above(eps, E, P.eta1)) eps = e;
   double pp = (g - 1.0) * rho * eps;
   if (pp < P.p_floor) pp = P.p_floor;
+  return pp;
+}
+__device__ __forceinline__ void eos(const Params &P, double rho, double u, double v1, double v2,
+                                    double E, double e, double &p, double &c) {
+  const double pp = eos_pressure(P, rho, u, v1, v2, E, e);
   p = pp;
-  c = dsqrt(ddiv(g * pp, rho));
+  c = dsqrt(ddiv(P.gamma * pp, rho));
+}
+// The pressure (double, from the selection rule) and the sound speed in the
+// reconstruction type T: for float, sqrt(g p / rho) with the float
+// reciprocal and square root (p / rho stays in range at the floors).
+template <class T>
+__device__ __forceinline__ void eos_cell(const Params &P, double rho, double u, double v1,
+                                         double v2, double E, double e, double &p, T &c) {
+  if constexpr (sizeof(T) == sizeof(double)) {
+    double cd;
+    eos(P, rho, u, v1, v2, E, e, p, cd);
+    c = cd;
+  } else {
+    p = eos_pressure(P, rho, u, v1, v2, E, e);
+    c = __builtin_amdgcn_sqrtf(float(P.gamma) * float(p) * __builtin_amdgcn_rcpf(float(rho)));
+  }
 }
 
 // CW84 limited slope of a cell from its two neighbours.
@@ -156,12 +184,12 @@ template <class T> __device__ __forceinline__ T limited_slope(T qm, T q0, T qp) 
 
 // Fourth-order interface value between two cells from their limited slopes.
 template <class T> __device__ __forceinline__ T interface_value(T q0, T q1, T dm0, T dm1) {
-  return T(0.5) * (q0 + q1) - T(kC16) * (dm1 - dm0);
+  return mad<T>(T(-kC16), dm1 - dm0, T(0.5) * (q0 + q1));
 }
 
 // Second difference of the density centred on a cell.
 template <class T> __device__ __forceinline__ T second_diff(T qm, T q0, T qp) {
-  return qp - T(2) * q0 + qm;
+  return mad<T>(T(-2), q0, qp) + qm;
 }
 
 // Contact-steepening weight eta of a cell (0 = no steepening).
@@ -200,22 +228,24 @@ template <class T> __device__ __forceinline__ void monotonize(T q, T &l, T &r, T
     r = q;
   } else {
     T d = r - l;
-    T s = d * (q - T(0.5) * (l + r));
+    T s = d * mad<T>(T(-0.5), l + r, q);
     T d2 = d * d * T(kC16);
-    if (s > d2) l = T(3) * q - T(2) * r;
-    else if (-d2 > s) r = T(3) * q - T(2) * l;
+    if (s > d2) l = mad<T>(T(-2), r, T(3) * q);
+    else if (-d2 > s) r = mad<T>(T(-2), l, T(3) * q);
   }
   dq = r - l;
-  q6 = T(6) * (q - T(0.5) * (l + r));
+  q6 = T(6) * mad<T>(T(-0.5), l + r, q);
 }
 
 // Average of the parabola over the right-edge domain of a right-moving wave
 // of Courant number y, and over the left-edge domain of a left-moving one.
 template <class T> __device__ __forceinline__ T avg_right(T qr, T dq, T q6, T y) {
-  return qr - T(0.5) * y * (dq - (T(1) - T(kC23) * y) * q6);
+  const T a = mad<T>(T(-kC23), y, T(1));
+  return mad<T>(-(T(0.5) * y), mad<T>(-a, q6, dq), qr);
 }
 template <class T> __device__ __forceinline__ T avg_left(T ql, T dq, T q6, T y) {
-  return ql + T(0.5) * y * (dq + (T(1) - T(kC23) * y) * q6);
+  const T a = mad<T>(T(-kC23), y, T(1));
+  return mad<T>(T(0.5) * y, mad<T>(a, q6, dq), ql);
 }
 
 // A cell's parabola for the five reconstructed quantities.
@@ -284,19 +314,19 @@ __device__ __forceinline__ State<T> trace_edge(double g, const T (&ql)[5], const
   }
   if (slow_on) {
     T us = avg(1, yslow), ps = avg(4, yslow);
-    if (RightEdge) bslow = T(0.5) * iC * ((ut - us) - (pt - ps) * iC);          // beta-minus
-    else bslow = T(-0.5) * iC * ((ut - us) + (pt - ps) * iC);                   // beta-plus
+    if (RightEdge) bslow = T(0.5) * iC * mad<T>(-(pt - ps), iC, ut - us);     // beta-minus
+    else bslow = T(-0.5) * iC * mad<T>(pt - ps, iC, ut - us);                  // beta-plus
   }
   if (zero_on) {
     T r0 = avg(0, y0), p0 = avg(4, y0);
-    b0 = (pt - p0) * iC * iC + irt - xdiv<T>(T(1), r0);
+    b0 = mad<T>((pt - p0) * iC, iC, irt) - xdiv<T>(T(1), r0);
   }
   T bp = RightEdge ? bref : bslow;
   T bm = RightEdge ? bslow : bref;
   T ps;
-  if constexpr (sizeof(T) == sizeof(double)) ps = pt + C * C * (bp + bm);
-  else ps = pt + C * (C * (bp + bm));  // C^2 alone can lie below the float range
-  T us = ut + C * (bp - bm);
+  if constexpr (sizeof(T) == sizeof(double)) ps = mad<T>(C * C, bp + bm, pt);
+  else ps = mad<T>(C, C * (bp + bm), pt);  // C^2 alone can lie below the float range
+  T us = mad<T>(C, bp - bm, ut);
   T tau = irt - (bp + bm + b0);
   T rs = tau > T(0) ? xdiv<T>(T(1), tau) : rt;
   s.r = vmax<T>(rs, rho_floor);
@@ -444,8 +474,70 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   return F;
 }
 
+// Double reciprocal and reciprocal square root to about an ulp: the
+// hardware estimates refined by two Newton steps (fused multiply-adds).
+// For the mixed precision's double arithmetic, which needs double accuracy
+// but not the correctly rounded results of the FP64 path.
+__device__ __forceinline__ double rcp64(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  y = fma(y, fma(-h * y, y, 0.5), y);
+  return fma(y, fma(-h * y, y, 0.5), y);
+}
+
+// Star pressure of the two-shock problem for the mixed precision, in double
+// with the same iteration, stopping rule and cap as two_shock_star: with
+// X = 1 + (g+1)/(2g) (p/p_s - 1) and y = 1/sqrt(X), the Lagrangian speed is
+// W_s = C_s X y, 1/W_s = y / C_s, and Newton's step needs 1/Z_s =
+// (W_s^2 + C_s^2) / (2 W_s^3) = (1 + y^2) / (2 W_s), so an iteration takes one
+// reciprocal square root per side and one reciprocal, each to about an ulp.
+__device__ __forceinline__ StarState two_shock_star_mixed(const Params &P, double rl, double ul,
+                                                          double pl, double rr, double ur,
+                                                          double pr) {
+  const double g = P.gamma;
+  const double G1 = (g + 1.0) / (2.0 * g);
+  const double al = g * pl * rl, ar = g * pr * rr;
+  const double icl = rsqrt64(al), icr = rsqrt64(ar);
+  const double cl = al * icl, cr = ar * icr;
+  const double ipl = rcp64(pl), ipr = rcp64(pr);
+  double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) * rcp64(cl + cr);
+  if (ps < P.p_floor) ps = P.p_floor;
+  int it = 0;
+  bool capped = false;
+  double wl, wr, iwl, iwr, usl, usr, yl, yr;
+  for (;;) {
+    const double xl = fma(G1, fma(ps, ipl, -1.0), 1.0);
+    const double xr = fma(G1, fma(ps, ipr, -1.0), 1.0);
+    yl = rsqrt64(xl);
+    yr = rsqrt64(xr);
+    wl = cl * (xl * yl);
+    wr = cr * (xr * yr);
+    iwl = icl * yl;
+    iwr = icr * yr;
+    usl = fma(-(ps - pl), iwl, ul);
+    usr = fma(ps - pr, iwr, ur);
+    if (capped || it == P.riemann_max_iter) break;
+    const double izl = fma(yl, yl, 1.0) * (0.5 * iwl);
+    const double izr = fma(yr, yr, 1.0) * (0.5 * iwr);
+    double pn = fma(-(usr - usl), rcp64(izl + izr), ps);
+    if (pn < P.p_floor) pn = P.p_floor;
+    ++it;
+    if (fabs(pn - ps) <= P.riemann_rtol * pn) break;
+    ps = pn;
+    if (it == P.riemann_max_iter) capped = true;
+  }
+  return StarState{ps, wl, wr, iwl, iwr, usl, usr, it};
+}
+
 // Two-shock flux of the mixed precision: the traced states come in float; the
-// star pressure is iterated in double exactly as above; the sampling of the
+// star pressure is iterated in double (two_shock_star_mixed); the sampling of the
 // solution at x/t = 0 and the mass, momentum and internal-energy fluxes are
 // formed in float (hardware reciprocal and square root), the total-energy
 // flux in double from the sampled float state.
@@ -453,8 +545,8 @@ __device__ __forceinline__ FluxT<float> two_shock_flux_mixed(const Params &P, fl
                                                              float v1l, float v2l, float pl,
                                                              float rr, float ur, float v1r,
                                                              float v2r, float pr) {
-  const StarState st = two_shock_star(P, double(rl), double(ul), double(pl), double(rr),
-                                      double(ur), double(pr));
+  const StarState st = two_shock_star_mixed(P, double(rl), double(ul), double(pl), double(rr),
+                                            double(ur), double(pr));
   const float g = float(P.gamma);
   const float ps = float(st.ps);
   const float us = float(0.5 * (st.usl + st.usr));
@@ -462,11 +554,11 @@ __device__ __forceinline__ FluxT<float> two_shock_flux_mixed(const Params &P, fl
   const float rK = left ? rl : rr, uK = left ? ul : ur, pK = left ? pl : pr;
   const float wK = float(left ? st.wl : st.wr), iwK = float(left ? st.iwl : st.iwr);
   const float irK = __builtin_amdgcn_rcpf(rK);
-  float rs = __builtin_amdgcn_rcpf(irK - (ps - pK) * iwK * iwK);
+  float rs = __builtin_amdgcn_rcpf(__builtin_fmaf(-(ps - pK) * iwK, iwK, irK));
   if (rs < float(P.rho_floor)) rs = float(P.rho_floor);
   float rb, ub, pb;
   if (ps > pK) {  // shock on the upwind side: its speed u_K -+ W_K / rho_K
-    const float S = left ? uK - wK * irK : uK + wK * irK;
+    const float S = __builtin_fmaf(left ? -wK : wK, irK, uK);
     const bool keep = left ? S >= 0.0f : S <= 0.0f;
     if (keep) { rb = rK; ub = uK; pb = pK; }
     else { rb = rs; ub = us; pb = ps; }
@@ -481,9 +573,9 @@ __device__ __forceinline__ FluxT<float> two_shock_flux_mixed(const Params &P, fl
     else if (star) { rb = rs; ub = us; pb = ps; }
     else {
       const float w = head * __builtin_amdgcn_rcpf(head - tail);
-      rb = (1.0f - w) * rK + w * rs;
-      ub = (1.0f - w) * uK + w * us;
-      pb = (1.0f - w) * pK + w * ps;
+      rb = __builtin_fmaf(w, rs - rK, rK);
+      ub = __builtin_fmaf(w, us - uK, uK);
+      pb = __builtin_fmaf(w, ps - pK, pK);
     }
   }
   const float v1 = left ? v1l : v1r;
@@ -491,7 +583,7 @@ __device__ __forceinline__ FluxT<float> two_shock_flux_mixed(const Params &P, fl
   FluxT<float> F;
   const float fr = rb * ub;
   F.m[0] = fr;
-  F.m[1] = fr * ub + pb;
+  F.m[1] = __builtin_fmaf(fr, ub, pb);
   F.m[2] = fr * v1;
   F.m[3] = fr * v2;
   F.e = fr * (pb * __builtin_amdgcn_rcpf((g - 1.0f) * rb));
@@ -706,17 +798,17 @@ __device__ __forceinline__ bool update_cell(const Params &P, double lam,
                                             bool grav = false, double hg = 0.0) {
   const bool dual = (P.flags & kDualEnergy) != 0;
   const float lf = float(lam);
-  const float rn = c.rho - lf * (Fp.m[0] - Fm.m[0]);
-  float mu = c.rho * c.u - lf * (Fp.m[1] - Fm.m[1]);
-  const float m1 = c.rho * c.v1 - lf * (Fp.m[2] - Fm.m[2]);
-  const float m2 = c.rho * c.v2 - lf * (Fp.m[3] - Fm.m[3]);
+  const float rn = __builtin_fmaf(-lf, Fp.m[0] - Fm.m[0], c.rho);
+  float mu = __builtin_fmaf(-lf, Fp.m[1] - Fm.m[1], c.rho * c.u);
+  const float m1 = __builtin_fmaf(-lf, Fp.m[2] - Fm.m[2], c.rho * c.v1);
+  const float m2 = __builtin_fmaf(-lf, Fp.m[3] - Fm.m[3], c.rho * c.v2);
   const double rd = c.rho;
   double mE = rd * c.E - lam * (Fp.E - Fm.E);
   const double me = rd * c.e - lam * (double(Fp.e) - double(Fm.e)) -
                     lam * c.p * (double(Fp.ub) - double(Fm.ub));
   if (grav) {
     const float hf = float(hg);
-    mu = mu + hf * (c.rho + rn);
+    mu = __builtin_fmaf(hf, c.rho + rn, mu);
     mE = mE + hg * (rd * double(c.u) + double(mu));
   }
   const float irf = __builtin_amdgcn_rcpf(rn);

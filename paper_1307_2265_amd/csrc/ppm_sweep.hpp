@@ -243,8 +243,8 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   T q[5][5];       // cells k-4..k: rho, u, v1, v2, p
   double pd[5];    // cells k-4..k: pressure in double (update source term)
   T cw[2];         // cells k-3 and k-2: sound speed (cw[0] is cell r)
-  double c_head;   // sound speed of the head cell
-  double c_km1;
+  T c_head;        // sound speed of the head cell
+  T c_km1;
   double rE[3];    // cells k-2..k: rho*E of the sweep input
   double m3[5];    // cells k-5..k-1: max of rho*E over the cell and its neighbours
   T dm[4][5];      // cells k-4..k-1: limited slopes
@@ -280,7 +280,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     for (int j = 0; j < 5; ++j) fc[i][j] = T(0);
   }
   cw[0] = cw[1] = T(0);
-  c_head = c_km1 = 0.0;
+  c_head = c_km1 = T(0);
   lcarry = State<T>{T(0), T(0), T(0), T(0), T(0)};
   ft_b = zero_flux<T>();
 #pragma unroll
@@ -314,8 +314,9 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
         const int64_t o = pc.base + int64_t(k + 1) * pc.stride;
         nr = pc.rho[o]; nu = pc.u[o]; nv1 = pc.v1[o]; nv2 = pc.v2[o]; nE = pc.E[o]; ne = pc.e[o];
       }
-      double p, c;
-      eos(P, r, u, v1, v2, E, e, p, c);
+      double p;
+      T c;
+      eos_cell<T>(P, r, u, v1, v2, E, e, p, c);
       q[4][0] = T(r); q[4][1] = T(u); q[4][2] = T(v1); q[4][3] = T(v2); q[4][4] = T(p);
       if (!kExactP) pd[4] = p;
       c_head = c;
@@ -353,8 +354,8 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       if (steepen) {
         T eta = steepen_eta<T>(gam, q[0][0], q[2][0], q[0][4], q[2][4], d2[0], d2[2]);
         if (eta != T(0)) {
-          l[0] = l[0] * (T(1) - eta) + (q[0][0] + T(0.5) * dm[0][0]) * eta;
-          rr[0] = rr[0] * (T(1) - eta) + (q[2][0] - T(0.5) * dm[2][0]) * eta;
+          l[0] = mad<T>(l[0], T(1) - eta, mad<T>(T(0.5), dm[0][0], q[0][0]) * eta);
+          rr[0] = mad<T>(rr[0], T(1) - eta, mad<T>(T(-0.5), dm[2][0], q[2][0]) * eta);
         }
       }
       if (flatten) {
@@ -363,8 +364,8 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
         if (f != T(0)) {
 #pragma unroll
           for (int j = 0; j < 5; ++j) {
-            l[j] = f * q[1][j] + (T(1) - f) * l[j];
-            rr[j] = f * q[1][j] + (T(1) - f) * rr[j];
+            l[j] = mad<T>(f, q[1][j], (T(1) - f) * l[j]);
+            rr[j] = mad<T>(f, q[1][j], (T(1) - f) * rr[j]);
           }
         }
       }
@@ -518,7 +519,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       for (int j = 0; j < 5; ++j) fc[i][j] = fc[i + 1][j];
     }
     cw[0] = cw[1];
-    cw[1] = T(c_km1);
+    cw[1] = c_km1;
     c_km1 = c_head;
   }
 }
