@@ -591,7 +591,7 @@ __device__ __forceinline__ FluxT<float> two_shock_flux_mixed(const Params &P, fl
   // total energy flux in double: rho u is exact in double for float factors
   const double rbd = rb, ubd = ub, pbd = pb, v1d = v1, v2d = v2;
   const double frd = rbd * ubd;
-  const double eb = ddiv(pbd, (P.gamma - 1.0) * rbd);
+  const double eb = pbd * rcp64((P.gamma - 1.0) * rbd);
   F.E = frd * (eb + 0.5 * (ubd * ubd + v1d * v1d + v2d * v2d)) + ubd * pbd;
   return F;
 }
@@ -814,7 +814,7 @@ __device__ __forceinline__ bool update_cell(const Params &P, double lam,
   const float irf = __builtin_amdgcn_rcpf(rn);
   const float unf = mu * irf, v1f = m1 * irf, v2f = m2 * irf;
   const double rnd = rn;
-  const double ir = ddiv(1.0, rnd);
+  const double ir = rcp64(rnd);
   const double un = unf, v1n = v1f, v2n = v2f;
   const double En = mE * ir, eraw = me * ir;
   const double ke = 0.5 * (un * un + v1n * v1n + v2n * v2n);

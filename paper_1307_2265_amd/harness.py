@@ -246,3 +246,92 @@ def batch_input(npatch: int, seed: int = 1003):
             f[k] = f[k].astype(np.float32).astype(np.float64)
         fields.append(f)
     return specs, fields
+
+
+def active(a, ghost: int = W.GHOST):
+    """The active block of a ghosted (z, y, x) array."""
+    g = ghost
+    return a[g:-g, g:-g, g:-g]
+
+
+def swept_cells(dims: tuple, order: tuple, ghost: int = W.GHOST) -> tuple:
+    """(cells written, pencils) of each sweep of one step of a patch with
+    active dims (nx, ny, nz) in sweep order `order`: the k-th sweep updates
+    the cells active along the axes swept so far and along its own axis and
+    every index along the axes still to come."""
+    out = []
+    done = set()
+    for axis in order:
+        w = 1
+        for t in range(3):
+            if t == axis:
+                continue
+            w *= dims[t] if t in done else dims[t] + 2 * ghost
+        out.append((w * dims[axis], w))
+        done.add(axis)
+    return out
+
+
+def step_bytes(dims_list, read_b: float, write_b: float, ghost: int = W.GHOST) -> float:
+    """Algorithmic HBM bytes of one step over patches of the given active dims
+    (the mean of the xyz and zyx orders): every sweep reads each pencil's
+    n + 2g cells and writes its n active ones, and the last sweep's
+    timestep needs no extra pass."""
+    tot = 0.0
+    for dims in dims_list:
+        for order in ORDERS:
+            for (cells, pencils) in swept_cells(dims, order, ghost):
+                tot += 0.5 * (cells * (read_b + write_b) + pencils * 2 * ghost * read_b)
+    return tot
+
+
+class Hierarchy:
+    """The cosmology-shaped hierarchy on the device: an n_root^3 periodic root
+    grid (log-normal Gaussian random field density, cold bulk flows) and
+    `npatch` patches of 16^3-48^3 on levels 1-8 with ghosts injected from the
+    root, stored as views into one flat buffer per field, flux registers on.
+    FP64 or mixed storage."""
+
+    NLEV = 9
+
+    def __init__(self, prec: int, n_root: int = 1024, npatch: int = 20000, seed: int = 1004,
+                 ghost: int = W.GHOST, log=None):
+        torch = _torch()
+        say = log or (lambda m: None)
+        G = ghost
+        low = torch.float32 if prec == ppm.PPM_MIXED else torch.float64
+        self.prec, self.n_root, self.ghost = prec, n_root, ghost
+        say(f"generating the {n_root}^3 root")
+        root64 = W.hierarchy_root(n_root, seed, ghost=ghost)
+        self.specs = W.hierarchy_specs(npatch, n_root, seed)
+        sizes = [(s.nz + 2 * G) * (s.ny + 2 * G) * (s.nx + 2 * G) for s in self.specs]
+        self.offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        say(f"injecting {npatch} patches ({self.offs[-1] / 1e9:.2f} G cells)")
+        self.flat = {f: torch.empty(int(self.offs[-1]), device="cuda",
+                                    dtype=torch.float64 if f in ("etot", "eint") else low)
+                     for f in FIELDS}
+        for i, s in enumerate(self.specs):
+            pf = W.inject_patch(root64, s, n_root, ghost)
+            for f in FIELDS:
+                self.flat[f][self.offs[i]:self.offs[i + 1]].copy_(pf[f].reshape(-1))
+            if (i + 1) % 5000 == 0:
+                say(f"  {i + 1} patches")
+        rsz = [ppm.ppm_flux_reg_size(s.nx, s.ny, s.nz) for s in self.specs]
+        self.roffs = np.concatenate([[0], np.cumsum(rsz)]).astype(np.int64)
+        self.reg = torch.zeros(int(self.roffs[-1]), dtype=torch.float64, device="cuda")
+        self.root = {f: root64[f] if f in ("etot", "eint") else root64[f].to(low)
+                     for f in FIELDS}
+        del root64
+        torch.cuda.empty_cache()
+        h = 1.0 / n_root
+        self.patches = [ppm.Patch(**self.root, dx=h, dy=h, dz=h, ghost=G, level=0,
+                                  bc=ppm.PPM_BC_PERIODIC)]
+        for i, s in enumerate(self.specs):
+            shape = (s.nz + 2 * G, s.ny + 2 * G, s.nx + 2 * G)
+            views = {f: self.flat[f][self.offs[i]:self.offs[i + 1]].view(shape) for f in FIELDS}
+            self.patches.append(ppm.Patch(**views, dx=s.dx, dy=s.dx, dz=s.dx, ghost=G,
+                                          level=s.level,
+                                          flux_reg=self.reg[self.roffs[i]:self.roffs[i + 1]],
+                                          bc=ppm.PPM_BC_SUPPLIED))
+        self.dims = [(n_root,) * 3] + [(s.nx, s.ny, s.nz) for s in self.specs]
+        self.cells = int(sum(a * b * c for a, b, c in self.dims))

@@ -57,38 +57,10 @@ def P():
 
 def _build(P, prec):
     """Device fields of the root and the flat patch buffers, and the plan."""
-    import torch
-    low = torch.float32 if prec == P.PPM_MIXED else torch.float64
-    say(f"generating the {N_ROOT}^3 root")
-    root64 = W.hierarchy_root(N_ROOT, SEED)
-    specs = W.hierarchy_specs(NPATCH, N_ROOT, SEED)
-    sizes = [(s.nz + 2 * G) * (s.ny + 2 * G) * (s.nx + 2 * G) for s in specs]
-    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    say(f"injecting {NPATCH} patches ({offs[-1] / 1e9:.2f} G cells)")
-    flat = {f: torch.empty(int(offs[-1]), device="cuda",
-                           dtype=torch.float64 if f in ("etot", "eint") else low)
-            for f in FIELDS}
-    for i, s in enumerate(specs):
-        pf = W.inject_patch(root64, s, N_ROOT)
-        for f in FIELDS:
-            flat[f][offs[i]:offs[i + 1]].copy_(pf[f].reshape(-1))
-        if (i + 1) % 5000 == 0:
-            say(f"  {i + 1} patches")
-    rsz = [P.ppm_flux_reg_size(s.nx, s.ny, s.nz) for s in specs]
-    roffs = np.concatenate([[0], np.cumsum(rsz)]).astype(np.int64)
-    reg = torch.zeros(int(roffs[-1]), dtype=torch.float64, device="cuda")
-    root = {f: root64[f] if f in ("etot", "eint") else root64[f].to(low) for f in FIELDS}
-    del root64
-    torch.cuda.empty_cache()
-    h = 1.0 / N_ROOT
-    patches = [P.Patch(**root, dx=h, dy=h, dz=h, ghost=G, level=0, bc=P.PPM_BC_PERIODIC)]
-    for i, s in enumerate(specs):
-        shape = (s.nz + 2 * G, s.ny + 2 * G, s.nx + 2 * G)
-        views = {f: flat[f][offs[i]:offs[i + 1]].view(shape) for f in FIELDS}
-        patches.append(P.Patch(**views, dx=s.dx, dy=s.dx, dz=s.dx, ghost=G, level=s.level,
-                               flux_reg=reg[roffs[i]:roffs[i + 1]], bc=P.PPM_BC_SUPPLIED))
-    plan = P.Plan(patches, NLEV, prec, P.params())
-    return root, flat, offs, reg, roffs, specs, patches, plan
+    from paper_1307_2265_amd import harness as H
+    h = H.Hierarchy(prec, N_ROOT, NPATCH, SEED, G, log=say)
+    plan = P.Plan(h.patches, NLEV, prec, P.params())
+    return h.root, h.flat, h.offs, h.reg, h.roffs, h.specs, h.patches, plan
 
 
 def _host(t):
