@@ -643,8 +643,10 @@ ppm_status ppm_amr_create(ppm_amr **out, const ppm_patch *patches, const ppm_pat
     if (h->members[l].empty()) continue;
     std::vector<ppm_patch> lp;
     for (int32_t p : h->members[l]) lp.push_back(patches[p]);
+    // per-sweep launches over all of a level's patches (faster than a
+    // workgroup per patch for many small patches)
     if ((st = ppm_plan_create(&h->lplan[l], lp.data(), int32_t(lp.size()), nlevels, prec, params,
-                              nullptr, hip_stream)) != PPM_OK)
+                              "persistent=0", hip_stream)) != PPM_OK)
       return bail(st);
   }
   hipError_t e;

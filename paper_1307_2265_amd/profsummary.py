@@ -122,8 +122,10 @@ def _per_dispatch(path: str, counter: str):
 
 
 def traffic(fetch_csv: str, write_csv: str, n: int, ghost: int, cmd_fetch: str, cmd_write: str,
-            out: str, json_out: str | None):
-    copy_bytes = float((n + 2 * ghost) ** 3 * 8)
+            out: str, json_out: str | None, copy_bytes: float = float(1 << 31)):
+    """copy_bytes: size of the largest device-to-device copies of the run
+    (bench.py's achievable-bandwidth copy, 2 GiB), whose counter readings
+    calibrate each counter."""
     F = _per_dispatch(fetch_csv, "FETCH_SIZE")
     Wr = _per_dispatch(write_csv, "WRITE_SIZE")
 
@@ -148,8 +150,9 @@ def traffic(fetch_csv: str, write_csv: str, n: int, ghost: int, cmd_fetch: str, 
     lines = [f"# HBM bytes per dispatch: {os.path.basename(out)[:-3]}", "",
              "Commands (from the repository root, `cd /tmp && export TMPDIR=/tmp` first):", "",
              "```", cmd_fetch, cmd_write, "```", "",
-             f"Calibration: the run copies whole fields of (n+2g)^3 = {(n + 2 * ghost) ** 3} doubles "
-             f"({copy_bytes / 1e9:.4f} GB) device to device; FETCH_SIZE reads "
+             f"Calibration: the largest device-to-device copies of the run move "
+             f"{copy_bytes / 1e9:.4f} GB each (the benchmark's achievable-bandwidth copy); "
+             f"FETCH_SIZE reads "
              f"{copy_bytes / cf / 1e9:.4f} GB for such a copy ({nf} copies), WRITE_SIZE "
              f"{copy_bytes / cw / 1e9:.4f} GB ({nw} copies).  Scale factors: fetch x{cf:.4f}, "
              f"write x{cw:.4f}.", "",
@@ -178,6 +181,7 @@ def traffic(fetch_csv: str, write_csv: str, n: int, ghost: int, cmd_fetch: str, 
     if json_out:
         with open(json_out, "w") as fo:
             json.dump({"source_digest": kernel_source_digest(), "workload_n": n, "ghost": ghost,
+                   "calibration_copy_bytes": copy_bytes,
                        "fetch_scale": cf, "write_scale": cw, "profile": os.path.basename(out),
                        "kernels": per_kernel}, fo, indent=1)
 
@@ -295,6 +299,7 @@ def main():
     t.add_argument("fetch")
     t.add_argument("write")
     t.add_argument("--n", type=int, default=512)
+    t.add_argument("--copy-bytes", type=float, default=float(1 << 31))
     t.add_argument("--ghost", type=int, default=3)
     t.add_argument("--cmd-fetch", required=True)
     t.add_argument("--cmd-write", required=True)
@@ -314,7 +319,8 @@ def main():
     elif a.mode == "valu":
         valu(a.flops, a.lds, a.cmd_flops, a.cmd_lds, a.out)
     else:
-        traffic(a.fetch, a.write, a.n, a.ghost, a.cmd_fetch, a.cmd_write, a.out, a.json)
+        traffic(a.fetch, a.write, a.n, a.ghost, a.cmd_fetch, a.cmd_write, a.out, a.json,
+                a.copy_bytes)
 
 
 if __name__ == "__main__":

@@ -40,3 +40,27 @@ def test_valu_mix_and_lds_tables(tmp_path):
     assert "| 2 | 1.000 | 1.0 / 2.0 / 3.0 / 1.0 | 0.64 (0.008) |" in row[0], row[0]
     assert "| 2 | 4.00 | 8.00 | 2.000 | 0.250 |" in row[1], row[1]
     assert "cmd-flops" in text and "cmd-lds" in text
+
+
+def test_traffic_is_calibrated_by_the_largest_copies(tmp_path):
+    # a 2 GiB device-to-device copy for which FETCH_SIZE reads half the bytes
+    # and WRITE_SIZE all of them; a sweep dispatch reading 4 and writing 3 GB
+    cols = ["Dispatch_Id", "Grid_Size", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    gib2 = float(1 << 31)
+
+    def write(path, counter, copy_v, sweep_v):
+        with open(path, "w", newline="") as f:
+            w = csv.writer(f)
+            w.writerow(cols)
+            for d in (1, 2, 3):
+                w.writerow([d, 4096, "__amd_rocclr_copyBuffer", counter, copy_v])
+            w.writerow([4, 4096, "__amd_rocclr_copyBuffer", counter, copy_v / 8])  # smaller copy
+            w.writerow([5, 262144, KERNEL, counter, sweep_v])
+    fetch, wr = tmp_path / "f.csv", tmp_path / "w.csv"
+    write(fetch, "FETCH_SIZE", gib2 / 2 / 1024, 2e9 / 1024)
+    write(wr, "WRITE_SIZE", gib2 / 1024, 3e9 / 1024)
+    out, js = tmp_path / "t.md", tmp_path / "t.json"
+    S.traffic(str(fetch), str(wr), 512, 3, "cf", "cw", str(out), str(js))
+    import json
+    k = json.load(open(js))["kernels"]["sweep_kernel<PrecF64, false, false, false, false>"]
+    assert abs(k["fetch_bytes"] - 4e9) < 1e3 and abs(k["write_bytes"] - 3e9) < 1e3
