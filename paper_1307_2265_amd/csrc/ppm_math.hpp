@@ -491,23 +491,36 @@ __device__ __forceinline__ double rsqrt64(double x) {
   y = fma(y, fma(-h * y, y, 0.5), y);
   return fma(y, fma(-h * y, y, 0.5), y);
 }
+// The same with one Newton step: the hardware estimates carry about 24
+// correct bits, so the result is good to about 2^-47 -- ample where the value
+// feeds an iteration that corrects it or a float result.
+__device__ __forceinline__ double rcp64_1(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return fma(y, fma(-x, y, 1.0), y);
+}
+__device__ __forceinline__ double rsqrt64_1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(y, fma(-(0.5 * x) * y, y, 0.5), y);
+}
 
 // Star pressure of the two-shock problem for the mixed precision, in double
 // with the same iteration, stopping rule and cap as two_shock_star: with
 // X = 1 + (g+1)/(2g) (p/p_s - 1) and y = 1/sqrt(X), the Lagrangian speed is
 // W_s = C_s X y, 1/W_s = y / C_s, and Newton's step needs 1/Z_s =
 // (W_s^2 + C_s^2) / (2 W_s^3) = (1 + y^2) / (2 W_s), so an iteration takes one
-// reciprocal square root per side and one reciprocal, each to about an ulp.
+// reciprocal square root per side and one reciprocal, each good to about
+// 2^-47 (the iteration converges to the root of the function so evaluated,
+// within a few 1e-15 of the exact one).
 __device__ __forceinline__ StarState two_shock_star_mixed(const Params &P, double rl, double ul,
                                                           double pl, double rr, double ur,
                                                           double pr) {
   const double g = P.gamma;
   const double G1 = (g + 1.0) / (2.0 * g);
   const double al = g * pl * rl, ar = g * pr * rr;
-  const double icl = rsqrt64(al), icr = rsqrt64(ar);
+  const double icl = rsqrt64_1(al), icr = rsqrt64_1(ar);
   const double cl = al * icl, cr = ar * icr;
-  const double ipl = rcp64(pl), ipr = rcp64(pr);
-  double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) * rcp64(cl + cr);
+  const double ipl = rcp64_1(pl), ipr = rcp64_1(pr);
+  double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) * rcp64_1(cl + cr);
   if (ps < P.p_floor) ps = P.p_floor;
   int it = 0;
   bool capped = false;
@@ -515,8 +528,8 @@ __device__ __forceinline__ StarState two_shock_star_mixed(const Params &P, doubl
   for (;;) {
     const double xl = fma(G1, fma(ps, ipl, -1.0), 1.0);
     const double xr = fma(G1, fma(ps, ipr, -1.0), 1.0);
-    yl = rsqrt64(xl);
-    yr = rsqrt64(xr);
+    yl = rsqrt64_1(xl);
+    yr = rsqrt64_1(xr);
     wl = cl * (xl * yl);
     wr = cr * (xr * yr);
     iwl = icl * yl;
@@ -526,7 +539,7 @@ __device__ __forceinline__ StarState two_shock_star_mixed(const Params &P, doubl
     if (capped || it == P.riemann_max_iter) break;
     const double izl = fma(yl, yl, 1.0) * (0.5 * iwl);
     const double izr = fma(yr, yr, 1.0) * (0.5 * iwr);
-    double pn = fma(-(usr - usl), rcp64(izl + izr), ps);
+    double pn = fma(-(usr - usl), rcp64_1(izl + izr), ps);
     if (pn < P.p_floor) pn = P.p_floor;
     ++it;
     if (fabs(pn - ps) <= P.riemann_rtol * pn) break;
