@@ -158,7 +158,11 @@ int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
  *                  to a wavefront with its cells across the lanes (pencils of
  *                  at most 64 cells are packed side by side, 64/n per wave);
  *                  the other sweeps give each pencil to one thread that
- *                  marches it.  Default 1 (x only).
+ *                  marches it.  Default 1 (x only), except for one patch
+ *                  with (nx + 2 ghost)(nz + 2 ghost) below 128 x the number
+ *                  of compute units (too few pencils to fill the device one
+ *                  thread each) and a tile_config that sets none of lanes,
+ *                  block, tail and tail_round: then 7 (every axis).
  *   block=B        threads per block of the marching kernel (64..256;
  *                  default 256 for one patch, 64 for several).
  *   lanes_block=B  threads per block of the lane-parallel kernel (64..256;

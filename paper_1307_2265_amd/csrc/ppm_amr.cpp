@@ -74,15 +74,13 @@ struct ppm_amr {
   double h_dt[64] = {}, h_cfl = 0.0;
   // parents' states before their last step, and blended to a child's time
   std::vector<void *> old_bufs, blend_bufs;
-  PatchDev *d_blend = nullptr;                 // patch table with the parents' blends
-  ppm::BlendItem *d_blend_s = nullptr, *d_blend_d = nullptr;  // per level: float/double fields
-  int64_t *d_blend_sp = nullptr, *d_blend_dp = nullptr;
-  std::vector<int32_t> blend_sbeg, blend_dbeg;  // nlevels + 1
-  std::vector<int64_t> blend_stot, blend_dtot;
-  ppm::CopyItem *d_copyitems = nullptr;        // per level: the fields of its parents
-  int64_t *d_copyprefix = nullptr;
-  std::vector<int32_t> copy_beg;               // nlevels + 1
-  std::vector<int64_t> copy_total;
+  PatchDev *d_old = nullptr;                   // patch tables with the saved states and
+  PatchDev *d_blend = nullptr;                 // the blends of the parents
+  // per parent level: the parent cells its children's interpolation reads
+  ppm::CellBox *d_need = nullptr;
+  int64_t *d_needprefix = nullptr;             // one extra entry per level
+  std::vector<int32_t> need_beg;               // nlevels + 1
+  std::vector<int64_t> need_total;
   // coarse fluxes through child footprints, per level and axis
   double *d_cap = nullptr;
   ppm::CaptureRow *d_rows = nullptr;
@@ -120,16 +118,17 @@ void destroy(ppm_amr *h) {
     if (p) ppm_plan_destroy(p);
   for (void *b : h->old_bufs) (void)hipFree(b);
   for (void *b : h->blend_bufs) (void)hipFree(b);
-  void *bufs[] = {h->d_dt,      h->d_cfl,       h->d_blend,   h->d_cap,      h->d_rows,
-                  h->d_acc,     h->d_accitems,  h->d_accprefix, h->d_targets, h->d_contribs,
-                  h->d_proj,    h->d_projprefix, h->d_copyitems, h->d_copyprefix,
-                  h->d_blend_s, h->d_blend_d,   h->d_blend_sp, h->d_blend_dp};
+  void *bufs[] = {h->d_dt,   h->d_cfl,      h->d_old,       h->d_blend,   h->d_cap,
+                  h->d_rows, h->d_acc,      h->d_accitems,  h->d_accprefix, h->d_targets,
+                  h->d_contribs, h->d_proj, h->d_projprefix, h->d_need,   h->d_needprefix};
   for (void *b : bufs)
     if (b) (void)hipFree(b);
   delete h;
 }
 
 size_t storage_bytes(ppm_precision prec) { return prec == PPM_FP64 ? 8 : 4; }
+
+int64_t floor_div(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
 
 int64_t ghosted_cells(const ppm_patch &q) {
   return (int64_t(q.nx) + 2 * q.ghost) * (int64_t(q.ny) + 2 * q.ghost) *
@@ -149,13 +148,14 @@ ppm_status fill(ppm_amr *h, int l, hipStream_t s) {
     return ppm_detail::fill_ghosts(h->all, l, nullptr, s);
   // the parents' stored fields at this level's time, blended in double
   const double w = (h->t[l] - h->t_old[pl]) / (h->t[pl] - h->t_old[pl]);
-  const int32_t s0 = h->blend_sbeg[pl], ns = h->blend_sbeg[pl + 1] - s0;
-  const int32_t d0 = h->blend_dbeg[pl], nd = h->blend_dbeg[pl + 1] - d0;
-  hipError_t e = ppm::launch_blend(h->d_blend_s + s0, h->d_blend_sp + s0 + pl, ns,
-                                   h->blend_stot[pl], h->prec == PPM_MIXED, w, s);
-  if (e == hipSuccess)
-    e = ppm::launch_blend(h->d_blend_d + d0, h->d_blend_dp + d0 + pl, nd, h->blend_dtot[pl],
-                          false, w, s);
+  const int32_t b0 = h->need_beg[pl], nb = h->need_beg[pl + 1] - b0;
+  hipError_t e = h->prec == PPM_FP64
+      ? ppm::launch_box_state<ppm::PrecF64>(h->all->d_patches, h->d_old, h->d_blend,
+                                            h->d_need + b0, h->d_needprefix + b0 + pl, nb,
+                                            h->need_total[pl], true, w, s)
+      : ppm::launch_box_state<ppm::PrecMixed>(h->all->d_patches, h->d_old, h->d_blend,
+                                              h->d_need + b0, h->d_needprefix + b0 + pl, nb,
+                                              h->need_total[pl], true, w, s);
   if (e != hipSuccess) return hip_fail(e, "time blend launch");
   return ppm_detail::fill_ghosts(h->all, l, h->d_blend, s);
 }
@@ -193,10 +193,15 @@ ppm_status step_level(ppm_amr *h, int l, int order, hipStream_t s) {
 }
 
 ppm_status save_old(ppm_amr *h, int l, hipStream_t s) {
-  const int32_t i0 = h->copy_beg[l], ni = h->copy_beg[l + 1] - i0;
-  if (ni == 0) return PPM_OK;
-  hipError_t e = ppm::launch_copy_words(h->d_copyitems + i0, h->d_copyprefix + i0 + l, ni,
-                                        h->copy_total[l], s);
+  const int32_t b0 = h->need_beg[l], nb = h->need_beg[l + 1] - b0;
+  if (nb == 0) return PPM_OK;
+  hipError_t e = h->prec == PPM_FP64
+      ? ppm::launch_box_state<ppm::PrecF64>(h->all->d_patches, h->d_old, h->d_blend,
+                                            h->d_need + b0, h->d_needprefix + b0 + l, nb,
+                                            h->need_total[l], false, 0.0, s)
+      : ppm::launch_box_state<ppm::PrecMixed>(h->all->d_patches, h->d_old, h->d_blend,
+                                              h->d_need + b0, h->d_needprefix + b0 + l, nb,
+                                              h->need_total[l], false, 0.0, s);
   if (e != hipSuccess) return hip_fail(e, "old-state copy launch");
   return PPM_OK;
 }
@@ -279,10 +284,11 @@ ppm_status build_lists(ppm_amr *h) {
   const size_t sb = storage_bytes(h->prec);
   hipError_t e;
   // old-state and blend buffers of every patch with children, and the patch
-  // table through which the parent interpolation reads the blends
+  // tables through which the saves and blends write them and the parent
+  // interpolation reads the blends
   h->old_bufs.assign(size_t(np) * 6, nullptr);
   h->blend_bufs.assign(size_t(np) * 6, nullptr);
-  std::vector<PatchDev> blend_tab(h->all->host);
+  std::vector<PatchDev> old_tab(h->all->host), blend_tab(h->all->host);
   for (int p = 0; p < np; ++p) {
     if (h->children[p].empty()) continue;
     const int64_t n = ghosted_cells(h->patches[p]);
@@ -292,87 +298,65 @@ ppm_status build_lists(ppm_amr *h) {
           (e = hipMalloc(&h->blend_bufs[size_t(p) * 6 + f], bytes)) != hipSuccess)
         return hip_fail(e, "old-state allocation");
     }
-    PatchDev &d = blend_tab[p];
-    d.rho = h->blend_bufs[size_t(p) * 6];
-    for (int a = 0; a < 3; ++a) d.vel[a] = h->blend_bufs[size_t(p) * 6 + 1 + a];
-    d.etot = static_cast<double *>(h->blend_bufs[size_t(p) * 6 + 4]);
-    d.eint = static_cast<double *>(h->blend_bufs[size_t(p) * 6 + 5]);
+    for (int k = 0; k < 2; ++k) {
+      PatchDev &d = k ? blend_tab[p] : old_tab[p];
+      const std::vector<void *> &bufs = k ? h->blend_bufs : h->old_bufs;
+      d.rho = bufs[size_t(p) * 6];
+      for (int a = 0; a < 3; ++a) d.vel[a] = bufs[size_t(p) * 6 + 1 + a];
+      d.etot = static_cast<double *>(bufs[size_t(p) * 6 + 4]);
+      d.eint = static_cast<double *>(bufs[size_t(p) * 6 + 5]);
+    }
   }
-  if ((e = upload(&h->d_blend, blend_tab)) != hipSuccess) return hip_fail(e, "blend table");
-  // per level, the blends of its parents: the float fields of the mixed
-  // precision, and the double fields (all six in FP64, so one launch blends
-  // them) (prefix arrays with one extra entry per level)
+  if ((e = upload(&h->d_old, old_tab)) != hipSuccess ||
+      (e = upload(&h->d_blend, blend_tab)) != hipSuccess)
+    return hip_fail(e, "saved-state tables");
+  // The parent cells that the children's ghost interpolation reads: the
+  // 27-cell neighbourhoods of the parent cells that its boxes refine, merged
+  // per parent into disjoint boxes.  Only these cells are saved before a
+  // parent's step and blended to a child's time.
   {
-    std::vector<ppm::BlendItem> bs, bd;
-    std::vector<int64_t> ps, pd;
-    h->blend_sbeg.assign(size_t(L) + 1, 0);
-    h->blend_dbeg.assign(size_t(L) + 1, 0);
-    h->blend_stot.assign(size_t(L) + 1, 0);
-    h->blend_dtot.assign(size_t(L) + 1, 0);
+    std::vector<std::vector<ppm_detail::IBox>> need(static_cast<size_t>(np));
+    const ppm_plan *A = h->all;
+    for (const ppm::InterpItem &it : A->h_interp) {
+      const PatchDev &f = A->host[it.patch], &c = A->host[it.parent];
+      ppm_detail::IBox b{};
+      for (int a = 0; a < 3; ++a) {
+        const int64_t c0 = floor_div(int64_t(it.start[a]) + it.lo[a] - f.ghost, it.r);
+        const int64_t c1 = floor_div(int64_t(it.start[a]) + it.hi[a] - 1 - f.ghost, it.r);
+        b.lo[a] = c0 - 1 - it.pstart[a] + c.ghost;
+        b.hi[a] = c1 + 2 - it.pstart[a] + c.ghost;
+      }
+      std::vector<ppm_detail::IBox> pieces{b};
+      for (const ppm_detail::IBox &q : need[size_t(it.parent)]) ppm_detail::boxes_minus(pieces, q);
+      need[size_t(it.parent)].insert(need[size_t(it.parent)].end(), pieces.begin(), pieces.end());
+    }
+    std::vector<ppm::CellBox> boxes;
+    std::vector<int64_t> prefix;
+    h->need_beg.assign(size_t(L) + 1, 0);
+    h->need_total.assign(size_t(L) + 1, 0);
     for (int l = 0; l < L; ++l) {
-      h->blend_sbeg[l] = int32_t(bs.size());
-      h->blend_dbeg[l] = int32_t(bd.size());
-      int64_t rs = 0, rd = 0;
-      for (int32_t p : h->members[l]) {
-        if (h->children[p].empty()) continue;
-        const ppm_patch &q = h->patches[p];
-        const int64_t n = ghosted_cells(q);
-        const void *cur[6] = {q.rho, q.vx, q.vy, q.vz, q.etot, q.eint};
-        for (int f = 0; f < 6; ++f) {
-          const ppm::BlendItem it{h->old_bufs[size_t(p) * 6 + f], cur[f],
-                                  h->blend_bufs[size_t(p) * 6 + f]};
-          if (f < 4 && h->prec == PPM_MIXED) {
-            bs.push_back(it);
-            ps.push_back(rs);
-            rs += n;
-          } else {
-            bd.push_back(it);
-            pd.push_back(rd);
-            rd += n;
+      h->need_beg[l] = int32_t(boxes.size());
+      int64_t run = 0;
+      for (int32_t p : h->members[l])
+        for (const ppm_detail::IBox &q : need[size_t(p)]) {
+          ppm::CellBox cb{};
+          cb.patch = p;
+          for (int a = 0; a < 3; ++a) {
+            cb.lo[a] = int32_t(q.lo[a]);
+            cb.hi[a] = int32_t(q.hi[a]);
           }
+          boxes.push_back(cb);
+          prefix.push_back(run);
+          run += q.volume();
         }
-      }
-      ps.push_back(rs);
-      pd.push_back(rd);
-      h->blend_stot[l] = rs;
-      h->blend_dtot[l] = rd;
+      prefix.push_back(run);
+      h->need_total[l] = run;
     }
-    h->blend_sbeg[L] = int32_t(bs.size());
-    h->blend_dbeg[L] = int32_t(bd.size());
-    if ((e = upload(&h->d_blend_s, bs)) != hipSuccess ||
-        (e = upload(&h->d_blend_d, bd)) != hipSuccess ||
-        (e = upload(&h->d_blend_sp, ps)) != hipSuccess ||
-        (e = upload(&h->d_blend_dp, pd)) != hipSuccess)
-      return hip_fail(e, "blend lists");
+    h->need_beg[L] = int32_t(boxes.size());
+    if ((e = upload(&h->d_need, boxes)) != hipSuccess ||
+        (e = upload(&h->d_needprefix, prefix)) != hipSuccess)
+      return hip_fail(e, "saved-cell lists");
   }
-  // the copies that save them, per level, in 32-bit words (prefix arrays with
-  // one extra entry per level)
-  std::vector<ppm::CopyItem> copies;
-  std::vector<int64_t> cprefix;
-  h->copy_beg.assign(size_t(L) + 1, 0);
-  h->copy_total.assign(size_t(L) + 1, 0);
-  for (int l = 0; l < L; ++l) {
-    h->copy_beg[l] = int32_t(copies.size());
-    int64_t run = 0;
-    for (int32_t p : h->members[l]) {
-      if (h->children[p].empty()) continue;
-      const ppm_patch &q = h->patches[p];
-      const int64_t n = ghosted_cells(q);
-      const void *src[6] = {q.rho, q.vx, q.vy, q.vz, q.etot, q.eint};
-      for (int f = 0; f < 6; ++f) {
-        copies.push_back(ppm::CopyItem{static_cast<const uint32_t *>(src[f]),
-                                       static_cast<uint32_t *>(h->old_bufs[size_t(p) * 6 + f])});
-        cprefix.push_back(run);
-        run += n * int64_t(f < 4 ? sb : 8) / 4;
-      }
-    }
-    cprefix.push_back(run);
-    h->copy_total[l] = run;
-  }
-  h->copy_beg[L] = int32_t(copies.size());
-  if ((e = upload(&h->d_copyitems, copies)) != hipSuccess ||
-      (e = upload(&h->d_copyprefix, cprefix)) != hipSuccess)
-    return hip_fail(e, "old-state copy lists");
 
   // capture blocks: per parent, per child, a register-shaped block
   std::vector<int64_t> cap_off(size_t(np), -1);  // per child

@@ -144,9 +144,11 @@ ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
     if (k == "block") {
       if (v < 64 || v > ppm::kMaxBlock || v % 64) return fail(PPM_EINVAL, "tile_config: block must be 64..256, a multiple of 64");
       pl->block = int32_t(v);
+      pl->lanes_set = true;
     } else if (k == "lanes") {
       if (v < 0 || v > 7) return fail(PPM_EINVAL, "tile_config: lanes is an axis bitmask 0..7");
       pl->lanes_mask = int32_t(v);
+      pl->lanes_set = true;
     } else if (k == "lanes_block") {
       if (v < 64 || v > ppm::kMaxBlock || v % 64) return fail(PPM_EINVAL, "tile_config: lanes_block must be 64..256, a multiple of 64");
       pl->lanes_block = int32_t(v);
@@ -157,9 +159,11 @@ ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
     } else if (k == "tail") {
       if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: tail must be 0 or 1");
       pl->tail = int32_t(v);
+      pl->lanes_set = true;
     } else if (k == "tail_round") {
       if (v < 64 || v > (1 << 26) || v % 64) return fail(PPM_EINVAL, "tile_config: tail_round must be a multiple of 64 in 64..2^26");
       pl->tail_round = int32_t(v);
+      pl->lanes_set = true;
     } else if (k == "persistent") {
       if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: persistent must be 0 or 1");
       pl->persistent = int32_t(v);
@@ -295,6 +299,20 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
                 (long long)kPersistentMaxCells);
   }
   (void)hipGetDevice(&pl->device);
+  // One small patch: a marching sweep would give each of its few pencils a
+  // thread and leave most of the device idle (a 128^3 grid's y sweep has
+  // 134^2 pencils for 2 x 256 resident threads on each of 256 CUs), so every
+  // sweep streams its pencils through the lanes instead (measured: 128^3 FP64
+  // 1.80 -> 1.25 ms per step; from 192^3 on the marching sweeps are faster).
+  if (npatch == 1 && !pl->lanes_set) {
+    int cus0 = 0;
+    if (hipDeviceGetAttribute(&cus0, hipDeviceAttributeMultiprocessorCount, pl->device) !=
+        hipSuccess)
+      cus0 = 0;
+    const ppm_patch &q = patches[0];
+    const int64_t pencils = (int64_t(q.nx) + 2 * q.ghost) * (int64_t(q.nz) + 2 * q.ghost);
+    if (cus0 > 0 && pencils * 8 < int64_t(cus0) * 2 * 256 * 2) pl->lanes_mask = 7;
+  }
   pl->host.resize(npatch);
   pl->bc.resize(npatch);
   for (int i = 0; i < npatch; ++i) pl->bc[i] = patches[i].bc;
@@ -565,17 +583,41 @@ ppm_status ppm_fill_boundary(ppm_plan *plan, int32_t patch, const int32_t *kinds
 
 namespace {
 int64_t floor_div64(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
-// Parent cells (in the parent's level) whose r^3 fine cells meet the
-// ghosted box of a patch that starts at `start` of its level: one thread each
-// in the parent-interpolation launch.
-int64_t parent_box_count(const PatchDev &d, const int32_t start[3], int32_t r) {
+// Parent cells (in the parent's level) whose r^3 fine cells meet the box
+// [lo, hi) of local (ghosted) cells of a patch that starts at `start` of its
+// level: one thread each in the parent-interpolation launch.
+int64_t parent_box_count(const PatchDev &d, const int32_t start[3], int32_t r,
+                         const int32_t lo[3], const int32_t hi[3]) {
   int64_t v = 1;
   for (int a = 0; a < 3; ++a) {
-    const int64_t lo = floor_div64(int64_t(start[a]) - d.ghost, r);
-    const int64_t hi = floor_div64(int64_t(start[a]) + d.n[a] + d.ghost - 1, r);
-    v *= hi - lo + 1;
+    const int64_t c0 = floor_div64(int64_t(start[a]) + lo[a] - d.ghost, r);
+    const int64_t c1 = floor_div64(int64_t(start[a]) + hi[a] - 1 - d.ghost, r);
+    v *= c1 - c0 + 1;
   }
   return v;
+}
+// The ghost cells of a patch as six disjoint slabs of local (ghosted)
+// indices: below and above the active cells along z (whole x-y planes), then
+// along y (active z), then along x (active y and z).
+void ghost_slabs(const PatchDev &d, std::vector<ppm_detail::IBox> &v) {
+  const int64_t g = d.ghost;
+  v.clear();
+  for (int a = 2; a >= 0; --a)
+    for (int side = 0; side < 2; ++side) {
+      ppm_detail::IBox b{};
+      for (int k = 0; k < 3; ++k) {
+        const int64_t n = d.n[k];
+        if (k == a) {
+          b.lo[k] = side ? g + n : 0;
+          b.hi[k] = side ? n + 2 * g : g;
+        } else if (k > a) {
+          b.lo[k] = g; b.hi[k] = g + n;
+        } else {
+          b.lo[k] = 0; b.hi[k] = n + 2 * g;
+        }
+      }
+      if (b.volume() > 0) v.push_back(b);
+    }
 }
 }  // namespace
 
@@ -602,7 +644,9 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
                                 "(axis %d)", i, q.parent, a);
     }
   }
-  // interpolation items and sibling boxes, grouped by level
+  // sibling boxes, and the ghost cells that no sibling covers, which the
+  // parent interpolation fills (the others would be overwritten by the
+  // sibling copies that follow it), grouped by level
   std::vector<ppm::InterpItem> items;
   std::vector<ppm::SiblingBox> boxes;
   std::vector<int64_t> ipre, bpre;
@@ -610,27 +654,13 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
   std::vector<int64_t> itot(nl, 0), btot(nl, 0);
   std::vector<std::vector<int>> bylevel(nl);
   for (int i = 0; i < np; ++i) bylevel[H[i].level].push_back(i);
+  std::vector<std::vector<ppm_detail::IBox>> uncovered(np);
   for (int L = 0; L < nl; ++L) {
-    ibeg[L] = int32_t(items.size());
-    int64_t acc = 0;
-    for (int i : bylevel[L]) {
-      if (place[i].parent < 0) continue;
-      ppm::InterpItem it{};
-      it.patch = i; it.parent = place[i].parent; it.r = place[i].refine;
-      for (int a = 0; a < 3; ++a) {
-        it.start[a] = place[i].start[a];
-        it.pstart[a] = place[place[i].parent].start[a];
-      }
-      items.push_back(it);
-      ipre.push_back(acc);
-      acc += parent_box_count(H[i], place[i].start, place[i].refine);
-    }
-    ipre.push_back(acc);
-    itot[L] = acc;
     bbeg[L] = int32_t(boxes.size());
     int64_t bacc = 0;
     for (int d : bylevel[L]) {
       if (place[d].parent < 0) continue;
+      ghost_slabs(H[d], uncovered[d]);
       for (int src : bylevel[L]) {
         if (src == d) continue;
         ppm::SiblingBox b{};
@@ -650,10 +680,34 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
         boxes.push_back(b);
         bpre.push_back(bacc);
         bacc += int64_t(b.hi[0] - b.lo[0]) * (b.hi[1] - b.lo[1]) * (b.hi[2] - b.lo[2]);
+        ppm_detail::boxes_minus(uncovered[d], ppm_detail::IBox{{b.lo[0], b.lo[1], b.lo[2]},
+                                                               {b.hi[0], b.hi[1], b.hi[2]}});
       }
     }
     bpre.push_back(bacc);
     btot[L] = bacc;
+  }
+  for (int L = 0; L < nl; ++L) {
+    ibeg[L] = int32_t(items.size());
+    int64_t acc = 0;
+    for (int i : bylevel[L]) {
+      if (place[i].parent < 0) continue;
+      for (const ppm_detail::IBox &u : uncovered[i]) {
+        ppm::InterpItem it{};
+        it.patch = i; it.parent = place[i].parent; it.r = place[i].refine;
+        for (int a = 0; a < 3; ++a) {
+          it.start[a] = place[i].start[a];
+          it.pstart[a] = place[place[i].parent].start[a];
+          it.lo[a] = int32_t(u.lo[a]);
+          it.hi[a] = int32_t(u.hi[a]);
+        }
+        items.push_back(it);
+        ipre.push_back(acc);
+        acc += parent_box_count(H[i], it.start, it.r, it.lo, it.hi);
+      }
+    }
+    ipre.push_back(acc);
+    itot[L] = acc;
   }
   ibeg[nl] = int32_t(items.size());
   bbeg[nl] = int32_t(boxes.size());
@@ -681,6 +735,7 @@ ppm_status ppm_set_hierarchy(ppm_plan *plan, const ppm_patch_place *place, void 
     return hip_fail(e, "hierarchy upload");
   if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hierarchy upload");
   plan->ibeg = ibeg; plan->bbeg = bbeg; plan->itotal = itot; plan->btotal = btot;
+  plan->h_interp = std::move(items);
   plan->hier = true;
   return PPM_OK;
 }
@@ -690,6 +745,36 @@ ppm_status ppm_fill_ghosts(ppm_plan *plan, int32_t level, void *hip_stream) {
 }
 
 }  // extern "C"
+
+void ppm_detail::boxes_minus(std::vector<IBox> &list, const IBox &b) {
+  std::vector<IBox> out;
+  out.reserve(list.size() + 6);
+  for (IBox a : list) {
+    bool meets = true;
+    for (int k = 0; k < 3; ++k) meets = meets && a.lo[k] < b.hi[k] && b.lo[k] < a.hi[k];
+    if (!meets) {
+      out.push_back(a);
+      continue;
+    }
+    // peel off the parts below and above b along each axis in turn; what
+    // remains of a lies inside b
+    for (int k = 0; k < 3; ++k) {
+      if (a.lo[k] < b.lo[k]) {
+        IBox piece = a;
+        piece.hi[k] = b.lo[k];
+        out.push_back(piece);
+        a.lo[k] = b.lo[k];
+      }
+      if (a.hi[k] > b.hi[k]) {
+        IBox piece = a;
+        piece.lo[k] = b.hi[k];
+        out.push_back(piece);
+        a.hi[k] = b.hi[k];
+      }
+    }
+  }
+  list.swap(out);
+}
 
 ppm_status ppm_detail::fill_ghosts(ppm_plan *plan, int32_t level, const PatchDev *parent_tab,
                                    hipStream_t s) {

@@ -585,14 +585,14 @@ __device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64
   return lo;
 }
 
-// One thread per parent cell whose fine cells meet a listed patch's ghosted
-// box (the box of such cells in the parent's level, in x-fastest order): if
-// any of its r^3 fine cells is a ghost cell of the patch, the 27-cell
+// One thread per parent cell that a listed box's cells refine (the box of
+// such cells in the parent's level, in x-fastest order): the 27-cell
 // neighbourhood of rho, rho v, rho E, rho e around it, the SecondOrderA slopes
-// of each, and for every such fine cell the interpolant's values, stored as
-// rho, v = (rho v)/rho, E, e.  The parent's state is read through
-// parent_tab[parent] when given (the parent blended in time), else from the
-// patch table.
+// of each, and for every one of its r^3 fine cells inside the box the
+// interpolant's values, stored as rho, v = (rho v)/rho, E, e.  A parent cell
+// whose fine cells fall in two boxes is interpolated by both, to the same
+// values.  The parent's state is read through parent_tab[parent] when given
+// (the parent blended in time), else from the patch table.
 template <class Prec>
 __global__ void __launch_bounds__(256)
 fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *__restrict__ items,
@@ -606,38 +606,30 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
   const PatchDev fd = patches[item.patch];
   const PatchDev cd = parent_tab ? parent_tab[item.parent] : patches[item.parent];
   const int gf = fd.ghost, gc = cd.ghost, r = item.r;
-  const int64_t Nf[3] = {fd.n[0], fd.n[1], fd.n[2]};
-  const int64_t nf[3] = {Nf[0] + 2 * gf, Nf[1] + 2 * gf, Nf[2] + 2 * gf};
+  const int64_t nf[3] = {int64_t(fd.n[0]) + 2 * gf, int64_t(fd.n[1]) + 2 * gf,
+                         int64_t(fd.n[2]) + 2 * gf};
   const int64_t nc[3] = {int64_t(cd.n[0]) + 2 * gc, int64_t(cd.n[1]) + 2 * gc,
                          int64_t(cd.n[2]) + 2 * gc};
   int64_t clo[3], cext[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    clo[a] = floor_div(int64_t(item.start[a]) - gf, r);
-    cext[a] = floor_div(int64_t(item.start[a]) + Nf[a] + gf - 1, r) - clo[a] + 1;
+    clo[a] = floor_div(int64_t(item.start[a]) + item.lo[a] - gf, r);
+    cext[a] = floor_div(int64_t(item.start[a]) + item.hi[a] - 1 - gf, r) - clo[a] + 1;
   }
   const int64_t u = t - prefix[it];
   const int64_t cc[3] = {clo[0] + u % cext[0], clo[1] + (u / cext[0]) % cext[1],
                          clo[2] + u / (cext[0] * cext[1])};
-  // local index of the first of its fine cells in the patch; which are ghosts
+  // local index of the first of its fine cells in the patch; which are in the box
   int64_t f0[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) f0[a] = cc[a] * r - item.start[a] + gf;
-  auto ghost_at = [&](int i, int j, int k) {
+  auto in_box = [&](int i, int j, int k) {
     const int64_t f[3] = {f0[0] + i, f0[1] + j, f0[2] + k};
-    bool inside = true, active = true;
+    bool in = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      inside = inside && f[a] >= 0 && f[a] < nf[a];
-      active = active && f[a] >= gf && f[a] < gf + Nf[a];
-    }
-    return inside && !active;
+    for (int a = 0; a < 3; ++a) in = in && f[a] >= item.lo[a] && f[a] < item.hi[a];
+    return in;
   };
-  bool any = false;
-  for (int k = 0; k < r; ++k)
-    for (int j = 0; j < r; ++j)
-      for (int i = 0; i < r; ++i) any = any || ghost_at(i, j, k);
-  if (!any) return;
   int64_t lc[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) lc[a] = cc[a] - item.pstart[a] + gc;
@@ -665,7 +657,7 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
   for (int k = 0; k < r; ++k)
     for (int j = 0; j < r; ++j)
       for (int i = 0; i < r; ++i) {
-        if (!ghost_at(i, j, k)) continue;
+        if (!in_box(i, j, k)) continue;
         double q[6];
 #pragma unroll
         for (int comp = 0; comp < 6; ++comp)
@@ -770,15 +762,45 @@ capture_kernel(const PatchDev *__restrict__ patches, const CaptureRow *__restric
   }
 }
 
+// One thread per cell of the listed boxes, all six fields (see
+// launch_box_state).
+template <class Prec, bool kBlend>
 __global__ void __launch_bounds__(256)
-copy_words_kernel(const CopyItem *__restrict__ items, const int64_t *__restrict__ prefix,
-                  int32_t nitems, int64_t total) {
+box_state_kernel(const PatchDev *__restrict__ cur_tab, const PatchDev *__restrict__ old_tab,
+                 const PatchDev *__restrict__ mid_tab, const CellBox *__restrict__ boxes,
+                 const int64_t *__restrict__ prefix, int32_t nboxes, int64_t total, double w) {
+  using S = typename Prec::S;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= total) return;
-  const int it = find_item(prefix, nitems, t);
-  const CopyItem item = items[it];
-  const int64_t u = t - prefix[it];
-  item.dst[u] = item.src[u];
+  const int b = find_item(prefix, nboxes, t);
+  const CellBox box = boxes[b];
+  const int64_t u = t - prefix[b];
+  const int64_t ex = box.hi[0] - box.lo[0], ey = box.hi[1] - box.lo[1];
+  const int64_t c[3] = {box.lo[0] + u % ex, box.lo[1] + (u / ex) % ey, box.lo[2] + u / (ex * ey)};
+  const PatchDev cd = cur_tab[box.patch];
+  const PatchDev od = old_tab[box.patch];
+  const int64_t g = cd.ghost;
+  const int64_t nx = cd.n[0] + 2 * g, ny = cd.n[1] + 2 * g;
+  const int64_t o = (c[2] * ny + c[1]) * nx + c[0];
+  const S *cs[4] = {static_cast<const S *>(cd.rho), static_cast<const S *>(cd.vel[0]),
+                    static_cast<const S *>(cd.vel[1]), static_cast<const S *>(cd.vel[2])};
+  S *os[4] = {static_cast<S *>(od.rho), static_cast<S *>(od.vel[0]),
+              static_cast<S *>(od.vel[1]), static_cast<S *>(od.vel[2])};
+  if (!kBlend) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f) os[f][o] = cs[f][o];
+    od.etot[o] = cd.etot[o];
+    od.eint[o] = cd.eint[o];
+    return;
+  }
+  const PatchDev md = mid_tab[box.patch];
+  S *ms[4] = {static_cast<S *>(md.rho), static_cast<S *>(md.vel[0]),
+              static_cast<S *>(md.vel[1]), static_cast<S *>(md.vel[2])};
+  const double wo = 1.0 - w;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) ms[f][o] = S(wo * double(os[f][o]) + w * double(cs[f][o]));
+  md.etot[o] = wo * od.etot[o] + w * cd.etot[o];
+  md.eint[o] = wo * od.eint[o] + w * cd.eint[o];
 }
 
 __global__ void __launch_bounds__(256)
@@ -1069,32 +1091,6 @@ hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *it
   return hipGetLastError();
 }
 
-template <class T>
-__global__ void __launch_bounds__(256)
-blend_kernel(const BlendItem *__restrict__ items, const int64_t *__restrict__ prefix,
-             int32_t nitems, int64_t total, double w) {
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int it = find_item(prefix, nitems, t);
-  const BlendItem item = items[it];
-  const int64_t u = t - prefix[it];
-  const double wo = 1.0 - w;
-  static_cast<T *>(item.dst)[u] =
-      T(wo * double(static_cast<const T *>(item.old)[u]) + w * double(static_cast<const T *>(item.cur)[u]));
-}
-
-hipError_t launch_blend(const BlendItem *items, const int64_t *prefix, int32_t nitems,
-                        int64_t total, bool single, double w, hipStream_t s) {
-  if (total <= 0) return hipSuccess;
-  const dim3 grid(unsigned((total + 255) / 256));
-  if (single)
-    hipLaunchKernelGGL(blend_kernel<float>, grid, dim3(256), 0, s, items, prefix, nitems, total, w);
-  else
-    hipLaunchKernelGGL(blend_kernel<double>, grid, dim3(256), 0, s, items, prefix, nitems, total,
-                       w);
-  return hipGetLastError();
-}
-
 template <class Prec>
 hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32_t nrows,
                           int32_t axis, const double *dt_dev, const Params &P, hipStream_t s) {
@@ -1111,11 +1107,18 @@ hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32
   return hipGetLastError();
 }
 
-hipError_t launch_copy_words(const CopyItem *items, const int64_t *prefix, int32_t nitems,
-                             int64_t total, hipStream_t s) {
+template <class Prec>
+hipError_t launch_box_state(const PatchDev *cur, const PatchDev *old, const PatchDev *mid,
+                            const CellBox *boxes, const int64_t *prefix, int32_t nboxes,
+                            int64_t total, bool blend, double w, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  hipLaunchKernelGGL(copy_words_kernel, dim3(unsigned((total + 255) / 256)), dim3(256), 0, s,
-                     items, prefix, nitems, total);
+  const dim3 grid(unsigned((total + 255) / 256));
+  if (blend)
+    hipLaunchKernelGGL((box_state_kernel<Prec, true>), grid, dim3(256), 0, s, cur, old, mid,
+                       boxes, prefix, nboxes, total, w);
+  else
+    hipLaunchKernelGGL((box_state_kernel<Prec, false>), grid, dim3(256), 0, s, cur, old, mid,
+                       boxes, prefix, nboxes, total, w);
   return hipGetLastError();
 }
 
@@ -1264,6 +1267,13 @@ template hipError_t launch_fill_from_parent<PrecF64>(const PatchDev *, const Int
 template hipError_t launch_fill_from_parent<PrecMixed>(const PatchDev *, const InterpItem *,
                                                        const int64_t *, int32_t, int64_t,
                                                        const PatchDev *, hipStream_t);
+template hipError_t launch_box_state<PrecF64>(const PatchDev *, const PatchDev *,
+                                              const PatchDev *, const CellBox *, const int64_t *,
+                                              int32_t, int64_t, bool, double, hipStream_t);
+template hipError_t launch_box_state<PrecMixed>(const PatchDev *, const PatchDev *,
+                                                const PatchDev *, const CellBox *,
+                                                const int64_t *, int32_t, int64_t, bool, double,
+                                                hipStream_t);
 template hipError_t launch_copy_from_siblings<PrecF64>(const PatchDev *, const SiblingBox *,
                                                        const int64_t *, int32_t, int64_t,
                                                        hipStream_t);

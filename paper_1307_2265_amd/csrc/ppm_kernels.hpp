@@ -81,12 +81,14 @@ struct FaceRules {
 template <class Prec>
 hipError_t launch_fill_boundary(const PatchDev &pd, const FaceRules &fr, hipStream_t s);
 
-// A patch whose ghost cells come from its parent: indices into the patch
-// table, refinement factor, global start of the first active cell of the
-// patch (in its level) and of its parent (in the parent's level).
+// A box of a patch's ghost cells that take their values from its parent:
+// indices into the patch table, refinement factor, global start of the first
+// active cell of the patch (in its level) and of its parent (in the parent's
+// level), and the box [lo, hi) in the patch's local (ghosted) indices.
 struct InterpItem {
   int32_t patch, parent, r;
   int32_t start[3], pstart[3];
+  int32_t lo[3], hi[3];
 };
 // Cells of patch dst outside its active region that lie in the active
 // region of sibling src: the box [lo, hi) in dst's local (ghosted) indices,
@@ -97,24 +99,31 @@ struct SiblingBox {
 };
 
 // Ghost cells of items[0..nitems): SecondOrderA interpolation of the parent's
-// conserved quantities.  prefix[i] = first ghost cell of item i in the launch
-// (prefix[nitems] = total).  parent_tab (nullable): a patch table to read
-// the parents' states from instead of `patches` (the parents blended in
-// time).
+// conserved quantities.  prefix[i] = first parent cell of item i in the launch
+// (prefix[nitems] = total), an item counting the parent cells that its box's
+// cells refine.  parent_tab (nullable): a patch table to read the parents'
+// states from instead of `patches` (the parents blended in time).
 template <class Prec>
 hipError_t launch_fill_from_parent(const PatchDev *patches, const InterpItem *items,
                                    const int64_t *prefix, int32_t nitems, int64_t total,
                                    const PatchDev *parent_tab, hipStream_t s);
 
-// dst[i] = (1 - w) old[i] + w cur[i], evaluated in double, over the listed
-// arrays of float (single) or double elements (prefix over their lengths):
-// a parent's stored fields at a time between its last two states.
-struct BlendItem {
-  const void *old, *cur;
-  void *dst;
+// A box [lo, hi) of one patch's local (ghosted) cells.
+struct CellBox {
+  int32_t patch;
+  int32_t lo[3], hi[3];
+  int32_t pad;
 };
-hipError_t launch_blend(const BlendItem *items, const int64_t *prefix, int32_t nitems,
-                        int64_t total, bool single, double w, hipStream_t s);
+
+// Over the cells of boxes[0..nboxes) (prefix over their volumes), in all six
+// fields of the patch tables, which share dimensions and differ in their
+// field pointers: blend false, old <- cur (a parent's state saved before its
+// step); blend true, mid <- (1 - w) old + w cur evaluated in double (the
+// parent at a time between its last two states).
+template <class Prec>
+hipError_t launch_box_state(const PatchDev *cur, const PatchDev *old, const PatchDev *mid,
+                            const CellBox *boxes, const int64_t *prefix, int32_t nboxes,
+                            int64_t total, bool blend, double w, hipStream_t s);
 
 // A face whose flux a coarse step records: the pencil (i1, i2) of `patch`
 // along the capture launch's axis, the face between its cells j and j+1
@@ -131,15 +140,6 @@ struct CaptureRow {
 template <class Prec>
 hipError_t launch_capture(const PatchDev *patches, const CaptureRow *rows, int32_t nrows,
                           int32_t axis, const double *dt_dev, const Params &P, hipStream_t s);
-
-// dst[i] = src[i] over the listed blocks of 32-bit words (prefix over their
-// lengths): the parents' states saved before their steps, in one launch.
-struct CopyItem {
-  const uint32_t *src;
-  uint32_t *dst;
-};
-hipError_t launch_copy_words(const CopyItem *items, const int64_t *prefix, int32_t nitems,
-                             int64_t total, hipStream_t s);
 
 // acc[i] += reg[i] over the listed register blocks (prefix over their sizes).
 struct AccItem {

@@ -20,6 +20,7 @@ struct ppm_plan {
   int32_t block = 256;            // threads (pencils) per marching-sweep block
   int32_t lanes_block = 256;      // threads per lane-parallel block (64 per pencil)
   int32_t lanes_mask = 1;         // bit a: sweeps along axis a use the lane-parallel kernel
+  bool lanes_set = false;         // lanes, or a marching-sweep shape, given in the tile config
   int32_t cfl_cells = 4096;       // active cells per CFL block
   int32_t persistent = 0;         // ppm_step as one persistent launch over all patches
   int32_t batch_block = 256;      // threads per workgroup of the persistent kernel
@@ -47,11 +48,12 @@ struct ppm_plan {
   int device = 0;
   // AMR ghost fill work lists, grouped by level (ppm_set_hierarchy)
   bool hier = false;
+  std::vector<ppm::InterpItem> h_interp;  // host copy of the interpolation boxes
   ppm::InterpItem *d_interp = nullptr;
   ppm::SiblingBox *d_boxes = nullptr;
   int64_t *d_iprefix = nullptr, *d_bprefix = nullptr;  // per level: items+1 / boxes+1 entries
   std::vector<int32_t> ibeg, bbeg;        // per level: first item / box (nlevels+1 entries)
-  std::vector<int64_t> itotal, btotal;    // per level: ghost cells / box cells
+  std::vector<int64_t> itotal, btotal;    // per level: parent cells / box cells
 };
 
 namespace ppm_detail {
@@ -71,6 +73,15 @@ double float_at_or_above(double x);
 // The device parameters of a precision (PPM_MIXED floors raised to floats;
 // no expansion factors).
 ppm::Params device_params(ppm_precision prec, const ppm_params *p);
+
+// A box [lo, hi) of cell indices.
+struct IBox {
+  int64_t lo[3], hi[3];
+  int64_t volume() const { return (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]); }
+};
+// Replace the boxes of `list` by their parts outside b: each box that meets b
+// splits into at most six disjoint pieces, so disjoint boxes stay disjoint.
+void boxes_minus(std::vector<IBox> &list, const IBox &b);
 
 // ppm_fill_ghosts of `level`, with the parents' states read through
 // parent_tab (a device patch table in the plan's order) when it is given.

@@ -32,7 +32,7 @@ def _flags(P, O):
     return P.PPM_ALL_FLAGS | P.PPM_HLLC
 
 
-@pytest.mark.parametrize("tiles", [None, "lanes=0", "lanes=7", "lanes=7 lanes_block=64",
+@pytest.mark.parametrize("tiles", [None, "lanes=1", "lanes=0", "lanes=7", "lanes=7 lanes_block=64",
                                    "block=64 lanes_block=64 tail_round=320"])
 @pytest.mark.parametrize("recipe", ["gentle", "shocked"])
 def test_hllc_single_grid_fp64(P, O, tiles, recipe):
@@ -47,7 +47,7 @@ def test_hllc_single_grid_fp64(P, O, tiles, recipe):
     assert gcnt == ocnt
 
 
-@pytest.mark.parametrize("tiles", [None, "lanes=0", "lanes=7"])
+@pytest.mark.parametrize("tiles", [None, "lanes=1", "lanes=0", "lanes=7"])
 def test_hllc_on_a_vacuum_forming_rarefaction(P, O, tiles):
     # two-shock needs the HLL fallback here; HLLC stays positive on its own
     nx, ny, nz = 4, 100, 3

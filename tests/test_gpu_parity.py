@@ -121,7 +121,7 @@ def test_flux_registers_and_seeded_ghosts_fp64(P, O):
     assert gcnt == ocnt
 
 
-@pytest.mark.parametrize("tiles", [None, "lanes=0", "lanes=7"])
+@pytest.mark.parametrize("tiles", [None, "lanes=1", "lanes=0", "lanes=7"])
 def test_hll_fallback_fires_identically(P, O, tiles):
     # Vacuum-generating double rarefaction along y in a 3-D box; the
     # two-shock update first goes non-positive after about a dozen steps.

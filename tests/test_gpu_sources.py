@@ -43,7 +43,7 @@ def _stored_accel(shape, seed, prec, P, amp=3.0):
     return acc
 
 
-@pytest.mark.parametrize("tiles", [None, "lanes=0", "lanes=7",
+@pytest.mark.parametrize("tiles", [None, "lanes=1", "lanes=0", "lanes=7",
                                    "block=64 lanes_block=64 tail_round=320"])
 @pytest.mark.parametrize("hllc", [False, True])
 def test_single_patch_gravity_and_expansion_equal_oracle(P, O, tiles, hllc):

@@ -35,7 +35,7 @@ def _field(seed, ghost=GH):
                             ghost=ghost)
 
 
-@pytest.mark.parametrize("tiles", [None, "lanes=0", "lanes=7",
+@pytest.mark.parametrize("tiles", [None, "lanes=1", "lanes=0", "lanes=7",
                                    "block=64 lanes_block=64 tail_round=320"])
 @pytest.mark.parametrize("hllc", [False, True])
 def test_single_patch_equals_oracle(P, O, tiles, hllc):
