@@ -32,6 +32,10 @@ CANDIDATES = {
         "lanes=1 block=128 lanes_block=64",
         "lanes=1 block=256 lanes_block=128 tail=0",
         "lanes=0 block=256",
+        "lanes=3 block=256 lanes_block=256",
+        "lanes=5 block=256 lanes_block=256",
+        "lanes=7 lanes_block=256",
+        "lanes=7 lanes_block=64",
     ],
     "batch": [
         "persistent=1 lanes=1 batch_block=256",
@@ -43,6 +47,14 @@ CANDIDATES = {
         "persistent=0 lanes=1 block=256 lanes_block=64",
         "persistent=0 lanes=1 block=64 lanes_block=64 group=0",
         "persistent=0 lanes=0 block=64",
+        "persistent=0 lanes=1 block=256 lanes_block=128",
+        "persistent=0 lanes=1 block=256 lanes_block=256",
+        "persistent=0 lanes=3 block=256 lanes_block=64",
+        "persistent=0 lanes=5 block=256 lanes_block=64",
+        "persistent=0 lanes=7 lanes_block=64",
+        "persistent=0 lanes=7 lanes_block=128",
+        "persistent=0 lanes=7 lanes_block=256",
+        "persistent=1 lanes=7 batch_block=256",
     ],
 }
 
