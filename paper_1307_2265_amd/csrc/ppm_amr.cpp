@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -91,7 +92,8 @@ struct ppm_amr {
   ppm::AccItem *d_accitems = nullptr;
   int64_t *d_accprefix = nullptr;
   std::vector<int32_t> acc_beg;                // per level: first item (nlevels + 1)
-  std::vector<int64_t> acc_total;              // per level
+  std::vector<int64_t> acc_total;              // per level: values summed
+  std::vector<int64_t> acc_span;               // per level: its registers' whole block
   // flux correction, per coarse level
   ppm::CorrTarget *d_targets = nullptr;
   ppm::CorrContrib *d_contribs = nullptr;
@@ -221,7 +223,7 @@ ppm_status correct_and_project(ppm_amr *h, int l, hipStream_t s) {
   const int c = l + 1;
   if (h->acc_total[c] > 0) {
     const int64_t first = h->acc_off[h->members[c].front()];
-    e = hipMemsetAsync(h->d_acc + first, 0, sizeof(double) * size_t(h->acc_total[c]), s);
+    e = hipMemsetAsync(h->d_acc + first, 0, sizeof(double) * size_t(h->acc_span[c]), s);
     if (e != hipSuccess) return hip_fail(e, "register sums reset");
   }
   const int32_t p0 = h->proj_beg[c], np = h->proj_beg[c + 1] - p0;
@@ -358,6 +360,40 @@ ppm_status build_lists(ppm_amr *h) {
       return hip_fail(e, "saved-cell lists");
   }
 
+  // The coarse cell next to face `face` of child c's footprint at transverse
+  // position (c1, c2) of the face, in the parent's active-cell indices, and
+  // whether flux correction uses it: only where no child of the parent
+  // covers that coarse cell does the coarse flux through the face meet the
+  // fine fluxes (elsewhere both sides are fine cells).
+  auto face_cell = [&](int32_t c, int face, int c1, int c2, int cc[3]) {
+    const Box &b = h->footprint[c];
+    const int a = face / 2, side = face % 2;
+    const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+    cc[a] = side == 0 ? b.lo[a] - 1 : b.hi[a];
+    cc[t1] = b.lo[t1] + c1;
+    cc[t2] = b.lo[t2] + c2;
+    bool covered = false;
+    for (int32_t o : h->children[h->place[c].parent])
+      covered = covered || h->footprint[o].has(cc[0], cc[1], cc[2]);
+    return !covered;
+  };
+  // faces of each child that some correction reads
+  std::vector<std::array<bool, 6>> face_used(static_cast<size_t>(np));
+  for (int c = 0; c < np; ++c) {
+    face_used[size_t(c)].fill(false);
+    if (h->place[c].parent < 0) continue;
+    const Box &b = h->footprint[c];
+    for (int face = 0; face < 6; ++face) {
+      const int a = face / 2;
+      const int t1 = a == 0 ? 1 : 0, t2 = a == 2 ? 1 : 2;
+      int cc[3];
+      bool used = false;
+      for (int c2 = 0; c2 < b.dim(t2) && !used; ++c2)
+        for (int c1 = 0; c1 < b.dim(t1) && !used; ++c1) used = face_cell(c, face, c1, c2, cc);
+      face_used[size_t(c)][size_t(face)] = used;
+    }
+  }
+
   // capture blocks: per parent, per child, a register-shaped block
   std::vector<int64_t> cap_off(size_t(np), -1);  // per child
   int64_t cap_total = 0;
@@ -374,9 +410,11 @@ ppm_status build_lists(ppm_amr *h) {
   int64_t acc_total = 0;
   h->acc_beg.assign(size_t(L) + 1, 0);
   h->acc_total.assign(size_t(L) + 1, 0);
+  h->acc_span.assign(size_t(L) + 1, 0);
   std::vector<int64_t> acc_item_off;       // offset of each item's sum in d_acc
   std::vector<const double *> acc_item_reg;
   std::vector<int64_t> accprefix;
+  // (only the faces that a correction reads are summed)
   for (int l = 0; l < L; ++l) {
     h->acc_beg[l] = int32_t(acc_item_off.size());
     int64_t run = 0;
@@ -385,11 +423,17 @@ ppm_status build_lists(ppm_amr *h) {
       const ppm_patch &q = h->patches[p];
       const int64_t n = ppm_flux_reg_size(q.nx, q.ny, q.nz);
       h->acc_off[p] = acc_total;
-      acc_item_off.push_back(acc_total);
-      acc_item_reg.push_back(q.flux_reg);
-      accprefix.push_back(run);
-      run += n;
+      for (int face = 0; face < 6; ++face) {
+        if (!face_used[size_t(p)][size_t(face)]) continue;
+        const int64_t f0 = reg_face_offset(q.nx, q.ny, q.nz, face);
+        const int64_t f1 = reg_face_offset(q.nx, q.ny, q.nz, face + 1);
+        acc_item_off.push_back(acc_total + f0);
+        acc_item_reg.push_back(q.flux_reg + f0);
+        accprefix.push_back(run);
+        run += f1 - f0;
+      }
       acc_total += n;
+      h->acc_span[l] += n;
     }
     accprefix.push_back(run);
     h->acc_total[l] = run;
@@ -422,9 +466,11 @@ ppm_status build_lists(ppm_amr *h) {
           for (int side = 0; side < 2; ++side) {
             double *face = h->d_cap + cap_off[c] +
                            reg_face_offset(b.dim(0), b.dim(1), b.dim(2), 2 * axis + side);
+            int cc[3];
             for (int c2 = 0; c2 < b.dim(t2); ++c2)
               for (int c1 = 0; c1 < b.dim(t1); ++c1)
-                rows.push_back(ppm::CaptureRow{
+                if (face_cell(c, 2 * axis + side, c1, c2, cc))
+                  rows.push_back(ppm::CaptureRow{
                     p, g + b.lo[t1] + c1, g + b.lo[t2] + c2,
                     g + (side == 0 ? b.lo[axis] - 1 : b.hi[axis] - 1),
                     face + int64_t(c2) * b.dim(t1) + c1, fs});
@@ -463,12 +509,7 @@ ppm_status build_lists(ppm_amr *h) {
           for (int c2 = 0; c2 < b.dim(t2); ++c2)
             for (int c1 = 0; c1 < b.dim(t1); ++c1) {
               int cc[3];
-              cc[a] = side == 0 ? b.lo[a] - 1 : b.hi[a];
-              cc[t1] = b.lo[t1] + c1;
-              cc[t2] = b.lo[t2] + c2;
-              bool covered = false;
-              for (int32_t o : ch) covered = covered || h->footprint[o].has(cc[0], cc[1], cc[2]);
-              if (covered) continue;
+              if (!face_cell(c, face, c1, c2, cc)) continue;
               const int64_t cell = ((int64_t(cc[2]) + g) * n1 + (cc[1] + g)) * n0 + (cc[0] + g);
               ppm::CorrContrib cb;
               cb.cap = cface + int64_t(c2) * b.dim(t1) + c1;
