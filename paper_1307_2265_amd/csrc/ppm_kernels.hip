@@ -1008,23 +1008,6 @@ hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start
   return hipGetLastError();
 }
 
-template <class Prec, bool kCFL>
-const void *march_kernel_ptr(uint32_t flags) {
-  if (flags & (kAnyGravity | kDiffusion))
-    return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, true, true>);
-  if (flags & kHLLC)
-    return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, true, false>);
-  return reinterpret_cast<const void *>(sweep_kernel<Prec, kCFL, false, false, false>);
-}
-
-template <class Prec>
-int march_blocks_per_cu(int32_t block, bool cfl, uint32_t flags) {
-  const size_t lds = size_t(kLdsMarch + (cfl ? 1 : 0)) * block * sizeof(double);
-  const void *k = cfl ? march_kernel_ptr<Prec, true>(flags) : march_kernel_ptr<Prec, false>(flags);
-  int nb = 0;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, block, lds) == hipSuccess ? nb : 0;
-}
-
 template <class Prec>
 hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t npatch,
                         int32_t nblocks, int32_t block, int32_t sweep_order, int32_t lanes_mask,
@@ -1185,7 +1168,6 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                               int32_t, int32_t, int32_t, const double *,          \
                                               const Params &, unsigned long long *,               \
                                               unsigned long long *, hipStream_t);                  \
-  template int march_blocks_per_cu<Prec>(int32_t, bool, uint32_t);                                \
   template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *, unsigned int *,    \

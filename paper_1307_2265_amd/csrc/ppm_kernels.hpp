@@ -36,12 +36,6 @@ hipError_t launch_sweep_tail(const PatchDev *patches, const int32_t *chunk_start
                              const double *dt_dev, const Params &P, unsigned long long *counters,
                              unsigned long long *smax_bits, hipStream_t s);
 
-// Resident workgroups per compute unit of the (ungrouped) marching sweep
-// with `block` threads, with or without the CFL maximum, for the build that
-// the plan flags select; 0 if unknown.
-template <class Prec>
-int march_blocks_per_cu(int32_t block, bool cfl, uint32_t flags);
-
 // Persistent batch kernel: the whole step of every patch in one launch.
 template <class Prec>
 hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t npatch,

@@ -225,18 +225,16 @@ extern "C" ppm_status ppm_step_cfl_noalloc(const ppm_patch *patches, int32_t npa
     chunks[24 * kStride + npatch] = int32_t(acc);
     cfl_blocks = int32_t(acc);
   }
-  // one patch: whole rounds of resident marching threads, the few pencils
-  // left over to the lane-parallel tail launch (as a one-patch plan does)
+  // one patch: whole rounds of one marching block per compute unit, the few
+  // pencils left over to the lane-parallel tail launch (as a one-patch plan
+  // does)
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     cus = 0;
   if (npatch == 1 && cus > 0)
     for (int c = 0; c < 2; ++c) {
-      const int bpc = prec == PPM_FP64
-                          ? ppm::march_blocks_per_cu<ppm::PrecF64>(sh.block, c, P.flags)
-                          : ppm::march_blocks_per_cu<ppm::PrecMixed>(sh.block, c, P.flags);
-      const int64_t cap = int64_t(cus) * bpc * sh.block;
+      const int64_t cap = int64_t(cus) * sh.block;
       if (cap <= 0) continue;
       for (int slot = 0; slot < 12; ++slot) {
         const int axis = slot / 4, tm = slot % 4;
