@@ -594,7 +594,7 @@ __device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64
 // values.  The parent's state is read through parent_tab[parent] when given
 // (the parent blended in time), else from the patch table.
 template <class Prec>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 2)
 fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *__restrict__ items,
                         const int64_t *__restrict__ prefix, int32_t nitems, int64_t total,
                         const PatchDev *__restrict__ parent_tab) {
@@ -633,20 +633,33 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
   int64_t lc[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) lc[a] = cc[a] - item.pstart[a] + gc;
+  // the density of the neighbourhood, read once for all six quantities
+  double rn[3][3][3];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) {
+        const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
+        rn[dz][dy][dx] = double(static_cast<const S *>(cd.rho)[o]);
+      }
   double q0[6], fx[6], fy[6], fz[6];
-#pragma unroll 1
+#pragma unroll
   for (int comp = 0; comp < 6; ++comp) {
     // the stored field whose product with rho is this component (none for rho)
     const S *xs = comp >= 1 && comp <= 3 ? static_cast<const S *>(cd.vel[comp - 1]) : nullptr;
     const double *xd = comp == 4 ? cd.etot : cd.eint;
     double nb[3][3][3];
+#pragma unroll
     for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
       for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
           const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
-          const double rho = double(static_cast<const S *>(cd.rho)[o]);
           const double x = comp == 0 ? 0.0 : (xs ? double(xs[o]) : xd[o]);
-          nb[dz][dy][dx] = comp == 0 ? rho : rho * x;
+          nb[dz][dy][dx] = comp == 0 ? rn[dz][dy][dx] : rn[dz][dy][dx] * x;
         }
     q0[comp] = nb[1][1][1];
     second_order_a_slopes(nb, fx[comp], fy[comp], fz[comp]);
