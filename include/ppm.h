@@ -182,10 +182,11 @@ int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
  *   batch_block=B  threads per workgroup of the persistent launch (64..256).
  *   batch_blocks=W workgroups of the persistent launch (default: 512/B per CU).
  *   tail=0|1       one ungrouped patch: when a marching sweep's pencils
- *                  exceed a whole number of rounds of resident marching
- *                  threads by at most an eighth of a round, march the whole
- *                  rounds and stream the rest with the lane-parallel kernel,
- *                  one pencil per wavefront, in a second launch (default 1).
+ *                  exceed a whole number of rounds of one marching block per
+ *                  compute unit by at most an eighth of a round, march the
+ *                  whole rounds and stream the rest with the lane-parallel
+ *                  kernel, one pencil per wavefront, in a second launch
+ *                  (default 1).
  *   tail_round=R   take R pencils (a multiple of block) as the round and give
  *                  any rest to the lane-parallel launch (for tests and tuning).
  * Results do not depend on the launch shapes.  Uploads the patch table to

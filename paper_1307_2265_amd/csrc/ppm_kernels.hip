@@ -9,7 +9,7 @@
 //     the lanes of a wave (ppm_lanes.hpp), for x sweeps.
 //   * sweep_tail_kernel: the same lane-parallel code over the last pencils of
 //     a big patch's marching sweep, one pencil per wave, after the marching
-//     launch has taken whole rounds of resident threads.
+//     launch has taken whole rounds of one block per compute unit.
 //   * batch_persistent_kernel: a whole step of every patch in one launch.
 //   * Each sweep kernel has a variant for the last sweep of a step that also
 //     takes the max signal speed of the cells it writes, so the next step's
@@ -186,7 +186,7 @@ sweep_lanes_kernel(const PatchDev *__restrict__ patches, const int32_t *__restri
 }
 
 // The pencils of one patch from `pencil0` on, one per wavefront: what is
-// left of a marching sweep after whole rounds of resident marching threads.
+// left of a marching sweep after whole rounds of one block per compute unit.
 template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __global__ void __launch_bounds__(kMaxBlock, 4)
 sweep_tail_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ chunk_start,
