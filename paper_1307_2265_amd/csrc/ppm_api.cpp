@@ -160,6 +160,9 @@ ppm_status parse_tiles(ppm_plan *pl, const char *cfg) {
       if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: tail must be 0 or 1");
       pl->tail = int32_t(v);
       pl->lanes_set = true;
+    } else if (k == "split") {
+      if (v != 0 && v != 1) return fail(PPM_EINVAL, "tile_config: split must be 0 or 1");
+      pl->split = int32_t(v);
     } else if (k == "tail_round") {
       if (v < 64 || v > (1 << 26) || v % 64) return fail(PPM_EINVAL, "tile_config: tail_round must be a multiple of 64 in 64..2^26");
       pl->tail_round = int32_t(v);
@@ -190,6 +193,7 @@ void free_plan(ppm_plan *p) {
   if (p->d_counters) (void)hipFree(p->d_counters);
   if (p->d_smax) (void)hipFree(p->d_smax);
   if (p->d_order) (void)hipFree(p->d_order);
+  if (p->d_defer) (void)hipFree(p->d_defer);
   if (p->d_queue) (void)hipFree(p->d_queue);
   if (p->d_groups) (void)hipFree(p->d_groups);
   if (p->d_interp) (void)hipFree(p->d_interp);
@@ -217,15 +221,20 @@ hipError_t do_sweep(ppm_plan *pl, const double *dt, int axis, int mask, unsigned
   const int32_t *groups = pl->group ? pl->d_groups + pl->gofs[slot] : nullptr;
   const int c = smax ? 1 : 0;
   const int32_t *chunks = pl->d_chunks + slot * (pl->npatch + 1);
+  double *defer = pl->split_on[c][slot] ? pl->d_defer : nullptr;
   if (pl->tail_blocks[c][slot] > 0) {  // whole rounds marched, the rest one pencil per wave
     hipError_t e = ppm::launch_sweep<Prec>(pl->d_patches, chunks, pl->npatch,
                                            pl->tail_main[c][slot], pl->block, axis, mask, dt,
-                                           pl->P, pl->d_counters, smax, nullptr, 0, s);
+                                           pl->P, pl->d_counters, smax, nullptr, 0, s, defer);
     if (e != hipSuccess) return e;
     return ppm::launch_sweep_tail<Prec>(pl->d_patches, chunks, pl->tail_blocks[c][slot],
                                         pl->lanes_block, axis, mask, pl->tail_pencil0[c][slot],
                                         dt, pl->P, pl->d_counters, smax, s);
   }
+  if (defer)
+    return ppm::launch_sweep<Prec>(pl->d_patches, chunks, pl->npatch, pl->split_blocks[c][slot],
+                                   pl->block, axis, mask, dt, pl->P, pl->d_counters, smax,
+                                   nullptr, 0, s, defer);
   return ppm::launch_sweep<Prec>(pl->d_patches, chunks, pl->npatch, pl->nblocks[slot], pl->block,
                                  axis, mask, dt, pl->P, pl->d_counters, smax, groups,
                                  pl->ngroups[slot], s);
@@ -434,7 +443,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
         pl->nblocks[slot] = chunks[size_t(slot + 1) * stride - 1];
     }
   }
-  // One patch, marched pencils just over a whole number of rounds of one
+  // One patch, few pencils: a marching sweep with fewer pencils than two
+  // blocks per compute unit leaves the device at one wave per SIMD or less,
+  // so two threads march each pencil (split; pencils of at least 16 active
+  // cells).  And marched threads just over a whole number of rounds of one
   // block per compute unit: march the whole rounds and give the few pencils
   // left (at most an eighth of a round) to the lane-parallel kernel, one
   // pencil per wave, instead of a last round in which a few compute units
@@ -444,22 +456,32 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, pl->device) != hipSuccess)
     cus = 0;
-  if (npatch == 1 && !pl->group && pl->tail && (cus > 0 || pl->tail_round > 0)) {
+  int64_t defer_pencils = 0;
+  if (npatch == 1 && !pl->group && (cus > 0 || pl->tail_round > 0)) {
     for (int c = 0; c < 2; ++c) {
-      int64_t cap = pl->tail_round;
-      if (cap == 0) cap = int64_t(cus) * pl->block;
-      if (cap <= 0) continue;
       for (int slot = 0; slot < 12; ++slot) {
         const int axis = slot / 4, tm = slot % 4;
         const PatchDev &d = pl->host[0];
         const int64_t w1 = (tm & 1) ? d.n[t1_of(axis)] : d.n[t1_of(axis)] + 2 * d.ghost;
         const int64_t w2 = (tm & 2) ? d.n[t2_of(axis)] : d.n[t2_of(axis)] + 2 * d.ghost;
-        const int64_t np = w1 * w2, rest = np % cap;
-        if (np < cap || rest == 0 || (pl->tail_round == 0 && rest * 8 > cap)) continue;
+        const int64_t np = w1 * w2;
+        const bool split = pl->split && cus > 0 && d.n[axis] >= 16 &&
+                           np < 2 * int64_t(cus) * pl->block;
+        const int64_t tpp = split ? 2 : 1, threads = tpp * np;
+        // threads per round: tail_round pencils, else one block per compute unit
+        const int64_t cap = pl->tail_round ? pl->tail_round * tpp : int64_t(cus) * pl->block;
+        if (split) {
+          pl->split_on[c][slot] = 1;
+          pl->split_blocks[c][slot] = int32_t((threads + pl->block - 1) / pl->block);
+          defer_pencils = std::max(defer_pencils, np);
+        }
+        if (!pl->tail || cap <= 0) continue;
+        const int64_t rest = threads % cap;
+        if (threads < cap || rest == 0 || (pl->tail_round == 0 && rest * 8 > cap)) continue;
         const int64_t waves = pl->lanes_block / 64;
-        pl->tail_pencil0[c][slot] = int32_t(np - rest);
-        pl->tail_main[c][slot] = int32_t((np - rest) / pl->block);
-        pl->tail_blocks[c][slot] = int32_t((rest + waves - 1) / waves);
+        pl->tail_pencil0[c][slot] = int32_t((threads - rest) / tpp);
+        pl->tail_main[c][slot] = int32_t((threads - rest) / pl->block);
+        pl->tail_blocks[c][slot] = int32_t((rest / tpp + waves - 1) / waves);
       }
     }
   }
@@ -503,7 +525,10 @@ ppm_status ppm_plan_create(ppm_plan **out, const ppm_patch *patches, int32_t npa
       (e = hipMalloc(&pl->d_counters, 2 * sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMalloc(&pl->d_smax, nlevels * sizeof(unsigned long long))) != hipSuccess ||
       (!gmap.empty() &&
-       (e = hipMalloc(&pl->d_groups, sizeof(int32_t) * gmap.size())) != hipSuccess)) {
+       (e = hipMalloc(&pl->d_groups, sizeof(int32_t) * gmap.size())) != hipSuccess) ||
+      (defer_pencils > 0 &&
+       (e = hipMalloc(&pl->d_defer, sizeof(double) * size_t(defer_pencils) * 30)) !=
+           hipSuccess)) {
     free_plan(pl);
     return fail(PPM_ENOMEM, "hipMalloc: %s", hipGetErrorString(e));
   }

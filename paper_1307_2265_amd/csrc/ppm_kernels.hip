@@ -5,6 +5,8 @@
 //     patch by binary search in a prefix array of chunk counts, and each
 //     thread of the block marches one pencil (ppm_sweep.hpp).  A single big
 //     grid is the one-patch case of the same kernel.
+//   * sweep_split_kernel: the marching sweep of one patch with two threads
+//     per pencil, when the pencils are too few to fill the device.
 //   * sweep_lanes_kernel: the same sweep with the cells of a pencil across
 //     the lanes of a wave (ppm_lanes.hpp), for x sweeps.
 //   * sweep_tail_kernel: the same lane-parallel code over the last pencils of
@@ -142,6 +144,59 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
     if (kGrouped) cfl_commit_levels(*cfl.lds, pd.level, smax_bits);
     else cfl_commit(*cfl.lds, &smax_bits[pd.level]);
   }
+}
+
+// The marching sweep of one patch with two threads per pencil, for sweeps
+// with too few pencils to give every SIMD two waves: lanes 0-31 of a wave
+// march the first halves of 32 consecutive pencils and lanes 32-63 the second
+// halves, from five cells before their first own cell (see MarchSpan).  The
+// second half stores its first five cells only after its march, from
+// `defer` (30 doubles per pencil): the first half reads them as input at the
+// end of its own march, and has read them by then (the same wave).
+template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
+__global__ void __launch_bounds__(kMaxBlock, 2)
+sweep_split_kernel(const PatchDev *__restrict__ patches, int32_t axis, int32_t mask,
+                   const double *__restrict__ dt_dev, Params P,
+                   unsigned long long *__restrict__ counters,
+                   unsigned long long *__restrict__ smax_bits, double *__restrict__ defer) {
+  using S = typename Prec::S;
+  extern __shared__ double lds[];
+  const int t = int(blockIdx.x * blockDim.x + threadIdx.x);
+  const int half = (t >> 5) & 1;
+  const int idx = (t >> 6) * 32 + (t & 31);
+  const PatchDev pd = patches[0];
+  int i1 = pd.ghost, i2 = pd.ghost;
+  const bool has = pencil_index(pd, axis, mask, idx, i1, i2);
+  if (!kCFL && !has) return;
+  CflAcc cfl = cfl_acc(pd, axis, lds + kLdsCfl * int(blockDim.x) + threadIdx.x);
+  if (kCFL) *cfl.lds = 0.0;
+  uint32_t nfb = 0, nfl = 0;
+  if (has) {
+    const PencilRef<S> pc = make_pencil<S>(pd, axis, i1, i2);
+    const double dt = dt_dev[pd.level];
+    const int g = pc.g, a1 = pc.n - g - 1;
+    const int m = g + (pc.n - 2 * g + 1) / 2;  // first cell of the second half
+    double *mine = defer + int64_t(idx) * (kDeferCells * 6);
+    const MarchSpan span = half ? MarchSpan{m - kDeferCells, pc.n - g + 4, m, a1, m, mine}
+                                : MarchSpan{0, m + 4, g, m - 1, 0, nullptr};
+    march_pencil<Prec, kCFL, kUseHLLC, kGrav>(P, pc, dt, expansion_a(P, pd.level),
+                                              lds + threadIdx.x, blockDim.x, nfb, nfl, cfl, &span);
+    if (half) {
+      for (int c = 0; c < kDeferCells; ++c) {
+        const int64_t o = pc.base + int64_t(m + c) * pc.stride;
+        const double *d = mine + c * 6;
+        pc.rho[o] = S(d[0]);
+        pc.u[o] = S(d[1]);
+        pc.v1[o] = S(d[2]);
+        pc.v2[o] = S(d[3]);
+        pc.E[o] = d[4];
+        pc.e[o] = d[5];
+      }
+    }
+  }
+  if (nfb) atomicAdd(&counters[0], (unsigned long long)nfb);
+  if (nfl) atomicAdd(&counters[1], (unsigned long long)nfl);
+  if (kCFL) cfl_commit(*cfl.lds, &smax_bits[pd.level]);  // every lane of the wave takes part
 }
 
 // One wavefront streams a run of `rows` consecutive pencils (rows_per_wave(n)
@@ -973,13 +1028,19 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned long long *smax_bits, const int32_t *groups, int32_t ngroups,
-                        hipStream_t s) {
+                        hipStream_t s, double *defer) {
   const size_t lds = size_t(kLdsMarch + (smax_bits ? 1 : 0)) * block * sizeof(double);
 #define PPM_LAUNCH_MARCH(CFL, GRP, HLLC, GRAV)                                               \
   hipLaunchKernelGGL((sweep_kernel<Prec, CFL, GRP, HLLC, GRAV>), dim3(nblocks), dim3(block), \
                      lds, s, patches, chunk_start, npatch, axis, mask, dt_dev, P, counters,   \
                      smax_bits, groups, ngroups)
-  if (groups) {
+#define PPM_LAUNCH_SPLIT(CFL, HLLC, GRAV)                                                      \
+  hipLaunchKernelGGL((sweep_split_kernel<Prec, CFL, HLLC, GRAV>), dim3(nblocks), dim3(block),  \
+                     lds, s, patches, axis, mask, dt_dev, P, counters, smax_bits, defer)
+  if (defer) {
+    if (smax_bits) { PPM_BUILD(P, PPM_LAUNCH_SPLIT, true); }
+    else { PPM_BUILD(P, PPM_LAUNCH_SPLIT, false); }
+  } else if (groups) {
     if (smax_bits) { PPM_BUILD(P, PPM_LAUNCH_MARCH, true, true); }
     else { PPM_BUILD(P, PPM_LAUNCH_MARCH, false, true); }
   } else {
@@ -987,6 +1048,7 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
     else { PPM_BUILD(P, PPM_LAUNCH_MARCH, false, false); }
   }
 #undef PPM_LAUNCH_MARCH
+#undef PPM_LAUNCH_SPLIT
   return hipGetLastError();
 }
 
@@ -1171,7 +1233,7 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *,                    \
                                          unsigned long long *, const int32_t *, int32_t,          \
-                                         hipStream_t);                                             \
+                                         hipStream_t, double *);                                   \
   template hipError_t launch_sweep_lanes<Prec>(const PatchDev *, const int32_t *, int32_t,        \
                                                int32_t, int32_t, int32_t, int32_t,                \
                                                const double *, const Params &,                    \

@@ -14,10 +14,13 @@ hipError_t launch_sweep(const PatchDev *patches, const int32_t *chunk_start, int
                         int32_t nblocks, int32_t block, int32_t axis, int32_t mask,
                         const double *dt_dev, const Params &P, unsigned long long *counters,
                         unsigned long long *smax_bits, const int32_t *groups, int32_t ngroups,
-                        hipStream_t s);
+                        hipStream_t s, double *defer = nullptr);
 
 // groups (nullable): the marching sweep numbers the pencils of runs of
 // equal-length patches consecutively (layout in ppm_kernels.hip).
+// defer (nullable; a plan of one patch, no groups): sweep_split_kernel, two
+// threads per pencil, nblocks covering two threads per pencil, `defer` 30
+// doubles per pencil of workspace.
 // Lane-parallel variant (a wavefront streams a run of pencils); block = 64 * waves.
 // smax_bits (nullable) of a sweep launch: the sweep is the last of its step and
 // also takes the max signal speed per level of the cells it writes.

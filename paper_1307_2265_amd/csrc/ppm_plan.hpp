@@ -32,6 +32,10 @@ struct ppm_plan {
   int32_t tail_pencil0[2][12] = {};  // [cfl][slot]: first pencil of the lanes tail
   int32_t tail_main[2][12] = {};     // marching blocks before it
   int32_t tail_blocks[2][12] = {};   // lane-parallel blocks of the tail (0: no tail)
+  int32_t split = 1;              // one patch, few pencils: two threads march each pencil
+  int32_t split_on[2][12] = {};   // [cfl][slot]: this marching sweep is split
+  int32_t split_blocks[2][12] = {};  // its marching blocks when there is no tail
+  double *d_defer = nullptr;      // split marching: 30 doubles per pencil
   int32_t *d_order = nullptr;     // patches by descending cost (persistent queue order)
   unsigned int *d_queue = nullptr;  // persistent queue head and exit count
   std::vector<PatchDev> host;

@@ -204,21 +204,54 @@ __device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis, double *
   return CflAcc{axis, {pd.dx[0], pd.dx[1], pd.dx[2]}, 0.0, lds};
 }
 
-// One thread marches one pencil.  kCFL: also take the signal speed of every
-// cell written (the sweep must then be the last of its step).
+// The part of a pencil that one thread marches when two threads share a
+// pencil.  The head walks cells begin .. last; the rules of the pencil's
+// start (stages that need more cells than have been read yet are skipped,
+// the flattening indicator of the first cells is zero, the first g cells are
+// treated as ghosts) apply relative to `begin`, those of its end to the real
+// end.  A thread that starts inside the pencil thereby computes its first
+// cells differently from the whole march, but no cell it writes depends on
+// them: a cell's update reaches five cells either side (the flattening of its
+// neighbours' parabolas three, the HLL fallback of a neighbouring face two
+// more), and `own_lo` is begin + 5.  Cells own_lo .. own_hi are written (the
+// faces between them, and below own_lo when own_lo is the pencil's first
+// active cell, are counted); cells defer_lo .. defer_lo + kDeferCells - 1 go
+// to `defer` (6 doubles per cell) instead, for the caller to store after the
+// march: the other thread of the pencil reads them as input late in its own
+// march.
+constexpr int kDeferCells = 5;
+struct MarchSpan {
+  int begin, last, own_lo, own_hi, defer_lo;
+  double *defer;
+};
+
+// One thread marches one pencil (or the part of it `span` gives).  kCFL: also
+// take the signal speed of every cell written (the sweep must then be the
+// last of its step).
 // a: the level's expansion factor (1 for the static equations).  kGrav: the
 // general build, with the gravity source terms (applied where the pencil has
 // an acceleration field) and the optional diffusive flux.
 template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
                              double a, double *lds_slots, int slot_stride, uint32_t &n_fallback,
-                             uint32_t &n_floor, CflAcc &cfl) {
+                             uint32_t &n_floor, CflAcc &cfl, const MarchSpan *span = nullptr) {
   using S = typename Prec::S;
   using T = typename Prec::T;
   // with T = double the window already holds the exact pressure
   constexpr bool kExactP = sizeof(T) == sizeof(double);
   const int n = pc.n, g = pc.g;
   const int a0 = g, a1 = n - g - 1;
+  // the march's own start (cell begin is its first, begin + g its first
+  // active cell) and what it writes
+  const bool spanned = span != nullptr;  // known where the call is inlined
+  const int begin = spanned ? span->begin : 0;
+  const int kend = spanned ? span->last : n - g + 4;  // the iteration that finalises its last cell
+  const int b0 = begin + g;
+  const int own_lo = spanned ? span->own_lo : a0, own_hi = spanned ? span->own_hi : a1;
+  const int face_lo = own_lo == a0 ? a0 - 1 : own_lo;
+  const bool deferring = spanned && span->defer != nullptr;
+  const int defer_lo = deferring ? span->defer_lo : 0;
+  auto owned = [&](int c) { return !spanned || (c >= own_lo && c <= own_hi); };
   const double lam = dt / (a * pc.dx);
   const T tlam = T(lam);
   const bool grav = kGrav && pc.acc != nullptr;
@@ -291,16 +324,16 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
   // prefetch of the head cell
   S nr = S(0), nu = S(0), nv1 = S(0), nv2 = S(0);
   double nE = 0.0, ne = 0.0;
-  if (n > 0) {
-    const int64_t o = pc.base;
+  if (begin < n) {
+    const int64_t o = pc.base + int64_t(begin) * pc.stride;
     nr = pc.rho[o]; nu = pc.u[o]; nv1 = pc.v1[o]; nv2 = pc.v2[o]; nE = pc.E[o]; ne = pc.e[o];
   }
 
-  const int kend = n - g + 4;  // the iteration that finalises cell a1
-  for (int k = 0; k <= kend; ++k) {
+  for (int k = begin; k <= kend; ++k) {
+    const int t = k - begin;  // cells read so far, less one
     // energies of cell B = k-4 (updated below), fetched early to hide latency
     double EB = 0.0, eB = 0.0, gB = 0.0;
-    if (k - 4 >= a0 && k - 4 <= a1) {
+    if (k - 4 >= b0 && k - 4 <= a1) {
       const int64_t o = pc.base + int64_t(k - 4) * pc.stride;
       EB = pc.E[o];
       eB = pc.e[o];
@@ -310,7 +343,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     if (k < n) {
       const double r = double(nr), u = double(nu), v1 = double(nv1), v2 = double(nv2);
       const double E = nE, e = ne;
-      if (k + 1 < n) {
+      if (k + 1 < n && (!spanned || k + 1 <= kend)) {
         const int64_t o = pc.base + int64_t(k + 1) * pc.stride;
         nr = pc.rho[o]; nu = pc.u[o]; nv1 = pc.v1[o]; nv2 = pc.v2[o]; nE = pc.E[o]; ne = pc.e[o];
       }
@@ -323,27 +356,27 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
       rE[2] = r * E;
     }
     // ---- 2. slope and second difference of cell k-1, max rho*E around it
-    if (k >= 2 && k <= n - 1) {
+    if (t >= 2 && k <= n - 1) {
 #pragma unroll
       for (int j = 0; j < 5; ++j) dm[3][j] = limited_slope<T>(q[2][j], q[3][j], q[4][j]);
       d2[3] = second_diff<T>(q[2][0], q[3][0], q[4][0]);
       m3[4] = vmax<double>(vmax<double>(rE[0], rE[1]), rE[2]);
     }
     // ---- 3. interface value between cells k-2 and k-1
-    if (k >= 3 && k <= n - 1) {
+    if (t >= 3 && k <= n - 1) {
 #pragma unroll
       for (int j = 0; j < 5; ++j) fc[2][j] = interface_value<T>(q[2][j], q[3][j], dm[2][j], dm[3][j]);
     }
     // ---- 4. flattening indicator of cell k-2 (zero where its stencil leaves the pencil)
     ft[2] = T(0);
-    if (flatten && k >= 4 && k <= n - 1)
+    if (flatten && t >= 4 && k <= n - 1)
       ft[2] = flatten_indicator<T>(q[0][4], q[1][4], q[3][4], q[4][4], q[1][1], q[3][1]);
 
     // ---- 5. parabola of cell r = k-3, traced to both edges
     const int r = k - 3;
     State<T> rstate = lcarry, lnew = lcarry;
-    const bool need_left_edge = r >= a0 && r <= a1 + 1;   // right state of face (r-1)+1/2
-    const bool need_right_edge = r >= a0 - 1 && r <= a1;  // left state of face r+1/2
+    const bool need_left_edge = r >= b0 && r <= a1 + 1;   // right state of face (r-1)+1/2
+    const bool need_right_edge = r >= b0 - 1 && r <= a1;  // left state of face r+1/2
     if (need_left_edge || need_right_edge) {
       T l[5], rr[5], dq[5], q6[5];
 #pragma unroll
@@ -381,7 +414,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     // ---- 6. Riemann problem at face fc = (r-1)+1/2
     FluxT<T> ft_c = zero_flux<T>();
     double *slot_c = lds_slots + (k & 1) * kSlotDoubles * slot_stride;
-    if (r - 1 >= a0 - 1 && r - 1 <= a1) {
+    if (r - 1 >= b0 - 1 && r - 1 <= a1) {
       ft_c = face_flux<kUseHLLC, T>(P, lcarry, rstate);
       if (diffuse) diffuse_face(ft_c, r - 1);
       if (fallback) {
@@ -402,7 +435,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     const int B = r - 1;
     bool bad_b = false;
     double prov_b[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (B >= a0 && B <= a1) {
+    if (B >= b0 && B <= a1) {
       CellInT<T> cin;
       cin.rho = q[0][0]; cin.u = q[0][1];
       cin.v1 = q[0][2]; cin.v2 = q[0][3];
@@ -417,7 +450,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     const int fb = r - 2;  // face index: fb+1/2 lies between cells A and B
     FluxT<T> ff_b = ft_b;
     bool hll_b = false;
-    if (fb >= a0 - 1 && fb <= a1) {
+    if (fb >= b0 - 1 && fb <= a1) {
       hll_b = fallback && (bad_a || bad_b);
       if (hll_b) {
         const double *slot_b = lds_slots + ((k - 1) & 1) * kSlotDoubles * slot_stride;
@@ -429,7 +462,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
         }
         ff_b = narrow_flux<T>(hll_flux(P, sl, sr));
         if (diffuse) diffuse_face(ff_b, fb);
-        ++n_fallback;
+        if (!spanned || (fb >= face_lo && fb <= own_hi)) ++n_fallback;
       }
       if (fb == a0 - 1 && pc.reg_lo) {
 #pragma unroll
@@ -442,7 +475,7 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
     }
 
     // ---- 9. finalise and write cell A = r-2
-    if (A >= a0 && A <= a1) {
+    if (A >= b0 && A <= a1) {
       const int64_t o = pc.base + int64_t(A) * pc.stride;
       double out[6];
 #pragma unroll
@@ -471,19 +504,29 @@ __device__ void march_pencil(const Params &P, const PencilRef<typename Prec::S> 
         cin.v1 = T(pc.v1[o]); cin.v2 = T(pc.v2[o]);
         cin.E = pc.E[o]; cin.e = pc.e[o]; cin.p = 0.0; cin.rhoEmax = 0.0;
         floor_cell(P, cin, out);
-        ++n_floor;
+        if (owned(A)) ++n_floor;
       }
-      pc.rho[o] = S(out[0]);
-      pc.u[o] = S(out[1]);
-      pc.v1[o] = S(out[2]);
-      pc.v2[o] = S(out[3]);
-      pc.E[o] = out[4];
-      pc.e[o] = out[5];
-      if (kCFL) {
-        const double s = cell_signal<S>(P, cfl.axis, cfl.dx, S(out[0]), S(out[1]), S(out[2]),
-                                        S(out[3]), out[4], out[5]);
-        const double m = *cfl.lds;
-        *cfl.lds = s > m ? s : m;
+      if (owned(A)) {
+        if (deferring && A >= defer_lo && A < defer_lo + kDeferCells) {
+          double *d = span->defer + (A - defer_lo) * 6;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) d[j] = double(S(out[j]));
+          d[4] = out[4];
+          d[5] = out[5];
+        } else {
+          pc.rho[o] = S(out[0]);
+          pc.u[o] = S(out[1]);
+          pc.v1[o] = S(out[2]);
+          pc.v2[o] = S(out[3]);
+          pc.E[o] = out[4];
+          pc.e[o] = out[5];
+        }
+        if (kCFL) {
+          const double s = cell_signal<S>(P, cfl.axis, cfl.dx, S(out[0]), S(out[1]), S(out[2]),
+                                          S(out[3]), out[4], out[5]);
+          const double m = *cfl.lds;
+          *cfl.lds = s > m ? s : m;
+        }
       }
     }
 

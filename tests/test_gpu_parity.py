@@ -121,7 +121,7 @@ def test_flux_registers_and_seeded_ghosts_fp64(P, O):
     assert gcnt == ocnt
 
 
-@pytest.mark.parametrize("tiles", [None, "lanes=1", "lanes=0", "lanes=7"])
+@pytest.mark.parametrize("tiles", [None, "lanes=1", "lanes=0", "lanes=0 split=0", "lanes=7"])
 def test_hll_fallback_fires_identically(P, O, tiles):
     # Vacuum-generating double rarefaction along y in a 3-D box; the
     # two-shock update first goes non-positive after about a dozen steps.
@@ -222,8 +222,9 @@ def test_sweep_extents_on_gpu(P, O):
             plan.close()
 
 
-@pytest.mark.parametrize("tiles", ["lanes=0", "lanes=7", "lanes=7 lanes_block=64",
+@pytest.mark.parametrize("tiles", ["lanes=0", "lanes=0 split=0", "lanes=7", "lanes=7 lanes_block=64",
                                    "block=64", "lanes=0 block=64 tail_round=640",
+                                   "lanes=0 split=0 block=64 tail_round=640",
                                    "block=128 lanes_block=64 tail_round=1024"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_both_sweep_kernels_on_every_axis(P, O, tiles, prec):
@@ -231,6 +232,8 @@ def test_both_sweep_kernels_on_every_axis(P, O, tiles, prec):
     # the oracle along every axis, on grids long enough for several 54-cell
     # lane segments and with ragged tails; tail_round: each marching sweep
     # marches whole rounds of pencils and streams the rest one per wave.
+    # These grids have few pencils, so marching sweeps run two threads per
+    # pencil unless split=0.
     d = W.random_grid(131, 37, 61, 31337, W.SHOCKED)
     pr = P.PPM_FP64 if prec == "fp64" else P.PPM_MIXED
     d = stored_inputs(d, pr)
