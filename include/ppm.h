@@ -192,7 +192,8 @@ int64_t ppm_flux_reg_size(int32_t nx, int32_t ny, int32_t nz);
  *   split=0|1      one ungrouped patch: a marching sweep with fewer pencils
  *                  than two blocks per compute unit, of at least 16 active
  *                  cells each, runs two threads per pencil (each marches half
- *                  of it, from five cells before its first own cell), which
+ *                  of it, from max(5, ghost) cells before its first own
+ *                  cell), which
  *                  doubles the waves on a device the pencils cannot fill
  *                  (default 1).
  * Results do not depend on the launch shapes.  Uploads the patch table to

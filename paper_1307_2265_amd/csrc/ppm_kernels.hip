@@ -149,7 +149,7 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
 // The marching sweep of one patch with two threads per pencil, for sweeps
 // with too few pencils to give every SIMD two waves: lanes 0-31 of a wave
 // march the first halves of 32 consecutive pencils and lanes 32-63 the second
-// halves, from five cells before their first own cell (see MarchSpan).  The
+// halves, from max(5, g) cells before their first own cell (see MarchSpan).  The
 // second half stores its first five cells only after its march, from
 // `defer` (30 doubles per pencil): the first half reads them as input at the
 // end of its own march, and has read them by then (the same wave).
@@ -177,7 +177,10 @@ sweep_split_kernel(const PatchDev *__restrict__ patches, int32_t axis, int32_t m
     const int g = pc.g, a1 = pc.n - g - 1;
     const int m = g + (pc.n - 2 * g + 1) / 2;  // first cell of the second half
     double *mine = defer + int64_t(idx) * (kDeferCells * 6);
-    const MarchSpan span = half ? MarchSpan{m - kDeferCells, pc.n - g + 4, m, a1, m, mine}
+    // the second half starts at least five cells, and at least g, before its
+    // first own cell (its first g cells are its ghosts)
+    const int lead = g > kDeferCells ? g : kDeferCells;
+    const MarchSpan span = half ? MarchSpan{m - lead, pc.n - g + 4, m, a1, m, mine}
                                 : MarchSpan{0, m + 4, g, m - 1, 0, nullptr};
     march_pencil<Prec, kCFL, kUseHLLC, kGrav>(P, pc, dt, expansion_a(P, pd.level),
                                               lds + threadIdx.x, blockDim.x, nfb, nfl, cfl, &span);

@@ -251,6 +251,25 @@ def test_both_sweep_kernels_on_every_axis(P, O, tiles, prec):
             assert l1 <= 1e-5, (f, l1)
 
 
+@pytest.mark.parametrize("ghost", [3, 4, 5, 6])
+@pytest.mark.parametrize("tiles", ["lanes=0", "lanes=0 split=0"])
+def test_split_marching_every_ghost_width(P, O, ghost, tiles):
+    # Shocked input with flux registers, marching sweeps along every axis:
+    # with split=1 (the default for so few pencils) each pencil is marched by
+    # two threads, the second from max(5, ghost) cells before its first own
+    # cell; results, counts and registers must equal the oracle's.
+    d = W.random_grid(40, 24, 20, 4400 + ghost, W.SHOCKED, ghost=ghost)
+    g, gdt, gcnt, greg = _run_gpu_steps(P, d, 2, P.PPM_FP64, ghost=ghost, with_reg=True,
+                                        tiles=tiles)
+    o, odt, ocnt, oreg = _run_oracle_steps(O, d, 2, ghost=ghost, with_reg=True)
+    assert gdt == odt
+    worst, differ = compare_fields(g, o, TOL64)
+    print(f"ghost {ghost} {tiles}: worst {worst:.2e}, not bitwise {differ}, counts {gcnt}")
+    assert differ == 0
+    assert gcnt == ocnt
+    assert np.array_equal(greg, oreg)
+
+
 def test_full_size_512_step_in_bench_configuration(P, O):
     # The benchmark's workload (512^3, strongly shocked, seed 1002) and launch
     # configuration (default tiles: lane-parallel x sweeps, marching y and z),
