@@ -121,6 +121,8 @@ def test_bad_tile_config_is_rejected():
     assert st == ppm.PPM_EINVAL and "unknown key" in L.ppm_last_error().decode()
     st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"tail=2", None)
     assert st == ppm.PPM_EINVAL and "tail" in L.ppm_last_error().decode()
+    st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm), b"split=2", None)
+    assert st == ppm.PPM_EINVAL and "split" in L.ppm_last_error().decode()
     st = L.ppm_plan_create(C.byref(h), arr, 1, 1, ppm.PPM_FP64, C.byref(prm),
                            b"block=128 tail_round=320", None)
     assert st == ppm.PPM_EINVAL and "multiple of block" in L.ppm_last_error().decode()
