@@ -103,6 +103,7 @@ ppm::Params device_params(ppm_precision prec, const ppm_params *p) {
   std::memcpy(&P, p, sizeof(ppm_params));
   static_assert(offsetof(ppm::Params, expand) == sizeof(ppm_params), "params layout");
   P.expand = nullptr;
+  P.shock_k0 = std::sqrt((p->gamma - 1.0) / (2.0 * p->gamma));
   if (prec == PPM_MIXED) {  // floors a float density and pressure can hold exactly
     P.rho_floor = float_at_or_above(p->rho_floor);
     P.p_floor = float_at_or_above(p->p_floor);

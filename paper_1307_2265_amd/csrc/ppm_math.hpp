@@ -45,6 +45,9 @@ struct Params {
   // nullable: per level, the expansion factor a and its rate adot at the
   // level's half step (device memory); null is the static case a = 1
   const double *expand;
+  // sqrt((gamma-1)/(2 gamma)): a shock wave's Lagrangian speed over the sound
+  // one, W_s / C_s, as the star pressure falls to zero
+  double shock_k0;
 };
 
 // Expansion factor of a level (1 without expansion factors).
@@ -504,7 +507,8 @@ __device__ __forceinline__ double rsqrt64_1(double x) {
 }
 
 // Star pressure of the two-shock problem for the mixed precision, in double
-// with the same iteration, stopping rule and cap as two_shock_star: with
+// with the same iteration, stopping rule and cap as two_shock_star (from a
+// better start on expanding faces, below): with
 // X = 1 + (g+1)/(2g) (p/p_s - 1) and y = 1/sqrt(X), the Lagrangian speed is
 // W_s = C_s X y, 1/W_s = y / C_s, and Newton's step needs 1/Z_s =
 // (W_s^2 + C_s^2) / (2 W_s^3) = (1 + y^2) / (2 W_s), so an iteration takes one
@@ -520,7 +524,18 @@ __device__ __forceinline__ StarState two_shock_star_mixed(const Params &P, doubl
   const double icl = rsqrt64_1(al), icr = rsqrt64_1(ar);
   const double cl = al * icl, cr = ar * icr;
   const double ipl = rcp64_1(pl), ipr = rcp64_1(pr);
-  double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) * rcp64_1(cl + cr);
+  const double iden = rcp64_1(cl + cr);
+  double ps = (cr * pl + cl * pr - cl * cr * (ur - ul)) * iden;
+  // Below the smaller side pressure the acoustic guess (impedances C_s) is far
+  // from the root of a strongly expanding face, often negative; start from
+  // the same linear estimate with the impedances the shock relation gives as
+  // p -> 0, W_s = k0 C_s, capped at that pressure.  Converges to the same
+  // star pressure, in fewer steps on the wave's slowest faces.
+  const double pmin = pl < pr ? pl : pr;
+  if (ps < pmin) {
+    const double ex = (cr * pl + cl * pr - P.shock_k0 * (cl * cr * (ur - ul))) * iden;
+    ps = ex < pmin ? ex : pmin;
+  }
   if (ps < P.p_floor) ps = P.p_floor;
   int it = 0;
   bool capped = false;
