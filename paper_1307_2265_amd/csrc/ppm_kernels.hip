@@ -149,10 +149,11 @@ sweep_kernel(const PatchDev *__restrict__ patches, const int32_t *__restrict__ c
 // The marching sweep of one patch with two threads per pencil, for sweeps
 // with too few pencils to give every SIMD two waves: lanes 0-31 of a wave
 // march the first halves of 32 consecutive pencils and lanes 32-63 the second
-// halves, from max(5, g) cells before their first own cell (see MarchSpan).  The
-// second half stores its first five cells only after its march, from
+// halves, from max(5, g) cells before their first own cell (see MarchSpan).
+// The second half stores its first five cells only after its march, from
 // `defer` (30 doubles per pencil): the first half reads them as input at the
-// end of its own march, and has read them by then (the same wave).
+// end of its own march, and the wave leaves the march loop only when both
+// halves have finished it.
 template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __global__ void __launch_bounds__(kMaxBlock, 2)
 sweep_split_kernel(const PatchDev *__restrict__ patches, int32_t axis, int32_t mask,

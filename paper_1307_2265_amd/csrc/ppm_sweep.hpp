@@ -213,12 +213,12 @@ __device__ __forceinline__ CflAcc cfl_acc(const PatchDev &pd, int axis, double *
 // cells differently from the whole march, but no cell it writes depends on
 // them: a cell's update reaches five cells either side (the flattening of its
 // neighbours' parabolas three, the HLL fallback of a neighbouring face two
-// more), and `own_lo` is at least begin + 5 (and begin + g).  Cells own_lo .. own_hi are written (the
-// faces between them, and below own_lo when own_lo is the pencil's first
-// active cell, are counted); cells defer_lo .. defer_lo + kDeferCells - 1 go
-// to `defer` (6 doubles per cell) instead, for the caller to store after the
-// march: the other thread of the pencil reads them as input late in its own
-// march.
+// more), and `own_lo` is at least begin + 5 (and begin + g).  Cells own_lo ..
+// own_hi are written (the faces between them, and below own_lo when own_lo is
+// the pencil's first active cell, are counted); cells defer_lo .. defer_lo +
+// kDeferCells - 1 go to `defer` (6 doubles per cell) instead, for the caller
+// to store after the march: the other thread of the pencil reads them as
+// input late in its own march.
 constexpr int kDeferCells = 5;
 struct MarchSpan {
   int begin, last, own_lo, own_hi, defer_lo;
