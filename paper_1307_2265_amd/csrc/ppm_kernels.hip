@@ -26,8 +26,19 @@
 //     shell only; fill_boundary_kernel: the same shell by per-face domain
 //     boundary conditions; fill_from_parent_kernel / copy_from_siblings_kernel:
 //     AMR patch ghosts from the parent (SecondOrderA) and from siblings.
+//
+// The file is compiled in two passes, each with the instruction scheduling
+// under which its sweeps run fastest (see build.py): PPM_KERNEL_PASS 1 emits
+// the double-precision sweeps and every other kernel, PPM_KERNEL_PASS 2 only
+// the mixed-precision sweeps; without the macro one pass emits everything.
 #include "ppm_kernels.hpp"
 #include "ppm_lanes.hpp"
+
+#ifndef PPM_KERNEL_PASS
+#define PPM_KERNEL_PASS 0
+#endif
+#define PPM_PASS_FP64 (PPM_KERNEL_PASS != 2)   // double sweeps and the rest
+#define PPM_PASS_MIXED (PPM_KERNEL_PASS != 1)  // mixed-precision sweeps
 
 namespace ppm {
 
@@ -348,6 +359,7 @@ batch_persistent_kernel(const PatchDev *__restrict__ patches, const int32_t *__r
   }
 }
 
+#if PPM_PASS_FP64
 // ---------------------------------------------------------------------------
 // CFL reduction
 
@@ -1018,6 +1030,8 @@ fill_periodic_kernel(PatchDev pd) {
 // ---------------------------------------------------------------------------
 // Launchers
 
+#endif  // PPM_PASS_FP64
+
 // The three builds of each sweep kernel (template arguments kUseHLLC, kGrav):
 // two-shock only; HLLC or two-shock as the flag says; the general build,
 // which adds the gravity source terms and the diffusive flux, for plans where
@@ -1104,6 +1118,7 @@ hipError_t launch_batch(const PatchDev *patches, const int32_t *order, int32_t n
 }
 #undef PPM_BUILD
 
+#if PPM_PASS_FP64
 template <class Prec>
 hipError_t launch_expansion(const PatchDev *patches, const int32_t *chunk_start, int32_t npatch,
                             int32_t nblocks, int32_t cells_per_block, double gamma,
@@ -1231,6 +1246,7 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
   hipLaunchKernelGGL(fill_periodic_kernel<Prec>, dim3(unsigned(blocks)), dim3(256), 0, s, pd);
   return hipGetLastError();
 }
+#endif  // PPM_PASS_FP64
 
 #define PPM_INSTANTIATE(Prec)                                                                  \
   template hipError_t launch_sweep<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
@@ -1251,9 +1267,14 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *, unsigned int *,    \
                                          unsigned long long *, hipStream_t);
+#if PPM_PASS_FP64
 PPM_INSTANTIATE(PrecF64)
+#endif
+#if PPM_PASS_MIXED
 PPM_INSTANTIATE(PrecMixed)
+#endif
 #undef PPM_INSTANTIATE
+#if PPM_PASS_FP64
 __global__ void __launch_bounds__(256)
 fp64_ops_kernel(const double *a, const double *b, double *quot, double *root, int64_t n) {
   const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1343,5 +1364,6 @@ template hipError_t launch_copy_from_siblings<PrecMixed>(const PatchDev *, const
                                                          hipStream_t);
 template hipError_t launch_fill_boundary<PrecMixed>(const PatchDev &, const FaceRules &,
                                                     hipStream_t);
+#endif  // PPM_PASS_FP64
 
 }  // namespace ppm
