@@ -27,18 +27,20 @@
 //     boundary conditions; fill_from_parent_kernel / copy_from_siblings_kernel:
 //     AMR patch ghosts from the parent (SecondOrderA) and from siblings.
 //
-// The file is compiled in two passes, each with the instruction scheduling
+// The file is compiled in three passes, each with the instruction scheduling
 // under which its sweeps run fastest (see build.py): PPM_KERNEL_PASS 1 emits
-// the double-precision sweeps and every other kernel, PPM_KERNEL_PASS 2 only
-// the mixed-precision sweeps; without the macro one pass emits everything.
+// the double-precision marching sweeps and every non-sweep kernel, 2 the
+// mixed-precision sweeps, 3 the double-precision lane-parallel sweeps
+// (lanes and tail); without the macro one pass emits everything.
 #include "ppm_kernels.hpp"
 #include "ppm_lanes.hpp"
 
 #ifndef PPM_KERNEL_PASS
 #define PPM_KERNEL_PASS 0
 #endif
-#define PPM_PASS_FP64 (PPM_KERNEL_PASS != 2)   // double sweeps and the rest
-#define PPM_PASS_MIXED (PPM_KERNEL_PASS != 1)  // mixed-precision sweeps
+#define PPM_PASS_FP64 (PPM_KERNEL_PASS == 0 || PPM_KERNEL_PASS == 1)
+#define PPM_PASS_MIXED (PPM_KERNEL_PASS == 0 || PPM_KERNEL_PASS == 2)
+#define PPM_PASS_FP64_LANES (PPM_KERNEL_PASS == 0 || PPM_KERNEL_PASS == 3)
 
 namespace ppm {
 
@@ -1248,12 +1250,17 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
 }
 #endif  // PPM_PASS_FP64
 
-#define PPM_INSTANTIATE(Prec)                                                                  \
+#define PPM_INSTANTIATE_MARCH(Prec)                                                            \
   template hipError_t launch_sweep<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
                                          int32_t, int32_t, int32_t, const double *,               \
                                          const Params &, unsigned long long *,                    \
                                          unsigned long long *, const int32_t *, int32_t,          \
                                          hipStream_t, double *);                                   \
+  template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
+                                         int32_t, int32_t, int32_t, const double *,               \
+                                         const Params &, unsigned long long *, unsigned int *,    \
+                                         unsigned long long *, hipStream_t);
+#define PPM_INSTANTIATE_LANES(Prec)                                                            \
   template hipError_t launch_sweep_lanes<Prec>(const PatchDev *, const int32_t *, int32_t,        \
                                                int32_t, int32_t, int32_t, int32_t,                \
                                                const double *, const Params &,                    \
@@ -1262,18 +1269,19 @@ hipError_t launch_fill(const PatchDev &pd, hipStream_t s) {
   template hipError_t launch_sweep_tail<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t, \
                                               int32_t, int32_t, int32_t, const double *,          \
                                               const Params &, unsigned long long *,               \
-                                              unsigned long long *, hipStream_t);                  \
-  template hipError_t launch_batch<Prec>(const PatchDev *, const int32_t *, int32_t, int32_t,     \
-                                         int32_t, int32_t, int32_t, const double *,               \
-                                         const Params &, unsigned long long *, unsigned int *,    \
-                                         unsigned long long *, hipStream_t);
+                                              unsigned long long *, hipStream_t);
 #if PPM_PASS_FP64
-PPM_INSTANTIATE(PrecF64)
+PPM_INSTANTIATE_MARCH(PrecF64)
+#endif
+#if PPM_PASS_FP64_LANES
+PPM_INSTANTIATE_LANES(PrecF64)
 #endif
 #if PPM_PASS_MIXED
-PPM_INSTANTIATE(PrecMixed)
+PPM_INSTANTIATE_MARCH(PrecMixed)
+PPM_INSTANTIATE_LANES(PrecMixed)
 #endif
-#undef PPM_INSTANTIATE
+#undef PPM_INSTANTIATE_MARCH
+#undef PPM_INSTANTIATE_LANES
 #if PPM_PASS_FP64
 __global__ void __launch_bounds__(256)
 fp64_ops_kernel(const double *a, const double *b, double *quot, double *root, int64_t n) {

@@ -439,23 +439,28 @@ __device__ __forceinline__ Flux two_shock_flux(const Params &P, double rl, doubl
   double iwK = left ? iwl : iwr;
   double rs = ddiv(1.0, ddiv(1.0, rK) - (ps - pK) * iwK * iwK);
   if (rs < P.rho_floor) rs = P.rho_floor;
+  // the upwind side's waves move away from the face: u - (speed) on the
+  // left, u + (speed) on the right.  Written once with the side's values
+  // and sign (x - y is x + (-y) exactly, and -h / (t - h) = h / (h - t)
+  // exactly), so a wave whose lanes sample both sides evaluates each
+  // division and square root once.
+  const double sgn = left ? -1.0 : 1.0;
+  const double wK = left ? wl : wr;
   double rb, ub, pb;
   if (ps > pK) {  // shock on the upwind side
-    bool keep;
-    if (left) keep = (ul - ddiv(wl, rl)) >= 0.0;
-    else keep = (ur + ddiv(wr, rr)) <= 0.0;
+    const double sK = uK + sgn * ddiv(wK, rK);
+    const bool keep = left ? sK >= 0.0 : sK <= 0.0;
     if (keep) { rb = rK; ub = uK; pb = pK; }
     else { rb = rs; ub = us; pb = ps; }
   } else {        // rarefaction: linear through the fan
-    double head, tail;
-    if (left) { head = ul - dsqrt(ddiv(g * pl, rl)); tail = us - dsqrt(ddiv(g * ps, rs)); }
-    else { head = ur + dsqrt(ddiv(g * pr, rr)); tail = us + dsqrt(ddiv(g * ps, rs)); }
+    const double head = uK + sgn * dsqrt(ddiv(g * pK, rK));
+    const double tail = us + sgn * dsqrt(ddiv(g * ps, rs));
     bool outside = left ? head >= 0.0 : head <= 0.0;
     bool star = left ? tail <= 0.0 : tail >= 0.0;
     if (outside) { rb = rK; ub = uK; pb = pK; }
     else if (star) { rb = rs; ub = us; pb = ps; }
     else {
-      double w = left ? ddiv(-head, tail - head) : ddiv(head, head - tail);
+      double w = ddiv(-head, tail - head);
       rb = (1.0 - w) * rK + w * rs;
       ub = (1.0 - w) * uK + w * us;
       pb = (1.0 - w) * pK + w * ps;
