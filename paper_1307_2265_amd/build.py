@@ -5,15 +5,16 @@ double-precision results are then fixed by IEEE-754 and the order the source
 writes each expression in.  Packed FP32 instructions are disabled
 (-packed-fp32-ops).
 
-ppm_kernels.hip is compiled three times (PPM_KERNEL_PASS 1, 2, 3), so that
+ppm_kernels.hip is compiled four times (PPM_KERNEL_PASS 1 to 4), so that
 each group of sweep kernels takes the LLVM machine scheduler that runs it
-fastest on gfx950: iterative-ilp for the double-precision marching sweeps
-(and every non-sweep kernel), max-ilp for the mixed-precision sweeps and
-for the double-precision lane-parallel ones (under iterative-ilp their
-last-sweep build spills four times as much in its loop).  Against the
-default scheduler: 512^3 grid about -1 % (FP64) and -2.4 % (mixed) per
-step, 4096-patch batch -1 % and -2 %.  Scheduling reorders instructions
-only, so results are unchanged bit for bit.
+fastest on gfx950 (measured, alternating runs on one box): iterative-ilp for
+the double-precision marching sweeps (and every non-sweep kernel) and for
+the mixed-precision lane-parallel ones, max-ilp for the mixed-precision
+marching sweeps and for the double-precision lane-parallel ones (under
+iterative-ilp their last-sweep build spills four times as much in its
+loop).  Against the default scheduler: 512^3 grid about -1 % (FP64) and
+-2.4 % (mixed) per step, 4096-patch batch -1 % and -2 %.  Scheduling
+reorders instructions only, so results are unchanged bit for bit.
 """
 from __future__ import annotations
 
@@ -33,6 +34,8 @@ UNITS = [
      ["-DPPM_KERNEL_PASS=2", "-mllvm", "--amdgpu-sched-strategy=max-ilp"]),
     ("ppm_kernels.hip", "ppm_kernels_fp64_lanes.o",
      ["-DPPM_KERNEL_PASS=3", "-mllvm", "--amdgpu-sched-strategy=max-ilp"]),
+    ("ppm_kernels.hip", "ppm_kernels_mixed_lanes.o",
+     ["-DPPM_KERNEL_PASS=4", "-mllvm", "--amdgpu-sched-strategy=iterative-ilp"]),
     ("ppm_api.cpp", "ppm_api.o", []),
     ("ppm_amr.cpp", "ppm_amr.o", []),
     ("ppm_noalloc.cpp", "ppm_noalloc.o", []),

@@ -27,11 +27,12 @@
 //     boundary conditions; fill_from_parent_kernel / copy_from_siblings_kernel:
 //     AMR patch ghosts from the parent (SecondOrderA) and from siblings.
 //
-// The file is compiled in three passes, each with the instruction scheduling
+// The file is compiled in four passes, each with the instruction scheduling
 // under which its sweeps run fastest (see build.py): PPM_KERNEL_PASS 1 emits
 // the double-precision marching sweeps and every non-sweep kernel, 2 the
-// mixed-precision sweeps, 3 the double-precision lane-parallel sweeps
-// (lanes and tail); without the macro one pass emits everything.
+// mixed-precision marching sweeps, 3 the double-precision lane-parallel
+// sweeps (lanes and tail), 4 the mixed-precision lane-parallel ones; without
+// the macro one pass emits everything.
 #include "ppm_kernels.hpp"
 #include "ppm_lanes.hpp"
 
@@ -41,6 +42,7 @@
 #define PPM_PASS_FP64 (PPM_KERNEL_PASS == 0 || PPM_KERNEL_PASS == 1)
 #define PPM_PASS_MIXED (PPM_KERNEL_PASS == 0 || PPM_KERNEL_PASS == 2)
 #define PPM_PASS_FP64_LANES (PPM_KERNEL_PASS == 0 || PPM_KERNEL_PASS == 3)
+#define PPM_PASS_MIXED_LANES (PPM_KERNEL_PASS == 0 || PPM_KERNEL_PASS == 4)
 
 namespace ppm {
 
@@ -840,8 +842,11 @@ capture_kernel(const PatchDev *__restrict__ patches, const CaptureRow *__restric
   }
   uint32_t nfb = 0, nfl = 0;
   CflAcc cfl = cfl_acc(pd, axis, nullptr);
-  const auto F = sweep_segment<Prec, false, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, false, cur,
-                                                             nfb, nfl, cfl);
+  // the face's final flux reads the provisional fluxes of faces j-1/2 ..
+  // j+3/2 (the fallback tests of cells j and j+1)
+  const bool need_face = pos >= 3 && pos <= 5;
+  const auto F = sweep_segment<Prec, false, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, false,
+                                                             need_face, cur, nfb, nfl, cfl);
   if (used && pos == 4) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) cr.dst[pc.lab[k] * cr.fstride] = dt * F.get(k);
@@ -1278,6 +1283,8 @@ PPM_INSTANTIATE_LANES(PrecF64)
 #endif
 #if PPM_PASS_MIXED
 PPM_INSTANTIATE_MARCH(PrecMixed)
+#endif
+#if PPM_PASS_MIXED_LANES
 PPM_INSTANTIATE_LANES(PrecMixed)
 #endif
 #undef PPM_INSTANTIATE_MARCH

@@ -27,14 +27,18 @@
 namespace ppm {
 
 
-// Neighbour values by whole-wave DPP shifts (a VALU move per 32 bits, no LDS
-// round trip): wave_shr:1 gives lane i the value of lane i-1, wave_shl:1 that
-// of lane i+1; the lane with no source (0, resp. 63) keeps its own value.
+// Neighbour values by whole-wave DPP shifts (one VALU move per 32 bits, no
+// LDS round trip): wave_shr:1 gives lane i the value of lane i-1, wave_shl:1
+// that of lane i+1; the lane with no source (0, resp. 63) reads zero, which
+// needs no copy of an old value into the destination first.  Lanes 0 and 63
+// are halo lanes, whose results no written cell uses; the Riemann solve,
+// whose iteration a zero state would drive to its cap, is confined to the
+// lanes whose face can reach a written cell (need_face below).
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppWaveShr1 = 0x138;
 
 template <int kCtrl> __device__ __forceinline__ int dpp_shift32(int v) {
-  return __builtin_amdgcn_update_dpp(v, v, kCtrl, 0xf, 0xf, false);
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xf, 0xf, true);
 }
 
 template <int kCtrl, class V> __device__ __forceinline__ V dpp_shift(V v) {
@@ -76,14 +80,18 @@ struct CellLoad {
 
 // One segment: lane holds cell j of pencil pc (j = -1 for a placeholder
 // lane beyond the stream, which no valid result uses).  `in` is this lane's
-// input cell; the lane writes its cell (and counts its events) if `mine`.
+// input cell; the lane writes its cell (and counts its events) if `mine`,
+// and solves the Riemann problem of its face j+1/2 only if `need_face` (the
+// face's provisional flux can reach a written cell or the face the caller
+// reads).
 // lam = dt / (a pc.dx) and hgdt = (dt / 2) / a, with a the level's expansion
 // factor (the same for every pencil of the patch).  Returns the final flux
 // (after the fallback) of face j+1/2.
 template <class Prec, bool kCFL, bool kUseHLLC, bool kGrav>
 __device__ FluxT<typename Prec::T> sweep_segment(const Params &P, const PencilRef<typename Prec::S> &pc, double dt,
-                              double lam, double hgdt, int j, bool mine, const CellLoad &in,
-                              uint32_t &n_fallback, uint32_t &n_floor, CflAcc &cfl) {
+                              double lam, double hgdt, int j, bool mine, bool need_face,
+                              const CellLoad &in, uint32_t &n_fallback, uint32_t &n_floor,
+                              CflAcc &cfl) {
   using S = typename Prec::S;
   using T = typename Prec::T;
   const int n = pc.n, g = pc.g;
@@ -171,7 +179,7 @@ __device__ FluxT<typename Prec::T> sweep_segment(const Params &P, const PencilRe
 
   // ---- Riemann problem at face j+1/2 (faces a0-1..a1), with the optional
   // diffusive flux from this cell's and the right neighbour's input values
-  const bool face_ok = j >= a0 - 1 && j <= a1;
+  const bool face_ok = need_face && j >= a0 - 1 && j <= a1;
   const bool diffuse = kGrav && (P.flags & kDiffusion) != 0;
   // the diffusive flux, from this cell's and the right neighbour's input
   // values (the shifts run on every lane, outside divergent branches)
@@ -294,8 +302,11 @@ __device__ void sweep_rows_lanes(const Params &P, const PatchDev &pd, int axis, 
       cur = CellLoad{1.0, 0.0, 0.0, 0.0, 1.0, 1.0};
     }
     const bool mine = in && lane >= kLaneHalo && lane < kLaneHalo + kLaneOut;
-    sweep_segment<Prec, kCFL, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, mine, cur, n_fallback, n_floor,
-                                        cfl);
+    // the written cells' faces, and the provisional fluxes of the faces one
+    // further out that the fallback tests of the end cells read
+    const bool need_face = lane >= kLaneHalo - 2 && lane <= kLaneHalo + kLaneOut;
+    sweep_segment<Prec, kCFL, kUseHLLC, kGrav>(P, pc, dt, lam, hgdt, j, mine, need_face, cur,
+                                               n_fallback, n_floor, cfl);
   }
 }
 
