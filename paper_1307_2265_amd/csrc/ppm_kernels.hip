@@ -578,27 +578,44 @@ __device__ __forceinline__ double minmod(double a, double b) {
   return a < 0.0 ? -m : m;
 }
 
-__device__ __forceinline__ double corner_avg(const double (&nb)[3][3][3], int sx, int sy, int sz) {
-  const int z0 = sz < 0 ? 0 : 1, y0 = sy < 0 ? 0 : 1, x0 = sx < 0 ? 0 : 1;
-  double sum = 0.0;
+// The eight 2x2x2 corner sums of a 3x3x3 neighbourhood, accumulated while
+// its cells arrive in z, y, x order: corner (sx, sy, sz), index
+// (sx > 0) + 2 (sy > 0) + 4 (sz > 0), holds the cells whose offsets lie on its
+// side of the centre or at the centre along each axis, each sum starting
+// from zero and taking its eight cells in that same z, y, x order.
+struct CornerSums {
+  double c[8];
+  double centre;
+};
+__device__ __forceinline__ void corner_sums_begin(CornerSums &cs) {
 #pragma unroll
-  for (int z = 0; z < 2; ++z)
+  for (int n = 0; n < 8; ++n) cs.c[n] = 0.0;
+}
+template <int dz, int dy, int dx>
+__device__ __forceinline__ void corner_sums_add(CornerSums &cs, double v) {
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-      for (int x = 0; x < 2; ++x) sum = sum + nb[z0 + z][y0 + y][x0 + x];
-  return sum * 0.125;
+  for (int n = 0; n < 8; ++n) {
+    const int sx = n & 1, sy = (n >> 1) & 1, sz = (n >> 2) & 1;  // 1: the + side
+    const bool in_x = sx ? dx >= 1 : dx <= 1;
+    const bool in_y = sy ? dy >= 1 : dy <= 1;
+    const bool in_z = sz ? dz >= 1 : dz <= 1;
+    if (in_x && in_y && in_z) cs.c[n] = cs.c[n] + v;
+  }
+  if (dz == 1 && dy == 1 && dx == 1) cs.centre = v;
+}
+__device__ __forceinline__ double corner_avg(const CornerSums &cs, int sx, int sy, int sz) {
+  return cs.c[(sx > 0 ? 1 : 0) + (sy > 0 ? 2 : 0) + (sz > 0 ? 4 : 0)] * 0.125;
 }
 
-__device__ void second_order_a_slopes(const double (&nb)[3][3][3], double &fx, double &fy,
-                                      double &fz) {
-  const double q0 = nb[1][1][1];
+__device__ __forceinline__ void second_order_a_slopes(const CornerSums &cs, double &fx, double &fy,
+                                                      double &fz) {
+  const double q0 = cs.centre;
   const int c[4][3] = {{1, 1, 1}, {-1, 1, 1}, {1, -1, 1}, {1, 1, -1}};
   double dq[4];
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
-    const double up = corner_avg(nb, c[n][0], c[n][1], c[n][2]);
-    const double dn = corner_avg(nb, -c[n][0], -c[n][1], -c[n][2]);
+    const double up = corner_avg(cs, c[n][0], c[n][1], c[n][2]);
+    const double dn = corner_avg(cs, -c[n][0], -c[n][1], -c[n][2]);
     dq[n] = minmod(up - q0, q0 - dn);
   }
   const double sum = dq[1] + dq[2] + dq[3];
@@ -662,8 +679,10 @@ __device__ __forceinline__ int find_item(const int64_t *prefix, int32_t n, int64
 
 // One thread per parent cell that a listed box's cells refine (the box of
 // such cells in the parent's level, in x-fastest order): the 27-cell
-// neighbourhood of rho, rho v, rho E, rho e around it, the SecondOrderA slopes
-// of each, and for every one of its r^3 fine cells inside the box the
+// neighbourhood of rho, rho v, rho E, rho e around it (the density read once,
+// each quantity folded into its eight corner sums as its cells are read, so
+// no quantity's neighbourhood is held whole), the SecondOrderA slopes of
+// each, and for every one of its r^3 fine cells inside the box the
 // interpolant's values, stored as rho, v = (rho v)/rho, E, e.  A parent cell
 // whose fine cells fall in two boxes is interpolated by both, to the same
 // values.  The parent's state is read through parent_tab[parent] when given
@@ -708,37 +727,49 @@ fill_from_parent_kernel(const PatchDev *__restrict__ patches, const InterpItem *
   int64_t lc[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) lc[a] = cc[a] - item.pstart[a] + gc;
+  const int64_t o0 = ((lc[2] - 1) * nc[1] + (lc[1] - 1)) * nc[0] + (lc[0] - 1);
+  const S *rho_c = static_cast<const S *>(cd.rho);
   // the density of the neighbourhood, read once for all six quantities
-  double rn[3][3][3];
+  double rn[27];
+  auto cell = [&](int dz, int dy, int dx) __attribute__((always_inline)) {
+    return o0 + (dz * nc[1] + dy) * nc[0] + dx;
+  };
 #pragma unroll
-  for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
-        rn[dz][dy][dx] = double(static_cast<const S *>(cd.rho)[o]);
-      }
+  for (int m = 0; m < 27; ++m) rn[m] = double(rho_c[cell(m / 9, (m / 3) % 3, m % 3)]);
+  // one quantity's slopes from its neighbourhood: rho (comp 0), then rho times
+  // the stored field (velocities, E, e), folded into the corner sums as read
+  auto slopes = [&](int comp, double &q0, double &fx, double &fy,
+                    double &fz) __attribute__((always_inline)) {
+    // (pointers picked by value, not by a run-time index into the table's
+    // arrays, which would put the table in scratch memory)
+    const S *xs = comp == 1   ? static_cast<const S *>(cd.vel[0])
+                  : comp == 2 ? static_cast<const S *>(cd.vel[1])
+                  : comp == 3 ? static_cast<const S *>(cd.vel[2])
+                              : nullptr;
+    const double *xd = comp == 4 ? cd.etot : cd.eint;
+    CornerSums cs;
+    corner_sums_begin(cs);
+    auto value = [&](int m) __attribute__((always_inline)) {
+      if (comp == 0) return rn[m];
+      const int64_t o = cell(m / 9, (m / 3) % 3, m % 3);
+      return rn[m] * (xs ? double(xs[o]) : xd[o]);
+    };
+#define PPM_CORNER_CELL(DZ, DY, DX) corner_sums_add<DZ, DY, DX>(cs, value(DZ * 9 + DY * 3 + DX))
+#define PPM_CORNER_ROW(DZ, DY) \
+  PPM_CORNER_CELL(DZ, DY, 0); PPM_CORNER_CELL(DZ, DY, 1); PPM_CORNER_CELL(DZ, DY, 2)
+#define PPM_CORNER_PLANE(DZ) PPM_CORNER_ROW(DZ, 0); PPM_CORNER_ROW(DZ, 1); PPM_CORNER_ROW(DZ, 2)
+    PPM_CORNER_PLANE(0);
+    PPM_CORNER_PLANE(1);
+    PPM_CORNER_PLANE(2);
+#undef PPM_CORNER_PLANE
+#undef PPM_CORNER_ROW
+#undef PPM_CORNER_CELL
+    q0 = cs.centre;
+    second_order_a_slopes(cs, fx, fy, fz);
+  };
   double q0[6], fx[6], fy[6], fz[6];
 #pragma unroll
-  for (int comp = 0; comp < 6; ++comp) {
-    // the stored field whose product with rho is this component (none for rho)
-    const S *xs = comp >= 1 && comp <= 3 ? static_cast<const S *>(cd.vel[comp - 1]) : nullptr;
-    const double *xd = comp == 4 ? cd.etot : cd.eint;
-    double nb[3][3][3];
-#pragma unroll
-    for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-          const int64_t o = ((lc[2] + dz - 1) * nc[1] + (lc[1] + dy - 1)) * nc[0] + (lc[0] + dx - 1);
-          const double x = comp == 0 ? 0.0 : (xs ? double(xs[o]) : xd[o]);
-          nb[dz][dy][dx] = comp == 0 ? rn[dz][dy][dx] : rn[dz][dy][dx] * x;
-        }
-    q0[comp] = nb[1][1][1];
-    second_order_a_slopes(nb, fx[comp], fy[comp], fz[comp]);
-  }
+  for (int comp = 0; comp < 6; ++comp) slopes(comp, q0[comp], fx[comp], fy[comp], fz[comp]);
   S *rho_p = static_cast<S *>(fd.rho);
   S *vel[3] = {static_cast<S *>(fd.vel[0]), static_cast<S *>(fd.vel[1]),
                static_cast<S *>(fd.vel[2])};
